@@ -1,0 +1,72 @@
+"""Planted mistakes in a copy of the oracle must be caught by the dense replay pin.
+
+The copy is made from the oracle's source text on the CPU; the real oracle module
+is never modified.
+"""
+import os
+import sys
+import types
+
+import numpy as np
+import pytest
+
+from oracle import rss_oracle as O
+from paper_1609_08130_amd import workloads as W
+from tests import dense_rss
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "rss_oracle.py")
+
+MUTATIONS = {
+    "sign_in_X_RR": ("X_RR = Z_R - T.T @ Z_S", "X_RR = Z_R + T.T @ Z_S"),
+    "dropped_term_Z_N": ("Z_N = A_NR - A_NS @ T", "Z_N = A_NR + 0.0 * (A_NS @ T)"),
+    "wrong_index_schur": ("lev.store[(c, b)][spos, :] -= blk", "lev.store[(c, b)][spos, :] += 0.0 * blk"),
+    "transposed_solve": ("z[r.R] -= r.T.T @ z[r.S]", "z[r.R] -= (r.T.T @ z[r.S]) * 0.5"),
+    "proxy_rows_dropped": ("M = np.vstack(rows)", "M = np.vstack(rows[:-1] or [np.zeros((1, n))])"),
+}
+
+
+def _mutant(old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, old
+    name = "rss_oracle_mutant_%d" % abs(hash((old, new)))
+    mod = types.ModuleType(name)
+    sys.modules[name] = mod
+    exec(compile(text.replace(old, new), name, "exec"), mod.__dict__)
+    return mod
+
+
+_REF = {}
+
+
+def _agrees(mod, pts, p):
+    F = mod.factor(pts, mod.Params(**p.__dict__))
+    if "ref" not in _REF:
+        _REF["ref"] = dense_rss.replay(pts, p)
+    ref = _REF["ref"]
+    if len(F.records) != len(ref["steps"]):
+        return False
+    for st, rec in zip(ref["steps"], F.records):
+        if not (np.array_equal(st["S"], rec.S) and np.array_equal(st["R"], rec.R)):
+            return False
+    if not np.array_equal(F.top, ref["top"]):
+        return False
+    eye = np.eye(len(pts))
+    ok = np.allclose(mod.apply(F, eye), ref["F"], rtol=0, atol=1e-9)
+    ok &= np.allclose(mod.solve(F, eye), np.linalg.inv(ref["F"]), rtol=0, atol=1e-8)
+    return bool(ok)
+
+
+def test_unmutated_copy_agrees():
+    pts, p = W.grid_points(24), O.Params(**W.problem(24, 1e-3, leaf_size=16))
+    assert _agrees(_mutant("TAU = 1e-11", "TAU = 1e-11"), pts, p)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name):
+    pts, p = W.grid_points(24), O.Params(**W.problem(24, 1e-3, leaf_size=16))
+    mod = _mutant(*MUTATIONS[name])
+    try:
+        agrees = _agrees(mod, pts, p)
+    except Exception:
+        agrees = False
+    assert not agrees
