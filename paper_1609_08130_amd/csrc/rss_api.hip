@@ -1,0 +1,845 @@
+// C ABI of librss and the host-side driver of Algorithm 1 (Section 3.3).
+//
+// rss_factor_create: tree -> leaf block store -> for every skeletonized level (leaves
+// first): for every colour of the 3x3 colouring, one launch each of the ID, elimination
+// and Schur kernels over all boxes of that colour -> level transition (B_parent = union
+// of child skeletons) -> top block LU.  The host synchronizes once per level to size the
+// next level's store and to collect statistics.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rss_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    rss_status st;
+};
+
+[[noreturn]] void fail(rss_status st, const std::string& msg) {
+    g_err = msg;
+    throw Fail{st};
+}
+
+#define HIPCHK(x)                                                                                 \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) fail(RSS_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(RSS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+template <class T>
+T* dalloc(rss_factor f, size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(RSS_E_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    f->allocs.push_back(p);
+    f->bytes_device += n * sizeof(T);
+    return (T*)p;
+}
+
+void dfree(rss_factor f, void* p, size_t bytes) {
+    if (!p) return;
+    auto it = std::find(f->allocs.begin(), f->allocs.end(), p);
+    if (it != f->allocs.end()) f->allocs.erase(it);
+    f->bytes_device -= bytes;
+    (void)hipFree(p);
+}
+
+template <class T>
+std::vector<T> d2h(const T* d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) {
+        HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return h;
+}
+
+template <class T>
+T* h2d(rss_factor f, const std::vector<T>& h, hipStream_t s) {
+    T* d = dalloc<T>(f, h.size());
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+int colour_of(int b, int nb) { return (b % nb) % 3 + 3 * ((b / nb) % 3); }
+
+__global__ void k_init_active(const int* cnt, int* nact, int* apos, int nbox, int nmax) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nbox * nmax) return;
+    int b = (int)(e / nmax), i = (int)(e % nmax);
+    apos[e] = i;
+    if (i == 0) nact[b] = cnt[b];
+}
+
+void init_active(rss::Level& L, hipStream_t s) {
+    int64_t tot = (int64_t)L.nbox * L.nmax;
+    k_init_active<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(L.cnt, L.nact, L.apos, L.nbox, L.nmax);
+    check_launch();
+}
+
+void alloc_level_lists(rss_factor f, rss::Level& L) {
+    L.cnt = dalloc<int>(f, L.nbox);
+    L.gidx = dalloc<int>(f, (size_t)L.nbox * L.nmax);
+    L.nact = dalloc<int>(f, L.nbox);
+    L.apos = dalloc<int>(f, (size_t)L.nbox * L.nmax);
+    L.store = dalloc<double>(f, (size_t)L.nbox * rss::kNbr * L.nmax * L.nmax);
+}
+
+void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
+    size_t nbox = L.nbox, nm = L.nmax, ldJ = L.ldJ;
+    L.krank = dalloc<int>(f, nbox);
+    L.nJ = dalloc<int>(f, nbox);
+    L.spos = dalloc<int>(f, nbox * nm);
+    L.rpos = dalloc<int>(f, nbox * nm);
+    L.Sg = dalloc<int>(f, nbox * nm);
+    L.Rg = dalloc<int>(f, nbox * nm);
+    L.Jg = dalloc<int>(f, nbox * ldJ);
+    L.T = dalloc<double>(f, nbox * nm * nm);
+    L.XJR = dalloc<double>(f, nbox * ldJ * nm);
+    L.G = dalloc<double>(f, nbox * nm * ldJ);
+    L.XRR = dalloc<double>(f, nbox * nm * nm);
+    L.Xinv = dalloc<double>(f, nbox * nm * nm);
+    L.mrows = dalloc<int>(f, nbox);
+    L.logdet_part = dalloc<double>(f, nbox);
+    L.sign_part = dalloc<int>(f, nbox);
+    if (mixed) {
+        L.XJR32 = dalloc<float>(f, nbox * ldJ * nm);
+        L.G32 = dalloc<float>(f, nbox * nm * ldJ);
+        L.Xinv32 = dalloc<float>(f, nbox * nm * nm);
+        L.T32 = dalloc<float>(f, nbox * nm * nm);
+    }
+}
+
+void free_store(rss_factor f, rss::Level& L) {
+    dfree(f, L.store, sizeof(double) * (size_t)L.nbox * rss::kNbr * L.nmax * L.nmax);
+    L.store = nullptr;
+}
+
+struct EvTimer {
+    std::vector<hipEvent_t> ev;
+    hipEvent_t rec(hipStream_t s) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventRecord(e, s));
+        ev.push_back(e);
+        return e;
+    }
+    ~EvTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+float ev_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+}
+
+void destroy_all(rss_factor f) {
+    for (void* p : f->allocs) (void)hipFree(p);
+    f->allocs.clear();
+}
+
+// phase indices of rss_factor_s::phase_ms
+enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
+const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "transition", "top", "total"};
+
+void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
+    const rss_params& p = f->params;
+    auto t_start = std::chrono::steady_clock::now();
+    EvTimer evs;
+    hipEvent_t e0 = evs.rec(s);
+    f->phase_ms.assign(PH_N, 0.0);
+    f->kernel_launches.assign(PH_N, 0);
+
+    f->pts = dalloc<double>(f, (size_t)f->n * 2);
+    HIPCHK(hipMemcpyAsync(f->pts, d_points, sizeof(double) * 2 * f->n, hipMemcpyDeviceToDevice, s));
+    f->flag = dalloc<int>(f, 4);
+    HIPCHK(hipMemsetAsync(f->flag, 0, sizeof(int) * 4, s));
+
+    // root box
+    double lo_x = p.root_lo[0], lo_y = p.root_lo[1], side = p.root_side;
+    if (!(side > 0)) {
+        std::vector<double> hp = d2h(f->pts, (size_t)f->n * 2, s);
+        double mnx = hp[0], mny = hp[1], mxx = hp[0], mxy = hp[1];
+        for (int64_t i = 0; i < f->n; ++i) {
+            mnx = std::min(mnx, hp[2 * i]); mxx = std::max(mxx, hp[2 * i]);
+            mny = std::min(mny, hp[2 * i + 1]); mxy = std::max(mxy, hp[2 * i + 1]);
+        }
+        lo_x = mnx; lo_y = mny;
+        side = std::max(mxx - mnx, mxy - mny);
+        if (!(side > 0)) side = 1.0;
+        if (!std::isfinite(side)) fail(RSS_E_ARG, "non-finite point");
+    }
+    f->kp.lo_x = lo_x; f->kp.lo_y = lo_y; f->kp.side = side;
+    rss::launch_validate_points(f->pts, f->n, lo_x, lo_y, side, f->flag, s);
+    check_launch();
+
+    // depth: shallowest uniform level whose boxes hold <= leaf_size points
+    int* counts = nullptr;
+    size_t counts_n = 0;
+    int depth = -1, maxcount = 0;
+    int t0 = 0;
+    while (t0 < rss::kMaxDepth && (double)p.leaf_size * std::pow(4.0, t0 + 1) < (double)f->n) ++t0;
+    for (int t = t0; t <= rss::kMaxDepth; ++t) {
+        size_t nbox = (size_t)1 << (2 * t);
+        if (counts_n < nbox + 1) {
+            if (counts) dfree(f, counts, counts_n * sizeof(int));
+            counts = dalloc<int>(f, nbox + 1);
+            counts_n = nbox + 1;
+        }
+        rss::launch_count_boxes(f->pts, f->n, t, lo_x, lo_y, side, counts, s);
+        check_launch();
+        int mx = 0, flag = 0;
+        HIPCHK(hipMemcpyAsync(&mx, counts + nbox, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (flag & 1) fail(RSS_E_ARG, "non-finite point or point outside the root box");
+        if (mx <= p.leaf_size) {
+            depth = t;
+            maxcount = mx;
+            break;
+        }
+    }
+    if (depth < 0) fail(RSS_E_UNSUPPORTED, "tree deeper than 12 levels (clustered or duplicate points)");
+    f->depth = depth;
+
+    // leaf level
+    rss::Level L;
+    L.t = depth; L.nb = 1 << depth; L.nbox = L.nb * L.nb;
+    L.nmax = std::max(maxcount, 1);
+    L.ldJ = 9 * L.nmax;
+    alloc_level_lists(f, L);
+    rss::launch_leaf_lists(f->pts, f->n, depth, lo_x, lo_y, side, L.cnt, L.gidx, L.nmax, L.nbox, s);
+    check_launch();
+    dfree(f, counts, counts_n * sizeof(int));
+    hipEvent_t e1 = evs.rec(s);
+    rss::launch_leaf_store(L, f->pts, f->kp, f->flag, s);
+    check_launch();
+    hipEvent_t e2 = evs.rec(s);
+    init_active(L, s);
+
+    // proxy template (unit circle, equispaced from angle 0)
+    std::vector<double> tmpl(2 * p.n_proxy);
+    for (int i = 0; i < p.n_proxy; ++i) {
+        double th = 2.0 * M_PI * (double)i / (double)p.n_proxy;
+        tmpl[2 * i] = std::cos(th);
+        tmpl[2 * i + 1] = std::sin(th);
+    }
+    double* ptmpl = h2d(f, tmpl, s);
+
+    HIPCHK(hipStreamSynchronize(s));
+    f->phase_ms[PH_TREE] += ev_ms(e0, e1);
+    f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
+    {
+        int flag = 0;
+        HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (flag & 2) fail(RSS_E_ARG, "duplicate points");
+    }
+
+    const bool mixed = p.precision == RSS_MIXED;
+    double* work = nullptr;
+    size_t work_n = 0;
+
+    while (L.t >= 2) {
+        const int nb = L.nb;
+        L.colour_boxes.assign(9, {});
+        for (int b = 0; b < L.nbox; ++b) L.colour_boxes[colour_of(b, nb)].push_back(b);
+        size_t maxc = 0;
+        for (auto& v : L.colour_boxes) maxc = std::max(maxc, v.size());
+        for (auto& v : L.colour_boxes) L.d_colour_boxes.push_back(h2d(f, v, s));
+        alloc_level_records(f, L, mixed);
+        int cpt = L.nmax <= 64 ? 1 : (L.nmax <= 128 ? 2 : 4);
+        size_t np = 64 * cpt;
+        size_t need = maxc * std::max(np * np, (size_t)L.nmax * L.nmax);
+        if (need > work_n) {
+            if (work) dfree(f, work, work_n * sizeof(double));
+            work = dalloc<double>(f, need);
+            work_n = need;
+        }
+        std::vector<hipEvent_t> ev;
+        ev.push_back(evs.rec(s));
+        for (int col = 0; col < 9; ++col) {
+            int nbx = (int)L.colour_boxes[col].size();
+            if (nbx == 0) continue;
+            const int* bx = L.d_colour_boxes[col];
+            rss::launch_id(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
+            check_launch();
+            ev.push_back(evs.rec(s));
+            rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, s);
+            check_launch();
+            ev.push_back(evs.rec(s));
+            rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, s);
+            check_launch();
+            ev.push_back(evs.rec(s));
+            f->kernel_launches[PH_ID] += 1;
+            f->kernel_launches[PH_ELIM] += 1;
+            f->kernel_launches[PH_SCHUR] += 1;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 1; i < ev.size(); i += 3) {
+            f->phase_ms[PH_ID] += ev_ms(ev[i - 1], ev[i]);
+            f->phase_ms[PH_ELIM] += ev_ms(ev[i], ev[i + 1]);
+            f->phase_ms[PH_SCHUR] += ev_ms(ev[i + 1], ev[i + 2]);
+        }
+        int flag = 0;
+        HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (flag & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
+
+        // statistics and solve schedule
+        L.h_cnt = d2h(L.cnt, L.nbox, s);
+        L.h_k = d2h(L.krank, L.nbox, s);
+        std::vector<int> hJ = d2h(L.nJ, L.nbox, s);
+        std::vector<int> hm = d2h(L.mrows, L.nbox, s);
+        L.rec_boxes.assign(9, {});
+        for (int col = 0; col < 9; ++col)
+            for (int b : L.colour_boxes[col])
+                if (hJ[b] > 0) L.rec_boxes[col].push_back(b);
+        for (auto& v : L.rec_boxes) L.d_rec_boxes.push_back(h2d(f, v, s));
+        rss::LevelStats st;
+        st.depth = L.t; st.boxes = L.nbox; st.nmax = L.nmax;
+        for (int b = 0; b < L.nbox; ++b) {
+            double n = L.h_cnt[b], k = L.h_k[b], r = n - k, J = hJ[b], m = hm[b];
+            if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
+            if (J <= 0) continue;
+            st.records += 1;
+            st.sum_k += k; st.sum_r += r; st.sum_J += J;
+            st.max_k = std::max(st.max_k, (int)k);
+            st.max_J = std::max(st.max_J, (int)J);
+            st.flops_x += 4.0 * J * r * k + 4.0 * r * r * k;
+            st.flops_lu += 2.0 / 3.0 * r * r * r;
+            st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
+            st.flops_schur += 2.0 * J * J * r;
+            st.bytes_schur += 16.0 * J * J + (mixed ? 4.0 : 8.0) * 2.0 * J * r;
+            st.bytes_solve64 += 8.0 * (2.0 * J * r + 2.0 * k * r + r * r);
+            st.bytes_solve32 += 4.0 * (2.0 * J * r + 2.0 * k * r + r * r);
+        }
+        f->stats.push_back(st);
+
+        if (L.t == 2) break;
+
+        // level transition
+        hipEvent_t et0 = evs.rec(s);
+        rss::Level P;
+        P.t = L.t - 1; P.nb = L.nb / 2; P.nbox = P.nb * P.nb;
+        P.cnt = dalloc<int>(f, P.nbox);
+        rss::launch_parent_counts(L, P, s);
+        check_launch();
+        std::vector<int> pc = d2h(P.cnt, P.nbox, s);
+        int pmax = 1;
+        for (int v : pc) pmax = std::max(pmax, v);
+        if (pmax > rss::kMaxBox) fail(RSS_E_UNSUPPORTED, "a box holds " + std::to_string(pmax) +
+                                                             " active DOFs (limit 256); lower the tolerance demand");
+        P.nmax = pmax;
+        P.ldJ = 9 * P.nmax;
+        P.gidx = dalloc<int>(f, (size_t)P.nbox * P.nmax);
+        P.nact = dalloc<int>(f, P.nbox);
+        P.apos = dalloc<int>(f, (size_t)P.nbox * P.nmax);
+        P.store = dalloc<double>(f, (size_t)P.nbox * rss::kNbr * P.nmax * P.nmax);
+        int* pmap = dalloc<int>(f, (size_t)P.nbox * P.nmax);
+        rss::launch_parent_lists(L, P, pmap, s);
+        check_launch();
+        rss::launch_parent_store(L, P, pmap, f->pts, f->kp, s);
+        check_launch();
+        init_active(P, s);
+        hipEvent_t et1 = evs.rec(s);
+        HIPCHK(hipStreamSynchronize(s));
+        f->phase_ms[PH_TRANS] += ev_ms(et0, et1);
+        dfree(f, pmap, sizeof(int) * (size_t)P.nbox * P.nmax);
+        free_store(f, L);
+        f->levels.push_back(std::move(L));
+        L = std::move(P);
+    }
+    if (work) dfree(f, work, work_n * sizeof(double));
+
+    // top block
+    hipEvent_t eT0 = evs.rec(s);
+    std::vector<int> hn = d2h(L.nact, L.nbox, s);
+    int64_t ntop = 0;
+    for (int v : hn) ntop += v;
+    f->ntop = ntop;
+    f->top_idx = dalloc<int>(f, ntop);
+    int* tmap = dalloc<int>(f, ntop);
+    f->top_A = dalloc<double>(f, (size_t)ntop * ntop);
+    double* LU = dalloc<double>(f, (size_t)ntop * ntop);
+    f->top_inv = dalloc<double>(f, (size_t)ntop * ntop);
+    int* piv = dalloc<int>(f, ntop);
+    double* dlog = dalloc<double>(f, 1);
+    int* dsign = dalloc<int>(f, 1);
+    rss::launch_top_lists(L, f->top_idx, tmap, ntop, s);
+    check_launch();
+    rss::launch_top_assemble(L, tmap, f->top_idx, ntop, f->pts, f->kp, f->top_A, s);
+    check_launch();
+    HIPCHK(hipMemcpyAsync(LU, f->top_A, sizeof(double) * ntop * ntop, hipMemcpyDeviceToDevice, s));
+    rss::launch_lu_inverse(LU, f->top_inv, ntop, piv, nullptr, f->flag, dlog, dsign, s);
+    check_launch();
+    if (mixed && ntop > 0) {
+        f->top_inv32 = dalloc<float>(f, (size_t)ntop * ntop);
+        rss::launch_convert_f32(f->top_inv, f->top_inv32, ntop * ntop, s);
+        check_launch();
+    }
+    hipEvent_t eT1 = evs.rec(s);
+    HIPCHK(hipStreamSynchronize(s));
+    f->phase_ms[PH_TOP] += ev_ms(eT0, eT1);
+    {
+        int flag = 0;
+        HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
+        if (flag & 8) fail(RSS_E_SINGULAR, "singular top block");
+        double lg = 0;
+        int sg = 1;
+        if (ntop > 0) {
+            HIPCHK(hipMemcpy(&lg, dlog, sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&sg, dsign, sizeof(int), hipMemcpyDeviceToHost));
+        }
+        f->top_logdet = lg;
+        f->top_sign = sg;
+    }
+    dfree(f, LU, sizeof(double) * ntop * ntop);
+    dfree(f, tmap, sizeof(int) * ntop);
+    dfree(f, piv, sizeof(int) * ntop);
+    free_store(f, L);
+    if (L.krank) f->levels.push_back(std::move(L));
+    else {
+        // unskeletonized final level: lists are no longer needed
+        dfree(f, L.cnt, sizeof(int) * L.nbox);
+        dfree(f, L.gidx, sizeof(int) * (size_t)L.nbox * L.nmax);
+        dfree(f, L.nact, sizeof(int) * L.nbox);
+        dfree(f, L.apos, sizeof(int) * (size_t)L.nbox * L.nmax);
+    }
+    f->work_elems = (size_t)f->n * 4 + (size_t)ntop * 8 + 4096;
+    f->work = dalloc<double>(f, f->work_elems);
+    hipEvent_t eE = evs.rec(s);
+    HIPCHK(hipStreamSynchronize(s));
+    f->phase_ms[PH_TOTAL] = ev_ms(e0, eE);
+    f->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+}
+
+rss_status guard_factor(rss_factor f) {
+    if (!f) {
+        g_err = "NULL factor";
+        return RSS_E_ARG;
+    }
+    return RSS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+void rss_params_default(rss_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(rss_params);
+    p->dim = 2;
+    p->diag = 1.0;
+    p->weight = 1.0;
+    p->tol = 1e-6;
+    p->leaf_size = 64;
+    p->n_proxy = 16;
+    p->proxy_radius = 1.25;
+    p->root_lo[0] = 0.0;
+    p->root_lo[1] = 0.0;
+    p->root_side = 1.0;
+    p->precision = RSS_FP64;
+}
+
+const char* rss_last_error(void) { return g_err.c_str(); }
+
+rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params* p, void* stream,
+                             rss_factor* out) {
+    g_err.clear();
+    if (out) *out = nullptr;
+    if (!out || !p || !d_points) {
+        g_err = "NULL argument";
+        return RSS_E_ARG;
+    }
+    if (p->struct_size != sizeof(rss_params)) {
+        g_err = "rss_params.struct_size mismatch (header/library version)";
+        return RSS_E_ARG;
+    }
+    if (p->dim != 2) { g_err = "dim must be 2"; return RSS_E_UNSUPPORTED; }
+    if (n < 1 || n > (int64_t)1 << 30) { g_err = "n out of range"; return RSS_E_ARG; }
+    if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) { g_err = "tol must be finite and >= 0"; return RSS_E_ARG; }
+    if (p->leaf_size < 1 || p->leaf_size > rss::kMaxBox) { g_err = "leaf_size must be in [1, 256]"; return RSS_E_ARG; }
+    if (p->n_proxy < 1 || p->n_proxy > rss::kMaxProxy) { g_err = "n_proxy must be in [1, 64]"; return RSS_E_ARG; }
+    if (!(p->proxy_radius > 0.5 * std::sqrt(2.0)) || !(p->proxy_radius <= 2.5)) {
+        g_err = "proxy_radius must be in (0.5*sqrt(2), 2.5] box sides";
+        return RSS_E_ARG;
+    }
+    if (!std::isfinite(p->diag) || !std::isfinite(p->weight)) { g_err = "diag/weight not finite"; return RSS_E_ARG; }
+    if (p->precision != RSS_FP64 && p->precision != RSS_MIXED) { g_err = "bad precision"; return RSS_E_ARG; }
+    rss_factor f = new (std::nothrow) rss_factor_s();
+    if (!f) { g_err = "host allocation failed"; return RSS_E_NOMEM; }
+    f->params = *p;
+    f->n = n;
+    f->kp.coef = -p->weight / (4.0 * M_PI);
+    f->kp.diag = p->diag;
+    f->kp.tol = p->tol;
+    f->kp.tau = rss::kTau;
+    f->kp.n_proxy = p->n_proxy;
+    f->kp.proxy_radius = p->proxy_radius;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        factor_impl(f, d_points, s);
+    } catch (const Fail& e) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        destroy_all(f);
+        delete f;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        (void)hipStreamSynchronize(s);
+        destroy_all(f);
+        delete f;
+        g_err = "host allocation failed";
+        return RSS_E_NOMEM;
+    }
+    *out = f;
+    return RSS_OK;
+}
+
+rss_status rss_factor_destroy(rss_factor f) {
+    if (!f) return RSS_OK;
+    destroy_all(f);
+    delete f;
+    return RSS_OK;
+}
+
+static void solve_impl(rss_factor f, double* z, int nrhs, int64_t ld, int use32, hipStream_t s) {
+    for (auto& L : f->levels)
+        for (int col = 0; col < 9; ++col) {
+            rss::launch_solve_fwd(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), z, nrhs, ld, use32, s);
+            check_launch();
+        }
+    if ((size_t)f->ntop * nrhs > f->work_elems) fail(RSS_E_ARG, "nrhs too large for the top workspace");
+    rss::launch_top_apply(f->top_idx, f->ntop, f->top_inv, use32 ? f->top_inv32 : nullptr, z, nrhs, ld, f->work, s);
+    check_launch();
+    for (auto it = f->levels.rbegin(); it != f->levels.rend(); ++it)
+        for (int col = 8; col >= 0; --col) {
+            rss::launch_solve_bwd(*it, it->d_rec_boxes[col], (int)it->rec_boxes[col].size(), z, nrhs, ld, use32, s);
+            check_launch();
+        }
+}
+
+rss_status rss_solve(rss_factor f, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, int32_t use_fp32,
+                     void* stream) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_b || !d_x || nrhs < 1 || ld < f->n) { g_err = "bad solve arguments"; return RSS_E_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    const int use32 = (use_fp32 && f->params.precision == RSS_MIXED) ? 1 : 0;
+    try {
+        if (d_x != d_b) rss::launch_copy_cols(d_b, ld, d_x, ld, f->n, nrhs, s);
+        check_launch();
+        solve_impl(f, d_x, nrhs, ld, use32, s);
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+rss_status rss_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld, void* stream) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_x || !d_y || nrhs < 1 || ld < f->n || d_x == d_y) { g_err = "bad apply arguments"; return RSS_E_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        rss::launch_copy_cols(d_x, ld, d_y, ld, f->n, nrhs, s);
+        check_launch();
+        for (auto& L : f->levels)
+            for (int col = 0; col < 9; ++col) {
+                rss::launch_apply_fwd(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), d_y, nrhs, ld, s);
+                check_launch();
+            }
+        if ((size_t)f->ntop * nrhs > f->work_elems) fail(RSS_E_ARG, "nrhs too large for the top workspace");
+        rss::launch_top_apply(f->top_idx, f->ntop, f->top_A, nullptr, d_y, nrhs, ld, f->work, s);
+        check_launch();
+        for (auto it = f->levels.rbegin(); it != f->levels.rend(); ++it)
+            for (int col = 8; col >= 0; --col) {
+                rss::launch_apply_bwd(*it, it->d_rec_boxes[col], (int)it->rec_boxes[col].size(), d_y, nrhs, ld, s);
+                check_launch();
+            }
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+rss_status rss_matvec(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld, void* stream) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_x || !d_y || nrhs < 1 || ld < f->n || d_x == d_y) { g_err = "bad matvec arguments"; return RSS_E_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        for (int h = 0; h < nrhs; ++h) {
+            rss::launch_matvec_direct(f->pts, f->n, f->kp, d_x + h * ld, d_y + h * ld, s);
+            check_launch();
+        }
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+static double ddot(rss_factor f, const double* x, const double* y, double* part, hipStream_t s) {
+    int nbk = rss::dot_partial_blocks(f->n);
+    rss::launch_dot_partial(x, y, f->n, part, s);
+    check_launch();
+    std::vector<double> h = d2h(part, nbk, s);
+    double acc = 0.0;
+    for (double v : h) acc += v;
+    return acc;
+}
+
+rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, int32_t maxit, int32_t restart,
+                     int32_t use_fp32, void* stream, int32_t* iters, double* relres) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_b || !d_x || d_b == d_x || !(rtol > 0) || maxit < 1 || restart < 1 || restart > 200) {
+        g_err = "bad gmres arguments";
+        return RSS_E_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int use32 = (use_fp32 && f->params.precision == RSS_MIXED) ? 1 : 0;
+    const int64_t n = f->n;
+    double* V = nullptr;
+    double* Z = nullptr;
+    double* rvec = nullptr;
+    double* wvec = nullptr;
+    double* part = nullptr;
+    rss_status st = RSS_OK;
+    int it = 0;
+    double rr = 1.0;
+    try {
+        V = dalloc<double>(f, (size_t)n * (restart + 1));
+        Z = dalloc<double>(f, (size_t)n * restart);
+        rvec = dalloc<double>(f, n);
+        wvec = dalloc<double>(f, n);
+        part = dalloc<double>(f, 1024);
+        HIPCHK(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
+        const double nb = std::sqrt(ddot(f, d_b, d_b, part, s));
+        if (nb == 0.0) {
+            rr = 0.0;
+        } else {
+            rss::launch_scal_copy(1.0, d_b, rvec, n, s);
+            check_launch();
+            std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1);
+            while (true) {
+                double beta = std::sqrt(ddot(f, rvec, rvec, part, s));
+                rr = beta / nb;
+                if (rr <= rtol || it >= maxit) break;
+                rss::launch_scal_copy(1.0 / beta, rvec, V, n, s);
+                check_launch();
+                std::fill(H.begin(), H.end(), 0.0);
+                std::fill(g.begin(), g.end(), 0.0);
+                g[0] = beta;
+                int m = 0;
+                for (int j = 0; j < restart; ++j) {
+                    double* vj = V + (size_t)j * n;
+                    double* zj = Z + (size_t)j * n;
+                    rss::launch_scal_copy(1.0, vj, zj, n, s);
+                    check_launch();
+                    solve_impl(f, zj, 1, n, use32, s);
+                    rss::launch_matvec_direct(f->pts, n, f->kp, zj, wvec, s);
+                    check_launch();
+                    for (int i = 0; i <= j; ++i) {
+                        double hij = ddot(f, wvec, V + (size_t)i * n, part, s);
+                        H[i + (size_t)j * (restart + 1)] = hij;
+                        rss::launch_axpy(-hij, V + (size_t)i * n, wvec, n, s);
+                        check_launch();
+                    }
+                    double hn = std::sqrt(ddot(f, wvec, wvec, part, s));
+                    H[j + 1 + (size_t)j * (restart + 1)] = hn;
+                    for (int i = 0; i < j; ++i) {
+                        double a = H[i + (size_t)j * (restart + 1)], c2 = H[i + 1 + (size_t)j * (restart + 1)];
+                        H[i + (size_t)j * (restart + 1)] = cs[i] * a + sn[i] * c2;
+                        H[i + 1 + (size_t)j * (restart + 1)] = -sn[i] * a + cs[i] * c2;
+                    }
+                    double hjj = H[j + (size_t)j * (restart + 1)], hj1 = H[j + 1 + (size_t)j * (restart + 1)];
+                    double den = std::hypot(hjj, hj1);
+                    cs[j] = hjj / den;
+                    sn[j] = hj1 / den;
+                    H[j + (size_t)j * (restart + 1)] = den;
+                    H[j + 1 + (size_t)j * (restart + 1)] = 0.0;
+                    g[j + 1] = -sn[j] * g[j];
+                    g[j] = cs[j] * g[j];
+                    ++it;
+                    m = j + 1;
+                    if (std::fabs(g[j + 1]) / nb <= rtol || hn == 0.0 || it >= maxit) break;
+                    rss::launch_scal_copy(1.0 / hn, wvec, V + (size_t)(j + 1) * n, n, s);
+                    check_launch();
+                }
+                std::vector<double> y(m);
+                for (int i = m - 1; i >= 0; --i) {
+                    double acc = g[i];
+                    for (int l = i + 1; l < m; ++l) acc -= H[i + (size_t)l * (restart + 1)] * y[l];
+                    y[i] = acc / H[i + (size_t)i * (restart + 1)];
+                }
+                for (int i = 0; i < m; ++i) {
+                    rss::launch_axpy(y[i], Z + (size_t)i * n, d_x, n, s);
+                    check_launch();
+                }
+                rss::launch_matvec_direct(f->pts, n, f->kp, d_x, wvec, s);
+                check_launch();
+                rss::launch_scal_copy(1.0, d_b, rvec, n, s);
+                check_launch();
+                rss::launch_axpy(-1.0, wvec, rvec, n, s);
+                check_launch();
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (rr > rtol) {
+            st = RSS_E_NOCONV;
+            g_err = "gmres did not reach rtol within maxit";
+        }
+    } catch (const Fail& e) {
+        st = e.st;
+    }
+    (void)hipStreamSynchronize(s);
+    if (V) dfree(f, V, sizeof(double) * n * (restart + 1));
+    if (Z) dfree(f, Z, sizeof(double) * n * restart);
+    if (rvec) dfree(f, rvec, sizeof(double) * n);
+    if (wvec) dfree(f, wvec, sizeof(double) * n);
+    if (part) dfree(f, part, sizeof(double) * 1024);
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    return st;
+}
+
+rss_status rss_logdet(rss_factor f, double* sign, double* logabs) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!sign || !logabs) { g_err = "NULL argument"; return RSS_E_ARG; }
+    try {
+        double total = f->top_logdet;
+        int sg = f->top_sign;
+        for (auto& L : f->levels) {
+            std::vector<double> ld = d2h(L.logdet_part, L.nbox, nullptr);
+            std::vector<int> sgs = d2h(L.sign_part, L.nbox, nullptr);
+            std::vector<int> hJ = d2h(L.nJ, L.nbox, nullptr);
+            for (int b = 0; b < L.nbox; ++b)
+                if (hJ[b] > 0) {
+                    total += ld[b];
+                    sg *= sgs[b];
+                }
+        }
+        *sign = (double)sg;
+        *logabs = total;
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+rss_status rss_shape(rss_factor f, int32_t* depth, int64_t* n_top) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (depth) *depth = f->depth;
+    if (n_top) *n_top = f->ntop;
+    return RSS_OK;
+}
+
+rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel, int32_t cap_s, int32_t* ns,
+                        int64_t* red, int32_t cap_r, int32_t* nr) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    const rss::Level* L = nullptr;
+    for (auto& l : f->levels)
+        if (l.t == depth) L = &l;
+    if (!L || box < 0 || box >= L->nbox || !ns || !nr) {
+        g_err = "no skeletonized level / box with these indices";
+        return RSS_E_ARG;
+    }
+    try {
+        int n = L->h_cnt[box], k = L->h_k[box];
+        int nJ = 0;
+        HIPCHK(hipMemcpy(&nJ, L->nJ + box, sizeof(int), hipMemcpyDeviceToHost));
+        int r = nJ > 0 ? n - k : 0;
+        int s_cnt = nJ > 0 ? k : n;
+        *ns = s_cnt;
+        *nr = r;
+        if (s_cnt > cap_s || r > cap_r || (s_cnt && !skel) || (r && !red)) {
+            g_err = "capacity too small";
+            return RSS_E_ARG;
+        }
+        std::vector<int> hs(std::max(s_cnt, 1)), hr(std::max(r, 1));
+        if (nJ > 0) {
+            if (k) HIPCHK(hipMemcpy(hs.data(), L->Sg + (size_t)box * L->nmax, sizeof(int) * k, hipMemcpyDeviceToHost));
+            if (r) HIPCHK(hipMemcpy(hr.data(), L->Rg + (size_t)box * L->nmax, sizeof(int) * r, hipMemcpyDeviceToHost));
+        } else if (n) {
+            HIPCHK(hipMemcpy(hs.data(), L->gidx + (size_t)box * L->nmax, sizeof(int) * n, hipMemcpyDeviceToHost));
+        }
+        for (int i = 0; i < s_cnt; ++i) skel[i] = hs[i];
+        for (int i = 0; i < r; ++i) red[i] = hr[i];
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+rss_status rss_top_set(rss_factor f, int64_t* idx, int64_t cap, int64_t* count) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!count) { g_err = "NULL count"; return RSS_E_ARG; }
+    *count = f->ntop;
+    if (cap < f->ntop || (f->ntop && !idx)) { g_err = "capacity too small"; return RSS_E_ARG; }
+    try {
+        std::vector<int> h = d2h(f->top_idx, f->ntop, nullptr);
+        for (int64_t i = 0; i < f->ntop; ++i) idx[i] = h[i];
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!buf || cap < 1) { g_err = "bad buffer"; return RSS_E_ARG; }
+    std::ostringstream o;
+    o.precision(17);
+    o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
+      << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
+      << ",\"bytes_device\":" << f->bytes_device << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
+    for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
+    o << "},\"launches\":{";
+    for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->kernel_launches[i];
+    o << "},\"levels\":[";
+    for (size_t i = 0; i < f->stats.size(); ++i) {
+        const auto& s = f->stats[i];
+        o << (i ? "," : "") << "{\"depth\":" << s.depth << ",\"boxes\":" << s.boxes << ",\"nmax\":" << s.nmax
+          << ",\"records\":" << s.records << ",\"sum_k\":" << s.sum_k << ",\"sum_r\":" << s.sum_r
+          << ",\"sum_J\":" << s.sum_J << ",\"max_k\":" << s.max_k << ",\"max_J\":" << s.max_J
+          << ",\"flops_id\":" << s.flops_id << ",\"flops_x\":" << s.flops_x << ",\"flops_lu\":" << s.flops_lu
+          << ",\"flops_g\":" << s.flops_g << ",\"flops_schur\":" << s.flops_schur
+          << ",\"bytes_schur\":" << s.bytes_schur << ",\"bytes_solve64\":" << s.bytes_solve64
+          << ",\"bytes_solve32\":" << s.bytes_solve32 << "}";
+    }
+    o << "]}";
+    std::string js = o.str();
+    int64_t m = std::min<int64_t>(cap - 1, (int64_t)js.size());
+    std::memcpy(buf, js.data(), m);
+    buf[m] = 0;
+    return RSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations of librss: level data, factor records and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rss.h"
+
+namespace rss {
+
+constexpr int kMaxDepth = 12;      // deepest uniform tree level (4^12 leaf boxes)
+constexpr int kMaxBox = 256;       // largest active DOF count of one box
+constexpr int kMaxProxy = 64;
+constexpr int kNbr = 25;           // stored block pairs per box: offsets (dx, dy) in [-2, 2]^2
+constexpr double kTau = 1e-11;     // pivot tie window relative to the first pivot norm
+
+// offset slot of box b seen from box a: (dy + 2) * 5 + (dx + 2)
+__host__ __device__ inline int nbr_slot(int dx, int dy) { return (dy + 2) * 5 + (dx + 2); }
+
+struct KernelParams {
+    double coef;     // w K(z) = coef * log|z|^2, coef = -w / (4 pi)
+    double diag;
+    double tol;
+    double tau;
+    int n_proxy;
+    double proxy_radius;
+    double lo_x, lo_y, side;   // root box
+};
+
+// One tree level: active lists at the start of the level, the block store, and the
+// strong-skeletonization records of its boxes.
+struct Level {
+    int t = 0, nb = 0, nbox = 0;
+    int nmax = 0;        // max |B| at level start; leading dimension of store blocks
+    int ldJ = 0;         // 9 * nmax: capacity of J lists
+    double* store = nullptr;   // nbox * 25 * nmax * nmax
+    int* cnt = nullptr;        // |B| at level start
+    int* gidx = nullptr;       // nbox * nmax global DOF indices (ascending)
+    int* nact = nullptr;       // current active count
+    int* apos = nullptr;       // nbox * nmax active positions in B (ascending)
+    // records
+    int* krank = nullptr;      // |S| (= |B| when nothing was eliminated)
+    int* nJ = nullptr;         // |J|
+    int* spos = nullptr;       // nbox * nmax
+    int* rpos = nullptr;       // nbox * nmax
+    int* Jg = nullptr;         // nbox * ldJ global indices of J = S then active near field
+    int* Sg = nullptr;         // nbox * nmax
+    int* Rg = nullptr;         // nbox * nmax
+    double* T = nullptr;       // nbox * nmax * nmax, |S| x |R| col-major (ld nmax)
+    double* XJR = nullptr;     // nbox * ldJ * nmax, |J| x |R| (ld ldJ)
+    double* G = nullptr;       // nbox * nmax * ldJ, |R| x |J| (ld nmax)
+    double* XRR = nullptr;     // nbox * nmax * nmax
+    double* Xinv = nullptr;    // nbox * nmax * nmax
+    float* XJR32 = nullptr;    // mixed: FP32 copies
+    float* G32 = nullptr;
+    float* Xinv32 = nullptr;
+    float* T32 = nullptr;
+    int* mrows = nullptr;            // per box: rows of its ID input
+    double* logdet_part = nullptr;   // per box: log|det X_RR|
+    int* sign_part = nullptr;        // per box: sign of det X_RR (+-1)
+    // host-side schedule
+    std::vector<int> h_cnt, h_k;
+    std::vector<std::vector<int>> colour_boxes;   // ascending box ids per colour
+    std::vector<int*> d_colour_boxes;
+    std::vector<std::vector<int>> rec_boxes;      // boxes with a record, per colour
+    std::vector<int*> d_rec_boxes;
+};
+
+// Realized sizes and algorithmic counts of one skeletonized level: F_ID = 2 m n^2 - 2/3 n^3,
+// F_X = 4 |J| |R| |S| + 4 |R|^2 |S|, F_LU = 2/3 |R|^3, F_G = 2 |R|^2 |J| + 4/3 |R|^3,
+// F_Schur = 2 |J|^2 |R|; Schur bytes = 16 |J|^2 (FP64 target read + write) plus the two
+// operands; solve bytes = factor data streamed by one solve.
+struct LevelStats {
+    int depth = 0, boxes = 0, nmax = 0, records = 0, max_k = 0, max_J = 0;
+    double sum_k = 0, sum_r = 0, sum_J = 0;
+    double flops_id = 0, flops_x = 0, flops_lu = 0, flops_g = 0, flops_schur = 0;
+    double bytes_schur = 0, bytes_solve64 = 0, bytes_solve32 = 0;
+};
+
+}  // namespace rss
+
+struct rss_factor_s {
+    rss_params params;
+    rss::KernelParams kp;
+    int64_t n = 0;
+    int depth = 0;
+    double* pts = nullptr;          // n x 2
+    std::vector<rss::Level> levels; // levels[i] = depth D - i (skeletonized levels only)
+    // top block
+    int64_t ntop = 0;
+    int* top_idx = nullptr;
+    double* top_A = nullptr;        // ntop x ntop
+    double* top_inv = nullptr;      // explicit inverse
+    float* top_inv32 = nullptr;
+    double top_logdet = 0;
+    int top_sign = 1;
+    // workspaces
+    double* work = nullptr;         // solve / gmres scratch
+    size_t work_elems = 0;
+    int* flag = nullptr;            // device error flags
+    std::vector<void*> allocs;
+    std::vector<rss::LevelStats> stats;
+    std::vector<double> phase_ms;   // tree, leaf store, id, elim, schur, transition, top, total
+    std::vector<int> kernel_launches;
+    double wall_ms = 0;
+    size_t bytes_device = 0;
+};
+
+namespace rss {
+
+// ---- launchers (each enqueues on `s`) -------------------------------------------------
+// tree / store (rss_tree.hip)
+void launch_validate_points(const double* pts, int64_t n, double lo_x, double lo_y, double side,
+                            int* flag, hipStream_t s);
+void launch_count_boxes(const double* pts, int64_t n, int t, double lo_x, double lo_y, double side,
+                        int* counts, hipStream_t s);
+void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double lo_y, double side,
+                       int* fill, int* gidx, int nmax, int nbox, hipStream_t s);
+void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag,
+                       hipStream_t s);
+void launch_parent_counts(const Level& C, Level& P, hipStream_t s);
+void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s);
+void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
+                         const KernelParams& kp, hipStream_t s);
+void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, int64_t ntop,
+                         const double* pts, const KernelParams& kp, double* A, hipStream_t s);
+void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
+
+// skeletonization (rss_id.hip, rss_elim.hip, rss_schur.hip)
+void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+               const KernelParams& kp, double* work, hipStream_t s);
+void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
+                 hipStream_t s);
+void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s);
+
+// dense top block (rss_solve.hip)
+void launch_lu_inverse(double* A, double* Ainv, int64_t n, int* piv, double* work, int* flag,
+                       double* logdet, int* sign, hipStream_t s);
+
+// solve / apply sweeps (rss_solve.hip)
+void launch_solve_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                      int use32, hipStream_t s);
+void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                      int use32, hipStream_t s);
+void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                      hipStream_t s);
+void launch_apply_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                      hipStream_t s);
+void launch_top_apply(const int* top_idx, int64_t ntop, const double* M, const float* M32, double* z,
+                      int nrhs, int64_t ld, double* tmp, hipStream_t s);
+void launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+void launch_copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int nrhs,
+                      hipStream_t s);
+
+// exact operator and BLAS-1 (rss_matvec.hip)
+void launch_matvec_direct(const double* pts, int64_t n, const KernelParams& kp, const double* x,
+                          double* y, hipStream_t s);
+void launch_dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s);
+int dot_partial_blocks(int64_t n);
+void launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
+void launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
+
+}  // namespace rss

@@ -1,0 +1,157 @@
+// Schur complement update of one skeletonization step (Section 2.1,
+// S_JJ = A_JJ - A_JR A_RR^{-1} A_RJ, here A_JJ -= X_JR G with G = X_RR^{-1} X_RJ).
+//
+// The |J| x |J| update is computed in 64 x 64 tiles and subtracted in place from the
+// block store: J row jj lies in box slot s (the 3x3 neighbourhood of c) at position p of
+// that box's level-start list, so entry (jj, ll) lives in block (box(s_jj), box(s_ll)) of
+// the store.  Boxes of one colour have disjoint neighbourhoods, so no two workgroups of
+// a launch write the same entry and no atomics are needed.
+//
+// TT = double: FP64 products.  TT = float: the products of the FP32 copies of X_JR and G
+// are accumulated in FP32 and subtracted from the FP64 store.
+#include "rss_internal.h"
+
+namespace rss {
+
+struct SchurArgs {
+    double* store;
+    int nb, nmax, ldJ;
+    const int* cnt;
+    const int* nact;
+    const int* apos;
+    const int* krank;
+    const int* nJ;
+    const int* spos;
+    const void* XJR;
+    const void* G;
+};
+
+template <typename TT>
+__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int tpd) {
+    constexpr int TM = 64, TK = 16;
+    __shared__ TT As[TK][TM + 1];
+    __shared__ TT Bs[TK][TM + 1];
+    __shared__ int rslot[TM], rpos_[TM], cslot[TM], cpos_[TM];
+    __shared__ int slot_box[9];
+    __shared__ int joff[10];
+    __shared__ int jslot[9];
+    __shared__ int nS;
+
+    const int tid = threadIdx.x;
+    const int c = boxes[blockIdx.y];
+    const int ti = blockIdx.x % tpd, tj = blockIdx.x / tpd;
+    const int nj = a.nJ[c];
+    if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
+    const int n = a.cnt[c], k = a.krank[c], r = n - k;
+    const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
+    const int64_t bsz = (int64_t)nmax * nmax;
+    const int cx = c % nb, cy = c / nb;
+    if (tid == 0) {
+        // J segments: S of c (slot 4), then adjacent boxes in ascending index
+        int cntS = 0;
+        joff[0] = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int s = (dy + 1) * 3 + (dx + 1);
+                int ox = cx + dx, oy = cy + dy;
+                slot_box[s] = (ox < 0 || oy < 0 || ox >= nb || oy >= nb) ? -1 : ox + nb * oy;
+            }
+        jslot[0] = 4;
+        joff[1] = k;
+        cntS = 1;
+        for (int s = 0; s < 9; ++s) {
+            if (s == 4 || slot_box[s] < 0) continue;
+            jslot[cntS] = s;
+            joff[cntS + 1] = joff[cntS] + a.nact[slot_box[s]];
+            ++cntS;
+        }
+        nS = cntS;
+    }
+    __syncthreads();
+    if (tid < 2 * TM) {
+        int i = tid & (TM - 1);
+        int jj = (tid < TM ? ti : tj) * TM + i;
+        int sl = -1, ps = 0;
+        if (jj < nj) {
+            int seg = 0;
+            while (joff[seg + 1] <= jj) ++seg;
+            sl = jslot[seg];
+            int box = slot_box[sl];
+            int loc = jj - joff[seg];
+            ps = (seg == 0) ? a.spos[(int64_t)c * nmax + loc] : a.apos[(int64_t)box * nmax + loc];
+        }
+        if (tid < TM) { rslot[i] = sl; rpos_[i] = ps; }
+        else { cslot[i] = sl; cpos_[i] = ps; }
+    }
+    const TT* XJR = (const TT*)a.XJR + (int64_t)c * ldJ * nmax;
+    const TT* G = (const TT*)a.G + (int64_t)c * nmax * ldJ;
+    const int tx = tid & 15, ty = tid >> 4;
+    TT acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0;
+    const int row0 = ti * TM, col0 = tj * TM;
+    for (int k0 = 0; k0 < r; k0 += TK) {
+        __syncthreads();
+        for (int e = tid; e < TM * TK; e += 256) {
+            int i = e % TM, kk = e / TM;
+            int row = row0 + i, kc = k0 + kk;
+            As[kk][i] = (row < nj && kc < r) ? XJR[row + (int64_t)kc * ldJ] : (TT)0;
+        }
+        for (int e = tid; e < TM * TK; e += 256) {
+            int kk = e % TK, j = e / TK;
+            int col = col0 + j, kc = k0 + kk;
+            Bs[kk][j] = (col < nj && kc < r) ? G[kc + (int64_t)col * nmax] : (TT)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            TT av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = As[kk][tx + 16 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][ty + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int j = ty + 16 * v;
+        int sb = cslot[j];
+        if (sb < 0) continue;
+        int bbox = slot_box[sb];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int i = tx + 16 * u;
+            int sa = rslot[i];
+            if (sa < 0) continue;
+            int abox = slot_box[sa];
+            int dx = (bbox % nb) - (abox % nb), dy = (bbox / nb) - (abox / nb);
+            double* blk = a.store + ((int64_t)abox * kNbr + nbr_slot(dx, dy)) * bsz;
+            blk[rpos_[i] + (int64_t)cpos_[j] * nmax] -= (double)acc[u][v];
+        }
+    }
+}
+
+void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s) {
+    if (nboxes <= 0) return;
+    SchurArgs a;
+    a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
+    a.cnt = L.cnt; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ; a.spos = L.spos;
+    int tpd = (maxJ + 63) / 64;
+    dim3 grid(tpd * tpd, nboxes), block(256);
+    if (mixed) {
+        a.XJR = L.XJR32; a.G = L.G32;
+        k_schur<float><<<grid, block, 0, s>>>(a, boxes, tpd);
+    } else {
+        a.XJR = L.XJR; a.G = L.G;
+        k_schur<double><<<grid, block, 0, s>>>(a, boxes, tpd);
+    }
+}
+
+}  // namespace rss

@@ -1,0 +1,332 @@
+// Uniform quadtree, block store generation, level transition and top-block assembly.
+//
+// Tree (Section 3, Figure 2): the root box is refined uniformly; a point at depth t
+// lies in box (floor((x - lo) * 2^t / side), floor((y - lo) * 2^t / side)), clamped,
+// with linear index bx + 2^t * by.  DOFs inside a box are kept in ascending global
+// index.  The block store of a level holds A(B_a, B_b) for every ordered pair of boxes
+// at Chebyshev distance <= 2; pairs further apart are never modified (Theorem 1,
+// Corollary 1) and are evaluated from the kernel when needed.
+#include "rss_internal.h"
+
+namespace rss {
+
+__device__ inline double kernel_entry(double xi, double yi, double xj, double yj, double coef) {
+#pragma clang fp contract(off)
+    double dx = xi - xj;
+    double dy = yi - yj;
+    return coef * log(dx * dx + dy * dy);
+}
+
+__device__ inline void box_coord(double x, double y, double lo_x, double lo_y, double s, int nb,
+                                 int& cx, int& cy) {
+#pragma clang fp contract(off)
+    double fx = floor((x - lo_x) * s);
+    double fy = floor((y - lo_y) * s);
+    cx = fx < 0 ? 0 : (fx > nb - 1 ? nb - 1 : (int)fx);
+    cy = fy < 0 ? 0 : (fy > nb - 1 ? nb - 1 : (int)fy);
+}
+
+// ------------------------------------------------------------------------------------
+__global__ void k_validate_points(const double* __restrict__ pts, int64_t n, double lo_x, double lo_y,
+                                  double side, int* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = pts[2 * i], y = pts[2 * i + 1];
+    bool ok = isfinite(x) && isfinite(y) && x >= lo_x && y >= lo_y && x <= lo_x + side && y <= lo_y + side;
+    if (!ok) atomicOr(flag, 1);
+}
+
+void launch_validate_points(const double* pts, int64_t n, double lo_x, double lo_y, double side,
+                            int* flag, hipStream_t s) {
+    int64_t nb = (n + 255) / 256;
+    k_validate_points<<<dim3((unsigned)nb), dim3(256), 0, s>>>(pts, n, lo_x, lo_y, side, flag);
+}
+
+// counts[box] += 1 for every point; counts[nbox] = max count (atomicMax)
+__global__ void k_count_boxes(const double* __restrict__ pts, int64_t n, int nb, double lo_x, double lo_y,
+                              double s, int* counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx, cy;
+    box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
+    atomicAdd(&counts[cx + nb * cy], 1);
+}
+
+__global__ void k_max_count(const int* __restrict__ counts, int64_t nbox, int* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = i < nbox ? counts[i] : 0;
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
+void launch_count_boxes(const double* pts, int64_t n, int t, double lo_x, double lo_y, double side,
+                        int* counts, hipStream_t s) {
+    int nb = 1 << t;
+    int64_t nbox = (int64_t)nb * nb;
+    double sc = ldexp(1.0, t) / side;
+    hipMemsetAsync(counts, 0, sizeof(int) * (nbox + 1), s);
+    k_count_boxes<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(pts, n, nb, lo_x, lo_y, sc, counts);
+    k_max_count<<<dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, s>>>(counts, nbox, counts + nbox);
+}
+
+__global__ void k_leaf_scatter(const double* __restrict__ pts, int64_t n, int nb, double lo_x, double lo_y,
+                               double s, int* fill, int* gidx, int nmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx, cy;
+    box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
+    int b = cx + nb * cy;
+    int p = atomicAdd(&fill[b], 1);
+    gidx[(int64_t)b * nmax + p] = (int)i;
+}
+
+// Sort each box's DOF list ascending (rank sort in LDS); fill[] holds the counts.
+__global__ void k_leaf_sort(const int* __restrict__ fill, int* gidx, int nmax) {
+    __shared__ int v[kMaxBox];
+    int b = blockIdx.x;
+    int c = fill[b];
+    int64_t base = (int64_t)b * nmax;
+    for (int i = threadIdx.x; i < c; i += blockDim.x) v[i] = gidx[base + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < c; i += blockDim.x) {
+        int x = v[i], r = 0;
+        for (int j = 0; j < c; ++j) r += v[j] < x;
+        gidx[base + r] = x;
+    }
+}
+
+void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double lo_y, double side,
+                       int* fill, int* gidx, int nmax, int nbox, hipStream_t s) {
+    int nb = 1 << t;
+    double sc = ldexp(1.0, t) / side;
+    hipMemsetAsync(fill, 0, sizeof(int) * nbox, s);
+    k_leaf_scatter<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(pts, n, nb, lo_x, lo_y, sc, fill,
+                                                                            gidx, nmax);
+    k_leaf_sort<<<dim3(nbox), dim3(256), 0, s>>>(fill, gidx, nmax);
+}
+
+// ------------------------------------------------------------------------------------
+// Leaf store: A(B_a, B_b) = diag on coincident DOFs, w K(x_i - x_j) otherwise.
+// One block per (box a, neighbour slot).  flag |= 2 on duplicate points.
+__global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, const int* __restrict__ cnt,
+                                                    const int* __restrict__ gidx, const double* __restrict__ pts,
+                                                    int nb, int nmax, double coef, double diag, int* flag) {
+    __shared__ double xa[kMaxBox], ya[kMaxBox], xb[kMaxBox], yb[kMaxBox];
+    __shared__ int ga[kMaxBox], gb[kMaxBox];
+    int a = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
+    int dx = o % 5 - 2, dy = o / 5 - 2;
+    int ax = a % nb, ay = a / nb;
+    int bx = ax + dx, by = ay + dy;
+    if (bx < 0 || by < 0 || bx >= nb || by >= nb) return;
+    int b = bx + nb * by;
+    int na = cnt[a], nbb = cnt[b];
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        int g = gidx[(int64_t)a * nmax + i];
+        ga[i] = g; xa[i] = pts[2 * (int64_t)g]; ya[i] = pts[2 * (int64_t)g + 1];
+    }
+    for (int i = threadIdx.x; i < nbb; i += blockDim.x) {
+        int g = gidx[(int64_t)b * nmax + i];
+        gb[i] = g; xb[i] = pts[2 * (int64_t)g]; yb[i] = pts[2 * (int64_t)g + 1];
+    }
+    __syncthreads();
+    double* blk = store + ((int64_t)a * kNbr + o) * nmax * nmax;
+    int tot = na * nbb;
+    bool dup = false;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        int i = e % na, j = e / na;
+        double v;
+        if (ga[i] == gb[j]) {
+            v = diag;
+        } else {
+            v = kernel_entry(xa[i], ya[i], xb[j], yb[j], coef);
+            dup |= (xa[i] == xb[j] && ya[i] == yb[j]);
+        }
+        blk[i + (int64_t)j * nmax] = v;
+    }
+    if (dup) atomicOr(flag, 2);
+}
+
+void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag, hipStream_t s) {
+    k_leaf_store<<<dim3(L.nbox * kNbr), dim3(256), 0, s>>>(L.store, L.cnt, L.gidx, pts, L.nb, L.nmax, kp.coef,
+                                                            kp.diag, flag);
+}
+
+// ------------------------------------------------------------------------------------
+// Level transition (Section 3.3, subsequent levels): B_P = union of the children's
+// active DOFs, ascending.  pmap[P*nmaxP + p] = (child slot << 16) | position of the DOF
+// in the child's level-start list (the child store is indexed by those positions).
+__global__ void k_parent_counts(const int* __restrict__ cnact, int cnb, int* pcnt, int pnb) {
+    int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= pnb * pnb) return;
+    int px = P % pnb, py = P / pnb;
+    int s = 0;
+    for (int iy = 0; iy < 2; ++iy)
+        for (int ix = 0; ix < 2; ++ix) s += cnact[(2 * px + ix) + cnb * (2 * py + iy)];
+    pcnt[P] = s;
+}
+
+__global__ void __launch_bounds__(256) k_parent_lists(const int* __restrict__ cnact, const int* __restrict__ capos,
+                                                      const int* __restrict__ cgidx, int cnb, int cnmax,
+                                                      int* __restrict__ pgidx, int* __restrict__ pmap, int pnb,
+                                                      int pnmax) {
+    __shared__ int vals[4][kMaxBox];
+    __shared__ int posn[4][kMaxBox];
+    __shared__ int len[4];
+    int P = blockIdx.x;
+    int px = P % pnb, py = P / pnb;
+    if (threadIdx.x < 4) {
+        int ix = threadIdx.x & 1, iy = threadIdx.x >> 1;
+        len[threadIdx.x] = cnact[(2 * px + ix) + cnb * (2 * py + iy)];
+    }
+    __syncthreads();
+    for (int c = 0; c < 4; ++c) {
+        int ch = (2 * px + (c & 1)) + cnb * (2 * py + (c >> 1));
+        for (int i = threadIdx.x; i < len[c]; i += blockDim.x) {
+            int p = capos[(int64_t)ch * cnmax + i];
+            posn[c][i] = p;
+            vals[c][i] = cgidx[(int64_t)ch * cnmax + p];
+        }
+    }
+    __syncthreads();
+    for (int c = 0; c < 4; ++c) {
+        for (int i = threadIdx.x; i < len[c]; i += blockDim.x) {
+            int g = vals[c][i];
+            int rank = i;
+            for (int c2 = 0; c2 < 4; ++c2) {
+                if (c2 == c) continue;
+                int lo = 0, hi = len[c2];
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (vals[c2][mid] < g) lo = mid + 1; else hi = mid;
+                }
+                rank += lo;
+            }
+            pgidx[(int64_t)P * pnmax + rank] = g;
+            pmap[(int64_t)P * pnmax + rank] = (c << 16) | posn[c][i];
+        }
+    }
+}
+
+void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s) {
+    k_parent_lists<<<dim3(P.nbox), dim3(256), 0, s>>>(C.nact, C.apos, C.gidx, C.nb, C.nmax, P.gidx, pmap, P.nb,
+                                                      P.nmax);
+}
+
+void launch_parent_counts(const Level& C, Level& P, hipStream_t s) {
+    k_parent_counts<<<dim3((P.nbox + 255) / 256), dim3(256), 0, s>>>(C.nact, C.nb, P.cnt, P.nb);
+}
+
+__global__ void __launch_bounds__(256) k_parent_store(const double* __restrict__ cstore, int cnb, int cnmax,
+                                                      double* __restrict__ pstore, const int* __restrict__ pcnt,
+                                                      const int* __restrict__ pgidx, const int* __restrict__ pmap,
+                                                      int pnb, int pnmax, const double* __restrict__ pts,
+                                                      double coef) {
+    __shared__ int mp[kMaxBox], mq[kMaxBox];
+    __shared__ double xp[kMaxBox], yp[kMaxBox], xq[kMaxBox], yq[kMaxBox];
+    int P = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
+    int dx = o % 5 - 2, dy = o / 5 - 2;
+    int Px = P % pnb, Py = P / pnb;
+    int Qx = Px + dx, Qy = Py + dy;
+    if (Qx < 0 || Qy < 0 || Qx >= pnb || Qy >= pnb) return;
+    int Q = Qx + pnb * Qy;
+    int np = pcnt[P], nq = pcnt[Q];
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        mp[i] = pmap[(int64_t)P * pnmax + i];
+        int g = pgidx[(int64_t)P * pnmax + i];
+        xp[i] = pts[2 * (int64_t)g]; yp[i] = pts[2 * (int64_t)g + 1];
+    }
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+        mq[i] = pmap[(int64_t)Q * pnmax + i];
+        int g = pgidx[(int64_t)Q * pnmax + i];
+        xq[i] = pts[2 * (int64_t)g]; yq[i] = pts[2 * (int64_t)g + 1];
+    }
+    __syncthreads();
+    double* blk = pstore + ((int64_t)P * kNbr + o) * pnmax * pnmax;
+    int tot = np * nq;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        int i = e % np, j = e / np;
+        int sa = mp[i] >> 16, pa = mp[i] & 0xffff;
+        int sb = mq[j] >> 16, qb = mq[j] & 0xffff;
+        int ax = 2 * Px + (sa & 1), ay = 2 * Py + (sa >> 1);
+        int bx = 2 * Qx + (sb & 1), by = 2 * Qy + (sb >> 1);
+        int ddx = bx - ax, ddy = by - ay;
+        double v;
+        if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
+            int a = ax + cnb * ay;
+            const double* cb = cstore + ((int64_t)a * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
+            v = cb[pa + (int64_t)qb * cnmax];
+        } else {
+            v = kernel_entry(xp[i], yp[i], xq[j], yq[j], coef);
+        }
+        blk[i + (int64_t)j * pnmax] = v;
+    }
+}
+
+void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
+                         const KernelParams& kp, hipStream_t s) {
+    k_parent_store<<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(C.store, C.nb, C.nmax, P.store, P.cnt, P.gidx, pmap,
+                                                             P.nb, P.nmax, pts, kp.coef);
+}
+
+// ------------------------------------------------------------------------------------
+// Top block (Section 3.3, final factorization): the remaining active DOFs of the last
+// level, ascending; tmap[p] = (box << 16) | position in the box's level-start list.
+__global__ void k_top_lists(const int* __restrict__ nact, const int* __restrict__ apos, const int* __restrict__ gidx,
+                            int nbox, int nmax, int* top_idx, int* tmap) {
+    // one block; nbox <= 16 boxes of <= kMaxBox DOFs
+    for (int b = 0; b < nbox; ++b) {
+        int nb_ = nact[b];
+        for (int i = threadIdx.x; i < nb_; i += blockDim.x) {
+            int p = apos[(int64_t)b * nmax + i];
+            int g = gidx[(int64_t)b * nmax + p];
+            int rank = 0;
+            for (int c = 0; c < nbox; ++c) {
+                int nc = nact[c];
+                if (c == b) { rank += i; continue; }
+                int lo = 0, hi = nc;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    int gm = gidx[(int64_t)c * nmax + apos[(int64_t)c * nmax + mid]];
+                    if (gm < g) lo = mid + 1; else hi = mid;
+                }
+                rank += lo;
+            }
+            top_idx[rank] = g;
+            tmap[rank] = (b << 16) | p;
+        }
+    }
+}
+
+void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s) {
+    (void)ntop;
+    k_top_lists<<<dim3(1), dim3(1024), 0, s>>>(L.nact, L.apos, L.gidx, L.nbox, L.nmax, top_idx, tmap);
+}
+
+__global__ void k_top_assemble(const double* __restrict__ store, int nb, int nmax, const int* __restrict__ tmap,
+                               const int* __restrict__ top_idx, int64_t ntop, const double* __restrict__ pts,
+                               double coef, double* __restrict__ A) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntop * ntop) return;
+    int64_t i = e % ntop, j = e / ntop;
+    int a = tmap[i] >> 16, pa = tmap[i] & 0xffff;
+    int b = tmap[j] >> 16, qb = tmap[j] & 0xffff;
+    int dx = b % nb - a % nb, dy = b / nb - a / nb;
+    double v;
+    if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
+        v = store[((int64_t)a * kNbr + nbr_slot(dx, dy)) * nmax * nmax + pa + (int64_t)qb * nmax];
+    } else {
+        int gi = top_idx[i], gj = top_idx[j];
+        v = kernel_entry(pts[2 * (int64_t)gi], pts[2 * (int64_t)gi + 1], pts[2 * (int64_t)gj],
+                         pts[2 * (int64_t)gj + 1], coef);
+    }
+    A[e] = v;
+}
+
+void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, int64_t ntop, const double* pts,
+                         const KernelParams& kp, double* A, hipStream_t s) {
+    int64_t tot = ntop * ntop;
+    k_top_assemble<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(L.store, L.nb, L.nmax, tmap, top_idx,
+                                                                            ntop, pts, kp.coef, A);
+}
+
+}  // namespace rss

@@ -1,0 +1,225 @@
+"""Python binding of librss (ctypes over include/rss.h).
+
+Argument marshalling only: every step of the factorization, solve, apply, exact
+operator and GMRES runs in the HIP library.  torch provides device memory and the
+current HIP stream.  Importing this module fails loudly when librss.so has not been
+built (`python -m paper_1609_08130_amd.build` or `__graft_entry__.build()`).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librss.so")
+
+RSS_FP64 = 0
+RSS_MIXED = 1
+
+STATUS = {0: "RSS_OK", 1: "RSS_E_ARG", 2: "RSS_E_NOMEM", 3: "RSS_E_DEVICE", 4: "RSS_E_SINGULAR",
+          5: "RSS_E_UNSUPPORTED", 6: "RSS_E_NOCONV"}
+
+# exported names declared in include/rss.h
+EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_matvec", "rss_gmres",
+           "rss_logdet", "rss_shape", "rss_box_sets", "rss_top_set", "rss_info", "rss_factor_destroy",
+           "rss_last_error"]
+
+
+class RSSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("dim", ctypes.c_int32),
+        ("diag", ctypes.c_double),
+        ("weight", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("leaf_size", ctypes.c_int32),
+        ("n_proxy", ctypes.c_int32),
+        ("proxy_radius", ctypes.c_double),
+        ("root_lo", ctypes.c_double * 2),
+        ("root_side", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"librss.so not built at {path}; run `python -m paper_1609_08130_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.rss_params_default.argtypes = [P(Params)]
+    lib.rss_params_default.restype = None
+    lib.rss_factor_create.argtypes = [vp, i64, P(Params), vp, P(vp)]
+    lib.rss_solve.argtypes = [vp, vp, vp, i32, i64, i32, vp]
+    lib.rss_apply.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.rss_matvec.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.rss_gmres.argtypes = [vp, vp, vp, dbl, i32, i32, i32, vp, P(i32), P(dbl)]
+    lib.rss_logdet.argtypes = [vp, P(dbl), P(dbl)]
+    lib.rss_shape.argtypes = [vp, P(i32), P(i64)]
+    lib.rss_box_sets.argtypes = [vp, i32, i64, P(i64), i32, P(i32), P(i64), i32, P(i32)]
+    lib.rss_top_set.argtypes = [vp, P(i64), i64, P(i64)]
+    lib.rss_info.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.rss_factor_destroy.argtypes = [vp]
+    lib.rss_last_error.argtypes = []
+    lib.rss_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("rss_params_default", "rss_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(st: int):
+    if st != 0:
+        raise RSSError(st, lib().rss_last_error().decode())
+
+
+def make_params(**kw) -> Params:
+    p = Params()
+    lib().rss_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "root_lo":
+            p.root_lo[0], p.root_lo[1] = float(v[0]), float(v[1])
+        elif k == "precision":
+            p.precision = {"fp64": RSS_FP64, "mixed": RSS_MIXED}.get(v, v)
+        elif k == "dim":
+            p.dim = int(v)
+        elif hasattr(p, k):
+            setattr(p, k, type(getattr(p, k))(v))
+        else:
+            raise KeyError(k)
+    return p
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Factor:
+    """RS-S factorization F ~ A of the matrix defined by `points` and the parameters."""
+
+    def __init__(self, points, **params):
+        import torch
+        self._torch = torch
+        if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
+            raise ValueError("points must be a CUDA float64 tensor of shape (N, 2)")
+        self.points = points.contiguous()
+        self.n = int(points.shape[0])
+        self.params = make_params(**params)
+        h = ctypes.c_void_p()
+        _check(lib().rss_factor_create(ctypes.c_void_p(self.points.data_ptr()), self.n, ctypes.byref(self.params),
+                                       _stream(torch), ctypes.byref(h)))
+        self._h = h
+
+    def _vec(self, b):
+        torch = self._torch
+        if not (b.is_cuda and b.dtype == torch.float64):
+            raise ValueError("vectors must be CUDA float64 tensors")
+        if b.shape[0] != self.n:
+            raise ValueError("leading dimension must equal N")
+        single = b.dim() == 1
+        bb = b.reshape(self.n, 1) if single else b
+        # column-major N x nrhs storage
+        bb = bb.t().contiguous().t()
+        return bb, single
+
+    def solve(self, b, use_fp32: bool = False):
+        bb, single = self._vec(b)
+        x = self._torch.empty_like(bb).t().contiguous().t()
+        nrhs = bb.shape[1]
+        _check(lib().rss_solve(self._h, ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs,
+                               self.n, int(bool(use_fp32)), _stream(self._torch)))
+        return x.reshape(-1) if single else x
+
+    def apply(self, x):
+        xx, single = self._vec(x)
+        y = self._torch.empty_like(xx).t().contiguous().t()
+        _check(lib().rss_apply(self._h, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()), xx.shape[1],
+                               self.n, _stream(self._torch)))
+        return y.reshape(-1) if single else y
+
+    def matvec(self, x):
+        xx, single = self._vec(x)
+        y = self._torch.empty_like(xx).t().contiguous().t()
+        _check(lib().rss_matvec(self._h, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                xx.shape[1], self.n, _stream(self._torch)))
+        return y.reshape(-1) if single else y
+
+    def gmres(self, b, rtol: float = 1e-10, maxit: int = 100, restart: int = 30, use_fp32: bool = False,
+              raise_on_noconv: bool = True):
+        bb = b.contiguous()
+        x = self._torch.empty_like(bb)
+        it = ctypes.c_int32()
+        rr = ctypes.c_double()
+        st = lib().rss_gmres(self._h, ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(x.data_ptr()), float(rtol),
+                             int(maxit), int(restart), int(bool(use_fp32)), _stream(self._torch), ctypes.byref(it),
+                             ctypes.byref(rr))
+        if st != 6 or raise_on_noconv:
+            _check(st)
+        return x, it.value, rr.value
+
+    def logdet(self):
+        s, l = ctypes.c_double(), ctypes.c_double()
+        _check(lib().rss_logdet(self._h, ctypes.byref(s), ctypes.byref(l)))
+        return s.value, l.value
+
+    def shape(self):
+        d, nt = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().rss_shape(self._h, ctypes.byref(d), ctypes.byref(nt)))
+        return d.value, nt.value
+
+    def box_sets(self, depth: int, box: int):
+        cap = 256
+        S = (ctypes.c_int64 * cap)()
+        R = (ctypes.c_int64 * cap)()
+        ns, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rss_box_sets(self._h, depth, box, S, cap, ctypes.byref(ns), R, cap, ctypes.byref(nr)))
+        return (np.array(S[:ns.value], dtype=np.int64), np.array(R[:nr.value], dtype=np.int64))
+
+    def top_set(self):
+        d, nt = self.shape()
+        buf = (ctypes.c_int64 * max(nt, 1))()
+        cnt = ctypes.c_int64()
+        _check(lib().rss_top_set(self._h, buf, nt, ctypes.byref(cnt)))
+        return np.array(buf[:cnt.value], dtype=np.int64)
+
+    def info(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(lib().rss_info(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rss_factor_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

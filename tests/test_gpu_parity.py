@@ -1,0 +1,168 @@
+"""GPU parity: librss (through the C ABI) against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from oracle import rss_oracle as O
+from paper_1609_08130_amd import workloads as W
+from tests.parity_util import factor_tol, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08130_amd import rss as mod
+    return mod
+
+
+def _gpu_factor(rss, pts, p: O.Params, precision="fp64"):
+    d = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    return rss.Factor(d, diag=p.diag, weight=p.weight, tol=p.tol, leaf_size=p.leaf_size, n_proxy=p.n_proxy,
+                      proxy_radius=p.proxy_radius, root_lo=p.root_lo, root_side=p.root_side,
+                      precision=precision)
+
+
+def _compare(rss, name, pts, p, nrhs=1, precision="fp64"):
+    say(f"[parity] case={name} N={len(pts)} tol={p.tol} leaf={p.leaf_size} precision={precision}")
+    F = _gpu_factor(rss, pts, p, precision)
+    R = O.factor(pts, p)
+    depth, ntop = F.shape()
+    assert depth == R.depth
+    # skeleton index sets: exact, every box of every level
+    mism = []
+    for (t, box), (S, Rr) in R.skeletons.items():
+        Sg, Rg = F.box_sets(t, box)
+        if not (np.array_equal(Sg, S) and np.array_equal(Rg, Rr)):
+            mism.append((t, box, len(S), len(Sg)))
+    assert not mism, f"skeleton mismatches (depth, box, |S| oracle, |S| gpu): {mism[:10]}"
+    assert np.array_equal(F.top_set(), R.top)
+    b = W.rhs(len(pts), seed=0, nrhs=nrhs)
+    bt = torch.tensor(b, device="cuda")
+    tol = factor_tol(p.tol)
+    x = F.solve(bt).cpu().numpy()
+    xr = O.solve(R, b)
+    ex = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    y = F.apply(bt).cpu().numpy()
+    yr = O.apply(R, b)
+    ey = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+    sg, ld = F.logdet()
+    sr, lr = O.logdet(R)
+    say(f"[parity] case={name} solve_rel={ex:.2e} apply_rel={ey:.2e} logdet gpu={ld:.15e} oracle={lr:.15e} tol={tol:.1e}")
+    assert ex <= tol and ey <= tol
+    assert sg == sr and abs(ld - lr) <= tol * max(1.0, abs(lr)) + 1e-13 * len(pts)
+    F.close()
+    return ex, ey
+
+
+def test_parity_grid64_tol1e6(rss):
+    n = 64
+    _compare(rss, "grid64", W.grid_points(n), O.Params(**W.problem(n, 1e-6)))
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-9])
+def test_parity_grid64_other_tolerances(rss, tol):
+    n = 64
+    _compare(rss, f"grid64_tol{tol}", W.grid_points(n), O.Params(**W.problem(n, tol)))
+
+
+def test_parity_ragged_grid100_three_levels(rss):
+    # 100 x 100 grid with leaf 64: boxes of 36..49 points, depth 4 (levels 4, 3, 2)
+    n = 100
+    _compare(rss, "grid100", W.grid_points(n), O.Params(**W.problem(n, 1e-6)), nrhs=3)
+
+
+def test_parity_random_points_uneven_boxes(rss):
+    pts = W.random_points(3000, seed=7)
+    p = O.Params(weight=1.0 / 3000, tol=1e-6, leaf_size=24)
+    _compare(rss, "random3000", pts, p)
+
+
+def test_parity_jittered_grid_small_leaf(rss):
+    pts = W.jittered_grid_points(48, 0.1, seed=3)
+    p = O.Params(weight=1.0 / 48 ** 2, tol=1e-7, leaf_size=16)
+    _compare(rss, "jitter48_leaf16", pts, p)
+
+
+@pytest.mark.parametrize("npts,leaf", [(1, 64), (50, 64), (200, 64), (300, 40)])
+def test_small_and_degenerate_trees(rss, npts, leaf):
+    pts = W.random_points(npts, seed=npts)
+    p = O.Params(weight=1.0 / max(npts, 1), tol=1e-6, leaf_size=leaf)
+    say(f"[parity] case=small N={npts} leaf={leaf}")
+    F = _gpu_factor(rss, pts, p)
+    R = O.factor(pts, p)
+    assert F.shape()[0] == R.depth
+    A = O.dense_matrix(pts, p)
+    b = W.rhs(npts, seed=1)
+    x = F.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(x, O.solve(R, b), rtol=0, atol=factor_tol(p.tol) * np.abs(x).max())
+    if R.depth <= 1:
+        np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-12 * np.abs(x).max())
+    F.close()
+
+
+def test_solve_nrhs_matches_single(rss):
+    n = 64
+    p = O.Params(**W.problem(n, 1e-6))
+    F = _gpu_factor(rss, W.grid_points(n), p)
+    B = torch.tensor(W.rhs(n * n, seed=5, nrhs=4), device="cuda")
+    X = F.solve(B)
+    for j in range(4):
+        xj = F.solve(B[:, j].contiguous())
+        assert torch.equal(X[:, j], xj)
+    # F^{-1} F = I
+    Y = F.apply(B)
+    Z = F.solve(Y)
+    assert float((Z - B).abs().max()) <= 1e-12 * float(B.abs().max())
+    F.close()
+
+
+def test_gmres_refined_solution_matches_dense(rss):
+    n = 64
+    pts = W.grid_points(n)
+    p = O.Params(**W.problem(n, 1e-6))
+    A = O.dense_matrix(pts, p)
+    b = W.rhs(n * n, seed=0)
+    xe = np.linalg.solve(A, b)
+    for prec in ("fp64", "mixed"):
+        say(f"[parity] case=gmres precision={prec}")
+        F = _gpu_factor(rss, pts, p, prec)
+        x, it, rr = F.gmres(torch.tensor(b, device="cuda"), rtol=1e-12, maxit=20, use_fp32=(prec == "mixed"))
+        x = x.cpu().numpy()
+        err = np.linalg.norm(x - xe) / np.linalg.norm(xe)
+        say(f"[parity] gmres {prec}: iters={it} relres={rr:.2e} err_vs_dense={err:.2e}")
+        assert rr <= 1e-12 and it <= 6 and err <= 1e-10
+        F.close()
+
+
+def test_mixed_factor_is_accurate(rss):
+    n = 64
+    pts = W.grid_points(n)
+    p = O.Params(**W.problem(n, 1e-6))
+    F = _gpu_factor(rss, pts, p, "mixed")
+    R = O.factor(pts, p)
+    b = W.rhs(n * n, seed=0)
+    x64 = F.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    x32 = F.solve(torch.tensor(b, device="cuda"), use_fp32=True).cpu().numpy()
+    xr = O.solve(R, b)
+    e64 = np.linalg.norm(x64 - xr) / np.linalg.norm(xr)
+    e32 = np.linalg.norm(x32 - xr) / np.linalg.norm(xr)
+    say(f"[parity] mixed factor: fp64-apply err={e64:.2e} fp32-apply err={e32:.2e}")
+    # FP32 Schur products perturb the store by ~1e-7 of the (tiny) update; the
+    # preconditioner copy is FP32 (unit roundoff 6e-8).
+    assert e64 <= 1e-7 and e32 <= 1e-5
+    F.close()
+
+
+def test_argument_errors_on_device(rss):
+    pts = W.grid_points(16)
+    pts[3] = pts[7]
+    with pytest.raises(rss.RSSError) as ei:
+        _gpu_factor(rss, pts, O.Params(**W.problem(16, 1e-6)))
+    assert ei.value.name == "RSS_E_ARG"
+    pts = W.grid_points(16) + 2.0
+    with pytest.raises(rss.RSSError) as ei:
+        _gpu_factor(rss, pts, O.Params(**W.problem(16, 1e-6)))
+    assert ei.value.name == "RSS_E_ARG"
