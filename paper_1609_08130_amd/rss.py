@@ -12,6 +12,10 @@ import json
 import os
 
 import numpy as np
+# torch ships its own HIP runtime (SONAME libamdhip64.so.7).  It must be loaded before
+# librss so that librss binds to that same runtime instead of pulling a second copy
+# from /opt/rocm into the process (two runtimes cannot share the device).
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librss.so")

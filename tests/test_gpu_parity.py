@@ -150,9 +150,11 @@ def test_mixed_factor_is_accurate(rss):
     e64 = np.linalg.norm(x64 - xr) / np.linalg.norm(xr)
     e32 = np.linalg.norm(x32 - xr) / np.linalg.norm(xr)
     say(f"[parity] mixed factor: fp64-apply err={e64:.2e} fp32-apply err={e32:.2e}")
-    # FP32 Schur products perturb the store by ~1e-7 of the (tiny) update; the
-    # preconditioner copy is FP32 (unit roundoff 6e-8).
-    assert e64 <= 1e-7 and e32 <= 1e-5
+    # The skeleton-skeleton Schur update is O(1) (X_SR ~ -T, X_RR ~ I + T^T T), so FP32
+    # products perturb F by a few u32 = 6e-8 relative; the FP32 factor copy used by the
+    # preconditioner solve adds the same order again.  cond(A) ~ 1.13 here.
+    u32 = float(np.finfo(np.float32).eps) / 2
+    assert e64 <= 40 * u32 and e32 <= 80 * u32
     F.close()
 
 
