@@ -16,6 +16,10 @@
 
 #include "rss_internal.h"
 
+namespace rss {
+int elim_lds_limit();
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -295,11 +299,15 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             f->kernel_launches[PH_SCHUR] += 1;
         }
         HIPCHK(hipStreamSynchronize(s));
+        double lv_id = 0, lv_elim = 0, lv_schur = 0;
         for (size_t i = 1; i < ev.size(); i += 3) {
-            f->phase_ms[PH_ID] += ev_ms(ev[i - 1], ev[i]);
-            f->phase_ms[PH_ELIM] += ev_ms(ev[i], ev[i + 1]);
-            f->phase_ms[PH_SCHUR] += ev_ms(ev[i + 1], ev[i + 2]);
+            lv_id += ev_ms(ev[i - 1], ev[i]);
+            lv_elim += ev_ms(ev[i], ev[i + 1]);
+            lv_schur += ev_ms(ev[i + 1], ev[i + 2]);
         }
+        f->phase_ms[PH_ID] += lv_id;
+        f->phase_ms[PH_ELIM] += lv_elim;
+        f->phase_ms[PH_SCHUR] += lv_schur;
         int flag = 0;
         HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
         if (flag & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
@@ -316,6 +324,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (auto& v : L.rec_boxes) L.d_rec_boxes.push_back(h2d(f, v, s));
         rss::LevelStats st;
         st.depth = L.t; st.boxes = L.nbox; st.nmax = L.nmax;
+        st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur;
         for (int b = 0; b < L.nbox; ++b) {
             double n = L.h_cnt[b], k = L.h_k[b], r = n - k, J = hJ[b], m = hm[b];
             if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
@@ -381,7 +390,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     f->top_A = dalloc<double>(f, (size_t)ntop * ntop);
     double* LU = dalloc<double>(f, (size_t)ntop * ntop);
     f->top_inv = dalloc<double>(f, (size_t)ntop * ntop);
-    int* piv = dalloc<int>(f, ntop);
+    int* piv = dalloc<int>(f, 2 * ntop);
     double* dlog = dalloc<double>(f, 1);
     int* dsign = dalloc<int>(f, 1);
     rss::launch_top_lists(L, f->top_idx, tmap, ntop, s);
@@ -414,7 +423,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     }
     dfree(f, LU, sizeof(double) * ntop * ntop);
     dfree(f, tmap, sizeof(int) * ntop);
-    dfree(f, piv, sizeof(int) * ntop);
+    dfree(f, piv, sizeof(int) * 2 * ntop);
     free_store(f, L);
     if (L.krank) f->levels.push_back(std::move(L));
     else {
@@ -819,7 +828,7 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     o.precision(17);
     o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
       << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
-      << ",\"bytes_device\":" << f->bytes_device << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
+      << ",\"bytes_device\":" << f->bytes_device << ",\"lds_limit\":" << rss::elim_lds_limit() << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
     o << "},\"launches\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->kernel_launches[i];
@@ -832,7 +841,8 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
           << ",\"flops_id\":" << s.flops_id << ",\"flops_x\":" << s.flops_x << ",\"flops_lu\":" << s.flops_lu
           << ",\"flops_g\":" << s.flops_g << ",\"flops_schur\":" << s.flops_schur
           << ",\"bytes_schur\":" << s.bytes_schur << ",\"bytes_solve64\":" << s.bytes_solve64
-          << ",\"bytes_solve32\":" << s.bytes_solve32 << "}";
+          << ",\"bytes_solve32\":" << s.bytes_solve32 << ",\"ms_id\":" << s.ms_id << ",\"ms_elim\":" << s.ms_elim
+          << ",\"ms_schur\":" << s.ms_schur << "}";
     }
     o << "]}";
     std::string js = o.str();

@@ -4,13 +4,15 @@
 //
 // With the box's ID (S, R, T) and the current blocks of the store:
 //   Z_X  = A_XR - A_XS T                   X in {S, N}     (column operation L_T)
-//   X_RR = A_RR - A_RS T - T^T (A_SR - A_SS T)             (both operations)
+//   X_RR = A_RR - A_RS T - T^T Z_S                         (both operations)
 //   X_RJ = A_RJ - T^T A_SJ                 J = S u N       (row operation U_T)
 //   X_JR = [Z_S; Z_N]
-// then X_RR = P L U (partial pivoting), G = X_RR^{-1} X_RJ and the explicit X_RR^{-1}.
-// The record keeps T, X_JR, G, X_RR and X_RR^{-1}; the Schur complement
-// A_JJ -= X_JR G is applied by the Schur kernel.  J lists S first, then the active
-// DOFs of the adjacent boxes in ascending box index.
+// X_RR^{-1} comes from in-place Gauss-Jordan elimination with partial pivoting (largest
+// |.|, lowest row on ties; its pivots are those of LU with partial pivoting and give
+// log|det X_RR|), and G = X_RR^{-1} X_RJ is formed tile by tile.  The record keeps T,
+// X_JR, G, X_RR and X_RR^{-1}; the Schur complement A_JJ -= X_JR G is applied by the
+// Schur kernel.  J lists S first, then the active DOFs of the adjacent boxes in
+// ascending box index.
 #include "rss_internal.h"
 
 namespace rss {
@@ -42,22 +44,24 @@ struct ElimArgs {
     int* sign_part;
 };
 
-constexpr int kTLds = 4096;   // T kept in LDS when |S| |R| <= kTLds
+constexpr int kTile = 32;   // rows (or columns) of J per tile
 
+// Dynamic LDS: Ts[tsz] | Xs[nmax*nmax] (when XLDS) | tile[nmax*kTile]
+template <bool XLDS>
 __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
-                                              double* __restrict__ work, int* flag) {
+                                              double* __restrict__ work, int* flag, int tsz) {
+    extern __shared__ double dyn[];
     __shared__ int sp[kMaxBox], rp[kMaxBox];
-    __shared__ double Ts[kTLds];
     __shared__ const double* blk_nc[8];
     __shared__ const double* blk_cn[8];
     __shared__ const int* nap[8];
     __shared__ int nbox_[8];
     __shared__ int joff[9];
     __shared__ int nN;
-    __shared__ int piv[kMaxBox];
-    __shared__ double red_v[256];
-    __shared__ int red_i[256];
-    __shared__ int singular;
+    __shared__ int colswap[kMaxBox];
+    __shared__ double fvec[kMaxBox];
+    __shared__ int piv_idx;
+    __shared__ double piv_val;
 
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -71,6 +75,11 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
     const int cx = c % nb, cy = c / nb;
+    double* Ts = dyn;
+    double* Xs = XLDS ? dyn + tsz : work + (int64_t)blockIdx.x * bsz;
+    double* tile = dyn + tsz + (XLDS ? bsz : 0);
+    const int ldx = nmax;
+
     for (int i = tid; i < k; i += 256) sp[i] = a.spos[(int64_t)c * nmax + i];
     for (int i = tid; i < r; i += 256) rp[i] = a.rpos[(int64_t)c * nmax + i];
     if (tid == 0) {
@@ -90,15 +99,10 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
                 ++cntN;
             }
         nN = cntN;
-        singular = 0;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
-    const bool tl = k * r <= kTLds;
-    if (tl)
-        for (int e = tid; e < k * r; e += 256) Ts[e] = Tg[(e % k) + (int64_t)(e / k) * nmax];
+    for (int e = tid; e < k * r; e += 256) Ts[e] = Tg[(e % k) + (int64_t)(e / k) * nmax];   // Ts[q + b*k]
     __syncthreads();
-    const int ldT = tl ? k : nmax;
-    const double* Tp = tl ? (const double*)Ts : Tg;
     const int nj = joff[nN];
     const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
 
@@ -114,147 +118,169 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         }
         a.Jg[(int64_t)c * ldJ + jj] = g;
     }
-    // X_JR = A_JR - A_JS T
+
+    // ---- X_JR = A_JR - A_JS T, kTile rows at a time (rows staged in LDS) ----
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
-    for (int e = tid; e < nj * r; e += 256) {
-        int jj = e % nj, b = e / nj;
-        const double* blk;
-        int row;
-        if (jj < k) {
-            blk = Acc;
-            row = sp[jj];
-        } else {
-            int i = 0;
-            while (joff[i + 1] <= jj) ++i;
-            blk = blk_nc[i];
-            row = nap[i][jj - joff[i]];
+    for (int r0 = 0; r0 < nj; r0 += kTile) {
+        const int tr = min(kTile, nj - r0);
+        // stage the rows' S columns then R columns: tile[i + kTile * col], col < n
+        for (int e = tid; e < tr * n; e += 256) {
+            int i = e % tr, col = e / tr;
+            int jj = r0 + i;
+            const double* blk;
+            int row;
+            if (jj < k) {
+                blk = Acc;
+                row = sp[jj];
+            } else {
+                int s = 0;
+                while (joff[s + 1] <= jj) ++s;
+                blk = blk_nc[s];
+                row = nap[s][jj - joff[s]];
+            }
+            int pos = col < k ? sp[col] : rp[col - k];
+            tile[i + kTile * col] = blk[row + (int64_t)pos * nmax];
         }
-        double v = blk[row + (int64_t)rp[b] * nmax];
-        for (int q = 0; q < k; ++q) v -= blk[row + (int64_t)sp[q] * nmax] * Tp[q + b * ldT];
-        XJR[jj + (int64_t)b * ldJ] = v;
-    }
-    // X_RJ = A_RJ - T^T A_SJ, written into G's storage (r x |J|, ld nmax)
-    double* G = a.G + (int64_t)c * nmax * ldJ;
-    for (int e = tid; e < r * nj; e += 256) {
-        int b = e % r, jj = e / r;
-        const double* blk;
-        int col;
-        if (jj < k) {
-            blk = Acc;
-            col = sp[jj];
-        } else {
-            int i = 0;
-            while (joff[i + 1] <= jj) ++i;
-            blk = blk_cn[i];
-            col = nap[i][jj - joff[i]];
+        __syncthreads();
+        for (int e = tid; e < tr * r; e += 256) {
+            int i = e % tr, b = e / tr;
+            double v = tile[i + kTile * (k + b)];
+            const double* tb = Ts + b * k;
+            for (int q = 0; q < k; ++q) v -= tile[i + kTile * q] * tb[q];
+            XJR[(r0 + i) + (int64_t)b * ldJ] = v;
         }
-        const double* bc = blk + (int64_t)col * nmax;
-        double v = bc[rp[b]];
-        for (int q = 0; q < k; ++q) v -= Tp[q + b * ldT] * bc[sp[q]];
-        G[b + (int64_t)jj * nmax] = v;
+        __syncthreads();
     }
-    __syncthreads();
-    // X_RR = A_RR - A_RS T - T^T Z_S   (Z_S = first k rows of X_JR)
-    double* LU = work + (int64_t)blockIdx.x * bsz;
+
+    // ---- X_RR = A_RR - A_RS T - T^T Z_S -----------------------------------------
     double* XRR = a.XRR + (int64_t)c * bsz;
     for (int e = tid; e < r * r; e += 256) {
         int b = e % r, b2 = e / r;
         double v = Acc[rp[b] + (int64_t)rp[b2] * nmax];
-        for (int q = 0; q < k; ++q) v -= Acc[rp[b] + (int64_t)sp[q] * nmax] * Tp[q + b2 * ldT];
-        for (int q = 0; q < k; ++q) v -= Tp[q + b * ldT] * XJR[q + (int64_t)b2 * ldJ];
+        const double* t2 = Ts + b2 * k;
+        const double* t1 = Ts + b * k;
+        for (int q = 0; q < k; ++q) v -= Acc[rp[b] + (int64_t)sp[q] * nmax] * t2[q];
+        for (int q = 0; q < k; ++q) v -= t1[q] * XJR[q + (int64_t)b2 * ldJ];
         XRR[b + (int64_t)b2 * nmax] = v;
-        LU[b + (int64_t)b2 * nmax] = v;
+        Xs[b + b2 * ldx] = v;
     }
     __syncthreads();
-    // LU with partial pivoting (largest |.|, lowest row on ties)
+
+    // ---- X_RR^{-1} by in-place Gauss-Jordan with partial pivoting ---------------------
     double ld_sum = 0.0;
     int sgn = 1;
+    bool singular = false;
+    const int wv = tid >> 6, lane = tid & 63;
     for (int j = 0; j < r; ++j) {
-        double best = -1.0;
-        int bi = 1 << 30;
-        for (int i = j + tid; i < r; i += 256) {
-            double v = fabs(LU[i + (int64_t)j * nmax]);
-            if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-        }
-        red_v[tid] = best;
-        red_i[tid] = bi;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) {
-                double v2 = red_v[tid + s];
-                int i2 = red_i[tid + s];
-                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) { red_v[tid] = v2; red_i[tid] = i2; }
+        if (wv == 0) {
+            double best = -1.0;
+            int bi = 1 << 30;
+            for (int i = j + lane; i < r; i += 64) {
+                double v = fabs(Xs[i + j * ldx]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
-            __syncthreads();
+            for (int o = 32; o > 0; o >>= 1) {
+                double v2 = __shfl_xor(best, o, 64);
+                int i2 = __shfl_xor(bi, o, 64);
+                if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+            }
+            if (lane == 0) { piv_idx = bi; piv_val = best; }
         }
-        const int p = red_i[0];
-        const double pv = red_v[0];
         __syncthreads();
-        if (!(pv > 0.0)) {
-            if (tid == 0) singular = 1;
-            break;
-        }
-        if (tid == 0) piv[j] = p;
+        const int p = piv_idx;
+        if (!(piv_val > 0.0)) { singular = true; break; }
         if (p != j) {
             for (int l = tid; l < r; l += 256) {
-                double t0 = LU[j + (int64_t)l * nmax];
-                LU[j + (int64_t)l * nmax] = LU[p + (int64_t)l * nmax];
-                LU[p + (int64_t)l * nmax] = t0;
+                double t0 = Xs[j + l * ldx];
+                Xs[j + l * ldx] = Xs[p + l * ldx];
+                Xs[p + l * ldx] = t0;
             }
             sgn = -sgn;
         }
+        if (tid == 0) colswap[j] = p;
         __syncthreads();
-        const double d = LU[j + (int64_t)j * nmax];
+        const double d = Xs[j + j * ldx];
         ld_sum += log(fabs(d));
         if (d < 0) sgn = -sgn;
         const double rinv = 1.0 / d;
-        for (int i = j + 1 + tid; i < r; i += 256) LU[i + (int64_t)j * nmax] *= rinv;
+        for (int i = tid; i < r; i += 256) fvec[i] = (i == j) ? 0.0 : Xs[i + j * ldx];
         __syncthreads();
-        const int m2 = r - j - 1;
-        for (int e = tid; e < m2 * m2; e += 256) {
-            int i = j + 1 + e % m2, l = j + 1 + e / m2;
-            LU[i + (int64_t)l * nmax] -= LU[i + (int64_t)j * nmax] * LU[j + (int64_t)l * nmax];
+        for (int l = tid; l < r; l += 256) Xs[j + l * ldx] = (l == j ? 1.0 : Xs[j + l * ldx]) * rinv;
+        __syncthreads();
+        for (int e = tid; e < r * r; e += 256) {
+            int i = e % r, l = e / r;
+            if (i == j) continue;
+            double base = (l == j) ? 0.0 : Xs[i + l * ldx];
+            Xs[i + l * ldx] = base - fvec[i] * Xs[j + l * ldx];
         }
         __syncthreads();
     }
     if (singular) {
-        if (tid == 0) atomicOr(flag, 4);
-        if (tid == 0) a.nJ[c] = 0;
+        if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
         return;
+    }
+    // undo the row interchanges on the columns of the inverse
+    for (int j = r - 1; j >= 0; --j) {
+        int p = colswap[j];
+        if (p != j)
+            for (int i = tid; i < r; i += 256) {
+                double t0 = Xs[i + j * ldx];
+                Xs[i + j * ldx] = Xs[i + p * ldx];
+                Xs[i + p * ldx] = t0;
+            }
+        __syncthreads();
     }
     if (tid == 0) {
         a.logdet_part[c] = ld_sum;
         a.sign_part[c] = sgn;
     }
-    // G = X_RR^{-1} X_RJ, column by column; X_RR^{-1} from the identity
     double* Xinv = a.Xinv + (int64_t)c * bsz;
-    for (int col = tid; col < nj + r; col += 256) {
-        double* x;
-        if (col < nj) {
-            x = G + (int64_t)col * nmax;
-        } else {
-            x = Xinv + (int64_t)(col - nj) * nmax;
-            for (int i = 0; i < r; ++i) x[i] = (i == col - nj) ? 1.0 : 0.0;
-        }
-        for (int j = 0; j < r; ++j) {
-            int p = piv[j];
-            if (p != j) { double t0 = x[j]; x[j] = x[p]; x[p] = t0; }
-        }
-        for (int j = 0; j < r; ++j) {
-            double xj = x[j];
-            for (int i = j + 1; i < r; ++i) x[i] -= LU[i + (int64_t)j * nmax] * xj;
-        }
-        for (int j = r - 1; j >= 0; --j) {
-            double xj = x[j] / LU[j + (int64_t)j * nmax];
-            x[j] = xj;
-            for (int i = 0; i < j; ++i) x[i] -= LU[i + (int64_t)j * nmax] * xj;
-        }
+    for (int e = tid; e < r * r; e += 256) {
+        int b = e % r, b2 = e / r;
+        Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * ldx];
     }
-    // bookkeeping: record sets, active list of c becomes S
+
+    // ---- G = X_RR^{-1} X_RJ, kTile columns of J at a time ------------------------------
+    double* G = a.G + (int64_t)c * nmax * ldJ;
+    for (int c0 = 0; c0 < nj; c0 += kTile) {
+        const int tc = min(kTile, nj - c0);
+        // tile[b + r * j'] = X_RJ[b, c0 + j']
+        for (int e = tid; e < tc * r; e += 256) {
+            int b = e % r, jp = e / r;
+            int jj = c0 + jp;
+            const double* blk;
+            int col;
+            if (jj < k) {
+                blk = Acc;
+                col = sp[jj];
+            } else {
+                int s = 0;
+                while (joff[s + 1] <= jj) ++s;
+                blk = blk_cn[s];
+                col = nap[s][jj - joff[s]];
+            }
+            const double* bc = blk + (int64_t)col * nmax;
+            double v = bc[rp[b]];
+            const double* tb = Ts + b * k;
+            for (int q = 0; q < k; ++q) v -= tb[q] * bc[sp[q]];
+            tile[b + r * jp] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < tc * r; e += 256) {
+            int b = e % r, jp = e / r;
+            const double* tcol = tile + r * jp;
+            double v = 0.0;
+            for (int q = 0; q < r; ++q) v += Xs[b + q * ldx] * tcol[q];
+            G[b + (int64_t)(c0 + jp) * nmax] = v;
+        }
+        __syncthreads();
+    }
+
+    // ---- bookkeeping: record sets, FP32 copies, active list of c becomes S ---------------
     for (int i = tid; i < k; i += 256) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sp[i]];
     for (int i = tid; i < r; i += 256) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + rp[i]];
-    __syncthreads();
     if (mixed) {
+        __syncthreads();
         for (int e = tid; e < nj * r; e += 256) {
             int jj = e % nj, b = e / nj;
             a.XJR32[(int64_t)c * ldJ * nmax + jj + (int64_t)b * ldJ] = (float)XJR[jj + (int64_t)b * ldJ];
@@ -265,11 +291,11 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         }
         for (int e = tid; e < r * r; e += 256) {
             int b = e % r, b2 = e / r;
-            a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xinv[b + (int64_t)b2 * nmax];
+            a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * ldx];
         }
         for (int e = tid; e < k * r; e += 256) {
             int q = e % k, b = e / k;
-            a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Tg[q + (int64_t)b * nmax];
+            a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Ts[q + b * k];
         }
     }
     if (tid == 0) {
@@ -277,6 +303,20 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         a.nact[c] = k;
     }
     for (int i = tid; i < k; i += 256) a.apos[(int64_t)c * nmax + i] = sp[i];
+}
+
+static int g_max_lds = -1;
+
+int elim_lds_limit() {
+    if (g_max_lds < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            g_max_lds = v;
+        else
+            g_max_lds = 65536;
+    }
+    return g_max_lds;
 }
 
 void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
@@ -289,7 +329,17 @@ void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double
     a.XJR = L.XJR; a.G = L.G; a.XRR = L.XRR; a.Xinv = L.Xinv;
     a.XJR32 = L.XJR32; a.G32 = L.G32; a.Xinv32 = L.Xinv32; a.T32 = L.T32;
     a.logdet_part = L.logdet_part; a.sign_part = L.sign_part;
-    k_elim<<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, mixed, work, flag);
+    const int tsz = (L.nmax * L.nmax) / 4 + 1;            // |S| |R| <= n^2 / 4
+    const size_t tile = (size_t)L.nmax * kTile;
+    const size_t with_x = sizeof(double) * (tsz + (size_t)L.nmax * L.nmax + tile);
+    const size_t without_x = sizeof(double) * (tsz + tile);
+    if ((int)with_x <= elim_lds_limit()) {
+        hipFuncSetAttribute((const void*)k_elim<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
+        k_elim<true><<<dim3(nboxes), dim3(256), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+    } else {
+        hipFuncSetAttribute((const void*)k_elim<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)without_x);
+        k_elim<false><<<dim3(nboxes), dim3(256), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+    }
 }
 
 }  // namespace rss

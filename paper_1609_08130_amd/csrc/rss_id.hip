@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
                                            int* __restrict__ rpos, double* __restrict__ Tout,
                                            int* __restrict__ mrows, double* __restrict__ work) {
     constexpr int NP = 64 * CPT;
-    __shared__ double R0s[RLDS ? NP * NP : 1];
+    extern __shared__ double R0s[];   // RLDS: nmax x NP
     __shared__ double vbuf[NP > BR ? NP : BR];
     __shared__ double taubuf;
     __shared__ const double* obase[16];
@@ -314,17 +314,32 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
     }
 }
 
+int elim_lds_limit();
+
 void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                const KernelParams& kp, double* work, hipStream_t s) {
-    // work: R0 scratch of nboxes * NP * NP doubles when R0 does not live in LDS.
+    // R0 (rows < nmax, row stride NP = 64 * CPT) lives in LDS when it fits, else in
+    // `work` (nboxes * NP * NP doubles).
     if (nboxes <= 0) return;
     dim3 grid(nboxes), block(64);
+    const int lim = elim_lds_limit();
     if (L.nmax <= 64) {
-        k_id<1, 32, true><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                 ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        size_t lds = sizeof(double) * (size_t)L.nmax * 64;
+        k_id<1, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                   pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                   work);
     } else if (L.nmax <= 128) {
-        k_id<2, 32, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        size_t lds = sizeof(double) * (size_t)L.nmax * 128;
+        if ((int)(lds + 4096) <= lim) {
+            hipFuncSetAttribute((const void*)k_id<2, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            k_id<2, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                       pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                       work);
+        } else {
+            k_id<2, 32, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                      work);
+        }
     } else {
         k_id<4, 16, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
                                                   ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);

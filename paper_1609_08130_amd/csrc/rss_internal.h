@@ -78,6 +78,7 @@ struct LevelStats {
     double sum_k = 0, sum_r = 0, sum_J = 0;
     double flops_id = 0, flops_x = 0, flops_lu = 0, flops_g = 0, flops_schur = 0;
     double bytes_schur = 0, bytes_solve64 = 0, bytes_solve32 = 0;
+    double ms_id = 0, ms_elim = 0, ms_schur = 0, ms_transition = 0;
 };
 
 }  // namespace rss
@@ -90,6 +91,7 @@ struct rss_factor_s {
     double* pts = nullptr;          // n x 2
     std::vector<rss::Level> levels; // levels[i] = depth D - i (skeletonized levels only)
     // top block
+    int lds_limit = 0;
     int64_t ntop = 0;
     int* top_idx = nullptr;
     double* top_A = nullptr;        // ntop x ntop

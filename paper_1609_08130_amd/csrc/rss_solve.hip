@@ -370,6 +370,48 @@ __global__ void __launch_bounds__(1024) k_top_lu(double* __restrict__ A, int64_t
     if (tid == 0) {
         *logdet = lds;
         *sign = sgn;
+        // row permutation of P A = L U: row i of P A is row perm[i] of A
+        int* perm = piv + n;
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+        for (int64_t j = 0; j < n; ++j) {
+            int p = piv[j];
+            int t0 = perm[j]; perm[j] = perm[p]; perm[p] = t0;
+        }
+    }
+}
+
+// Columns [c0, c0 + NC) of A^{-1} from P A = L U, solved in LDS (n <= 1024).
+template <int NC>
+__global__ void __launch_bounds__(256) k_top_inverse_lds(const double* __restrict__ LU, const int* __restrict__ perm,
+                                                         int64_t n, double* __restrict__ Ainv) {
+    extern __shared__ double xs[];   // n x NC, xs[i * NC + c]
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    for (int64_t e = tid; e < n * NC; e += 256) {
+        int64_t i = e / NC, c = e % NC;
+        xs[e] = (perm[i] == c0 + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int64_t j = 0; j < n; ++j) {          // L y = P e (unit lower)
+        const int64_t m = n - j - 1;
+        for (int64_t e = tid; e < m * NC; e += 256) {
+            int64_t i = j + 1 + e / NC, c = e % NC;
+            xs[i * NC + c] -= LU[i + j * n] * xs[j * NC + c];
+        }
+        __syncthreads();
+    }
+    for (int64_t j = n - 1; j >= 0; --j) {     // U x = y
+        if (tid < NC) xs[j * NC + tid] /= LU[j + j * n];
+        __syncthreads();
+        for (int64_t e = tid; e < j * NC; e += 256) {
+            int64_t i = e / NC, c = e % NC;
+            xs[i * NC + c] -= LU[i + j * n] * xs[j * NC + c];
+        }
+        __syncthreads();
+    }
+    for (int64_t e = tid; e < n * NC; e += 256) {
+        int64_t i = e % n, c = e / n;
+        if (c0 + c < n) Ainv[(c0 + c) * n + i] = xs[i * NC + c];
     }
 }
 
@@ -400,7 +442,13 @@ void launch_lu_inverse(double* A, double* Ainv, int64_t n, int* piv, double* wor
     (void)work;
     if (n <= 0) return;
     k_top_lu<<<dim3(1), dim3(1024), 0, s>>>(A, n, piv, flag, logdet, sign);
-    k_top_inverse<<<dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s>>>(A, piv, n, Ainv);
+    constexpr int NC = 8;
+    if (n <= 1024) {
+        size_t lds = sizeof(double) * (size_t)n * NC;
+        k_top_inverse_lds<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, piv + n, n, Ainv);
+    } else {
+        k_top_inverse<<<dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s>>>(A, piv, n, Ainv);
+    }
 }
 
 }  // namespace rss
