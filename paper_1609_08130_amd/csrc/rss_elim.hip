@@ -47,8 +47,8 @@ struct ElimArgs {
 constexpr int kTile = 32;   // rows (or columns) of J per tile
 
 // Dynamic LDS: Ts[tsz] | Xs[nmax*nmax] (when XLDS) | tile[nmax*kTile]
-template <bool XLDS>
-__global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
+template <bool XLDS, int NTH>
+__global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
                                               double* __restrict__ work, int* flag, int tsz) {
     extern __shared__ double dyn[];
     __shared__ int sp[kMaxBox], rp[kMaxBox];
@@ -80,8 +80,8 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     double* tile = dyn + tsz + (XLDS ? bsz : 0);
     const int ldx = nmax;
 
-    for (int i = tid; i < k; i += 256) sp[i] = a.spos[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += 256) rp[i] = a.rpos[(int64_t)c * nmax + i];
+    for (int i = tid; i < k; i += NTH) sp[i] = a.spos[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) rp[i] = a.rpos[(int64_t)c * nmax + i];
     if (tid == 0) {
         int cntN = 0;
         joff[0] = k;
@@ -101,13 +101,13 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         nN = cntN;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
-    for (int e = tid; e < k * r; e += 256) Ts[e] = Tg[(e % k) + (int64_t)(e / k) * nmax];   // Ts[q + b*k]
+    for (int e = tid; e < k * r; e += NTH) Ts[e] = Tg[(e % k) + (int64_t)(e / k) * nmax];   // Ts[q + b*k]
     __syncthreads();
     const int nj = joff[nN];
     const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
 
     // J list (global indices)
-    for (int jj = tid; jj < nj; jj += 256) {
+    for (int jj = tid; jj < nj; jj += NTH) {
         int g;
         if (jj < k) {
             g = a.gidx[(int64_t)c * nmax + sp[jj]];
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     for (int r0 = 0; r0 < nj; r0 += kTile) {
         const int tr = min(kTile, nj - r0);
         // stage the rows' S columns then R columns: tile[i + kTile * col], col < n
-        for (int e = tid; e < tr * n; e += 256) {
+        for (int e = tid; e < tr * n; e += NTH) {
             int i = e % tr, col = e / tr;
             int jj = r0 + i;
             const double* blk;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
             tile[i + kTile * col] = blk[row + (int64_t)pos * nmax];
         }
         __syncthreads();
-        for (int e = tid; e < tr * r; e += 256) {
+        for (int e = tid; e < tr * r; e += NTH) {
             int i = e % tr, b = e / tr;
             double v = tile[i + kTile * (k + b)];
             const double* tb = Ts + b * k;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
 
     // ---- X_RR = A_RR - A_RS T - T^T Z_S -----------------------------------------
     double* XRR = a.XRR + (int64_t)c * bsz;
-    for (int e = tid; e < r * r; e += 256) {
+    for (int e = tid; e < r * r; e += NTH) {
         int b = e % r, b2 = e / r;
         double v = Acc[rp[b] + (int64_t)rp[b2] * nmax];
         const double* t2 = Ts + b2 * k;
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         const int p = piv_idx;
         if (!(piv_val > 0.0)) { singular = true; break; }
         if (p != j) {
-            for (int l = tid; l < r; l += 256) {
+            for (int l = tid; l < r; l += NTH) {
                 double t0 = Xs[j + l * ldx];
                 Xs[j + l * ldx] = Xs[p + l * ldx];
                 Xs[p + l * ldx] = t0;
@@ -203,11 +203,11 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         ld_sum += log(fabs(d));
         if (d < 0) sgn = -sgn;
         const double rinv = 1.0 / d;
-        for (int i = tid; i < r; i += 256) fvec[i] = (i == j) ? 0.0 : Xs[i + j * ldx];
+        for (int i = tid; i < r; i += NTH) fvec[i] = (i == j) ? 0.0 : Xs[i + j * ldx];
         __syncthreads();
-        for (int l = tid; l < r; l += 256) Xs[j + l * ldx] = (l == j ? 1.0 : Xs[j + l * ldx]) * rinv;
+        for (int l = tid; l < r; l += NTH) Xs[j + l * ldx] = (l == j ? 1.0 : Xs[j + l * ldx]) * rinv;
         __syncthreads();
-        for (int e = tid; e < r * r; e += 256) {
+        for (int e = tid; e < r * r; e += NTH) {
             int i = e % r, l = e / r;
             if (i == j) continue;
             double base = (l == j) ? 0.0 : Xs[i + l * ldx];
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     for (int j = r - 1; j >= 0; --j) {
         int p = colswap[j];
         if (p != j)
-            for (int i = tid; i < r; i += 256) {
+            for (int i = tid; i < r; i += NTH) {
                 double t0 = Xs[i + j * ldx];
                 Xs[i + j * ldx] = Xs[i + p * ldx];
                 Xs[i + p * ldx] = t0;
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         a.sign_part[c] = sgn;
     }
     double* Xinv = a.Xinv + (int64_t)c * bsz;
-    for (int e = tid; e < r * r; e += 256) {
+    for (int e = tid; e < r * r; e += NTH) {
         int b = e % r, b2 = e / r;
         Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * ldx];
     }
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     for (int c0 = 0; c0 < nj; c0 += kTile) {
         const int tc = min(kTile, nj - c0);
         // tile[b + r * j'] = X_RJ[b, c0 + j']
-        for (int e = tid; e < tc * r; e += 256) {
+        for (int e = tid; e < tc * r; e += NTH) {
             int b = e % r, jp = e / r;
             int jj = c0 + jp;
             const double* blk;
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
             tile[b + r * jp] = v;
         }
         __syncthreads();
-        for (int e = tid; e < tc * r; e += 256) {
+        for (int e = tid; e < tc * r; e += NTH) {
             int b = e % r, jp = e / r;
             const double* tcol = tile + r * jp;
             double v = 0.0;
@@ -277,23 +277,23 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
     }
 
     // ---- bookkeeping: record sets, FP32 copies, active list of c becomes S ---------------
-    for (int i = tid; i < k; i += 256) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sp[i]];
-    for (int i = tid; i < r; i += 256) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + rp[i]];
+    for (int i = tid; i < k; i += NTH) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sp[i]];
+    for (int i = tid; i < r; i += NTH) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + rp[i]];
     if (mixed) {
         __syncthreads();
-        for (int e = tid; e < nj * r; e += 256) {
+        for (int e = tid; e < nj * r; e += NTH) {
             int jj = e % nj, b = e / nj;
             a.XJR32[(int64_t)c * ldJ * nmax + jj + (int64_t)b * ldJ] = (float)XJR[jj + (int64_t)b * ldJ];
         }
-        for (int e = tid; e < r * nj; e += 256) {
+        for (int e = tid; e < r * nj; e += NTH) {
             int b = e % r, jj = e / r;
             a.G32[(int64_t)c * nmax * ldJ + b + (int64_t)jj * nmax] = (float)G[b + (int64_t)jj * nmax];
         }
-        for (int e = tid; e < r * r; e += 256) {
+        for (int e = tid; e < r * r; e += NTH) {
             int b = e % r, b2 = e / r;
             a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * ldx];
         }
-        for (int e = tid; e < k * r; e += 256) {
+        for (int e = tid; e < k * r; e += NTH) {
             int q = e % k, b = e / k;
             a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Ts[q + b * k];
         }
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(256) k_elim(ElimArgs a, const int* __restrict_
         a.nJ[c] = nj;
         a.nact[c] = k;
     }
-    for (int i = tid; i < k; i += 256) a.apos[(int64_t)c * nmax + i] = sp[i];
+    for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sp[i];
 }
 
 static int g_max_lds = -1;
@@ -333,12 +333,26 @@ void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double
     const size_t tile = (size_t)L.nmax * kTile;
     const size_t with_x = sizeof(double) * (tsz + (size_t)L.nmax * L.nmax + tile);
     const size_t without_x = sizeof(double) * (tsz + tile);
+    // few boxes in a colour (upper levels): one large workgroup per box to cut latency
+    const bool big = nboxes < 512;
     if ((int)with_x <= elim_lds_limit()) {
-        hipFuncSetAttribute((const void*)k_elim<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
-        k_elim<true><<<dim3(nboxes), dim3(256), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        if (big) {
+            hipFuncSetAttribute((const void*)k_elim<true, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
+            k_elim<true, 1024><<<dim3(nboxes), dim3(1024), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        } else {
+            hipFuncSetAttribute((const void*)k_elim<true, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
+            k_elim<true, 256><<<dim3(nboxes), dim3(256), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        }
     } else {
-        hipFuncSetAttribute((const void*)k_elim<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)without_x);
-        k_elim<false><<<dim3(nboxes), dim3(256), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        if (big) {
+            hipFuncSetAttribute((const void*)k_elim<false, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)without_x);
+            k_elim<false, 1024><<<dim3(nboxes), dim3(1024), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        } else {
+            hipFuncSetAttribute((const void*)k_elim<false, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)without_x);
+            k_elim<false, 256><<<dim3(nboxes), dim3(256), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        }
     }
 }
 

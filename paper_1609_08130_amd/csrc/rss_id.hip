@@ -30,19 +30,22 @@ __device__ inline int wave_min_int(int v) {
     return v;
 }
 
-template <int CPT, int BR, bool RLDS>
-__global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int nb, int nmax,
-                                           const int* __restrict__ cnt, const int* __restrict__ gidx,
-                                           const int* __restrict__ nact, const int* __restrict__ apos,
-                                           const int* __restrict__ boxes, const double* __restrict__ pts,
-                                           const double* __restrict__ ptmpl, KernelParams kp, int t,
-                                           int* __restrict__ krank, int* __restrict__ spos,
-                                           int* __restrict__ rpos, double* __restrict__ Tout,
-                                           int* __restrict__ mrows, double* __restrict__ work) {
-    constexpr int NP = 64 * CPT;
-    extern __shared__ double R0s[];   // RLDS: nmax x NP
-    __shared__ double vbuf[NP > BR ? NP : BR];
-    __shared__ double taubuf;
+// NW waves per box; thread q owns column q of B (n <= 64 NW).  R0 rows are n, row stride NT.
+template <int NW, bool RLDS>
+__global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store, int nb, int nmax,
+                                                const int* __restrict__ cnt, const int* __restrict__ gidx,
+                                                const int* __restrict__ nact, const int* __restrict__ apos,
+                                                const int* __restrict__ boxes, const double* __restrict__ pts,
+                                                const double* __restrict__ ptmpl, KernelParams kp, int t,
+                                                int* __restrict__ krank, int* __restrict__ spos,
+                                                int* __restrict__ rpos, double* __restrict__ Tout,
+                                                int* __restrict__ mrows, double* __restrict__ work) {
+    constexpr int NT = 64 * NW;
+    constexpr int BR = 64;
+    constexpr int VB = NT > BR ? NT : BR;
+    extern __shared__ double R0s[];   // RLDS: nmax x NT
+    __shared__ double vbuf[2][VB];
+    __shared__ double taubuf[2];
     __shared__ const double* obase[16];
     __shared__ const int* oap[16];
     __shared__ int obeg[17];
@@ -50,23 +53,26 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
     __shared__ const double* rowptr[BR];
     __shared__ int rowprox[BR];
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
-    __shared__ int piv[NP];
-    __shared__ int srank_s[NP];
-    __shared__ int pivsel;
+    __shared__ int piv[NT];
+    __shared__ int srank_s[NT];
+    __shared__ double redv[2][NW];
+    __shared__ int redi[2][NW];
+    __shared__ unsigned long long smask[NW];
 
-    const int lane = threadIdx.x;
+    const int q = threadIdx.x;           // column owned by this thread
+    const int wv = q >> 6, lane = q & 63;
     const int c = boxes[blockIdx.x];
     const int n = cnt[c];
-    double* R0 = RLDS ? R0s : (work + (int64_t)blockIdx.x * NP * NP);
+    double* R0 = RLDS ? R0s : (work + (int64_t)blockIdx.x * NT * NT);
     if (n == 0) {
-        if (lane == 0) { krank[c] = 0; mrows[c] = 0; }
+        if (q == 0) { krank[c] = 0; mrows[c] = 0; }
         return;
     }
     const int cx = c % nb, cy = c / nb;
     const int64_t bsz = (int64_t)nmax * nmax;
 
-    // O ring: boxes at distance exactly 2, ascending linear index.
-    if (lane == 0) {
+    if (q == 0) {
+        // O ring: boxes at distance exactly 2, ascending linear index
         int cntO = 0;
         obeg[0] = 0;
         for (int dy = -2; dy <= 2; ++dy)
@@ -82,41 +88,34 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
             }
         nO = cntO;
     }
-    // proxy points y_p = centre + radius * (cos, sin)(2 pi p / n_p)
     {
+        // proxy points y_p = centre + radius * (cos, sin)(2 pi p / n_p)
 #pragma clang fp contract(off)
         double side_t = kp.side / (double)(1 << t);
         double ccx = kp.lo_x + ((double)cx + 0.5) * side_t;
         double ccy = kp.lo_y + ((double)cy + 0.5) * side_t;
         double rr = kp.proxy_radius * side_t;
-        for (int p = lane; p < kp.n_proxy; p += 64) {
+        for (int p = q; p < kp.n_proxy; p += NT) {
             pxs[p] = ccx + rr * ptmpl[2 * p];
             pys[p] = ccy + rr * ptmpl[2 * p + 1];
         }
     }
-    double colx[CPT], coly[CPT];
-#pragma unroll
-    for (int cc = 0; cc < CPT; ++cc) {
-        int q = lane + 64 * cc;
-        colx[cc] = 0.0; coly[cc] = 0.0;
-        if (q < n) {
-            int g = gidx[(int64_t)c * nmax + q];
-            colx[cc] = pts[2 * (int64_t)g];
-            coly[cc] = pts[2 * (int64_t)g + 1];
-        }
+    double colx = 0.0, coly = 0.0;
+    if (q < n) {
+        int g = gidx[(int64_t)c * nmax + q];
+        colx = pts[2 * (int64_t)g];
+        coly = pts[2 * (int64_t)g + 1];
     }
-    for (int i = 0; i < n; ++i) {
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) R0[i * NP + lane + 64 * cc] = 0.0;
-    }
+    for (int i = 0; i < n; ++i) R0[i * NT + q] = 0.0;
     __syncthreads();
     const int mO = obeg[nO];
     const int m = mO + kp.n_proxy;
 
-    // ---- 1. TSQR ----------------------------------------------------------------
+    // ---- 1. TSQR: [R0; chunk] -> R0, BR rows at a time ----------------------------------
+    int step = 0;
     for (int r0 = 0; r0 < m; r0 += BR) {
-        if (lane < BR) {
-            int row = r0 + lane;
+        if (q < BR) {
+            int row = r0 + q;
             const double* ptr = nullptr;
             int kind = -2;
             if (row < mO) {
@@ -127,102 +126,88 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
             } else if (row < m) {
                 kind = row - mO;
             }
-            rowptr[lane] = ptr;
-            rowprox[lane] = kind;
+            rowptr[q] = ptr;
+            rowprox[q] = kind;
         }
         __syncthreads();
-        double cv[CPT][BR];
+        double cv[BR];
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             const int kind = rowprox[i];
-            const double* ptr = rowptr[i];
-#pragma unroll
-            for (int cc = 0; cc < CPT; ++cc) {
-                int q = lane + 64 * cc;
-                double v = 0.0;
-                if (q < n) {
-                    if (kind == -1) {
-                        v = ptr[(int64_t)q * nmax];
-                    } else if (kind >= 0) {
+            double v = 0.0;
+            if (q < n) {
+                if (kind == -1) {
+                    v = rowptr[i][(int64_t)q * nmax];
+                } else if (kind >= 0) {
 #pragma clang fp contract(off)
-                        double dx = pxs[kind] - colx[cc];
-                        double dy = pys[kind] - coly[cc];
-                        v = kp.coef * log(dx * dx + dy * dy);
-                    }
+                    double dx = pxs[kind] - colx;
+                    double dy = pys[kind] - coly;
+                    v = kp.coef * log(dx * dx + dy * dy);
                 }
-                cv[cc][i] = v;
+            }
+            cv[i] = v;
+        }
+        const int rows_here = min(BR, m - r0);
+        for (int j = 0; j < n; ++j, ++step) {
+            const int buf = step & 1;
+            if (q == j) {
+                double alpha = R0[j * NT + j];
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < BR; ++i) s4[i & 3] += cv[i] * cv[i];
+                double sigma = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                double tau = 0.0;
+                if (sigma != 0.0) {
+                    double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+                    tau = (beta - alpha) / beta;
+                    double sc = 1.0 / (alpha - beta);
+#pragma unroll
+                    for (int i = 0; i < BR; ++i) vbuf[buf][i] = cv[i] * sc;
+                    R0[j * NT + j] = beta;
+                }
+                taubuf[buf] = tau;
+            }
+            __syncthreads();
+            const double tau = taubuf[buf];
+            if (tau != 0.0 && q > j && q < n) {
+                const double* v = vbuf[buf];
+                double w4[4] = {R0[j * NT + q], 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < BR; ++i) w4[i & 3] += v[i] * cv[i];
+                double tw = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+                R0[j * NT + q] -= tw;
+#pragma unroll
+                for (int i = 0; i < BR; ++i) cv[i] -= tw * v[i];
             }
         }
-#pragma unroll
-        for (int cj = 0; cj < CPT; ++cj) {
-            for (int jj = 0; jj < 64; ++jj) {
-                const int j = cj * 64 + jj;
-                if (j >= n) break;
-                if (lane == jj) {
-                    double alpha = R0[j * NP + j];
-                    double sigma = 0.0;
-#pragma unroll
-                    for (int i = 0; i < BR; ++i) sigma += cv[cj][i] * cv[cj][i];
-                    double tau = 0.0;
-                    if (sigma != 0.0) {
-                        double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-                        tau = (beta - alpha) / beta;
-                        double sc = 1.0 / (alpha - beta);
-#pragma unroll
-                        for (int i = 0; i < BR; ++i) vbuf[i] = cv[cj][i] * sc;
-                        R0[j * NP + j] = beta;
-                    }
-                    taubuf = tau;
-                }
-                __syncthreads();
-                const double tau = taubuf;
-                if (tau != 0.0) {
-#pragma unroll
-                    for (int cc = 0; cc < CPT; ++cc) {
-                        int q = lane + 64 * cc;
-                        if (q > j && q < n) {
-                            double w = R0[j * NP + q];
-#pragma unroll
-                            for (int i = 0; i < BR; ++i) w += vbuf[i] * cv[cc][i];
-                            double tw = tau * w;
-                            R0[j * NP + q] -= tw;
-#pragma unroll
-                            for (int i = 0; i < BR; ++i) cv[cc][i] -= tw * vbuf[i];
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        (void)rows_here;
     }
+    __syncthreads();
 
-    // ---- 2. pivoted QR of R0 ------------------------------------------------------
-    bool done[CPT];
-#pragma unroll
-    for (int cc = 0; cc < CPT; ++cc) done[cc] = (lane + 64 * cc) >= n;
+    // ---- 2. pivoted QR of R0 with fresh trailing norms --------------------------------------
+    bool done = q >= n;
     const int kmax = min(m, n);
     double rnorm0 = 0.0;
     int k = 0;
-    for (int j = 0; j < kmax; ++j) {
-        double nu[CPT];
-        double lmax = -1.0;
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
-            nu[cc] = -1.0;
-            if (!done[cc]) {
-                int q = lane + 64 * cc;
-                double s = 0.0;
-                for (int i = j; i < n; ++i) {
-                    double v = R0[i * NP + q];
-                    s += v * v;
-                }
-                nu[cc] = s;
-                lmax = fmax(lmax, s);
+    for (int j = 0; j < kmax; ++j, ++step) {
+        const int buf = step & 1;
+        double nu = -1.0;
+        if (!done) {
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = j; i < n; ++i) {
+                double v = R0[i * NT + q];
+                s4[(i - j) & 3] += v * v;
             }
+            nu = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         }
-        const double numax = wave_max(lmax);
+        double wmax = wave_max(nu);
+        if (lane == 0) redv[buf][wv] = wmax;
+        __syncthreads();
+        double numax = redv[buf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) numax = fmax(numax, redv[buf][w]);
         const double mu = sqrt(numax);
-        if (!(mu == mu)) break;   // no finite trailing norm left
+        if (!(mu == mu)) break;
         if (j == 0) {
             if (!(mu > 0.0)) break;
             rnorm0 = mu;
@@ -230,17 +215,19 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
             break;
         }
         const double thr = mu - kp.tau * rnorm0;
-        int lmin = 1 << 30;
+        int cand = (!done && sqrt(nu) >= thr) ? q : (1 << 30);
+        int wmin = wave_min_int(cand);
+        if (lane == 0) redi[buf][wv] = wmin;
+        __syncthreads();
+        int p = redi[buf][0];
 #pragma unroll
-        for (int cc = 0; cc < CPT; ++cc)
-            if (!done[cc] && sqrt(nu[cc]) >= thr) lmin = min(lmin, lane + 64 * cc);
-        const int p = wave_min_int(lmin);
-        if (p >= n) break;        // no candidate (non-finite norms): stop the ID here
-        if (lane == (p & 63)) {
-            double alpha = R0[j * NP + p];
+        for (int w = 1; w < NW; ++w) p = min(p, redi[buf][w]);
+        if (p >= n) break;
+        if (q == p) {
+            double alpha = R0[j * NT + p];
             double sigma = 0.0;
             for (int i = j + 1; i < n; ++i) {
-                double v = R0[i * NP + p];
+                double v = R0[i * NT + p];
                 sigma += v * v;
             }
             double tau = 0.0;
@@ -248,68 +235,53 @@ __global__ void __launch_bounds__(64) k_id(const double* __restrict__ store, int
                 double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
                 tau = (beta - alpha) / beta;
                 double sc = 1.0 / (alpha - beta);
-                for (int i = j + 1; i < n; ++i) vbuf[i] = R0[i * NP + p] * sc;
-                R0[j * NP + p] = beta;
+                for (int i = j + 1; i < n; ++i) vbuf[buf][i] = R0[i * NT + p] * sc;
+                R0[j * NT + p] = beta;
             }
-            taubuf = tau;
+            taubuf[buf] = tau;
             piv[j] = p;
-            pivsel = p;
+            done = true;
         }
         __syncthreads();
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc)
-            if (lane + 64 * cc == p) done[cc] = true;
-        const double tau = taubuf;
-        if (tau != 0.0) {
-#pragma unroll
-            for (int cc = 0; cc < CPT; ++cc) {
-                if (done[cc]) continue;
-                int q = lane + 64 * cc;
-                double w = R0[j * NP + q];
-                for (int i = j + 1; i < n; ++i) w += vbuf[i] * R0[i * NP + q];
-                double tw = tau * w;
-                R0[j * NP + q] -= tw;
-                for (int i = j + 1; i < n; ++i) R0[i * NP + q] -= tw * vbuf[i];
-            }
+        const double tau = taubuf[buf];
+        if (tau != 0.0 && !done) {
+            const double* v = vbuf[buf];
+            double w4[4] = {R0[j * NT + q], 0.0, 0.0, 0.0};
+            for (int i = j + 1; i < n; ++i) w4[(i - j) & 3] += v[i] * R0[i * NT + q];
+            double tw = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+            R0[j * NT + q] -= tw;
+            for (int i = j + 1; i < n; ++i) R0[i * NT + q] -= tw * v[i];
         }
-        __syncthreads();
         k = j + 1;
     }
-
-    // ---- 3. sorted sets and T = R11^{-1} R12 -----------------------------------------
-    int srank[CPT];
-    {
-        int below = 0;
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
-            bool isS = (lane + 64 * cc < n) && done[cc];
-            unsigned long long mask = __ballot(isS);
-            srank[cc] = below + __popcll(mask & ((1ull << lane) - 1ull));
-            below += __popcll(mask);
-            if (isS) srank_s[lane + 64 * cc] = srank[cc];
-        }
-    }
     __syncthreads();
-    if (lane == 0) { krank[c] = k; mrows[c] = m; }
+
+    // ---- 3. sorted sets and T = R11^{-1} R12 -------------------------------------------------
+    const bool isS = (q < n) && done;
+    const unsigned long long mask = __ballot(isS);
+    if (lane == 0) smask[wv] = mask;
+    __syncthreads();
+    int below = 0;
+    for (int w = 0; w < wv; ++w) below += __popcll(smask[w]);
+    const int srank = below + __popcll(mask & ((1ull << lane) - 1ull));
+    if (isS) srank_s[q] = srank;
+    __syncthreads();
+    if (q == 0) { krank[c] = k; mrows[c] = m; }
     const int64_t boff = (int64_t)c * nmax;
     double* Tb = Tout + (int64_t)c * nmax * nmax;
-#pragma unroll
-    for (int cc = 0; cc < CPT; ++cc) {
-        int q = lane + 64 * cc;
-        if (q >= n) continue;
-        if (done[cc]) {
-            spos[boff + srank[cc]] = q;
+    if (q < n) {
+        if (isS) {
+            spos[boff + srank] = q;
         } else {
-            int rr = q - srank[cc];
+            int rr = q - srank;
             rpos[boff + rr] = q;
-            // back substitution, in place in the lane's own column
             for (int a = k - 1; a >= 0; --a) {
-                double s = R0[a * NP + q];
-                for (int b = a + 1; b < k; ++b) s -= R0[a * NP + piv[b]] * R0[b * NP + q];
-                s = s / R0[a * NP + piv[a]];
-                R0[a * NP + q] = s;
+                double s = R0[a * NT + q];
+                for (int b = a + 1; b < k; ++b) s -= R0[a * NT + piv[b]] * R0[b * NT + q];
+                s = s / R0[a * NT + piv[a]];
+                R0[a * NT + q] = s;
             }
-            for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = R0[a * NP + q];
+            for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = R0[a * NT + q];
         }
     }
 }
@@ -318,30 +290,25 @@ int elim_lds_limit();
 
 void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                const KernelParams& kp, double* work, hipStream_t s) {
-    // R0 (rows < nmax, row stride NP = 64 * CPT) lives in LDS when it fits, else in
-    // `work` (nboxes * NP * NP doubles).
+    // R0 (n rows, row stride 64 NW) lives in LDS when it fits, else in `work`
+    // (nboxes * (64 NW)^2 doubles).
     if (nboxes <= 0) return;
-    dim3 grid(nboxes), block(64);
-    const int lim = elim_lds_limit();
+    dim3 grid(nboxes);
+    const int lim = elim_lds_limit() - 16384;   // room for the static LDS arrays
     if (L.nmax <= 64) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 64;
-        k_id<1, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                   pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                   work);
-    } else if (L.nmax <= 128) {
+        k_id<1, true><<<grid, dim3(64), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
+                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+    } else if (L.nmax <= 128 && (int)(sizeof(double) * (size_t)L.nmax * 128) <= lim) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 128;
-        if ((int)(lds + 4096) <= lim) {
-            hipFuncSetAttribute((const void*)k_id<2, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            k_id<2, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                       pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                       work);
-        } else {
-            k_id<2, 32, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                      work);
-        }
+        hipFuncSetAttribute((const void*)k_id<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_id<2, true><<<grid, dim3(128), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
+                                                   ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+    } else if (L.nmax <= 128) {
+        k_id<2, false><<<grid, dim3(128), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
+                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
     } else {
-        k_id<4, 16, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
+        k_id<4, false><<<grid, dim3(256), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
                                                   ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
     }
 }
