@@ -30,21 +30,27 @@ __device__ inline int wave_min_int(int v) {
     return v;
 }
 
-// NW waves per box; thread q owns column q of B (n <= 64 NW).  R0 rows are n, row stride NT.
-template <int NW, bool RLDS>
-__global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store, int nb, int nmax,
-                                                const int* __restrict__ cnt, const int* __restrict__ gidx,
-                                                const int* __restrict__ nact, const int* __restrict__ apos,
-                                                const int* __restrict__ boxes, const double* __restrict__ pts,
-                                                const double* __restrict__ ptmpl, KernelParams kp, int t,
-                                                int* __restrict__ krank, int* __restrict__ spos,
-                                                int* __restrict__ rpos, double* __restrict__ Tout,
-                                                int* __restrict__ mrows, double* __restrict__ work) {
-    constexpr int NT = 64 * NW;
-    constexpr int BR = 64;
+// Thread layout: NWC column waves x RG row groups.  Thread (rg, q) owns column q of B
+// (n <= 64 NWC) and rows rg*RPT .. rg*RPT+RPT-1 of each TSQR chunk of RG*RPT rows.
+// R0 (n rows, row stride NT = 64 NWC) is private per column; rows of the chunk are
+// combined across the row groups through LDS (two barriers per reflector).
+template <int NWC, int RG, bool RLDS>
+__global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__ store, int nb, int nmax,
+                                                      const int* __restrict__ cnt, const int* __restrict__ gidx,
+                                                      const int* __restrict__ nact, const int* __restrict__ apos,
+                                                      const int* __restrict__ boxes, const double* __restrict__ pts,
+                                                      const double* __restrict__ ptmpl, KernelParams kp, int t,
+                                                      int* __restrict__ krank, int* __restrict__ spos,
+                                                      int* __restrict__ rpos, double* __restrict__ Tout,
+                                                      int* __restrict__ mrows, double* __restrict__ work) {
+    constexpr int NT = 64 * NWC;          // column threads
+    constexpr int RPT = 32;               // chunk rows per thread
+    constexpr int BR = RG * RPT;          // chunk rows
     constexpr int VB = NT > BR ? NT : BR;
-    extern __shared__ double R0s[];   // RLDS: nmax x NT
-    __shared__ double vbuf[2][VB];
+    extern __shared__ double R0s[];       // RLDS: nmax x NT
+    __shared__ double vraw[2][VB];
+    __shared__ double part[2][RG];
+    __shared__ double dpart[2][RG][NT];
     __shared__ double taubuf[2];
     __shared__ const double* obase[16];
     __shared__ const int* oap[16];
@@ -55,23 +61,25 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
     __shared__ int piv[NT];
     __shared__ int srank_s[NT];
-    __shared__ double redv[2][NW];
-    __shared__ int redi[2][NW];
-    __shared__ unsigned long long smask[NW];
+    __shared__ double redv[2][NWC];
+    __shared__ int redi[2][NWC];
+    __shared__ unsigned long long smask[NWC];
 
-    const int q = threadIdx.x;           // column owned by this thread
-    const int wv = q >> 6, lane = q & 63;
+    const int tid = threadIdx.x;
+    const int q = tid % NT;               // column
+    const int rg = tid / NT;              // row group
+    const int wv = q >> 6, lane = q & 63; // column wave (within row group 0)
     const int c = boxes[blockIdx.x];
     const int n = cnt[c];
     double* R0 = RLDS ? R0s : (work + (int64_t)blockIdx.x * NT * NT);
     if (n == 0) {
-        if (q == 0) { krank[c] = 0; mrows[c] = 0; }
+        if (tid == 0) { krank[c] = 0; mrows[c] = 0; }
         return;
     }
     const int cx = c % nb, cy = c / nb;
     const int64_t bsz = (int64_t)nmax * nmax;
 
-    if (q == 0) {
+    if (tid == 0) {
         // O ring: boxes at distance exactly 2, ascending linear index
         int cntO = 0;
         obeg[0] = 0;
@@ -95,7 +103,7 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
         double ccx = kp.lo_x + ((double)cx + 0.5) * side_t;
         double ccy = kp.lo_y + ((double)cy + 0.5) * side_t;
         double rr = kp.proxy_radius * side_t;
-        for (int p = q; p < kp.n_proxy; p += NT) {
+        for (int p = tid; p < kp.n_proxy; p += 64 * NWC * RG) {
             pxs[p] = ccx + rr * ptmpl[2 * p];
             pys[p] = ccy + rr * ptmpl[2 * p + 1];
         }
@@ -106,7 +114,7 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
         colx = pts[2 * (int64_t)g];
         coly = pts[2 * (int64_t)g + 1];
     }
-    for (int i = 0; i < n; ++i) R0[i * NT + q] = 0.0;
+    for (int i = rg; i < n; i += RG) R0[i * NT + q] = 0.0;
     __syncthreads();
     const int mO = obeg[nO];
     const int m = mO + kp.n_proxy;
@@ -114,8 +122,8 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
     // ---- 1. TSQR: [R0; chunk] -> R0, BR rows at a time ----------------------------------
     int step = 0;
     for (int r0 = 0; r0 < m; r0 += BR) {
-        if (q < BR) {
-            int row = r0 + q;
+        for (int i = tid; i < BR; i += 64 * NWC * RG) {
+            int row = r0 + i;
             const double* ptr = nullptr;
             int kind = -2;
             if (row < mO) {
@@ -126,18 +134,19 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
             } else if (row < m) {
                 kind = row - mO;
             }
-            rowptr[q] = ptr;
-            rowprox[q] = kind;
+            rowptr[i] = ptr;
+            rowprox[i] = kind;
         }
         __syncthreads();
-        double cv[BR];
+        double cv[RPT];
 #pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            const int kind = rowprox[i];
+        for (int i = 0; i < RPT; ++i) {
+            const int ri = rg * RPT + i;
+            const int kind = rowprox[ri];
             double v = 0.0;
             if (q < n) {
                 if (kind == -1) {
-                    v = rowptr[i][(int64_t)q * nmax];
+                    v = rowptr[ri][(int64_t)q * nmax];
                 } else if (kind >= 0) {
 #pragma clang fp contract(off)
                     double dx = pxs[kind] - colx;
@@ -147,44 +156,55 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
             }
             cv[i] = v;
         }
-        const int rows_here = min(BR, m - r0);
         for (int j = 0; j < n; ++j, ++step) {
             const int buf = step & 1;
+            // A: the threads of column j publish their rows and partial sum of squares
             if (q == j) {
-                double alpha = R0[j * NT + j];
                 double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int i = 0; i < BR; ++i) s4[i & 3] += cv[i] * cv[i];
-                double sigma = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                double tau = 0.0;
-                if (sigma != 0.0) {
-                    double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-                    tau = (beta - alpha) / beta;
-                    double sc = 1.0 / (alpha - beta);
-#pragma unroll
-                    for (int i = 0; i < BR; ++i) vbuf[buf][i] = cv[i] * sc;
-                    R0[j * NT + j] = beta;
+                for (int i = 0; i < RPT; ++i) {
+                    s4[i & 3] += cv[i] * cv[i];
+                    vraw[buf][rg * RPT + i] = cv[i];
                 }
-                taubuf[buf] = tau;
+                part[buf][rg] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
             __syncthreads();
-            const double tau = taubuf[buf];
-            if (tau != 0.0 && q > j && q < n) {
-                const double* v = vbuf[buf];
-                double w4[4] = {R0[j * NT + q], 0.0, 0.0, 0.0};
+            // B: every thread forms the reflector scalars and its partial w_q
+            double sigma = 0.0;
 #pragma unroll
-                for (int i = 0; i < BR; ++i) w4[i & 3] += v[i] * cv[i];
-                double tw = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
-                R0[j * NT + q] -= tw;
-#pragma unroll
-                for (int i = 0; i < BR; ++i) cv[i] -= tw * v[i];
+            for (int g = 0; g < RG; ++g) sigma += part[buf][g];
+            const double alpha = R0[j * NT + j];
+            double tau = 0.0, sc = 0.0, beta = alpha;
+            if (sigma != 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+                tau = (beta - alpha) / beta;
+                sc = 1.0 / (alpha - beta);
             }
+            const double* v = vraw[buf] + rg * RPT;
+            const bool act = tau != 0.0 && q > j && q < n;
+            if (act) {
+                double w4[4] = {rg == 0 ? R0[j * NT + q] : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) w4[i & 3] += (v[i] * sc) * cv[i];
+                dpart[buf][rg][q] = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+            }
+            __syncthreads();
+            // C: rank-one update of the chunk rows; row-group 0 updates R0
+            if (act) {
+                double w = 0.0;
+#pragma unroll
+                for (int g = 0; g < RG; ++g) w += dpart[buf][g][q];
+                const double tw = tau * w;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) cv[i] -= tw * (v[i] * sc);
+                if (rg == 0) R0[j * NT + q] -= tw;
+            }
+            if (q == j && rg == 0 && sigma != 0.0) R0[j * NT + j] = beta;
         }
-        (void)rows_here;
     }
     __syncthreads();
 
-    // ---- 2. pivoted QR of R0 with fresh trailing norms --------------------------------------
+    // ---- 2. pivoted QR of R0 with fresh trailing norms (row group 0) -----------------------
     bool done = q >= n;
     const int kmax = min(m, n);
     double rnorm0 = 0.0;
@@ -192,20 +212,22 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
     for (int j = 0; j < kmax; ++j, ++step) {
         const int buf = step & 1;
         double nu = -1.0;
-        if (!done) {
-            double s4[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int i = j; i < n; ++i) {
-                double v = R0[i * NT + q];
-                s4[(i - j) & 3] += v * v;
+        if (rg == 0) {
+            if (!done) {
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int i = j; i < n; ++i) {
+                    double vv = R0[i * NT + q];
+                    s4[(i - j) & 3] += vv * vv;
+                }
+                nu = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
-            nu = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+            double wmax = wave_max(nu);
+            if (lane == 0) redv[buf][wv] = wmax;
         }
-        double wmax = wave_max(nu);
-        if (lane == 0) redv[buf][wv] = wmax;
         __syncthreads();
         double numax = redv[buf][0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) numax = fmax(numax, redv[buf][w]);
+        for (int w = 1; w < NWC; ++w) numax = fmax(numax, redv[buf][w]);
         const double mu = sqrt(numax);
         if (!(mu == mu)) break;
         if (j == 0) {
@@ -215,37 +237,39 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
             break;
         }
         const double thr = mu - kp.tau * rnorm0;
-        int cand = (!done && sqrt(nu) >= thr) ? q : (1 << 30);
-        int wmin = wave_min_int(cand);
-        if (lane == 0) redi[buf][wv] = wmin;
+        if (rg == 0) {
+            int cand = (!done && sqrt(nu) >= thr) ? q : (1 << 30);
+            int wmin = wave_min_int(cand);
+            if (lane == 0) redi[buf][wv] = wmin;
+        }
         __syncthreads();
         int p = redi[buf][0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) p = min(p, redi[buf][w]);
+        for (int w = 1; w < NWC; ++w) p = min(p, redi[buf][w]);
         if (p >= n) break;
-        if (q == p) {
+        if (q == p && rg == 0) {
             double alpha = R0[j * NT + p];
             double sigma = 0.0;
             for (int i = j + 1; i < n; ++i) {
-                double v = R0[i * NT + p];
-                sigma += v * v;
+                double vv = R0[i * NT + p];
+                sigma += vv * vv;
             }
             double tau = 0.0;
             if (sigma != 0.0) {
                 double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
                 tau = (beta - alpha) / beta;
                 double sc = 1.0 / (alpha - beta);
-                for (int i = j + 1; i < n; ++i) vbuf[buf][i] = R0[i * NT + p] * sc;
+                for (int i = j + 1; i < n; ++i) vraw[buf][i] = R0[i * NT + p] * sc;
                 R0[j * NT + p] = beta;
             }
             taubuf[buf] = tau;
             piv[j] = p;
-            done = true;
         }
+        if (q == p) done = true;
         __syncthreads();
         const double tau = taubuf[buf];
-        if (tau != 0.0 && !done) {
-            const double* v = vbuf[buf];
+        if (rg == 0 && tau != 0.0 && !done) {
+            const double* v = vraw[buf];
             double w4[4] = {R0[j * NT + q], 0.0, 0.0, 0.0};
             for (int i = j + 1; i < n; ++i) w4[(i - j) & 3] += v[i] * R0[i * NT + q];
             double tw = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
@@ -256,16 +280,19 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
     }
     __syncthreads();
 
-    // ---- 3. sorted sets and T = R11^{-1} R12 -------------------------------------------------
+    // ---- 3. sorted sets and T = R11^{-1} R12 (row group 0) -------------------------------
     const bool isS = (q < n) && done;
-    const unsigned long long mask = __ballot(isS);
-    if (lane == 0) smask[wv] = mask;
+    if (rg == 0) {
+        const unsigned long long mask = __ballot(isS);
+        if (lane == 0) smask[wv] = mask;
+    }
     __syncthreads();
     int below = 0;
     for (int w = 0; w < wv; ++w) below += __popcll(smask[w]);
-    const int srank = below + __popcll(mask & ((1ull << lane) - 1ull));
-    if (isS) srank_s[q] = srank;
+    const int srank = below + __popcll(smask[wv] & ((1ull << lane) - 1ull));
+    if (rg == 0 && isS) srank_s[q] = srank;
     __syncthreads();
+    if (rg != 0) return;
     if (q == 0) { krank[c] = k; mrows[c] = m; }
     const int64_t boff = (int64_t)c * nmax;
     double* Tb = Tout + (int64_t)c * nmax * nmax;
@@ -276,10 +303,10 @@ __global__ void __launch_bounds__(64 * NW) k_id(const double* __restrict__ store
             int rr = q - srank;
             rpos[boff + rr] = q;
             for (int a = k - 1; a >= 0; --a) {
-                double s = R0[a * NT + q];
-                for (int b = a + 1; b < k; ++b) s -= R0[a * NT + piv[b]] * R0[b * NT + q];
-                s = s / R0[a * NT + piv[a]];
-                R0[a * NT + q] = s;
+                double sacc = R0[a * NT + q];
+                for (int b = a + 1; b < k; ++b) sacc -= R0[a * NT + piv[b]] * R0[b * NT + q];
+                sacc = sacc / R0[a * NT + piv[a]];
+                R0[a * NT + q] = sacc;
             }
             for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = R0[a * NT + q];
         }
@@ -290,26 +317,30 @@ int elim_lds_limit();
 
 void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                const KernelParams& kp, double* work, hipStream_t s) {
-    // R0 (n rows, row stride 64 NW) lives in LDS when it fits, else in `work`
-    // (nboxes * (64 NW)^2 doubles).
+    // R0 (n rows, row stride 64 NWC) lives in LDS when it fits, else in `work`
+    // (nboxes * (64 NWC)^2 doubles).
     if (nboxes <= 0) return;
     dim3 grid(nboxes);
-    const int lim = elim_lds_limit() - 16384;   // room for the static LDS arrays
+    const int lim = elim_lds_limit() - 24576;   // room for the static LDS arrays
     if (L.nmax <= 64) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 64;
-        k_id<1, true><<<grid, dim3(64), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        k_id<1, 4, true><<<grid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                      work);
     } else if (L.nmax <= 128 && (int)(sizeof(double) * (size_t)L.nmax * 128) <= lim) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 128;
-        hipFuncSetAttribute((const void*)k_id<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_id<2, true><<<grid, dim3(128), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                   ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        hipFuncSetAttribute((const void*)k_id<2, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_id<2, 4, true><<<grid, dim3(512), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                      work);
     } else if (L.nmax <= 128) {
-        k_id<2, false><<<grid, dim3(128), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        k_id<2, 4, false><<<grid, dim3(512), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                     pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                     work);
     } else {
-        k_id<4, false><<<grid, dim3(256), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                  ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows, work);
+        k_id<4, 2, false><<<grid, dim3(512), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                     pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                     work);
     }
 }
 
