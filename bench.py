@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=256)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: mixed factor + solve only, no baselines")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run only a device-to-device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -158,8 +162,27 @@ def cpu_baseline(args):
                 factor_s_scaled=(t1 - t0) * scale, solve_s_scaled=(t2 - t1) * scale)
 
 
+def copy_calibration(mib: int):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.profile:
+        args.steps, args.warmup, args.solves = 1, 0, 1
+        args.no_fp64 = True
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
                                    "design note, not implemented)"}))
@@ -191,7 +214,9 @@ def main():
         "phase_ms_mixed": mixed["info"]["phase_ms"],
         "phase_ms_fp64": None if fp64 is None else fp64["info"]["phase_ms"],
         "roofline": roof,
-        "levels": [{k: l[k] for k in ("depth", "boxes", "nmax", "records", "sum_k", "max_k", "max_J")}
+        "levels": [{k: (round(l[k], 3) if isinstance(l[k], float) else l[k])
+                    for k in ("depth", "boxes", "nmax", "records", "sum_k", "max_k", "max_J", "ms_id", "ms_elim",
+                              "ms_schur")}
                    for l in mixed["info"]["levels"]],
         "n_top": mixed["info"]["n_top"],
         "bytes_device": mixed["info"]["bytes_device"],
