@@ -557,13 +557,14 @@ def matvec_direct(pts: np.ndarray, p: Params, x: np.ndarray, chunk: int = 2048) 
     return y
 
 
-def matvec_grid_fft(n: int, p: Params, x: np.ndarray) -> np.ndarray:
-    """y = A x for the n x n cell-centre grid (DOF i + n*j), by FFT convolution.
+def matvec_grid_fft(n: int, p: Params, x: np.ndarray, h: float = None) -> np.ndarray:
+    """y = A x for the n x n cell-centre grid (DOF i + n*j, spacing h = 1/n unless given),
+    by FFT convolution.
 
     A - diag*I is block Toeplitz with Toeplitz blocks; its generator w*K(h*(di, dj)) with
     the zero offset set to 0 is embedded in a (2n) x (2n) circulant.
     """
-    h = 1.0 / n
+    h = 1.0 / n if h is None else h
     d = np.arange(-n + 1, n) * h
     dx, dy = np.meshgrid(d, d, indexing="xy")        # [dj, di]
     r2 = dx * dx + dy * dy

@@ -44,27 +44,49 @@ void check_launch() {
     if (e != hipSuccess) fail(RSS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
+// Device memory comes from the device's stream-ordered pool, which keeps freed memory
+// for reuse (release threshold raised once per device): repeated factorizations then do
+// not pay for mapping and unmapping multi-GB stores.
+void init_pool() {
+    static int done_dev[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done_dev[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done_dev[dev] = 1;
+}
+
 template <class T>
-T* dalloc(rss_factor f, size_t n) {
+T* dalloc(rss_factor f, size_t n, hipStream_t s) {
     if (n == 0) n = 1;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    hipError_t e = hipMallocAsync(&p, n * sizeof(T), s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        fail(RSS_E_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        fail(RSS_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
     }
     f->allocs.push_back(p);
     f->bytes_device += n * sizeof(T);
     return (T*)p;
 }
 
-void dfree(rss_factor f, void* p, size_t bytes) {
+template <class T>
+T* dalloc(rss_factor f, size_t n) {
+    return dalloc<T>(f, n, f->stream);
+}
+
+void dfree(rss_factor f, void* p, size_t bytes, hipStream_t s) {
     if (!p) return;
     auto it = std::find(f->allocs.begin(), f->allocs.end(), p);
     if (it != f->allocs.end()) f->allocs.erase(it);
     f->bytes_device -= bytes;
-    (void)hipFree(p);
+    (void)hipFreeAsync(p, s);
 }
+
+void dfree(rss_factor f, void* p, size_t bytes) { dfree(f, p, bytes, f->stream); }
 
 template <class T>
 std::vector<T> d2h(const T* d, size_t n, hipStream_t s) {
@@ -158,8 +180,12 @@ float ev_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 void destroy_all(rss_factor f) {
-    for (void* p : f->allocs) (void)hipFree(p);
+    // every stream may still use the factor's memory: wait for the device, then return
+    // the memory to the pool in null-stream order
+    (void)hipDeviceSynchronize();
+    for (void* p : f->allocs) (void)hipFreeAsync(p, nullptr);
     f->allocs.clear();
+    (void)hipStreamSynchronize(nullptr);
 }
 
 // phase indices of rss_factor_s::phase_ms
@@ -435,6 +461,15 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     }
     f->work_elems = (size_t)f->n * 4 + (size_t)ntop * 8 + 4096;
     f->work = dalloc<double>(f, f->work_elems);
+    // exact operator: FFT on uniform grids, direct summation otherwise
+    if (rss::fft_grid_detect(f->fft, f->pts, f->n, f->flag, s)) {
+        const size_t LL = (size_t)f->fft.L * f->fft.L;
+        f->fft.chat = dalloc<double>(f, 2 * LL);
+        f->fft.work = dalloc<double>(f, 2 * LL);
+        f->fft.tw = dalloc<double>(f, (size_t)f->fft.L);
+        if (!rss::fft_plan_init(f->fft, f->kp, s)) fail(RSS_E_DEVICE, "FFT plan initialization failed");
+    }
+    (void)hipGetLastError();
     hipEvent_t eE = evs.rec(s);
     HIPCHK(hipStreamSynchronize(s));
     f->phase_ms[PH_TOTAL] = ev_ms(e0, eE);
@@ -450,6 +485,8 @@ rss_status guard_factor(rss_factor f) {
 }
 
 }  // namespace
+
+static void exact_matvec(rss_factor f, const double* x, double* y, hipStream_t s);
 
 // ---------------------------------------------------------------------------------------
 extern "C" {
@@ -507,6 +544,8 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     f->kp.n_proxy = p->n_proxy;
     f->kp.proxy_radius = p->proxy_radius;
     hipStream_t s = (hipStream_t)stream;
+    f->stream = s;
+    init_pool();
     try {
         factor_impl(f, d_points, s);
     } catch (const Fail& e) {
@@ -600,13 +639,18 @@ rss_status rss_matvec(rss_factor f, const double* d_x, double* d_y, int32_t nrhs
     hipStream_t s = (hipStream_t)stream;
     try {
         for (int h = 0; h < nrhs; ++h) {
-            rss::launch_matvec_direct(f->pts, f->n, f->kp, d_x + h * ld, d_y + h * ld, s);
+            exact_matvec(f, d_x + h * ld, d_y + h * ld, s);
             check_launch();
         }
     } catch (const Fail& e) {
         return e.st;
     }
     return RSS_OK;
+}
+
+static void exact_matvec(rss_factor f, const double* x, double* y, hipStream_t s) {
+    if (f->fft.ready) rss::launch_matvec_fft(f->fft, f->kp, x, y, s);
+    else rss::launch_matvec_direct(f->pts, f->n, f->kp, x, y, s);
 }
 
 static double ddot(rss_factor f, const double* x, const double* y, double* part, hipStream_t s) {
@@ -639,11 +683,11 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
     int it = 0;
     double rr = 1.0;
     try {
-        V = dalloc<double>(f, (size_t)n * (restart + 1));
-        Z = dalloc<double>(f, (size_t)n * restart);
-        rvec = dalloc<double>(f, n);
-        wvec = dalloc<double>(f, n);
-        part = dalloc<double>(f, 1024);
+        V = dalloc<double>(f, (size_t)n * (restart + 1), s);
+        Z = dalloc<double>(f, (size_t)n * restart, s);
+        rvec = dalloc<double>(f, n, s);
+        wvec = dalloc<double>(f, n, s);
+        part = dalloc<double>(f, 1024, s);
         HIPCHK(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
         const double nb = std::sqrt(ddot(f, d_b, d_b, part, s));
         if (nb == 0.0) {
@@ -668,7 +712,7 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
                     rss::launch_scal_copy(1.0, vj, zj, n, s);
                     check_launch();
                     solve_impl(f, zj, 1, n, use32, s);
-                    rss::launch_matvec_direct(f->pts, n, f->kp, zj, wvec, s);
+                    exact_matvec(f, zj, wvec, s);
                     check_launch();
                     for (int i = 0; i <= j; ++i) {
                         double hij = ddot(f, wvec, V + (size_t)i * n, part, s);
@@ -707,7 +751,7 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
                     rss::launch_axpy(y[i], Z + (size_t)i * n, d_x, n, s);
                     check_launch();
                 }
-                rss::launch_matvec_direct(f->pts, n, f->kp, d_x, wvec, s);
+                exact_matvec(f, d_x, wvec, s);
                 check_launch();
                 rss::launch_scal_copy(1.0, d_b, rvec, n, s);
                 check_launch();
@@ -723,12 +767,12 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
     } catch (const Fail& e) {
         st = e.st;
     }
+    if (V) dfree(f, V, sizeof(double) * n * (restart + 1), s);
+    if (Z) dfree(f, Z, sizeof(double) * n * restart, s);
+    if (rvec) dfree(f, rvec, sizeof(double) * n, s);
+    if (wvec) dfree(f, wvec, sizeof(double) * n, s);
+    if (part) dfree(f, part, sizeof(double) * 1024, s);
     (void)hipStreamSynchronize(s);
-    if (V) dfree(f, V, sizeof(double) * n * (restart + 1));
-    if (Z) dfree(f, Z, sizeof(double) * n * restart);
-    if (rvec) dfree(f, rvec, sizeof(double) * n);
-    if (wvec) dfree(f, wvec, sizeof(double) * n);
-    if (part) dfree(f, part, sizeof(double) * 1024);
     if (iters) *iters = it;
     if (relres) *relres = rr;
     return st;
@@ -828,6 +872,7 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     o.precision(17);
     o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
       << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
+      << ",\"exact_operator\":\"" << (f->fft.ready ? "fft" : "direct") << "\""
       << ",\"bytes_device\":" << f->bytes_device << ",\"lds_limit\":" << rss::elim_lds_limit() << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
     o << "},\"launches\":{";

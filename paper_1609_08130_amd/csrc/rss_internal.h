@@ -69,6 +69,16 @@ struct Level {
     std::vector<int*> d_rec_boxes;
 };
 
+// FFT plan of the exact operator on a uniform n x n grid (L x L circulant embedding).
+struct FFTPlan {
+    bool ready = false;
+    int n = 0, L = 0, logL = 0;
+    double h = 0;
+    void* chat = nullptr;   // FFT2 of the circulant generator, L x L complex
+    void* work = nullptr;   // L x L complex scratch
+    void* tw = nullptr;     // L / 2 twiddles
+};
+
 // Realized sizes and algorithmic counts of one skeletonized level: F_ID = 2 m n^2 - 2/3 n^3,
 // F_X = 4 |J| |R| |S| + 4 |R|^2 |S|, F_LU = 2/3 |R|^3, F_G = 2 |R|^2 |J| + 4/3 |R|^3,
 // F_Schur = 2 |J|^2 |R|; Schur bytes = 16 |J|^2 (FP64 target read + write) plus the two
@@ -91,6 +101,8 @@ struct rss_factor_s {
     double* pts = nullptr;          // n x 2
     std::vector<rss::Level> levels; // levels[i] = depth D - i (skeletonized levels only)
     // top block
+    hipStream_t stream = nullptr;   // stream of rss_factor_create (allocations of the factor)
+    rss::FFTPlan fft;               // exact operator by FFT when the points form a grid
     int lds_limit = 0;
     int64_t ntop = 0;
     int* top_idx = nullptr;
@@ -160,6 +172,9 @@ void launch_copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, 
 // exact operator and BLAS-1 (rss_matvec.hip)
 void launch_matvec_direct(const double* pts, int64_t n, const KernelParams& kp, const double* x,
                           double* y, hipStream_t s);
+bool fft_grid_detect(FFTPlan& P, const double* pts, int64_t N, int* dflag, hipStream_t s);
+bool fft_plan_init(FFTPlan& P, const KernelParams& kp, hipStream_t s);
+void launch_matvec_fft(const FFTPlan& P, const KernelParams& kp, const double* x, double* y, hipStream_t s);
 void launch_dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s);
 int dot_partial_blocks(int64_t n);
 void launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
