@@ -91,7 +91,9 @@ rss_status rss_solve(rss_factor f, const double* d_b, double* d_x, int32_t nrhs,
 rss_status rss_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld,
                      void* stream);
 
-/* y = A x exactly, by direct summation on the device (d_x, d_y must not alias). */
+/* y = A x exactly (d_x, d_y must not alias): by FFT convolution when the points form a
+ * uniform n x n grid in DOF order i + n j (detected at factor creation; the matrix minus
+ * its diagonal is then block Toeplitz), otherwise by direct summation. */
 rss_status rss_matvec(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld,
                       void* stream);
 
@@ -125,8 +127,14 @@ rss_status rss_top_set(rss_factor f, int64_t* idx, int64_t cap, int64_t* count);
  * counts of the factorization; NUL-terminated, truncated to cap bytes. */
 rss_status rss_info(rss_factor f, char* buf, int64_t cap);
 
-/* Free all device memory of f.  NULL-safe. */
+/* Release all device memory of f to the library's block cache.  NULL-safe.
+ * Synchronizes the device (any stream may still be using the factor). */
 rss_status rss_factor_destroy(rss_factor f);
+
+/* Return every cached device block to the device.  The library keeps released blocks
+ * for reuse by later factorizations (repeated factorizations then allocate nothing);
+ * call this to hand the memory back, e.g. before other large allocations. */
+rss_status rss_trim(void);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char* rss_last_error(void);

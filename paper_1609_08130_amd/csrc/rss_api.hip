@@ -12,6 +12,8 @@
 #include <cstring>
 #include <sstream>
 #include <string>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "rss_internal.h"
@@ -44,29 +46,64 @@ void check_launch() {
     if (e != hipSuccess) fail(RSS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-// Device memory comes from the device's stream-ordered pool, which keeps freed memory
-// for reuse (release threshold raised once per device): repeated factorizations then do
-// not pay for mapping and unmapping multi-GB stores.
-void init_pool() {
-    static int done_dev[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done_dev[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done_dev[dev] = 1;
+// Device memory comes from a process-wide cache: a freed block is kept (per device) and
+// handed to a later request of at most its size and at least half of it, so repeated
+// factorizations of similar problems run without mapping or unmapping memory.
+// rss_trim() returns the cached blocks to the device.
+struct CachedBlock {
+    int dev;
+    size_t bytes;
+    void* ptr;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+std::unordered_map<void*, std::pair<int, size_t>> g_live;   // ptr -> (device, block bytes)
+
+size_t round_block(size_t b) {
+    const size_t g = (size_t)2 << 20;
+    return (b + g - 1) / g * g;
 }
 
 template <class T>
 T* dalloc(rss_factor f, size_t n, hipStream_t s) {
+    (void)s;
     if (n == 0) n = 1;
+    const size_t want = round_block(n * sizeof(T));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, n * sizeof(T), s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(RSS_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    size_t got = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        size_t best = SIZE_MAX;
+        int bi = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const CachedBlock& b = g_cache[i];
+            if (b.dev == dev && b.bytes >= want && b.bytes <= 2 * want && b.bytes < best) { best = b.bytes; bi = i; }
+        }
+        if (bi >= 0) {
+            p = g_cache[bi].ptr;
+            got = g_cache[bi].bytes;
+            g_cache.erase(g_cache.begin() + bi);
+        }
+    }
+    if (!p) {
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            // give cached memory back and retry once
+            rss_trim();
+            e = hipMalloc(&p, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(RSS_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+            }
+        }
+        got = want;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_live[p] = {dev, got};
     }
     f->allocs.push_back(p);
     f->bytes_device += n * sizeof(T);
@@ -78,12 +115,23 @@ T* dalloc(rss_factor f, size_t n) {
     return dalloc<T>(f, n, f->stream);
 }
 
+// Return a block to the cache.  The caller guarantees that no queued work still uses it
+// (the library synchronizes the stream before releasing memory a kernel may touch).
+void release_block(void* p) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    g_cache.push_back({it->second.first, it->second.second, p});
+    g_live.erase(it);
+}
+
 void dfree(rss_factor f, void* p, size_t bytes, hipStream_t s) {
     if (!p) return;
     auto it = std::find(f->allocs.begin(), f->allocs.end(), p);
     if (it != f->allocs.end()) f->allocs.erase(it);
     f->bytes_device -= bytes;
-    (void)hipFreeAsync(p, s);
+    (void)hipStreamSynchronize(s);
+    release_block(p);
 }
 
 void dfree(rss_factor f, void* p, size_t bytes) { dfree(f, p, bytes, f->stream); }
@@ -180,12 +228,10 @@ float ev_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 void destroy_all(rss_factor f) {
-    // every stream may still use the factor's memory: wait for the device, then return
-    // the memory to the pool in null-stream order
+    // any stream may still use the factor's memory: wait for the device first
     (void)hipDeviceSynchronize();
-    for (void* p : f->allocs) (void)hipFreeAsync(p, nullptr);
+    for (void* p : f->allocs) release_block(p);
     f->allocs.clear();
-    (void)hipStreamSynchronize(nullptr);
 }
 
 // phase indices of rss_factor_s::phase_ms
@@ -510,6 +556,16 @@ void rss_params_default(rss_params* p) {
 
 const char* rss_last_error(void) { return g_err.c_str(); }
 
+rss_status rss_trim(void) {
+    std::vector<CachedBlock> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        blocks.swap(g_cache);
+    }
+    for (auto& b : blocks) (void)hipFree(b.ptr);
+    return RSS_OK;
+}
+
 rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params* p, void* stream,
                              rss_factor* out) {
     g_err.clear();
@@ -545,7 +601,6 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     f->kp.proxy_radius = p->proxy_radius;
     hipStream_t s = (hipStream_t)stream;
     f->stream = s;
-    init_pool();
     try {
         factor_impl(f, d_points, s);
     } catch (const Fail& e) {

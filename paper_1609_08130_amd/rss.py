@@ -29,7 +29,7 @@ STATUS = {0: "RSS_OK", 1: "RSS_E_ARG", 2: "RSS_E_NOMEM", 3: "RSS_E_DEVICE", 4: "
 # exported names declared in include/rss.h
 EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_matvec", "rss_gmres",
            "rss_logdet", "rss_shape", "rss_box_sets", "rss_top_set", "rss_info", "rss_factor_destroy",
-           "rss_last_error"]
+           "rss_last_error", "rss_trim"]
 
 
 class RSSError(RuntimeError):
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rss_top_set.argtypes = [vp, P(i64), i64, P(i64)]
     lib.rss_info.argtypes = [vp, ctypes.c_char_p, i64]
     lib.rss_factor_destroy.argtypes = [vp]
+    lib.rss_trim.argtypes = []
     lib.rss_last_error.argtypes = []
     lib.rss_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -112,6 +113,11 @@ def make_params(**kw) -> Params:
         else:
             raise KeyError(k)
     return p
+
+
+def trim():
+    """Return the library's cached device blocks to the device."""
+    _check(lib().rss_trim())
 
 
 def _stream(torch):
