@@ -52,6 +52,8 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
     __shared__ double part[2][RG];
     __shared__ double dpart[2][RG][NT];
     __shared__ double taubuf[2];
+    __shared__ double scbuf[2];
+    __shared__ double rjq[2][NT];
     __shared__ const double* obase[16];
     __shared__ const int* oap[16];
     __shared__ int obeg[17];
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
         }
         for (int j = 0; j < n; ++j, ++step) {
             const int buf = step & 1;
-            // A: the threads of column j publish their rows and partial sum of squares
+            // A: the threads of column j publish their rows and partial sums of squares
             if (q == j) {
                 double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -169,37 +171,51 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
                 part[buf][rg] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
             __syncthreads();
-            // B: every thread forms the reflector scalars and its partial w_q
-            double sigma = 0.0;
+            // B: the owner forms the reflector scalars; every other column forms its
+            //    partial product with the unscaled reflector rows
+            if (q == j && rg == 0) {
+                double sigma = 0.0;
 #pragma unroll
-            for (int g = 0; g < RG; ++g) sigma += part[buf][g];
-            const double alpha = R0[j * NT + j];
-            double tau = 0.0, sc = 0.0, beta = alpha;
-            if (sigma != 0.0) {
-                beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-                tau = (beta - alpha) / beta;
-                sc = 1.0 / (alpha - beta);
+                for (int g = 0; g < RG; ++g) sigma += part[buf][g];
+                const double alpha = R0[j * NT + j];
+                double tau = 0.0, sc = 0.0;
+                if (sigma != 0.0) {
+                    const double beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+                    tau = (beta - alpha) / beta;
+                    sc = 1.0 / (alpha - beta);
+                    R0[j * NT + j] = beta;
+                }
+                taubuf[buf] = tau;
+                scbuf[buf] = sc;
             }
-            const double* v = vraw[buf] + rg * RPT;
-            const bool act = tau != 0.0 && q > j && q < n;
-            if (act) {
-                double w4[4] = {rg == 0 ? R0[j * NT + q] : 0.0, 0.0, 0.0, 0.0};
+            const bool col = q > j && q < n;
+            double vv[RPT];
+            if (col) {
+                const double* v = vraw[buf] + rg * RPT;
+                double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) w4[i & 3] += (v[i] * sc) * cv[i];
+                for (int i = 0; i < RPT; ++i) {
+                    vv[i] = v[i];
+                    w4[i & 3] += vv[i] * cv[i];
+                }
                 dpart[buf][rg][q] = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+                if (rg == 0) rjq[buf][q] = R0[j * NT + q];
             }
             __syncthreads();
-            // C: rank-one update of the chunk rows; row-group 0 updates R0
-            if (act) {
-                double w = 0.0;
+            // C: rank-one update of the chunk rows; row group 0 updates row j of R0
+            const double tau = taubuf[buf];
+            if (col && tau != 0.0) {
+                const double sc = scbuf[buf];
+                double sdot = 0.0;
 #pragma unroll
-                for (int g = 0; g < RG; ++g) w += dpart[buf][g][q];
-                const double tw = tau * w;
+                for (int g = 0; g < RG; ++g) sdot += dpart[buf][g][q];
+                const double rj = rjq[buf][q];
+                const double tw = tau * (rj + sc * sdot);
+                const double fct = tw * sc;
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) cv[i] -= tw * (v[i] * sc);
-                if (rg == 0) R0[j * NT + q] -= tw;
+                for (int i = 0; i < RPT; ++i) cv[i] -= fct * vv[i];
+                if (rg == 0) R0[j * NT + q] = rj - tw;
             }
-            if (q == j && rg == 0 && sigma != 0.0) R0[j * NT + j] = beta;
         }
     }
     __syncthreads();

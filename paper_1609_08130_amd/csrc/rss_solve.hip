@@ -314,32 +314,30 @@ void launch_copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, 
 // explicit inverse by solves against identity columns (many workgroups).
 __global__ void __launch_bounds__(1024) k_top_lu(double* __restrict__ A, int64_t n, int* __restrict__ piv,
                                                  int* flag, double* logdet, int* sign) {
-    __shared__ double red_v[1024];
-    __shared__ int red_i[1024];
+    __shared__ int piv_idx;
+    __shared__ double piv_val;
     const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
     double lds = 0.0;
     int sgn = 1;
     for (int64_t j = 0; j < n; ++j) {
-        double best = -1.0;
-        int64_t bi = INT64_MAX;
-        for (int64_t i = j + tid; i < n; i += 1024) {
-            double v = fabs(A[i + j * n]);
-            if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-        }
-        red_v[tid] = best;
-        red_i[tid] = (int)(bi == INT64_MAX ? 0x7fffffff : bi);
-        __syncthreads();
-        for (int s2 = 512; s2 > 0; s2 >>= 1) {
-            if (tid < s2) {
-                double v2 = red_v[tid + s2];
-                int i2 = red_i[tid + s2];
-                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) { red_v[tid] = v2; red_i[tid] = i2; }
+        if (wv == 0) {
+            double best = -1.0;
+            int64_t bi = INT64_MAX;
+            for (int64_t i = j + lane; i < n; i += 64) {
+                double v = fabs(A[i + j * n]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
-            __syncthreads();
+            for (int o = 32; o > 0; o >>= 1) {
+                double v2 = __shfl_xor(best, o, 64);
+                int64_t i2 = __shfl_xor(bi, o, 64);
+                if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+            }
+            if (lane == 0) { piv_idx = (int)bi; piv_val = best; }
         }
-        const int64_t p = red_i[0];
-        const double pv = red_v[0];
         __syncthreads();
+        const int64_t p = piv_idx;
+        const double pv = piv_val;
         if (!(pv > 0.0)) {
             if (tid == 0) atomicOr(flag, 8);
             return;
