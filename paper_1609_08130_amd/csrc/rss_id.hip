@@ -30,11 +30,11 @@ __device__ inline int wave_min_int(int v) {
     return v;
 }
 
-// Thread layout: NWC column waves x RG row groups.  Thread (rg, q) owns column q of B
+// Thread layout: NWC column waves x RG row groups, RPT chunk rows per thread.  Thread (rg, q) owns column q of B
 // (n <= 64 NWC) and rows rg*RPT .. rg*RPT+RPT-1 of each TSQR chunk of RG*RPT rows.
 // R0 (n rows, row stride NT = 64 NWC) is private per column; rows of the chunk are
 // combined across the row groups through LDS (two barriers per reflector).
-template <int NWC, int RG, bool RLDS>
+template <int NWC, int RG, int RPT, bool RLDS>
 __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__ store, int nb, int nmax,
                                                       const int* __restrict__ cnt, const int* __restrict__ gidx,
                                                       const int* __restrict__ nact, const int* __restrict__ apos,
@@ -44,9 +44,11 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
                                                       int* __restrict__ rpos, double* __restrict__ Tout,
                                                       int* __restrict__ mrows, double* __restrict__ work) {
     constexpr int NT = 64 * NWC;          // column threads
-    constexpr int RPT = 32;               // chunk rows per thread
     constexpr int BR = RG * RPT;          // chunk rows
     constexpr int VB = NT > BR ? NT : BR;
+    // keep the reflector rows in registers across the second barrier unless a
+    // 1024-thread group would run out of registers (then re-read them from LDS)
+    constexpr bool CACHE_V = NWC * RG * 64 <= 512 && RPT <= 32;
     extern __shared__ double R0s[];       // RLDS: nmax x NT
     __shared__ double vraw[2][VB];
     __shared__ double part[2][RG];
@@ -189,14 +191,15 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
                 scbuf[buf] = sc;
             }
             const bool col = q > j && q < n;
-            double vv[RPT];
+            const double* v = vraw[buf] + rg * RPT;
+            double vv[CACHE_V ? RPT : 1];
             if (col) {
-                const double* v = vraw[buf] + rg * RPT;
                 double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    vv[i] = v[i];
-                    w4[i & 3] += vv[i] * cv[i];
+                    const double vi = v[i];
+                    if (CACHE_V) vv[CACHE_V ? i : 0] = vi;
+                    w4[i & 3] += vi * cv[i];
                 }
                 dpart[buf][rg][q] = (w4[0] + w4[1]) + (w4[2] + w4[3]);
                 if (rg == 0) rjq[buf][q] = R0[j * NT + q];
@@ -213,7 +216,7 @@ __global__ void __launch_bounds__(64 * NWC * RG) k_id(const double* __restrict__
                 const double tw = tau * (rj + sc * sdot);
                 const double fct = tw * sc;
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) cv[i] -= fct * vv[i];
+                for (int i = 0; i < RPT; ++i) cv[i] -= fct * (CACHE_V ? vv[CACHE_V ? i : 0] : v[i]);
                 if (rg == 0) R0[j * NT + q] = rj - tw;
             }
         }
@@ -334,29 +337,29 @@ int elim_lds_limit();
 void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                const KernelParams& kp, double* work, hipStream_t s) {
     // R0 (n rows, row stride 64 NWC) lives in LDS when it fits, else in `work`
-    // (nboxes * (64 NWC)^2 doubles).
+    // (nboxes * (64 NWC)^2 doubles).  Chunks of 256 rows for |B| <= 64, else 128 (64 for |B| > 128).
     if (nboxes <= 0) return;
-    dim3 grid(nboxes);
-    const int lim = elim_lds_limit() - 24576;   // room for the static LDS arrays
+    dim3 grid(nboxes), block(512);
+    const int lim = elim_lds_limit() - 32768;   // room for the static LDS arrays
     if (L.nmax <= 64) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 64;
-        k_id<1, 4, true><<<grid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                      work);
+        k_id<1, 8, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                       pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                       work);
     } else if (L.nmax <= 128 && (int)(sizeof(double) * (size_t)L.nmax * 128) <= lim) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 128;
-        hipFuncSetAttribute((const void*)k_id<2, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_id<2, 4, true><<<grid, dim3(512), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+        hipFuncSetAttribute((const void*)k_id<2, 4, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_id<2, 4, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                       pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                       work);
+    } else if (L.nmax <= 128) {
+        k_id<2, 4, 32, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
                                                       pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
                                                       work);
-    } else if (L.nmax <= 128) {
-        k_id<2, 4, false><<<grid, dim3(512), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                     pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                     work);
     } else {
-        k_id<4, 2, false><<<grid, dim3(512), 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                     pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
-                                                     work);
+        k_id<4, 2, 32, false><<<grid, block, 0, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+                                                      pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
+                                                      work);
     }
 }
 

@@ -358,10 +358,13 @@ __global__ void __launch_bounds__(1024) k_top_lu(double* __restrict__ A, int64_t
         const double rinv = 1.0 / d;
         for (int64_t i = j + 1 + tid; i < n; i += 1024) A[i + j * n] *= rinv;
         __syncthreads();
-        const int64_t m2 = n - j - 1;
-        for (int64_t e = tid; e < m2 * m2; e += 1024) {
-            int64_t i = j + 1 + e % m2, l = j + 1 + e / m2;
-            A[i + l * n] -= A[i + j * n] * A[j + l * n];
+        {
+            // trailing update, 64 rows x 16 columns of threads (no integer division)
+            const int ni = (int)n, jj = (int)j;
+            for (int l = jj + 1 + wv; l < ni; l += 16) {
+                const double ajl = A[jj + (int64_t)l * n];
+                for (int i = jj + 1 + lane; i < ni; i += 64) A[i + (int64_t)l * n] -= A[i + j * n] * ajl;
+            }
         }
         __syncthreads();
     }
