@@ -343,7 +343,7 @@ void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, 
     const int lim = elim_lds_limit() - 32768;   // room for the static LDS arrays
     if (L.nmax <= 64) {
         size_t lds = sizeof(double) * (size_t)L.nmax * 64;
-        k_id<1, 8, 32, true><<<grid, block, lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
+        k_id<1, 4, 32, true><<<grid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
                                                        pts, ptmpl, kp, L.t, L.krank, L.spos, L.rpos, L.T, L.mrows,
                                                        work);
     } else if (L.nmax <= 128 && (int)(sizeof(double) * (size_t)L.nmax * 128) <= lim) {

@@ -104,6 +104,7 @@ struct rss_factor_s {
     hipStream_t stream = nullptr;   // stream of rss_factor_create (allocations of the factor)
     rss::FFTPlan fft;               // exact operator by FFT when the points form a grid
     int lds_limit = 0;
+    bool id_gram = true;            // ID through the compensated Gram matrix
     int64_t ntop = 0;
     int* top_idx = nullptr;
     double* top_A = nullptr;        // ntop x ntop
@@ -146,6 +147,9 @@ void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hip
 // skeletonization (rss_id.hip, rss_elim.hip, rss_schur.hip)
 void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                const KernelParams& kp, double* work, hipStream_t s);
+void launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+                    const KernelParams& kp, double* work, hipStream_t s);
+size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
 void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
                  hipStream_t s);
 void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s);
