@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librss.so")
-SOURCES = ["rss_api.hip", "rss_tree.hip", "rss_id.hip", "rss_elim.hip", "rss_schur.hip", "rss_solve.hip",
+SOURCES = ["rss_api.hip", "rss_tree.hip", "rss_elim.hip", "rss_schur.hip", "rss_solve.hip",
            "rss_matvec.hip", "rss_fft.hip", "rss_idgram.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off (compiler-generated forms only, never hand-written)

@@ -9,7 +9,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <sstream>
 #include <string>
@@ -344,10 +343,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (auto& v : L.colour_boxes) maxc = std::max(maxc, v.size());
         for (auto& v : L.colour_boxes) L.d_colour_boxes.push_back(h2d(f, v, s));
         alloc_level_records(f, L, mixed);
-        int cpt = L.nmax <= 64 ? 1 : (L.nmax <= 128 ? 2 : 4);
-        size_t np = 64 * cpt;
-        size_t need = maxc * std::max(np * np, (size_t)L.nmax * L.nmax);
-        if (f->id_gram) need = std::max(need, rss::id_work_doubles(L.nmax, p.n_proxy, maxc));
+        size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc));
         if (need > work_n) {
             if (work) dfree(f, work, work_n * sizeof(double));
             work = dalloc<double>(f, need);
@@ -359,8 +355,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             int nbx = (int)L.colour_boxes[col].size();
             if (nbx == 0) continue;
             const int* bx = L.d_colour_boxes[col];
-            if (f->id_gram) rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
-            else rss::launch_id(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
+            rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
             check_launch();
             ev.push_back(evs.rec(s));
             rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, s);
@@ -604,10 +599,6 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     f->kp.proxy_radius = p->proxy_radius;
     hipStream_t s = (hipStream_t)stream;
     f->stream = s;
-    {
-        const char* e = getenv("RSS_ID_HOUSEHOLDER");
-        f->id_gram = !(e && e[0] == '1');
-    }
     try {
         factor_impl(f, d_points, s);
     } catch (const Fail& e) {

@@ -16,6 +16,7 @@ constexpr int kMaxBox = 256;       // largest active DOF count of one box
 constexpr int kMaxProxy = 64;
 constexpr int kNbr = 25;           // stored block pairs per box: offsets (dx, dy) in [-2, 2]^2
 constexpr double kTau = 1e-11;     // pivot tie window relative to the first pivot norm
+int elim_lds_limit();
 
 // offset slot of box b seen from box a: (dy + 2) * 5 + (dx + 2)
 __host__ __device__ inline int nbr_slot(int dx, int dy) { return (dy + 2) * 5 + (dx + 2); }
@@ -104,7 +105,6 @@ struct rss_factor_s {
     hipStream_t stream = nullptr;   // stream of rss_factor_create (allocations of the factor)
     rss::FFTPlan fft;               // exact operator by FFT when the points form a grid
     int lds_limit = 0;
-    bool id_gram = true;            // ID through the compensated Gram matrix
     int64_t ntop = 0;
     int* top_idx = nullptr;
     double* top_A = nullptr;        // ntop x ntop
@@ -144,9 +144,7 @@ void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, in
                          const double* pts, const KernelParams& kp, double* A, hipStream_t s);
 void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
 
-// skeletonization (rss_id.hip, rss_elim.hip, rss_schur.hip)
-void launch_id(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
-               const KernelParams& kp, double* work, hipStream_t s);
+// skeletonization (rss_idgram.hip, rss_elim.hip, rss_schur.hip)
 void launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                     const KernelParams& kp, double* work, hipStream_t s);
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
