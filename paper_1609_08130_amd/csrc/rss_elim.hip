@@ -46,7 +46,7 @@ struct ElimArgs {
 
 constexpr int kTile = 32;   // rows (or columns) of J per tile
 
-// Dynamic LDS: Ts[tsz] | Xs[nmax*nmax] (when XLDS) | tile[nmax*kTile]
+// Dynamic LDS: Ts[tsz] (T, b-fastest) | Xs[nmax*nmax] (when XLDS) | tA[nmax*kTile] | tX[nmax*kTile]
 template <bool XLDS, int NTH>
 __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
                                               double* __restrict__ work, int* flag, int tsz) {
@@ -62,6 +62,8 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
     __shared__ double fvec[kMaxBox];
     __shared__ int piv_idx;
     __shared__ double piv_val;
+    __shared__ const double* srcp[kTile];
+    __shared__ int srcpos[kTile];
 
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -75,9 +77,10 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
     const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
     const int cx = c % nb, cy = c / nb;
-    double* Ts = dyn;
+    double* Ts = dyn;                                              // Ts[b + r q] = T[q][b]
     double* Xs = XLDS ? dyn + tsz : work + (int64_t)blockIdx.x * bsz;
-    double* tile = dyn + tsz + (XLDS ? bsz : 0);
+    double* tA = dyn + tsz + (XLDS ? bsz : 0);
+    double* tX = tA + (int64_t)nmax * kTile;
     const int ldx = nmax;
 
     for (int i = tid; i < k; i += NTH) sp[i] = a.spos[(int64_t)c * nmax + i];
@@ -101,7 +104,10 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
         nN = cntN;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
-    for (int e = tid; e < k * r; e += NTH) Ts[e] = Tg[(e % k) + (int64_t)(e / k) * nmax];   // Ts[q + b*k]
+    for (int e = tid; e < k * r; e += NTH) {
+        int b = e % r, q = e / r;
+        Ts[e] = Tg[q + (int64_t)b * nmax];
+    }
     __syncthreads();
     const int nj = joff[nN];
     const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
@@ -119,48 +125,54 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
         a.Jg[(int64_t)c * ldJ + jj] = g;
     }
 
-    // ---- X_JR = A_JR - A_JS T, kTile rows at a time (rows staged in LDS) ----
+    // ---- X_JR = A_JR - A_JS T, kTile rows of J at a time ------------------------------
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     for (int r0 = 0; r0 < nj; r0 += kTile) {
         const int tr = min(kTile, nj - r0);
-        // stage the rows' S columns then R columns: tile[i + kTile * col], col < n
-        for (int e = tid; e < tr * n; e += NTH) {
-            int i = e % tr, col = e / tr;
-            int jj = r0 + i;
-            const double* blk;
-            int row;
+        if (tid < tr) {
+            const int jj = r0 + tid;
             if (jj < k) {
-                blk = Acc;
-                row = sp[jj];
+                srcp[tid] = Acc;
+                srcpos[tid] = sp[jj];
             } else {
                 int s = 0;
                 while (joff[s + 1] <= jj) ++s;
-                blk = blk_nc[s];
-                row = nap[s][jj - joff[s]];
+                srcp[tid] = blk_nc[s];
+                srcpos[tid] = nap[s][jj - joff[s]];
             }
-            int pos = col < k ? sp[col] : rp[col - k];
-            tile[i + kTile * col] = blk[row + (int64_t)pos * nmax];
         }
         __syncthreads();
-        for (int e = tid; e < tr * r; e += NTH) {
-            int i = e % tr, b = e / tr;
-            double v = tile[i + kTile * (k + b)];
-            const double* tb = Ts + b * k;
-            for (int q = 0; q < k; ++q) v -= tile[i + kTile * q] * tb[q];
-            XJR[(r0 + i) + (int64_t)b * ldJ] = v;
+        // tA[i + kTile * col]: row i of the tile at B position (col < k ? sp[col] : rp[col - k])
+        for (int e = tid; e < tr * n; e += NTH) {
+            int i = e % tr, col = e / tr;
+            int pos = col < k ? sp[col] : rp[col - k];
+            tA[i + kTile * col] = srcp[i][srcpos[i] + (int64_t)pos * nmax];
+        }
+        __syncthreads();
+        const int rh = (r + 1) >> 1;
+        for (int e = tid; e < tr * rh; e += NTH) {
+            const int i = e % tr, b = 2 * (e / tr);
+            const bool two = b + 1 < r;
+            double v0 = tA[i + kTile * (k + b)];
+            double v1 = two ? tA[i + kTile * (k + b + 1)] : 0.0;
+            for (int q = 0; q < k; ++q) {
+                const double x = tA[i + kTile * q];
+                v0 -= x * Ts[b + r * q];
+                if (two) v1 -= x * Ts[b + 1 + r * q];
+            }
+            XJR[(r0 + i) + (int64_t)b * ldJ] = v0;
+            if (two) XJR[(r0 + i) + (int64_t)(b + 1) * ldJ] = v1;
         }
         __syncthreads();
     }
 
-    // ---- X_RR = A_RR - A_RS T - T^T Z_S -----------------------------------------
+    // ---- X_RR = A_RR - A_RS T - T^T Z_S ------------------------------------------------
     double* XRR = a.XRR + (int64_t)c * bsz;
     for (int e = tid; e < r * r; e += NTH) {
         int b = e % r, b2 = e / r;
         double v = Acc[rp[b] + (int64_t)rp[b2] * nmax];
-        const double* t2 = Ts + b2 * k;
-        const double* t1 = Ts + b * k;
-        for (int q = 0; q < k; ++q) v -= Acc[rp[b] + (int64_t)sp[q] * nmax] * t2[q];
-        for (int q = 0; q < k; ++q) v -= t1[q] * XJR[q + (int64_t)b2 * ldJ];
+        for (int q = 0; q < k; ++q) v -= Acc[rp[b] + (int64_t)sp[q] * nmax] * Ts[b2 + r * q];
+        for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * XJR[q + (int64_t)b2 * ldJ];
         XRR[b + (int64_t)b2 * nmax] = v;
         Xs[b + b2 * ldx] = v;
     }
@@ -207,11 +219,13 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
         __syncthreads();
         for (int l = tid; l < r; l += NTH) Xs[j + l * ldx] = (l == j ? 1.0 : Xs[j + l * ldx]) * rinv;
         __syncthreads();
-        for (int e = tid; e < r * r; e += NTH) {
-            int i = e % r, l = e / r;
-            if (i == j) continue;
-            double base = (l == j) ? 0.0 : Xs[i + l * ldx];
-            Xs[i + l * ldx] = base - fvec[i] * Xs[j + l * ldx];
+        for (int l = wv; l < r; l += NTH / 64) {
+            const double xjl = Xs[j + l * ldx];
+            for (int i = lane; i < r; i += 64) {
+                if (i == j) continue;
+                double base = (l == j) ? 0.0 : Xs[i + l * ldx];
+                Xs[i + l * ldx] = base - fvec[i] * xjl;
+            }
         }
         __syncthreads();
     }
@@ -240,38 +254,51 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
         Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * ldx];
     }
 
-    // ---- G = X_RR^{-1} X_RJ, kTile columns of J at a time ------------------------------
+    // ---- G = X_RR^{-1} X_RJ, X_RJ = A_RJ - T^T A_SJ, kTile columns of J at a time ------
     double* G = a.G + (int64_t)c * nmax * ldJ;
     for (int c0 = 0; c0 < nj; c0 += kTile) {
         const int tc = min(kTile, nj - c0);
-        // tile[b + r * j'] = X_RJ[b, c0 + j']
-        for (int e = tid; e < tc * r; e += NTH) {
-            int b = e % r, jp = e / r;
-            int jj = c0 + jp;
-            const double* blk;
-            int col;
+        if (tid < tc) {
+            const int jj = c0 + tid;
             if (jj < k) {
-                blk = Acc;
-                col = sp[jj];
+                srcp[tid] = Acc;
+                srcpos[tid] = sp[jj];
             } else {
                 int s = 0;
                 while (joff[s + 1] <= jj) ++s;
-                blk = blk_cn[s];
-                col = nap[s][jj - joff[s]];
+                srcp[tid] = blk_cn[s];
+                srcpos[tid] = nap[s][jj - joff[s]];
             }
-            const double* bc = blk + (int64_t)col * nmax;
-            double v = bc[rp[b]];
-            const double* tb = Ts + b * k;
-            for (int q = 0; q < k; ++q) v -= tb[q] * bc[sp[q]];
-            tile[b + r * jp] = v;
+        }
+        __syncthreads();
+        // tA[pos + nmax * jp] = A(B_c position pos, J column c0 + jp)
+        for (int e = tid; e < tc * n; e += NTH) {
+            int pos = e % n, jp = e / n;
+            tA[pos + nmax * jp] = srcp[jp][pos + (int64_t)srcpos[jp] * nmax];
         }
         __syncthreads();
         for (int e = tid; e < tc * r; e += NTH) {
-            int b = e % r, jp = e / r;
-            const double* tcol = tile + r * jp;
-            double v = 0.0;
-            for (int q = 0; q < r; ++q) v += Xs[b + q * ldx] * tcol[q];
-            G[b + (int64_t)(c0 + jp) * nmax] = v;
+            const int b = e % r, jp = e / r;
+            const double* col = tA + nmax * jp;
+            double v = col[rp[b]];
+            for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * col[sp[q]];
+            tX[b + nmax * jp] = v;
+        }
+        __syncthreads();
+        const int th = (tc + 1) >> 1;
+        for (int e = tid; e < th * r; e += NTH) {
+            const int b = e % r, jp = 2 * (e / r);
+            const bool two = jp + 1 < tc;
+            const double* x0 = tX + nmax * jp;
+            const double* x1 = x0 + nmax;
+            double v0 = 0.0, v1 = 0.0;
+            for (int q = 0; q < r; ++q) {
+                const double w = Xs[b + q * ldx];
+                v0 += w * x0[q];
+                if (two) v1 += w * x1[q];
+            }
+            G[b + (int64_t)(c0 + jp) * nmax] = v0;
+            if (two) G[b + (int64_t)(c0 + jp + 1) * nmax] = v1;
         }
         __syncthreads();
     }
@@ -280,7 +307,6 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
     for (int i = tid; i < k; i += NTH) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sp[i]];
     for (int i = tid; i < r; i += NTH) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + rp[i]];
     if (mixed) {
-        __syncthreads();
         for (int e = tid; e < nj * r; e += NTH) {
             int jj = e % nj, b = e / nj;
             a.XJR32[(int64_t)c * ldJ * nmax + jj + (int64_t)b * ldJ] = (float)XJR[jj + (int64_t)b * ldJ];
@@ -294,8 +320,8 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
             a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * ldx];
         }
         for (int e = tid; e < k * r; e += NTH) {
-            int q = e % k, b = e / k;
-            a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Ts[q + b * k];
+            int b = e % r, q = e / r;
+            a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Ts[e];
         }
     }
     if (tid == 0) {
@@ -330,7 +356,7 @@ void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double
     a.XJR32 = L.XJR32; a.G32 = L.G32; a.Xinv32 = L.Xinv32; a.T32 = L.T32;
     a.logdet_part = L.logdet_part; a.sign_part = L.sign_part;
     const int tsz = (L.nmax * L.nmax) / 4 + 1;            // |S| |R| <= n^2 / 4
-    const size_t tile = (size_t)L.nmax * kTile;
+    const size_t tile = 2 * (size_t)L.nmax * kTile;
     const size_t with_x = sizeof(double) * (tsz + (size_t)L.nmax * L.nmax + tile);
     const size_t without_x = sizeof(double) * (tsz + tile);
     // few boxes in a colour (upper levels): one large workgroup per box to cut latency
