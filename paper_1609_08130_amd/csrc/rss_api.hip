@@ -460,7 +460,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     f->top_A = dalloc<double>(f, (size_t)ntop * ntop);
     double* LU = dalloc<double>(f, (size_t)ntop * ntop);
     f->top_inv = dalloc<double>(f, (size_t)ntop * ntop);
-    int* piv = dalloc<int>(f, 2 * ntop);
+    int* piv = dalloc<int>(f, (size_t)rss::lu_piv_ints(ntop));
     double* dlog = dalloc<double>(f, 1);
     int* dsign = dalloc<int>(f, 1);
     rss::launch_top_lists(L, f->top_idx, tmap, ntop, s);

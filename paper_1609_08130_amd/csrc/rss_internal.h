@@ -153,6 +153,8 @@ void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double
 void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s);
 
 // dense top block (rss_solve.hip)
+// piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)
+int64_t lu_piv_ints(int64_t n);
 void launch_lu_inverse(double* A, double* Ainv, int64_t n, int* piv, double* work, int* flag,
                        double* logdet, int* sign, hipStream_t s);
 

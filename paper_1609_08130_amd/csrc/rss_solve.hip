@@ -310,145 +310,323 @@ void launch_copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, 
     k_copy_cols<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(src, lds, dst, ldd, n, nrhs);
 }
 
-// Dense LU with partial pivoting of the top block (one workgroup), log|det|, then the
-// explicit inverse by solves against identity columns (many workgroups).
-__global__ void __launch_bounds__(1024) k_top_lu(double* __restrict__ A, int64_t n, int* __restrict__ piv,
-                                                 int* flag, double* logdet, int* sign) {
+// Dense LU with partial pivoting of the top block, blocked right-looking (panels of
+// kNB columns): the panel is factored by one workgroup (in LDS when it fits), then the
+// row interchanges, the triangular solve for U12 and the trailing update A22 -= L21 U12
+// run over many workgroups.  Pivots: largest magnitude, lowest row on ties.  The
+// explicit inverse follows by blocked triangular solves against identity columns.
+constexpr int kNB = 32;
+
+// Panel [k0, k0 + nb): ipiv[k0 + j] = global pivot row of step j.  Also publishes the
+// net row permutation of the panel's interchanges restricted to the rows it moves:
+// sw[0] = count, then pairs (row, source row) meaning new A[row, :] = old A[source, :].
+template <bool INLDS>
+__global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n, int k0, int* __restrict__ ipiv,
+                                                   int* __restrict__ sw, int* flag, double* logdet, int* sign) {
+    extern __shared__ double pl[];
     __shared__ int piv_idx;
     __shared__ double piv_val;
+    __shared__ int sp[kNB];
+    __shared__ int cnt;
     const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
-    double lds = 0.0;
+    if (*flag & 8) return;
+    const int m = n - k0, nb = min(kNB, m);
+    const int ld = INLDS ? m : n;
+    double* P = INLDS ? pl : A + k0 + (int64_t)k0 * n;
+    if (INLDS) {
+        for (int e = tid; e < m * nb; e += 1024) {
+            int i = e % m, j = e / m;
+            P[e] = A[(k0 + i) + (int64_t)(k0 + j) * n];
+        }
+        __syncthreads();
+    }
+    double lsum = 0.0;
     int sgn = 1;
-    for (int64_t j = 0; j < n; ++j) {
+    for (int j = 0; j < nb; ++j) {
         if (wv == 0) {
             double best = -1.0;
-            int64_t bi = INT64_MAX;
-            for (int64_t i = j + lane; i < n; i += 64) {
-                double v = fabs(A[i + j * n]);
+            int bi = m;
+            for (int i = j + lane; i < m; i += 64) {
+                double v = fabs(P[i + (int64_t)j * ld]);
                 if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
             for (int o = 32; o > 0; o >>= 1) {
                 double v2 = __shfl_xor(best, o, 64);
-                int64_t i2 = __shfl_xor(bi, o, 64);
+                int i2 = __shfl_xor(bi, o, 64);
                 if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
             }
-            if (lane == 0) { piv_idx = (int)bi; piv_val = best; }
+            if (lane == 0) { piv_idx = bi; piv_val = best; }
         }
         __syncthreads();
-        const int64_t p = piv_idx;
-        const double pv = piv_val;
-        if (!(pv > 0.0)) {
+        const int p = piv_idx;
+        if (!(piv_val > 0.0) || p >= m) {
             if (tid == 0) atomicOr(flag, 8);
             return;
         }
-        if (tid == 0) piv[j] = (int)p;
+        if (tid == 0) { ipiv[k0 + j] = k0 + p; sp[j] = p; }
         if (p != j) {
-            for (int64_t l = tid; l < n; l += 1024) {
-                double t0 = A[j + l * n];
-                A[j + l * n] = A[p + l * n];
-                A[p + l * n] = t0;
+            for (int l = tid; l < nb; l += 1024) {
+                double t0 = P[j + (int64_t)l * ld];
+                P[j + (int64_t)l * ld] = P[p + (int64_t)l * ld];
+                P[p + (int64_t)l * ld] = t0;
             }
             sgn = -sgn;
         }
         __syncthreads();
-        const double d = A[j + j * n];
-        lds += log(fabs(d));
+        const double d = P[j + (int64_t)j * ld];
+        lsum += log(fabs(d));
         if (d < 0) sgn = -sgn;
         const double rinv = 1.0 / d;
-        for (int64_t i = j + 1 + tid; i < n; i += 1024) A[i + j * n] *= rinv;
+        for (int i = j + 1 + tid; i < m; i += 1024) P[i + (int64_t)j * ld] *= rinv;
         __syncthreads();
-        {
-            // trailing update, 64 rows x 16 columns of threads (no integer division)
-            const int ni = (int)n, jj = (int)j;
-            for (int l = jj + 1 + wv; l < ni; l += 16) {
-                const double ajl = A[jj + (int64_t)l * n];
-                for (int i = jj + 1 + lane; i < ni; i += 64) A[i + (int64_t)l * n] -= A[i + j * n] * ajl;
-            }
+        for (int l = j + 1 + wv; l < nb; l += 16) {
+            const double ajl = P[j + (int64_t)l * ld];
+            for (int i = j + 1 + lane; i < m; i += 64) P[i + (int64_t)l * ld] -= P[i + (int64_t)j * ld] * ajl;
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        *logdet = lds;
-        *sign = sgn;
-        // row permutation of P A = L U: row i of P A is row perm[i] of A
-        int* perm = piv + n;
-        for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
-        for (int64_t j = 0; j < n; ++j) {
-            int p = piv[j];
-            int t0 = perm[j]; perm[j] = perm[p]; perm[p] = t0;
+    if (INLDS) {
+        for (int e = tid; e < m * nb; e += 1024) {
+            int i = e % m, j = e / m;
+            A[(k0 + i) + (int64_t)(k0 + j) * n] = P[e];
         }
+    }
+    if (tid == 0) {
+        *logdet = (k0 == 0 ? 0.0 : *logdet) + lsum;
+        *sign = (k0 == 0 ? 1 : *sign) * sgn;
+        cnt = 0;
+    }
+    __syncthreads();
+    // net permutation: candidate rows are the panel rows and the pivot rows below it
+    if (wv == 0) {
+        int r = -1;
+        if (lane < nb) {
+            r = lane;
+        } else if (lane < 2 * nb) {
+            int q = sp[lane - nb];
+            bool dup = q < nb;
+            for (int i = 0; i < lane - nb && !dup; ++i) dup = sp[i] == q;
+            if (!dup) r = q;
+        }
+        int src = r;
+        if (r >= 0)
+            for (int j = nb - 1; j >= 0; --j) {
+                if (src == j) src = sp[j];
+                else if (src == sp[j]) src = j;
+            }
+        const bool moved = r >= 0 && src != r;
+        const unsigned long long mask = __ballot(moved);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (moved) {
+            sw[1 + 2 * before] = k0 + r;
+            sw[2 + 2 * before] = k0 + src;
+        }
+        if (lane == 0) sw[0] = __popcll(mask);
     }
 }
 
-// Columns [c0, c0 + NC) of A^{-1} from P A = L U, solved in LDS (n <= 1024).
-template <int NC>
-__global__ void __launch_bounds__(256) k_top_inverse_lds(const double* __restrict__ LU, const int* __restrict__ perm,
-                                                         int64_t n, double* __restrict__ Ainv) {
-    extern __shared__ double xs[];   // n x NC, xs[i * NC + c]
+// Row interchanges of panel k0 on every column block outside the panel, then
+// U12 = L11^{-1} A12 for the blocks right of it.  One workgroup per kNB columns.
+__global__ void __launch_bounds__(256) k_lu_swap_trsm(double* __restrict__ A, int n, int k0,
+                                                      const int* __restrict__ sw, const int* flag) {
+    __shared__ double vs[2 * kNB * kNB];
+    __shared__ double Ls[kNB * kNB];
+    __shared__ double Xs[kNB * kNB];
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * NC;
-    for (int64_t e = tid; e < n * NC; e += 256) {
-        int64_t i = e / NC, c = e % NC;
+    if (*flag & 8) return;
+    const int c0 = blockIdx.x * kNB;
+    if (c0 == k0) return;                      // the panel swapped its own rows
+    const int nc = min(kNB, n - c0);
+    const int ns = sw[0];
+    for (int e = tid; e < ns * nc; e += 256) {
+        int q = e % ns, c = e / ns;
+        vs[q + 2 * kNB * c] = A[sw[2 + 2 * q] + (int64_t)(c0 + c) * n];
+    }
+    __syncthreads();
+    for (int e = tid; e < ns * nc; e += 256) {
+        int q = e % ns, c = e / ns;
+        A[sw[1 + 2 * q] + (int64_t)(c0 + c) * n] = vs[q + 2 * kNB * c];
+    }
+    if (c0 < k0) return;
+    __syncthreads();
+    const int nb = min(kNB, n - k0);
+    for (int e = tid; e < nb * nb; e += 256) {
+        int i = e % nb, j = e / nb;
+        Ls[e] = A[(k0 + i) + (int64_t)(k0 + j) * n];
+    }
+    for (int e = tid; e < nb * nc; e += 256) {
+        int i = e % nb, c = e / nb;
+        Xs[e] = A[(k0 + i) + (int64_t)(c0 + c) * n];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb - 1; ++j) {
+        for (int e = tid; e < (nb - 1 - j) * nc; e += 256) {
+            int i = j + 1 + e % (nb - 1 - j), c = e / (nb - 1 - j);
+            Xs[i + nb * c] -= Ls[i + nb * j] * Xs[j + nb * c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nc; e += 256) {
+        int i = e % nb, c = e / nb;
+        A[(k0 + i) + (int64_t)(c0 + c) * n] = Xs[e];
+    }
+}
+
+// A22 -= L21 U12 for rows and columns >= k0 + nb, 64 x 64 tiles, 4 x 4 per thread.
+__global__ void __launch_bounds__(256) k_lu_gemm(double* __restrict__ A, int n, int k0, const int* flag) {
+    __shared__ double Ls[64 * kNB];
+    __shared__ double Us[(kNB + 1) * 64];
+    const int tid = threadIdx.x;
+    if (*flag & 8) return;
+    const int nb = min(kNB, n - k0);
+    const int s0 = k0 + nb;
+    const int r0 = s0 + blockIdx.y * 64, c0 = s0 + blockIdx.x * 64;
+    const int nr = min(64, n - r0), nc = min(64, n - c0);
+    for (int e = tid; e < 64 * nb; e += 256) {
+        int i = e % 64, q = e / 64;
+        Ls[e] = i < nr ? A[(r0 + i) + (int64_t)(k0 + q) * n] : 0.0;
+    }
+    for (int e = tid; e < nb * 64; e += 256) {
+        int q = e % nb, c = e / nb;
+        Us[q + (kNB + 1) * c] = c < nc ? A[(k0 + q) + (int64_t)(c0 + c) * n] : 0.0;
+    }
+    __syncthreads();
+    const int ti = tid % 16, tc = tid / 16;
+    double acc[4][4] = {};
+    for (int q = 0; q < nb; ++q) {
+        double a[4], b[4];
+        for (int u = 0; u < 4; ++u) a[u] = Ls[(ti + 16 * u) + 64 * q];
+        for (int v = 0; v < 4; ++v) b[v] = Us[q + (kNB + 1) * (tc + 16 * v)];
+        for (int u = 0; u < 4; ++u)
+            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            int i = ti + 16 * u, c = tc + 16 * v;
+            if (i < nr && c < nc) A[(r0 + i) + (int64_t)(c0 + c) * n] -= acc[u][v];
+        }
+}
+
+// perm[i] = source row of row i of P A, from the sequence of interchanges ipiv.
+__global__ void k_lu_perm(const int* __restrict__ ipiv, int n, int* __restrict__ perm, const int* flag, int in_lds) {
+    extern __shared__ int pm[];
+    if (threadIdx.x != 0 || (*flag & 8)) return;
+    int* w = in_lds ? pm : perm;
+    for (int i = 0; i < n; ++i) w[i] = i;
+    for (int j = 0; j < n; ++j) {
+        int p = ipiv[j];
+        int t0 = w[j]; w[j] = w[p]; w[p] = t0;
+    }
+    if (in_lds)
+        for (int i = 0; i < n; ++i) perm[i] = w[i];
+}
+
+// Columns [c0, c0 + NC) of A^{-1} = U^{-1} L^{-1} P: X = P e_c in LDS, then blocked
+// forward and backward substitution (a kNB x kNB diagonal block in LDS, then one
+// rectangular update per block).
+template <int NC>
+__global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restrict__ LU, const int* __restrict__ perm,
+                                                         int n, double* __restrict__ Ainv, const int* flag) {
+    extern __shared__ double xs[];   // n x NC, xs[i * NC + c]
+    __shared__ double D[kNB * kNB];
+    const int tid = threadIdx.x;
+    if (*flag & 8) return;
+    const int c0 = blockIdx.x * NC;
+    for (int e = tid; e < n * NC; e += 256) {
+        int i = e / NC, c = e % NC;
         xs[e] = (perm[i] == c0 + c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int64_t j = 0; j < n; ++j) {          // L y = P e (unit lower)
-        const int64_t m = n - j - 1;
-        for (int64_t e = tid; e < m * NC; e += 256) {
-            int64_t i = j + 1 + e / NC, c = e % NC;
-            xs[i * NC + c] -= LU[i + j * n] * xs[j * NC + c];
+    for (int jb = 0; jb < n; jb += kNB) {            // L y = P e (unit lower)
+        const int bs = min(kNB, n - jb);
+        for (int e = tid; e < bs * bs; e += 256) {
+            int i = e % bs, j = e / bs;
+            D[e] = LU[(jb + i) + (int64_t)(jb + j) * n];
+        }
+        __syncthreads();
+        for (int j = 0; j < bs - 1; ++j) {
+            for (int e = tid; e < (bs - 1 - j) * NC; e += 256) {
+                int i = j + 1 + e / NC, c = e % NC;
+                xs[(jb + i) * NC + c] -= D[i + bs * j] * xs[(jb + j) * NC + c];
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < (n - jb - bs) * NC; e += 256) {
+            int i = jb + bs + e / NC, c = e % NC;
+            double v = 0.0;
+            for (int j = 0; j < bs; ++j) v += LU[i + (int64_t)(jb + j) * n] * xs[(jb + j) * NC + c];
+            xs[i * NC + c] -= v;
         }
         __syncthreads();
     }
-    for (int64_t j = n - 1; j >= 0; --j) {     // U x = y
-        if (tid < NC) xs[j * NC + tid] /= LU[j + j * n];
+    const int nblk = (n + kNB - 1) / kNB;
+    for (int b = nblk - 1; b >= 0; --b) {            // U x = y
+        const int jb = b * kNB, bs = min(kNB, n - jb);
+        for (int e = tid; e < bs * bs; e += 256) {
+            int i = e % bs, j = e / bs;
+            D[e] = LU[(jb + i) + (int64_t)(jb + j) * n];
+        }
         __syncthreads();
-        for (int64_t e = tid; e < j * NC; e += 256) {
-            int64_t i = e / NC, c = e % NC;
-            xs[i * NC + c] -= LU[i + j * n] * xs[j * NC + c];
+        for (int j = bs - 1; j >= 0; --j) {
+            if (tid < NC) xs[(jb + j) * NC + tid] /= D[j + bs * j];
+            __syncthreads();
+            for (int e = tid; e < j * NC; e += 256) {
+                int i = e / NC, c = e % NC;
+                xs[(jb + i) * NC + c] -= D[i + bs * j] * xs[(jb + j) * NC + c];
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < jb * NC; e += 256) {
+            int i = e / NC, c = e % NC;
+            double v = 0.0;
+            for (int j = 0; j < bs; ++j) v += LU[i + (int64_t)(jb + j) * n] * xs[(jb + j) * NC + c];
+            xs[i * NC + c] -= v;
         }
         __syncthreads();
     }
-    for (int64_t e = tid; e < n * NC; e += 256) {
-        int64_t i = e % n, c = e / n;
-        if (c0 + c < n) Ainv[(c0 + c) * n + i] = xs[i * NC + c];
+    for (int e = tid; e < n * NC; e += 256) {
+        int i = e % n, c = e / n;
+        if (c0 + c < n) Ainv[(int64_t)(c0 + c) * n + i] = xs[i * NC + c];
     }
 }
 
-__global__ void k_top_inverse(const double* __restrict__ LU, const int* __restrict__ piv, int64_t n,
-                              double* __restrict__ Ainv) {
-    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= n) return;
-    double* x = Ainv + col * n;
-    for (int64_t i = 0; i < n; ++i) x[i] = (i == col) ? 1.0 : 0.0;
-    for (int64_t j = 0; j < n; ++j) {
-        int64_t p = piv[j];
-        if (p != j) { double t0 = x[j]; x[j] = x[p]; x[p] = t0; }
-    }
-    for (int64_t j = 0; j < n; ++j) {
-        double xj = x[j];
-        if (xj != 0.0)
-            for (int64_t i = j + 1; i < n; ++i) x[i] -= LU[i + j * n] * xj;
-    }
-    for (int64_t j = n - 1; j >= 0; --j) {
-        double xj = x[j] / LU[j + j * n];
-        x[j] = xj;
-        for (int64_t i = 0; i < j; ++i) x[i] -= LU[i + j * n] * xj;
-    }
-}
+int64_t lu_piv_ints(int64_t n) { return 2 * n + 4 * kNB + 1; }
 
-void launch_lu_inverse(double* A, double* Ainv, int64_t n, int* piv, double* work, int* flag, double* logdet,
+void launch_lu_inverse(double* A, double* Ainv, int64_t n64, int* piv, double* work, int* flag, double* logdet,
                        int* sign, hipStream_t s) {
     (void)work;
-    if (n <= 0) return;
-    k_top_lu<<<dim3(1), dim3(1024), 0, s>>>(A, n, piv, flag, logdet, sign);
+    if (n64 <= 0) return;
+    const int n = (int)n64;
+    int* ipiv = piv;
+    int* perm = piv + n;
+    int* sw = piv + 2 * n;
+    const int lim = elim_lds_limit();
+    const int nblk = (n + kNB - 1) / kNB;
+    for (int k0 = 0; k0 < n; k0 += kNB) {
+        const int m = n - k0, nb = std::min(kNB, m);
+        const size_t pl = sizeof(double) * (size_t)m * nb;
+        if ((long)pl + 1024 <= lim)
+            k_lu_panel<true><<<dim3(1), dim3(1024), pl, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
+        else
+            k_lu_panel<false><<<dim3(1), dim3(1024), 0, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
+        if (nblk > 1) k_lu_swap_trsm<<<dim3(nblk), dim3(256), 0, s>>>(A, n, k0, sw, flag);
+        const int rest = n - k0 - nb;
+        if (rest > 0) {
+            const unsigned g = (unsigned)((rest + 63) / 64);
+            k_lu_gemm<<<dim3(g, g), dim3(256), 0, s>>>(A, n, k0, flag);
+        }
+    }
+    const bool pl = (size_t)n * sizeof(int) + 1024 <= (size_t)lim;
+    k_lu_perm<<<dim3(1), dim3(64), pl ? sizeof(int) * (size_t)n : 0, s>>>(ipiv, n, perm, flag, pl ? 1 : 0);
     constexpr int NC = 8;
-    if (n <= 1024) {
-        size_t lds = sizeof(double) * (size_t)n * NC;
-        k_top_inverse_lds<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, piv + n, n, Ainv);
+    const size_t lds = sizeof(double) * (size_t)n * NC;
+    if ((long)lds + (long)sizeof(double) * kNB * kNB + 1024 > lim) {
+        // n beyond what one LDS column block holds (about 2000 DOFs)
+        hipLaunchKernelGGL(k_top_inverse_blk<1>, dim3((unsigned)n), dim3(256), sizeof(double) * (size_t)n, s, A, perm, n,
+                           Ainv, flag);
     } else {
-        k_top_inverse<<<dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s>>>(A, piv, n, Ainv);
+        k_top_inverse_blk<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, perm, n, Ainv, flag);
     }
 }
 

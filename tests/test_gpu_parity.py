@@ -100,6 +100,37 @@ def test_small_and_degenerate_trees(rss, npts, leaf):
     np.testing.assert_allclose(x, O.solve(R, b), rtol=0, atol=factor_tol(p.tol) * np.abs(x).max())
     if R.depth <= 1:
         np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-12 * np.abs(x).max())
+        sg, ld = F.logdet()
+        sr, lr = np.linalg.slogdet(A)
+        assert sg == sr and abs(ld - lr) <= 1e-12 * max(1.0, abs(lr)) + 1e-14 * npts
+    F.close()
+
+
+@pytest.mark.parametrize("diag,weight", [(1.0, None), (1e-3, 1.0)])
+def test_unskeletonized_top_block_961(rss, diag, weight):
+    # 31 x 31 grid, leaf 256: depth 1, nothing is skeletonized and the top block is the whole
+    # 961 x 961 matrix, so the blocked top LU runs its first panels from global memory and
+    # the later ones from LDS.  With diag 1e-3 and weight 1 the diagonal is small against the
+    # kernel, partial pivoting interchanges 290 rows and cond(A) is about 7.7e4.
+    n = 31
+    pts = W.grid_points(n)
+    d = W.problem(n, 1e-6, leaf_size=256)
+    d["diag"] = diag
+    if weight is not None:
+        d["weight"] = weight
+    p = O.Params(**d)
+    say(f"[parity] case=top961 diag={diag} N={n * n}")
+    F = _gpu_factor(rss, pts, p)
+    assert F.shape() == (1, n * n)
+    A = O.dense_matrix(pts, p)
+    b = W.rhs(n * n, seed=2)
+    x = F.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    xr = np.linalg.solve(A, b)
+    bound = 1e-12 if diag == 1.0 else 2e-10          # ~ 10 cond(A) eps
+    assert np.linalg.norm(x - xr) <= bound * np.linalg.norm(xr)
+    sg, ld = F.logdet()
+    sr, lr = np.linalg.slogdet(A)
+    assert sg == sr and abs(ld - lr) <= (1e-12 if diag == 1.0 else 1e-10) * max(1.0, abs(lr))
     F.close()
 
 
