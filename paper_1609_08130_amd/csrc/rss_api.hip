@@ -355,17 +355,18 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             int nbx = (int)L.colour_boxes[col].size();
             if (nbx == 0) continue;
             const int* bx = L.d_colour_boxes[col];
-            rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
+            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, s);
+            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, s);
+            if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
             check_launch();
             ev.push_back(evs.rec(s));
             rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            f->kernel_launches[PH_ID] += 1;
-            f->kernel_launches[PH_ELIM] += 1;
+            f->kernel_launches[PH_ID] += ni;
+            f->kernel_launches[PH_ELIM] += ne;
             f->kernel_launches[PH_SCHUR] += 1;
         }
         HIPCHK(hipStreamSynchronize(s));

@@ -13,6 +13,13 @@
 // X_JR, G, X_RR and X_RR^{-1}; the Schur complement A_JJ -= X_JR G is applied by the
 // Schur kernel.  J lists S first, then the active DOFs of the adjacent boxes in
 // ascending box index.
+//
+// Two launch shapes compute the same values in the same order:
+//  - fused (many boxes in the colour): one workgroup per box does everything;
+//  - split (few boxes, the upper levels): k_elim_rows forms X_JR and
+//    Y_RR = A_RR - A_RS T tile by tile over many workgroups per box, k_elim_inv forms
+//    X_RR = Y_RR - T^T Z_S and its inverse (one workgroup per box), and k_elim_g forms G
+//    tile by tile over many workgroups per box.
 #include "rss_internal.h"
 
 namespace rss {
@@ -44,145 +51,250 @@ struct ElimArgs {
     int* sign_part;
 };
 
-constexpr int kTile = 32;   // rows (or columns) of J per tile
+constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
 
-// Dynamic LDS: Ts[tsz] (T, b-fastest) | Xs[nmax*nmax] (when XLDS) | tA[nmax*kTile] | tX[nmax*kTile]
-template <bool XLDS, int NTH>
-__global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
-                                              double* __restrict__ work, int* flag, int tsz) {
-    extern __shared__ double dyn[];
-    __shared__ int sp[kMaxBox], rp[kMaxBox];
-    __shared__ const double* blk_nc[8];
-    __shared__ const double* blk_cn[8];
-    __shared__ const int* nap[8];
-    __shared__ int nbox_[8];
-    __shared__ int joff[9];
-    __shared__ int nN;
-    __shared__ int colswap[kMaxBox];
-    __shared__ double fvec[kMaxBox];
-    __shared__ int piv_idx;
-    __shared__ double piv_val;
-    __shared__ const double* srcp[kTile];
-    __shared__ int srcpos[kTile];
+// Per-workgroup tables of box c in LDS.
+struct ElimShared {
+    int sp[kMaxBox], rp[kMaxBox];   // B positions of S and R
+    const double* blk_nc[8];        // A(B_o, B_c) of the adjacent boxes o
+    const double* blk_cn[8];        // A(B_c, B_o)
+    const int* nap[8];              // active positions of o
+    int nbox[8];
+    int joff[9];                    // J segments: [0, k) is S, then one per adjacent box
+    int nN;
+    const double* srcp[kTileMax];   // source block and row/column of each tile line
+    int srcpos[kTileMax];
+};
 
-    const int tid = threadIdx.x;
-    const int c = boxes[blockIdx.x];
-    const int n = a.cnt[c];
-    const int k = a.krank[c];
-    const int r = n - k;
-    if (n == 0 || r == 0) {
-        if (tid == 0) a.nJ[c] = 0;
-        return;
-    }
-    const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
+// sp, rp, the adjacent-box tables and T (Ts[b + r q] = T[q][b]).  The caller synchronizes.
+template <int NTH>
+__device__ void elim_setup(ElimShared& sh, const ElimArgs& a, int c, int k, int r, double* Ts) {
+    const int tid = threadIdx.x, nmax = a.nmax, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
+    for (int i = tid; i < k; i += NTH) sh.sp[i] = a.spos[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) sh.rp[i] = a.rpos[(int64_t)c * nmax + i];
+    // adjacent boxes in ascending index: thread t < 8 looks at offset t (centre skipped),
+    // then thread 0 compacts and forms the segment offsets
     const int cx = c % nb, cy = c / nb;
-    double* Ts = dyn;                                              // Ts[b + r q] = T[q][b]
-    double* Xs = XLDS ? dyn + tsz : work + (int64_t)blockIdx.x * bsz;
-    double* tA = dyn + tsz + (XLDS ? bsz : 0);
-    double* tX = tA + (int64_t)nmax * kTile;
-    const int ldx = nmax;
-
-    for (int i = tid; i < k; i += NTH) sp[i] = a.spos[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += NTH) rp[i] = a.rpos[(int64_t)c * nmax + i];
-    if (tid == 0) {
-        int cntN = 0;
-        joff[0] = k;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dx == 0 && dy == 0) continue;
-                int ox = cx + dx, oy = cy + dy;
-                if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
-                int o = ox + nb * oy;
-                blk_nc[cntN] = a.store + ((int64_t)o * kNbr + nbr_slot(-dx, -dy)) * bsz;   // A(B_o, B_c)
-                blk_cn[cntN] = a.store + ((int64_t)c * kNbr + nbr_slot(dx, dy)) * bsz;     // A(B_c, B_o)
-                nap[cntN] = a.apos + (int64_t)o * nmax;
-                nbox_[cntN] = o;
-                joff[cntN + 1] = joff[cntN] + a.nact[o];
-                ++cntN;
-            }
-        nN = cntN;
+    if (tid < 8) {
+        const int t = tid < 4 ? tid : tid + 1;
+        const int dx = t % 3 - 1, dy = t / 3 - 1;
+        const int ox = cx + dx, oy = cy + dy;
+        const bool in = ox >= 0 && oy >= 0 && ox < nb && oy < nb;
+        sh.nbox[tid] = in ? ox + nb * oy : -1;
+        sh.srcpos[tid] = in ? a.nact[ox + nb * oy] : 0;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
     for (int e = tid; e < k * r; e += NTH) {
-        int b = e % r, q = e / r;
-        Ts[e] = Tg[q + (int64_t)b * nmax];
+        int q = e % k, b = e / k;
+        Ts[b + r * q] = Tg[q + (int64_t)b * nmax];
     }
     __syncthreads();
-    const int nj = joff[nN];
-    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
+    if (tid == 0) {
+        int cntN = 0;
+        sh.joff[0] = k;
+        for (int t = 0; t < 8; ++t) {
+            const int o = sh.nbox[t];
+            if (o < 0) continue;
+            const int tt = t < 4 ? t : t + 1;
+            const int dx = tt % 3 - 1, dy = tt / 3 - 1;
+            sh.blk_nc[cntN] = a.store + ((int64_t)o * kNbr + nbr_slot(-dx, -dy)) * bsz;   // A(B_o, B_c)
+            sh.blk_cn[cntN] = a.store + ((int64_t)c * kNbr + nbr_slot(dx, dy)) * bsz;     // A(B_c, B_o)
+            sh.nap[cntN] = a.apos + (int64_t)o * nmax;
+            sh.nbox[cntN] = o;
+            sh.joff[cntN + 1] = sh.joff[cntN] + sh.srcpos[t];
+            ++cntN;
+        }
+        sh.nN = cntN;
+    }
+}
 
-    // J list (global indices)
-    for (int jj = tid; jj < nj; jj += NTH) {
-        int g;
+// Global index of J entry jj.
+__device__ inline int j_global(const ElimShared& sh, const ElimArgs& a, int c, int jj, int k) {
+    if (jj < k) return a.gidx[(int64_t)c * a.nmax + sh.sp[jj]];
+    int i = 0;
+    while (sh.joff[i + 1] <= jj) ++i;
+    return a.gidx[(int64_t)sh.nbox[i] * a.nmax + sh.nap[i][jj - sh.joff[i]]];
+}
+
+// Rows [r0, r0 + tr) of E = [J; R] against the columns R: rows of J give X_JR (and its
+// FP32 copy when XJR32 != nullptr), rows past J give Y_RR = A_RR - A_RS T (into Y, ld nmax).
+// tA: tw x n.  Thread t takes row t % 32 of the tile and, per pass, 8 columns of R spaced
+// NTH / 32 apart, so each A(i, S_q) read from LDS serves 8 products.
+template <int NTH>
+__device__ void elim_rows_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
+                               int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
+    constexpr int BG = NTH / 32;   // column groups
+    const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
+    const int n = k + r;
+    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    if (tid < tr) {
+        const int jj = r0 + tid;
         if (jj < k) {
-            g = a.gidx[(int64_t)c * nmax + sp[jj]];
+            sh.srcp[tid] = Acc;
+            sh.srcpos[tid] = sh.sp[jj];
+        } else if (jj < nj) {
+            int s = 0;
+            while (sh.joff[s + 1] <= jj) ++s;
+            sh.srcp[tid] = sh.blk_nc[s];
+            sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
         } else {
-            int i = 0;
-            while (joff[i + 1] <= jj) ++i;
-            g = a.gidx[(int64_t)nbox_[i] * nmax + nap[i][jj - joff[i]]];
+            sh.srcp[tid] = Acc;
+            sh.srcpos[tid] = sh.rp[jj - nj];
         }
-        a.Jg[(int64_t)c * ldJ + jj] = g;
-    }
-
-    // ---- X_JR = A_JR - A_JS T, kTile rows of J at a time ------------------------------
-    double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
-    for (int r0 = 0; r0 < nj; r0 += kTile) {
-        const int tr = min(kTile, nj - r0);
-        if (tid < tr) {
-            const int jj = r0 + tid;
-            if (jj < k) {
-                srcp[tid] = Acc;
-                srcpos[tid] = sp[jj];
-            } else {
-                int s = 0;
-                while (joff[s + 1] <= jj) ++s;
-                srcp[tid] = blk_nc[s];
-                srcpos[tid] = nap[s][jj - joff[s]];
-            }
-        }
-        __syncthreads();
-        // tA[i + kTile * col]: row i of the tile at B position (col < k ? sp[col] : rp[col - k])
-        for (int e = tid; e < tr * n; e += NTH) {
-            int i = e % tr, col = e / tr;
-            int pos = col < k ? sp[col] : rp[col - k];
-            tA[i + kTile * col] = srcp[i][srcpos[i] + (int64_t)pos * nmax];
-        }
-        __syncthreads();
-        const int rh = (r + 1) >> 1;
-        for (int e = tid; e < tr * rh; e += NTH) {
-            const int i = e % tr, b = 2 * (e / tr);
-            const bool two = b + 1 < r;
-            double v0 = tA[i + kTile * (k + b)];
-            double v1 = two ? tA[i + kTile * (k + b + 1)] : 0.0;
-            for (int q = 0; q < k; ++q) {
-                const double x = tA[i + kTile * q];
-                v0 -= x * Ts[b + r * q];
-                if (two) v1 -= x * Ts[b + 1 + r * q];
-            }
-            XJR[(r0 + i) + (int64_t)b * ldJ] = v0;
-            if (two) XJR[(r0 + i) + (int64_t)(b + 1) * ldJ] = v1;
-        }
-        __syncthreads();
-    }
-
-    // ---- X_RR = A_RR - A_RS T - T^T Z_S ------------------------------------------------
-    double* XRR = a.XRR + (int64_t)c * bsz;
-    for (int e = tid; e < r * r; e += NTH) {
-        int b = e % r, b2 = e / r;
-        double v = Acc[rp[b] + (int64_t)rp[b2] * nmax];
-        for (int q = 0; q < k; ++q) v -= Acc[rp[b] + (int64_t)sp[q] * nmax] * Ts[b2 + r * q];
-        for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * XJR[q + (int64_t)b2 * ldJ];
-        XRR[b + (int64_t)b2 * nmax] = v;
-        Xs[b + b2 * ldx] = v;
     }
     __syncthreads();
+    // tA[i + tw col]: line i of the tile at B position (col < k ? sp[col] : rp[col - k])
+    for (int e = tid; e < tr * n; e += NTH) {
+        int i = e % tr, col = e / tr;
+        int pos = col < k ? sh.sp[col] : sh.rp[col - k];
+        tA[i + tw * col] = sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
+    }
+    __syncthreads();
+    const int i = tid & 31, bg = tid >> 5;
+    if (i < tr) {
+        const int row = r0 + i;
+        for (int b0 = bg; b0 < r; b0 += 8 * BG) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = min(b0 + BG * u, r - 1);
+                v[u] = tA[i + tw * (k + b)];
+            }
+            for (int q = 0; q < k; ++q) {
+                const double x = tA[i + tw * q];
+                const double* tq = Ts + r * q;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] -= x * tq[min(b0 + BG * u, r - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + BG * u;
+                if (b >= r) break;
+                if (row < nj) {
+                    XJR[row + (int64_t)b * ldJ] = v[u];
+                    if (XJR32) XJR32[row + (int64_t)b * ldJ] = (float)v[u];
+                } else {
+                    Y[(row - nj) + (int64_t)b * nmax] = v[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
 
-    // ---- X_RR^{-1} by in-place Gauss-Jordan with partial pivoting ---------------------
-    double ld_sum = 0.0;
-    int sgn = 1;
-    bool singular = false;
+// Columns [c0, c0 + tc) of J: X_RJ = A_RJ - T^T A_SJ (tX, ld nmax), then
+// G = X_RR^{-1} X_RJ.  tA, tX: nmax x tw.  X_RR^{-1} (ld nmax) is read from Xi when it is
+// in LDS (xi_lds); otherwise it is staged through tA, tw columns at a time.  Thread t
+// takes rows b = t % 64 + 64 h (h < HB, r <= 64 HB) of the result and the columns
+// t / 64 + NW v of the tile.
+template <int NTH, int HB>
+__device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int c0, int tc, int tw,
+                            const double* Ts, double* tA, double* tX, const double* Xi, bool xi_lds, double* G,
+                            float* G32) {
+    constexpr int NW = NTH / 64;
+    constexpr int VC = (kTileMax + NW - 1) / NW;   // tile columns per thread
+    const int tid = threadIdx.x, nmax = a.nmax;
+    const int n = k + r;
+    const int lane = tid & 63, jg = tid >> 6;
+    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    if (tid < tc) {
+        const int jj = c0 + tid;
+        if (jj < k) {
+            sh.srcp[tid] = Acc;
+            sh.srcpos[tid] = sh.sp[jj];
+        } else {
+            int s = 0;
+            while (sh.joff[s + 1] <= jj) ++s;
+            sh.srcp[tid] = sh.blk_cn[s];
+            sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
+        }
+    }
+    __syncthreads();
+    // tA[pos + nmax jp] = A(B_c position pos, J column c0 + jp)
+    for (int e = tid; e < tc * n; e += NTH) {
+        int pos = e % n, jp = e / n;
+        tA[pos + nmax * jp] = sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax];
+    }
+    __syncthreads();
+    // X_RJ[b][jp] = A(rp[b], jp) - sum_q T[q][b] A(sp[q], jp), q ascending
+    for (int b = lane; b < r; b += 64) {
+        double v[VC];
+#pragma unroll
+        for (int u = 0; u < VC; ++u) v[u] = tA[sh.rp[b] + nmax * min(jg + NW * u, tc - 1)];
+        for (int q = 0; q < k; ++q) {
+            const double t = Ts[b + r * q];
+            const int sq = sh.sp[q];
+#pragma unroll
+            for (int u = 0; u < VC; ++u) v[u] -= t * tA[sq + nmax * min(jg + NW * u, tc - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < VC; ++u)
+            if (jg + NW * u < tc) tX[b + nmax * (jg + NW * u)] = v[u];
+    }
+    __syncthreads();
+    // G = X_RR^{-1} X_RJ, q ascending; rows b = lane + 64 h
+    double acc[HB][VC];
+#pragma unroll
+    for (int h = 0; h < HB; ++h)
+#pragma unroll
+        for (int u = 0; u < VC; ++u) acc[h][u] = 0.0;
+    const int qc = xi_lds ? r : tw;
+    for (int q0 = 0; q0 < r; q0 += qc) {
+        const int qn = min(qc, r - q0);
+        const double* W = Xi + (int64_t)q0 * nmax;
+        if (!xi_lds) {
+            for (int e = tid; e < r * qn; e += NTH) {
+                int b = e % r, qq = e / r;
+                tA[b + nmax * qq] = W[b + (int64_t)qq * nmax];
+            }
+            __syncthreads();
+            W = tA;
+        }
+        for (int qq = 0; qq < qn; ++qq) {
+            double x[VC];
+#pragma unroll
+            for (int u = 0; u < VC; ++u) x[u] = tX[(q0 + qq) + nmax * min(jg + NW * u, tc - 1)];
+#pragma unroll
+            for (int h = 0; h < HB; ++h) {
+                if (64 * h >= r) break;
+                const double w = W[min(lane + 64 * h, r - 1) + nmax * qq];
+#pragma unroll
+                for (int u = 0; u < VC; ++u) acc[h][u] += w * x[u];
+            }
+        }
+        if (!xi_lds) __syncthreads();
+    }
+#pragma unroll
+    for (int h = 0; h < HB; ++h) {
+        const int b = lane + 64 * h;
+        if (b >= r) break;
+#pragma unroll
+        for (int u = 0; u < VC; ++u) {
+            const int jp = jg + NW * u;
+            if (jp >= tc) continue;
+            G[b + (int64_t)(c0 + jp) * nmax] = acc[h][u];
+            if (G32) G32[b + (int64_t)(c0 + jp) * nmax] = (float)acc[h][u];
+        }
+    }
+    __syncthreads();
+}
+
+// X_RR^{-1} of the r x r matrix Xs (ld ldx) in place: Gauss-Jordan with partial pivoting
+// (largest |.|, lowest row on ties), then the row interchanges undone on the columns.
+// Each step: one wave picks the pivot; the pivot column (after the interchange) and rows j
+// and p are copied to sc; then each wave updates whole columns, every element by the lane
+// that owns it (interchange, pivot-row scaling and rank-1 update in one pass).
+// sc: 4 * ldx doubles of LDS.  Returns false when a pivot column is exactly zero.
+template <int NTH>
+__device__ bool gj_inverse(double* Xs, int ldx, int r, int* colswap, double* sc, int& piv_idx, double& piv_val,
+                           double& ld_sum, int& sgn) {
+    const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
+    double* fvec = sc;
+    double* rowj = sc + ldx;
+    double* rowp = sc + 2 * ldx;
+    double* pivs = sc + 3 * ldx;
     for (int j = 0; j < r; ++j) {
         if (wv == 0) {
             double best = -1.0;
@@ -196,44 +308,60 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
                 int i2 = __shfl_xor(bi, o, 64);
                 if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
             }
-            if (lane == 0) { piv_idx = bi; piv_val = best; }
+            if (lane == 0) {
+                piv_idx = bi;
+                piv_val = (bi < r && best > 0.0) ? Xs[bi + j * ldx] : 0.0;
+            }
         }
         __syncthreads();
         const int p = piv_idx;
-        if (!(piv_val > 0.0)) { singular = true; break; }
-        if (p != j) {
-            for (int l = tid; l < r; l += NTH) {
-                double t0 = Xs[j + l * ldx];
-                Xs[j + l * ldx] = Xs[p + l * ldx];
-                Xs[p + l * ldx] = t0;
-            }
-            sgn = -sgn;
+        const double d = piv_val;
+        if (!(fabs(d) > 0.0) || p >= r) return false;
+        for (int i = tid; i < r; i += NTH) {
+            fvec[i] = (i == j) ? 0.0 : Xs[(i == p ? j : i) + j * ldx];   // column j after the interchange
+            rowj[i] = Xs[j + i * ldx];
+            rowp[i] = Xs[p + i * ldx];
         }
-        if (tid == 0) colswap[j] = p;
+        if (tid == 0) { colswap[j] = p; pivs[j] = d; }
         __syncthreads();
-        const double d = Xs[j + j * ldx];
-        ld_sum += log(fabs(d));
-        if (d < 0) sgn = -sgn;
         const double rinv = 1.0 / d;
-        for (int i = tid; i < r; i += NTH) fvec[i] = (i == j) ? 0.0 : Xs[i + j * ldx];
-        __syncthreads();
-        for (int l = tid; l < r; l += NTH) Xs[j + l * ldx] = (l == j ? 1.0 : Xs[j + l * ldx]) * rinv;
-        __syncthreads();
-        for (int l = wv; l < r; l += NTH / 64) {
-            const double xjl = Xs[j + l * ldx];
-            for (int i = lane; i < r; i += 64) {
-                if (i == j) continue;
-                double base = (l == j) ? 0.0 : Xs[i + l * ldx];
-                Xs[i + l * ldx] = base - fvec[i] * xjl;
+        // each wave takes 4 columns per pass and each lane rows lane and lane + 64, all loads
+        // issued before the first store (every element is read and written by its owner only)
+        for (int l0 = 4 * wv; l0 < r; l0 += 4 * (NTH / 64)) {
+            double xjl[4], xjo[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int l = min(l0 + u, r - 1);
+                xjl[u] = (l == j ? 1.0 : rowp[l]) * rinv;   // new pivot row
+                xjo[u] = rowj[l];                            // old row j, now row p
+            }
+            for (int i0 = lane; i0 < r; i0 += 128) {
+                double x[2][4], fv[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = min(i0 + 64 * h, r - 1);
+                    fv[h] = fvec[i];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x[h][u] = Xs[i + min(l0 + u, r - 1) * ldx];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = i0 + 64 * h;
+                    if (i >= r) continue;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = l0 + u;
+                        if (l >= r) continue;
+                        double v;
+                        if (i == j) v = xjl[u];
+                        else v = ((l == j) ? 0.0 : (i == p ? xjo[u] : x[h][u])) - fv[h] * xjl[u];
+                        Xs[i + l * ldx] = v;
+                    }
+                }
             }
         }
         __syncthreads();
     }
-    if (singular) {
-        if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
-        return;
-    }
-    // undo the row interchanges on the columns of the inverse
     for (int j = r - 1; j >= 0; --j) {
         int p = colswap[j];
         if (p != j)
@@ -244,6 +372,214 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
             }
         __syncthreads();
     }
+    // log|det| and sign: one log per thread, summed in pivot order
+    for (int i = tid; i < r; i += NTH) fvec[i] = log(fabs(pivs[i]));
+    __syncthreads();
+    ld_sum = 0.0;
+    sgn = 1;
+    for (int i = 0; i < r; ++i) {
+        ld_sum += fvec[i];
+        if (pivs[i] < 0) sgn = -sgn;
+        if (colswap[i] != i) sgn = -sgn;
+    }
+    return true;
+}
+
+// Value of v held by lane `ln` of the wave (ln wave-uniform).
+__device__ inline double lane_read(double v, int ln) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffff), ln);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), ln);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Register-resident variant of gj_inverse (same pivots, same arithmetic per element):
+// thread (wave w, lane) holds X[lane + 64 h][w + NW c] for h < RB, c < CB, which covers
+// r <= 64 RB and r <= NW CB.  One barrier per step: the wave that owns column j picks the
+// pivot (maximum of |x| as an unsigned 64-bit key, lowest row among equal keys) and
+// publishes column j and the pivot row index; every wave reads rows j and p of its own
+// columns from the lanes that hold them.  Column j goes through a buffer of two halves
+// used in alternate steps, so no second barrier is needed.  The result is written back to
+// Xs with the column interchanges undone.  sc: 4 * ldx doubles of LDS.
+template <int NTH, int RB, int CB>
+__device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double* sc, double& ld_sum, int& sgn) {
+    constexpr int NW = NTH / 64;
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    double* colj = sc;                  // two halves of ldx
+    double* pivs = sc + 2 * ldx;
+    int* dest = (int*)(sc + 3 * ldx);   // ldx doubles hold 2 ldx >= r ints
+    double x[RB][CB];
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = lane + 64 * h, l = wv + NW * c;
+            x[h][c] = (i < r && l < r) ? Xs[i + l * ldx] : 0.0;
+        }
+    for (int j = 0; j < r; ++j) {
+        double* cb = colj + (j & 1) * ldx;
+        const int cj = j / NW;
+        if (wv == j % NW) {
+            unsigned long long kb = 0;
+            int hb = 0;
+#pragma unroll
+            for (int h = 0; h < RB; ++h) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c == cj) v = x[h][c];
+                const int i = lane + 64 * h;
+                if (i < r) cb[i] = v;
+                const unsigned long long key = (i >= j && i < r) ? (unsigned long long)__double_as_longlong(fabs(v)) : 0ull;
+                if (key > kb) { kb = key; hb = h; }
+            }
+            unsigned long long km = kb;
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned lo = __shfl_xor((unsigned)(km & 0xffffffffull), o, 64);
+                const unsigned hi = __shfl_xor((unsigned)(km >> 32), o, 64);
+                const unsigned long long other = ((unsigned long long)hi << 32) | lo;
+                km = other > km ? other : km;
+            }
+            int p = -1;
+            if (km > 0) {
+#pragma unroll
+                for (int h = RB - 1; h >= 0; --h) {
+                    const unsigned long long b = __ballot(kb == km && hb == h);
+                    if (b) p = 64 * h + __ffsll((long long)b) - 1;
+                }
+            }
+            if (lane == 0) colswap[j] = p;
+        }
+        __syncthreads();
+        const int p = __builtin_amdgcn_readfirstlane(colswap[j]);
+        if (p < 0) return false;
+        const double d = cb[p];
+        if (!(fabs(d) > 0.0)) return false;
+        if (tid == 0) pivs[j] = d;
+        const double rinv = 1.0 / d;
+        double fv[RB];
+#pragma unroll
+        for (int h = 0; h < RB; ++h) {
+            const int i = lane + 64 * h;
+            fv[h] = (i == j || i >= r) ? 0.0 : cb[i == p ? j : i];   // column j after the interchange
+        }
+        const int jl = j & 63, jh = j >> 6, pl = p & 63, ph = p >> 6;
+        bool isj[RB], isp[RB];
+#pragma unroll
+        for (int h = 0; h < RB; ++h) {
+            isj[h] = lane + 64 * h == j;
+            isp[h] = lane + 64 * h == p;
+        }
+        // rows and columns >= r hold values that are never read back, so they are updated
+        // without bounds tests; rows j and p come from the lanes that hold them
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int l = wv + NW * c;
+            double rj = 0.0, rp = 0.0;   // old rows j and p of column l
+#pragma unroll
+            for (int h = 0; h < RB; ++h) {
+                if (h == jh) rj = lane_read(x[h][c], jl);
+                if (h == ph) rp = lane_read(x[h][c], pl);
+            }
+            if (l == j) {
+                const double xjl = rinv;
+#pragma unroll
+                for (int h = 0; h < RB; ++h) x[h][c] = isj[h] ? xjl : -fv[h] * xjl;
+            } else {
+                const double xjl = rp * rinv;
+#pragma unroll
+                for (int h = 0; h < RB; ++h) {
+                    const double v = (isp[h] ? rj : x[h][c]) - fv[h] * xjl;
+                    x[h][c] = isj[h] ? xjl : v;
+                }
+            }
+        }
+    }
+    // undo the row interchanges on the columns: final position of each column
+    __syncthreads();
+    if (tid == 0) {
+        int* orig = dest + r;   // orig[pos] = column now at position pos
+        for (int l = 0; l < r; ++l) orig[l] = l;
+        for (int j = r - 1; j >= 0; --j) {
+            const int p = colswap[j];
+            const int t0 = orig[j];
+            orig[j] = orig[p];
+            orig[p] = t0;
+        }
+        for (int q = 0; q < r; ++q) dest[orig[q]] = q;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = lane + 64 * h, l = wv + NW * c;
+            if (i < r && l < r) Xs[i + dest[l] * ldx] = x[h][c];
+        }
+    // log|det| and sign, summed in pivot order
+    for (int i = tid; i < r; i += NTH) colj[i] = log(fabs(pivs[i]));
+    __syncthreads();
+    ld_sum = 0.0;
+    sgn = 1;
+    for (int i = 0; i < r; ++i) {
+        ld_sum += colj[i];
+        if (pivs[i] < 0) sgn = -sgn;
+        if (colswap[i] != i) sgn = -sgn;
+    }
+    __syncthreads();
+    return true;
+}
+
+// X_RR = Y_RR - T^T Z_S (Y_RR read from Yg or, in the fused kernel, formed from the store),
+// then its inverse, log|det| and the per-box records.  Returns false when X_RR is singular.
+template <int NTH>
+__device__ bool elim_xrr_inverse(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int nj, const double* Ts,
+                                 const double* Yg, double* Xs, double* xsr, int mixed, int* colswap, double* sc,
+                                 int& piv_idx, double& piv_val) {
+    const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
+    const int64_t bsz = (int64_t)nmax * nmax;
+    const double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
+    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
+    double* XRR = a.XRR + (int64_t)c * bsz;
+    // Z_S = rows S of X_JR, staged in LDS (xsr[q + k b2]) when a buffer is given
+    const double* zs = XJR;
+    int ldz = ldJ;
+    if (xsr) {
+        for (int e = tid; e < k * r; e += NTH) {
+            int q = e % k, b2 = e / k;
+            xsr[e] = XJR[q + (int64_t)b2 * ldJ];
+        }
+        __syncthreads();
+        zs = xsr;
+        ldz = k;
+    }
+    for (int e = tid; e < r * r; e += NTH) {
+        int b = e % r, b2 = e / r;
+        double v;
+        if (Yg) {
+            v = Yg[b + (int64_t)b2 * nmax];
+        } else {
+            v = Acc[sh.rp[b] + (int64_t)sh.rp[b2] * nmax];
+            for (int q = 0; q < k; ++q) v -= Acc[sh.rp[b] + (int64_t)sh.sp[q] * nmax] * Ts[b2 + r * q];
+        }
+        for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * zs[q + (int64_t)b2 * ldz];
+        XRR[b + (int64_t)b2 * nmax] = v;
+        Xs[b + b2 * nmax] = v;
+    }
+    __syncthreads();
+    double ld_sum;
+    int sgn;
+    bool ok;
+    if constexpr (NTH == 1024) {
+        if (r <= 64) ok = gj_inverse_reg<NTH, 1, 4>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
+        else if (r <= 128) ok = gj_inverse_reg<NTH, 2, 8>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
+        else ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+    } else {
+        if (r <= 64) ok = gj_inverse_reg<NTH, 1, 16>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
+        else ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+    }
+    if (!ok) return false;
     if (tid == 0) {
         a.logdet_part[c] = ld_sum;
         a.sign_part[c] = sgn;
@@ -251,85 +587,166 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
     double* Xinv = a.Xinv + (int64_t)c * bsz;
     for (int e = tid; e < r * r; e += NTH) {
         int b = e % r, b2 = e / r;
-        Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * ldx];
+        Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * nmax];
+        if (mixed) a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * nmax];
     }
-
-    // ---- G = X_RR^{-1} X_RJ, X_RJ = A_RJ - T^T A_SJ, kTile columns of J at a time ------
-    double* G = a.G + (int64_t)c * nmax * ldJ;
-    for (int c0 = 0; c0 < nj; c0 += kTile) {
-        const int tc = min(kTile, nj - c0);
-        if (tid < tc) {
-            const int jj = c0 + tid;
-            if (jj < k) {
-                srcp[tid] = Acc;
-                srcpos[tid] = sp[jj];
-            } else {
-                int s = 0;
-                while (joff[s + 1] <= jj) ++s;
-                srcp[tid] = blk_cn[s];
-                srcpos[tid] = nap[s][jj - joff[s]];
-            }
-        }
-        __syncthreads();
-        // tA[pos + nmax * jp] = A(B_c position pos, J column c0 + jp)
-        for (int e = tid; e < tc * n; e += NTH) {
-            int pos = e % n, jp = e / n;
-            tA[pos + nmax * jp] = srcp[jp][pos + (int64_t)srcpos[jp] * nmax];
-        }
-        __syncthreads();
-        for (int e = tid; e < tc * r; e += NTH) {
-            const int b = e % r, jp = e / r;
-            const double* col = tA + nmax * jp;
-            double v = col[rp[b]];
-            for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * col[sp[q]];
-            tX[b + nmax * jp] = v;
-        }
-        __syncthreads();
-        const int th = (tc + 1) >> 1;
-        for (int e = tid; e < th * r; e += NTH) {
-            const int b = e % r, jp = 2 * (e / r);
-            const bool two = jp + 1 < tc;
-            const double* x0 = tX + nmax * jp;
-            const double* x1 = x0 + nmax;
-            double v0 = 0.0, v1 = 0.0;
-            for (int q = 0; q < r; ++q) {
-                const double w = Xs[b + q * ldx];
-                v0 += w * x0[q];
-                if (two) v1 += w * x1[q];
-            }
-            G[b + (int64_t)(c0 + jp) * nmax] = v0;
-            if (two) G[b + (int64_t)(c0 + jp + 1) * nmax] = v1;
-        }
-        __syncthreads();
-    }
-
-    // ---- bookkeeping: record sets, FP32 copies, active list of c becomes S ---------------
-    for (int i = tid; i < k; i += NTH) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sp[i]];
-    for (int i = tid; i < r; i += NTH) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + rp[i]];
-    if (mixed) {
-        for (int e = tid; e < nj * r; e += NTH) {
-            int jj = e % nj, b = e / nj;
-            a.XJR32[(int64_t)c * ldJ * nmax + jj + (int64_t)b * ldJ] = (float)XJR[jj + (int64_t)b * ldJ];
-        }
-        for (int e = tid; e < r * nj; e += NTH) {
-            int b = e % r, jj = e / r;
-            a.G32[(int64_t)c * nmax * ldJ + b + (int64_t)jj * nmax] = (float)G[b + (int64_t)jj * nmax];
-        }
-        for (int e = tid; e < r * r; e += NTH) {
-            int b = e % r, b2 = e / r;
-            a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * ldx];
-        }
+    if (mixed)
         for (int e = tid; e < k * r; e += NTH) {
             int b = e % r, q = e / r;
             a.T32[(int64_t)c * bsz + q + (int64_t)b * nmax] = (float)Ts[e];
         }
+    for (int i = tid; i < k; i += NTH) a.Sg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sh.sp[i]];
+    for (int i = tid; i < r; i += NTH) a.Rg[(int64_t)c * nmax + i] = a.gidx[(int64_t)c * nmax + sh.rp[i]];
+    return true;
+}
+
+// Dynamic LDS: Ts[tsz] | Xs[nmax^2] (when XLDS) | tA[nmax tw] | tX[nmax tw]
+template <bool XLDS, int NTH>
+__global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
+                                              double* __restrict__ work, int* flag, int tsz, int tw) {
+    extern __shared__ double dyn[];
+    __shared__ ElimShared sh;
+    __shared__ int colswap[kMaxBox];
+    __shared__ int piv_idx;
+    __shared__ double piv_val;
+    const int tid = threadIdx.x;
+    const int c = boxes[blockIdx.x];
+    const int n = a.cnt[c];
+    const int k = a.krank[c];
+    const int r = n - k;
+    if (n == 0 || r == 0) {
+        if (tid == 0) a.nJ[c] = 0;
+        return;
+    }
+    const int nmax = a.nmax, ldJ = a.ldJ;
+    const int64_t bsz = (int64_t)nmax * nmax;
+    double* Ts = dyn;
+    double* Xs = XLDS ? dyn + tsz : work + (int64_t)blockIdx.x * bsz;
+    double* tA = dyn + tsz + (XLDS ? bsz : 0);
+    double* tX = tA + (int64_t)nmax * tw;
+    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    __syncthreads();
+    const int nj = sh.joff[sh.nN];
+    for (int jj = tid; jj < nj; jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+    double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
+    float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
+    for (int r0 = 0; r0 < nj; r0 += tw)
+        elim_rows_tile<NTH>(sh, a, c, k, r, nj, r0, min(tw, nj - r0), tw, Ts, tA, XJR, XJR32, nullptr);
+    // the tile buffers (2 nmax tw >= 4 nmax doubles) are free here: Z_S when it fits, then
+    // the inversion's scratch
+    double* xsr = (k * r <= 2 * nmax * tw) ? tA : nullptr;
+    if (!elim_xrr_inverse<NTH>(sh, a, c, k, r, nj, Ts, nullptr, Xs, xsr, mixed, colswap, tA, piv_idx, piv_val)) {
+        if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
+        return;
+    }
+    double* G = a.G + (int64_t)c * nmax * ldJ;
+    float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
+    for (int c0 = 0; c0 < nj; c0 += tw)
+        elim_g_tile<NTH, kMaxBox / 64>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, Xs, XLDS, G, G32);
+    if (tid == 0) {
+        a.nJ[c] = nj;
+        a.nact[c] = k;
+    }
+    for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
+}
+
+// ---- split path ---------------------------------------------------------------------------
+// grid (row tiles of [J; R], boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw]
+template <int NTH>
+__global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int mixed,
+                                                   double* __restrict__ work, int tsz, int tw) {
+    extern __shared__ double dyn[];
+    __shared__ ElimShared sh;
+    const int tid = threadIdx.x;
+    const int c = boxes[blockIdx.y];
+    const int n = a.cnt[c];
+    const int k = a.krank[c];
+    const int r = n - k;
+    if (n == 0 || r == 0) return;
+    const int nmax = a.nmax, ldJ = a.ldJ;
+    double* Ts = dyn;
+    double* tA = dyn + tsz;
+    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    __syncthreads();
+    const int nj = sh.joff[sh.nN];
+    const int r0 = blockIdx.x * tw;
+    if (r0 >= nj + r) return;
+    const int tr = min(tw, nj + r - r0);
+    for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+    double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
+    float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
+    double* Y = work + (int64_t)blockIdx.y * nmax * nmax;
+    elim_rows_tile<NTH>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
+}
+
+// grid (boxes).  Dynamic LDS: Ts[tsz] | sc[4 nmax] | Z_S[tsz] (when use_zs) | Xs[nmax^2]
+// (when XLDS; else X_RR is inverted in place of Y_RR in the workspace)
+template <bool XLDS, int NTH>
+__global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restrict__ boxes, int mixed,
+                                                  double* __restrict__ work, int* flag, int tsz, int use_zs) {
+    extern __shared__ double dyn[];
+    __shared__ ElimShared sh;
+    __shared__ int colswap[kMaxBox];
+    __shared__ int piv_idx;
+    __shared__ double piv_val;
+    const int tid = threadIdx.x;
+    const int c = boxes[blockIdx.x];
+    const int n = a.cnt[c];
+    const int k = a.krank[c];
+    const int r = n - k;
+    if (n == 0 || r == 0) {
+        if (tid == 0) a.nJ[c] = 0;
+        return;
+    }
+    const int nmax = a.nmax;
+    double* Ts = dyn;
+    double* sc = dyn + tsz;
+    double* xsr = use_zs ? sc + 4 * nmax : nullptr;
+    double* Y = work + (int64_t)blockIdx.x * nmax * nmax;
+    double* Xs = XLDS ? sc + 4 * nmax + (use_zs ? tsz : 0) : Y;
+    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    __syncthreads();
+    const int nj = sh.joff[sh.nN];
+    if (!elim_xrr_inverse<NTH>(sh, a, c, k, r, nj, Ts, Y, Xs, xsr, mixed, colswap, sc, piv_idx, piv_val)) {
+        if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
+        return;
     }
     if (tid == 0) {
         a.nJ[c] = nj;
         a.nact[c] = k;
     }
-    for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sp[i];
+    for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
 }
+
+// grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw] | tX[nmax tw]
+template <int NTH, int HB>
+__global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int mixed, int* flag,
+                                                int tsz, int tw) {
+    extern __shared__ double dyn[];
+    __shared__ ElimShared sh;
+    const int c = boxes[blockIdx.y];
+    const int n = a.cnt[c];
+    const int k = a.krank[c];
+    const int r = n - k;
+    if (n == 0 || r == 0 || (*flag & 4)) return;
+    const int nmax = a.nmax, ldJ = a.ldJ;
+    const int64_t bsz = (int64_t)nmax * nmax;
+    double* Ts = dyn;
+    double* tA = dyn + tsz;
+    double* tX = tA + (int64_t)nmax * tw;
+    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    __syncthreads();
+    const int nj = sh.joff[sh.nN];
+    const int c0 = blockIdx.x * tw;
+    if (c0 >= nj) return;
+    double* G = a.G + (int64_t)c * nmax * ldJ;
+    float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
+    elim_g_tile<NTH, HB>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz, false, G,
+                         G32);
+}
+
+// Colours with fewer boxes than this take the split path.
+constexpr int kElimSplitBelow = 1 << 30;
 
 static int g_max_lds = -1;
 
@@ -345,9 +762,13 @@ int elim_lds_limit() {
     return g_max_lds;
 }
 
-void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
-                 hipStream_t s) {
-    if (nboxes <= 0) return;
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+    hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, hipStream_t s) {
+    if (nboxes <= 0) return 0;
     ElimArgs a;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;
@@ -355,31 +776,81 @@ void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double
     a.XJR = L.XJR; a.G = L.G; a.XRR = L.XRR; a.Xinv = L.Xinv;
     a.XJR32 = L.XJR32; a.G32 = L.G32; a.Xinv32 = L.Xinv32; a.T32 = L.T32;
     a.logdet_part = L.logdet_part; a.sign_part = L.sign_part;
-    const int tsz = (L.nmax * L.nmax) / 4 + 1;            // |S| |R| <= n^2 / 4
-    const size_t tile = 2 * (size_t)L.nmax * kTile;
-    const size_t with_x = sizeof(double) * (tsz + (size_t)L.nmax * L.nmax + tile);
-    const size_t without_x = sizeof(double) * (tsz + tile);
-    // few boxes in a colour (upper levels): one large workgroup per box to cut latency
-    const bool big = nboxes < 512;
-    if ((int)with_x <= elim_lds_limit()) {
-        if (big) {
-            hipFuncSetAttribute((const void*)k_elim<true, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
-            k_elim<true, 1024><<<dim3(nboxes), dim3(1024), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+    const size_t D = sizeof(double);
+    const size_t nm = (size_t)L.nmax;
+    const size_t tsz = nm * nm / 4 + 1;                    // |S| |R| <= n^2 / 4
+    const size_t lim = (size_t)elim_lds_limit() - 8192;    // room for the static tables
+    // widest tile (32, 16, 8 or 4 lines) whose buffers fit beside `fixed` doubles
+    auto tile_w = [&](size_t fixed, size_t bufs) {
+        for (int tw = kTileMax; tw >= 4; tw >>= 1)
+            if (D * (fixed + bufs * nm * tw) <= lim) return tw;
+        return 0;
+    };
+    if (nboxes < kElimSplitBelow) {
+        const int twr = tile_w(tsz, 1), twg = tile_w(tsz, 2);
+        if (twr == 0 || twg == 0) return -1;
+        const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
+        set_lds(k_elim_rows<256>, lr);
+        k_elim_rows<256><<<dim3((unsigned)((L.ldJ + L.nmax + twr - 1) / twr), nboxes), dim3(256), lr, s>>>(
+            a, boxes, mixed, work, (int)tsz, twr);
+        const size_t base = tsz + 4 * nm;
+        const bool xl = D * (base + nm * nm) <= lim;
+        const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
+        const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
+        // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
+        if (nboxes >= 256) {
+            if (xl) {
+                set_lds(k_elim_inv<true, 256>, li);
+                k_elim_inv<true, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+            } else {
+                set_lds(k_elim_inv<false, 256>, li);
+                k_elim_inv<false, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+            }
+        } else if (xl) {
+            set_lds(k_elim_inv<true, 1024>, li);
+            k_elim_inv<true, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         } else {
-            hipFuncSetAttribute((const void*)k_elim<true, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_x);
-            k_elim<true, 256><<<dim3(nboxes), dim3(256), with_x, s>>>(a, boxes, mixed, work, flag, tsz);
+            set_lds(k_elim_inv<false, 1024>, li);
+            k_elim_inv<false, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         }
-    } else {
-        if (big) {
-            hipFuncSetAttribute((const void*)k_elim<false, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)without_x);
-            k_elim<false, 1024><<<dim3(nboxes), dim3(1024), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+        const dim3 gg((unsigned)((L.ldJ + twg - 1) / twg), nboxes);
+        if (L.nmax <= 64) {
+            set_lds(k_elim_g<256, 1>, lg);
+            k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
+        } else if (L.nmax <= 128) {
+            set_lds(k_elim_g<256, 2>, lg);
+            k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
         } else {
-            hipFuncSetAttribute((const void*)k_elim<false, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)without_x);
-            k_elim<false, 256><<<dim3(nboxes), dim3(256), without_x, s>>>(a, boxes, mixed, work, flag, tsz);
+            set_lds(k_elim_g<256, 4>, lg);
+            k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
         }
+        return 3;
     }
+    // a large workgroup per box while the colour has fewer boxes than the chip has CUs x 2
+    const bool big = nboxes < 512;
+    const int twx = tile_w(tsz + nm * nm, 2);
+    if (twx > 0) {
+        const size_t l = D * (tsz + nm * nm + 2 * nm * twx);
+        if (big) {
+            set_lds(k_elim<true, 1024>, l);
+            k_elim<true, 1024><<<dim3(nboxes), dim3(1024), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, twx);
+        } else {
+            set_lds(k_elim<true, 256>, l);
+            k_elim<true, 256><<<dim3(nboxes), dim3(256), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, twx);
+        }
+        return 1;
+    }
+    const int tw = tile_w(tsz, 2);
+    if (tw == 0) return -1;
+    const size_t l = D * (tsz + 2 * nm * tw);
+    if (big) {
+        set_lds(k_elim<false, 1024>, l);
+        k_elim<false, 1024><<<dim3(nboxes), dim3(1024), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, tw);
+    } else {
+        set_lds(k_elim<false, 256>, l);
+        k_elim<false, 256><<<dim3(nboxes), dim3(256), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, tw);
+    }
+    return 1;
 }
 
 }  // namespace rss

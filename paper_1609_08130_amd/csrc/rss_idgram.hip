@@ -14,6 +14,8 @@
 //                j > 0 once the largest is <= tol |R_00|), then T = R11^{-1} R12 in FP64.
 // The ID input of box c is M = [A(O, B_c); w K(Gamma, B_c)] (O = boxes at Chebyshev
 // distance 2, Gamma = n_p proxy points on the circle of radius proxy_radius * side).
+#include <algorithm>
+
 #include "rss_internal.h"
 
 namespace rss {
@@ -93,15 +95,48 @@ __device__ inline int wave_min_i(int v) {
     return v;
 }
 
-constexpr int kSliceRows = 256;   // rows of M per Gram workgroup
 constexpr int kChunk = 32;        // rows staged in LDS at a time
 
-// Number of Gram slices per box and workspace of one colour batch (doubles).
-int id_slices(int nmax, int n_proxy) { return (16 * nmax + n_proxy + kSliceRows - 1) / kSliceRows; }
+// Launch shape of the Gram kernel for one colour.  With many boxes, one workgroup takes a
+// 256-row slice of M and the whole upper triangle of G; with few boxes (the upper levels)
+// the rows are cut into shorter slices and the triangle into groups of 256 2x2 tiles, so
+// that the colour still spreads over the whole chip.  The partial Gram matrices of the
+// slices are then summed by k_gram_reduce.
+struct GramPlan {
+    int slice_rows, nsl, groups, tpt;
+};
 
+static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes) {
+    const int mmax = 16 * nmax + n_proxy;   // rows of M: <= 16 boxes at distance 2, plus proxies
+    const int nt = (nmax + 1) / 2, ntiles = nt * (nt + 1) / 2;
+    GramPlan g;
+    if (nboxes >= 512) {
+        g.slice_rows = 256;
+        g.tpt = ntiles <= 3 * 256 ? 3 : ntiles <= 5 * 256 ? 5 : 9;
+        g.groups = (ntiles + 9 * 256 - 1) / (9 * 256);
+    } else {
+        g.tpt = 1;
+        g.groups = (ntiles + 255) / 256;
+        g.slice_rows = 128;
+        while (g.slice_rows > kChunk &&
+               nboxes * (size_t)((mmax + g.slice_rows - 1) / g.slice_rows) * g.groups < 2048)
+            g.slice_rows >>= 1;
+    }
+    g.nsl = (mmax + g.slice_rows - 1) / g.slice_rows;
+    return g;
+}
+
+// Rows of R kept in LDS by the pivoted Cholesky of a colour with few boxes (the rest stay
+// in the workspace).
+static int pchol_lds_rows(int nmax) { return std::max(1, std::min(nmax, 49152 / (16 * nmax))); }
+
+// Workspace (doubles) for any colour of at most nboxes boxes: the plan, and with it the
+// number of slices, depends on the colour's box count.
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes) {
     const size_t nn = (size_t)nmax * nmax;
-    return nboxes * ((size_t)id_slices(nmax, n_proxy) * nn * 2 + nn * 2);
+    size_t slices = 0;
+    for (size_t b = 1; b <= nboxes; ++b) slices = std::max(slices, b * (size_t)gram_plan(nmax, n_proxy, b).nsl);
+    return slices * nn * 2 + nboxes * nn * 2;
 }
 
 struct ORing {
@@ -132,14 +167,14 @@ __device__ inline void build_oring(ORing& o, const double* store, const int* nac
 }
 
 // ---- 1. partial Gram matrices -------------------------------------------------------------
-// grid (slices, boxes); thread owns TPT 2x2 tiles of the upper triangle of G.
+// grid (slices x tile groups, boxes); thread owns TPT 2x2 tiles of the upper triangle of G.
 template <int NTH, int TPT>
 __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, int nb, int nmax,
                                               const int* __restrict__ cnt, const int* __restrict__ gidx,
                                               const int* __restrict__ nact, const int* __restrict__ apos,
                                               const int* __restrict__ boxes, const double* __restrict__ pts,
                                               const double* __restrict__ ptmpl, KernelParams kp, int t,
-                                              double* __restrict__ gpart, int nslice) {
+                                              double* __restrict__ gpart, int nslice, int slice_rows) {
 #pragma clang fp contract(off)
     extern __shared__ double Ms[];   // kChunk x (nmax + 1)
     __shared__ ORing oring;
@@ -147,7 +182,8 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
     __shared__ double colx[kMaxBox], coly[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.y];
-    const int sl = blockIdx.x;
+    const int sl = blockIdx.x % nslice;
+    const int grp = blockIdx.x / nslice;
     const int n = cnt[c];
     if (n == 0) return;
     if (tid == 0) build_oring(oring, store, nact, apos, c, nb, nmax);
@@ -171,16 +207,17 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
     __syncthreads();
     const int mO = oring.beg[oring.cnt];
     const int m = mO + kp.n_proxy;
-    const int r_begin = sl * kSliceRows;
+    const int r_begin = sl * slice_rows;
     if (r_begin >= m) return;
-    const int r_end = min(m, r_begin + kSliceRows);
+    const int r_end = min(m, r_begin + slice_rows);
     const int ld = nmax + 1;
     const int nt = (n + 1) >> 1;                  // 2x2 tiles per dimension
     const int ntiles = nt * (nt + 1) / 2;
+    if (grp * NTH * TPT >= ntiles) return;        // this box has no tiles in the group
     int tp[TPT], tq[TPT];
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
-        int id = tid + u * NTH;
+        int id = tid + u * NTH + grp * NTH * TPT;
         tp[u] = -1;
         tq[u] = -1;
         if (id < ntiles) {
@@ -261,7 +298,44 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
     }
 }
 
-// ---- 2. pivoted Cholesky of G in double-double, then T ------------------------------------
+// ---- 2. sum of the partial Gram matrices (few-box colours) ---------------------------------
+// Rows of M of box c: active DOFs of the distance-2 boxes plus the proxies.
+__device__ inline int id_rows(const int* nact, int c, int nb, int n_proxy) {
+    const int cx = c % nb, cy = c / nb;
+    int mO = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            if (max(abs(dx), abs(dy)) != 2) continue;
+            int ox = cx + dx, oy = cy + dy;
+            if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
+            mO += nact[ox + nb * oy];
+        }
+    return mO + n_proxy;
+}
+
+// grid (nmax^2 / 256, boxes): slice 0 <- sum over the slices that hold rows, in slice order.
+__global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ cnt, const int* __restrict__ nact,
+                                                     const int* __restrict__ boxes, int nb, int nmax, int n_proxy,
+                                                     double* __restrict__ gpart, int nslice, int slice_rows) {
+#pragma clang fp contract(off)
+    const int c = boxes[blockIdx.y];
+    const int n = cnt[c];
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int pa = e / nmax, qa = e % nmax;
+    if (pa >= n || qa >= n || pa > qa) return;
+    const int m = id_rows(nact, c, nb, n_proxy);
+    const int nsl = (m + slice_rows - 1) / slice_rows;
+    const int64_t sstride = (int64_t)nmax * nmax;
+    double2* G = (double2*)gpart + (int64_t)blockIdx.y * nslice * sstride + e;
+    dd acc = {0.0, 0.0};
+    for (int sl = 0; sl < nsl; ++sl) {
+        double2 v = G[sl * sstride];
+        acc = dd_add(acc, {v.x, v.y});
+    }
+    G[0] = make_double2(acc.hi, acc.lo);
+}
+
+// ---- 3. pivoted Cholesky of G in double-double, then T ------------------------------------
 __device__ inline dd gram_entry(const double2* G, int nsl, int nmax, int64_t sstride, int a, int b) {
 #pragma clang fp contract(off)
     if (a > b) { int t0 = a; a = b; b = t0; }
@@ -273,22 +347,26 @@ __device__ inline dd gram_entry(const double2* G, int nsl, int nmax, int64_t sst
     return acc;
 }
 
+// One workgroup per box, thread q owns column q.  Rows j < kc of R live in LDS (hi and lo
+// parts apart), later rows in the workspace.  nsl_fixed > 0: the slices are already summed
+// into slice 0 (nsl_fixed = 1); otherwise every entry is summed over the box's slices here.
 template <int NTH>
 __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, const int* __restrict__ nact,
                                                const int* __restrict__ boxes, int nb, int nmax, KernelParams kp,
-                                               const double* __restrict__ gpart, int nslice,
-                                               double* __restrict__ rwork, int* __restrict__ krank,
-                                               int* __restrict__ spos, int* __restrict__ rpos,
-                                               double* __restrict__ Tout, int* __restrict__ mrows) {
+                                               const double* __restrict__ gpart, int nslice, int slice_rows,
+                                               int nsl_fixed, double* __restrict__ rwork, int kc,
+                                               int* __restrict__ krank, int* __restrict__ spos,
+                                               int* __restrict__ rpos, double* __restrict__ Tout,
+                                               int* __restrict__ mrows) {
 #pragma clang fp contract(off)
     constexpr int NW = NTH / 64;
+    extern __shared__ double rl[];   // Rh[kc * nmax] | Rl[kc * nmax]
     __shared__ int piv[kMaxBox];
     __shared__ int srank_s[kMaxBox];
-    __shared__ double rjj_hi, rjj_lo;
+    __shared__ double dh[2][kMaxBox], dl[2][kMaxBox];   // trailing norms^2, by step parity
     __shared__ double redv[2][NW];
     __shared__ int redi[2][NW];
     __shared__ unsigned long long smask[NW];
-    __shared__ int mrow_s;
     const int q = threadIdx.x;
     const int wv = q >> 6, lane = q & 63;
     const int c = boxes[blockIdx.x];
@@ -297,25 +375,31 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
         if (q == 0) { krank[c] = 0; mrows[c] = 0; }
         return;
     }
-    if (q == 0) {
-        // rows of the ID input: active DOFs of the distance-2 boxes plus the proxies
-        const int cx = c % nb, cy = c / nb;
-        int mO = 0;
-        for (int dy = -2; dy <= 2; ++dy)
-            for (int dx = -2; dx <= 2; ++dx) {
-                if (max(abs(dx), abs(dy)) != 2) continue;
-                int ox = cx + dx, oy = cy + dy;
-                if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
-                mO += nact[ox + nb * oy];
-            }
-        mrow_s = mO + kp.n_proxy;
-    }
-    __syncthreads();
-    const int m = mrow_s;
-    const int nsl = (m + kSliceRows - 1) / kSliceRows;
+    const int m = id_rows(nact, c, nb, kp.n_proxy);
+    const int nsl = nsl_fixed > 0 ? nsl_fixed : (m + slice_rows - 1) / slice_rows;
     const int64_t sstride = (int64_t)nmax * nmax;
     const double2* G = (const double2*)gpart + (int64_t)blockIdx.x * nslice * sstride;
-    double2* R = (double2*)rwork + (int64_t)blockIdx.x * sstride;   // R[j * nmax + q]
+    double2* Rg = (double2*)rwork + (int64_t)blockIdx.x * sstride;   // rows >= kc: Rg[j * nmax + q]
+    double* Rh = rl;
+    double* Rl = rl + (int64_t)kc * nmax;
+    auto rget = [&](int j, int col) -> dd {
+        if (j < kc) return {Rh[j * nmax + col], Rl[j * nmax + col]};
+        const double2 v = Rg[(int64_t)j * nmax + col];
+        return {v.x, v.y};
+    };
+    auto rput = [&](int j, int col, dd v) {
+        if (j < kc) {
+            Rh[j * nmax + col] = v.hi;
+            Rl[j * nmax + col] = v.lo;
+        } else {
+            Rg[(int64_t)j * nmax + col] = make_double2(v.hi, v.lo);
+        }
+    };
+    auto rhi = [&](int j, int col) -> double { return j < kc ? Rh[j * nmax + col] : Rg[(int64_t)j * nmax + col].x; };
+    auto rset_hi = [&](int j, int col, double v) {
+        if (j < kc) Rh[j * nmax + col] = v;
+        else Rg[(int64_t)j * nmax + col].x = v;
+    };
     dd d = {0.0, 0.0};
     if (q < n) d = gram_entry(G, nsl, nmax, sstride, q, q);
     bool done = q >= n;
@@ -325,6 +409,7 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
     for (int j = 0; j < kmax; ++j) {
         const int buf = j & 1;
         const double nu = done ? -1.0 : d.hi + d.lo;
+        if (q < n) { dh[buf][q] = d.hi; dl[buf][q] = d.lo; }
         double wmax = wave_max_d(nu);
         if (lane == 0) redv[buf][wv] = wmax;
         __syncthreads();
@@ -348,32 +433,36 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
 #pragma unroll
         for (int w = 1; w < NW; ++w) p = min(p, redi[buf][w]);
         if (p >= n) break;
+        // every thread forms r_jj itself (no extra barrier)
+        const dd rjj = dd_sqrt({dh[buf][p], dl[buf][p]});
         if (q == p) {
-            dd r = dd_sqrt(d);
-            rjj_hi = r.hi;
-            rjj_lo = r.lo;
             piv[j] = p;
-            R[(int64_t)j * nmax + p] = make_double2(r.hi, r.lo);
+            rput(j, p, rjj);
             done = true;
         }
-        __syncthreads();
         if (!done) {
-            // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2
-            dd acc = gram_entry(G, nsl, nmax, sstride, p, q);
-            for (int i = 0; i < j; ++i) {
-                const double2 rip = R[(int64_t)i * nmax + p];
-                const double2 riq = R[(int64_t)i * nmax + q];
-                acc = dd_sub(acc, dd_mul({rip.x, rip.y}, {riq.x, riq.y}));
+            // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2.  The sum runs in four
+            // partial sums while the load of G_pq is in flight.
+            const dd gpq = gram_entry(G, nsl, nmax, sstride, p, q);
+            dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0}, s2 = {0.0, 0.0}, s3 = {0.0, 0.0};
+            int i = 0;
+            for (; i + 3 < j; i += 4) {
+                s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+                s1 = dd_add(s1, dd_mul(rget(i + 1, p), rget(i + 1, q)));
+                s2 = dd_add(s2, dd_mul(rget(i + 2, p), rget(i + 2, q)));
+                s3 = dd_add(s3, dd_mul(rget(i + 3, p), rget(i + 3, q)));
             }
-            const dd rjq = dd_div(acc, {rjj_hi, rjj_lo});
-            R[(int64_t)j * nmax + q] = make_double2(rjq.hi, rjq.lo);
+            for (; i < j; ++i) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+            const dd acc = dd_sub(gpq, dd_add(dd_add(s0, s1), dd_add(s2, s3)));
+            const dd rjq = dd_div(acc, rjj);
+            rput(j, q, rjq);
             d = dd_sub(d, dd_mul(rjq, rjq));
         }
-        __syncthreads();
         k = j + 1;
     }
 
     // ---- sorted sets and T = R11^{-1} R12 (FP64 back substitution) ----------------------
+    __syncthreads();
     const bool isS = (q < n) && done;
     const unsigned long long mask = __ballot(isS);
     if (lane == 0) smask[wv] = mask;
@@ -392,51 +481,59 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
         } else {
             const int rr = q - srank;
             rpos[boff + rr] = q;
-            // in place in row-major R: R[a][q] <- t_a
+            // in place in column q of R: R[a][q] <- t_a, last row first
             for (int a = k - 1; a >= 0; --a) {
-                double acc = R[(int64_t)a * nmax + q].x;
-                for (int b = a + 1; b < k; ++b) acc -= R[(int64_t)a * nmax + piv[b]].x * R[(int64_t)b * nmax + q].x;
-                acc = acc / R[(int64_t)a * nmax + piv[a]].x;
-                R[(int64_t)a * nmax + q].x = acc;
+                double acc = rhi(a, q);
+                for (int b = a + 1; b < k; ++b) acc -= rhi(a, piv[b]) * rhi(b, q);
+                rset_hi(a, q, acc / rhi(a, piv[a]));
             }
-            for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = R[(int64_t)a * nmax + q].x;
+            for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = rhi(a, q);
         }
     }
 }
 
-void launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
-                    const KernelParams& kp, double* work, hipStream_t s) {
-    if (nboxes <= 0) return;
-    const int nsl = id_slices(L.nmax, kp.n_proxy);
+template <int NTH, int TPT>
+static void gram_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+                        const KernelParams& kp, double* gpart, const GramPlan& g, size_t lds, hipStream_t s) {
+    k_gram<NTH, TPT><<<dim3(g.nsl * g.groups, nboxes), dim3(NTH), lds, s>>>(
+        L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart, g.nsl, g.slice_rows);
+}
+
+template <int NTH>
+static void pchol_launch(const Level& L, const int* boxes, int nboxes, const KernelParams& kp, double* gpart,
+                         const GramPlan& g, int nsl_fixed, double* rwork, hipStream_t s) {
+    // many boxes: occupancy hides the workspace latency better than LDS rows would
+    const int kc = nboxes >= 512 ? 0 : pchol_lds_rows(L.nmax);
+    const size_t lds = sizeof(double) * 2 * (size_t)kc * L.nmax;
+    k_pchol<NTH><<<dim3(nboxes), dim3(NTH), lds, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, g.nsl,
+                                                     g.slice_rows, nsl_fixed, rwork, kc, L.krank, L.spos, L.rpos,
+                                                     L.T, L.mrows);
+}
+
+int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+                   const KernelParams& kp, double* work, hipStream_t s) {
+    if (nboxes <= 0) return 0;
+    const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes);
     const size_t nn = (size_t)L.nmax * L.nmax;
     double* gpart = work;
-    double* rwork = work + (size_t)nboxes * nsl * nn * 2;
+    double* rwork = work + (size_t)nboxes * g.nsl * nn * 2;
     const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 1);
-    dim3 ggrid(nsl, nboxes);
-    const int nt = (L.nmax + 1) / 2, ntiles = nt * (nt + 1) / 2;
-    if (ntiles <= 3 * 256) {
-        k_gram<256, 3><<<ggrid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                     ptmpl, kp, L.t, gpart, nsl);
-    } else if (ntiles <= 5 * 256) {
-        k_gram<256, 5><<<ggrid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                     ptmpl, kp, L.t, gpart, nsl);
-    } else if (ntiles <= 9 * 256) {
-        k_gram<256, 9><<<ggrid, dim3(256), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts,
-                                                     ptmpl, kp, L.t, gpart, nsl);
-    } else {
-        k_gram<1024, 9><<<ggrid, dim3(1024), lds, s>>>(L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes,
-                                                       pts, ptmpl, kp, L.t, gpart, nsl);
+    int launches = 2;
+    if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else if (g.tpt == 3) gram_launch<256, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else if (g.tpt == 5) gram_launch<256, 5>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else gram_launch<256, 9>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    int nsl_fixed = 0;
+    if (g.groups > 1 || g.slice_rows < 256) {
+        k_gram_reduce<<<dim3((unsigned)((nn + 255) / 256), nboxes), dim3(256), 0, s>>>(
+            L.cnt, L.nact, boxes, L.nb, L.nmax, kp.n_proxy, gpart, g.nsl, g.slice_rows);
+        nsl_fixed = 1;
+        ++launches;
     }
-    if (L.nmax <= 64) {
-        k_pchol<64><<<dim3(nboxes), dim3(64), 0, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, nsl, rwork,
-                                                     L.krank, L.spos, L.rpos, L.T, L.mrows);
-    } else if (L.nmax <= 128) {
-        k_pchol<128><<<dim3(nboxes), dim3(128), 0, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, nsl, rwork,
-                                                       L.krank, L.spos, L.rpos, L.T, L.mrows);
-    } else {
-        k_pchol<256><<<dim3(nboxes), dim3(256), 0, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, nsl, rwork,
-                                                       L.krank, L.spos, L.rpos, L.T, L.mrows);
-    }
+    if (L.nmax <= 64) pchol_launch<64>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    else if (L.nmax <= 128) pchol_launch<128>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    else pchol_launch<256>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    return launches;
 }
 
 }  // namespace rss

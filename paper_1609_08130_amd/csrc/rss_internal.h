@@ -145,10 +145,12 @@ void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, in
 void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
 
 // skeletonization (rss_idgram.hip, rss_elim.hip, rss_schur.hip)
-void launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+// Returns the number of kernels launched.
+int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                     const KernelParams& kp, double* work, hipStream_t s);
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
-void launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
+// Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
                  hipStream_t s);
 void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s);
 
