@@ -31,6 +31,23 @@ struct SweepArgs {
     const double* XRR;
 };
 
+// sum_{t < cnt} M[t * stride] v[t] in eight partial sums, so that eight loads of M are in
+// flight at a time.
+template <typename TT>
+__device__ inline double dot_strided(const TT* __restrict__ M, int64_t stride, const double* v, int cnt) {
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int t = 0;
+    for (; t + 8 <= cnt; t += 8) {
+        TT m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = M[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += (double)m[u] * v[t + u];
+    }
+    for (; t < cnt; ++t) s[0] += (double)M[(int64_t)t * stride] * v[t];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 template <typename TT>
 __global__ void __launch_bounds__(256) k_solve_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
@@ -55,22 +72,14 @@ __global__ void __launch_bounds__(256) k_solve_fwd(SweepArgs a, const int* __res
         for (int i = tid; i < k; i += 256) zS[i] = zc[sg[i]];
         for (int i = tid; i < r; i += 256) zR[i] = zc[rg[i]];
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {
-            double s = zR[b];
-            for (int q = 0; q < k; ++q) s -= (double)T[q + (int64_t)b * nmax] * zS[q];
-            zR[b] = s;
-        }
+        for (int b = tid; b < r; b += 256) zR[b] -= dot_strided(T + (int64_t)b * nmax, 1, zS, k);   // z_R -= T^T z_S
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {
-            double s = 0.0;
-            for (int q = 0; q < r; ++q) s += (double)Xi[b + (int64_t)q * nmax] * zR[q];
-            w[b] = s;
-        }
+        for (int b = tid; b < r; b += 256) w[b] = dot_strided(Xi + b, nmax, zR, r);   // X_RR^{-1} z_R
         __syncthreads();
-        for (int jj = tid; jj < nj; jj += 256) {
-            double s = 0.0;
-            for (int b = 0; b < r; ++b) s += (double)E[jj + (int64_t)b * ldJ] * w[b];
-            zc[J[jj]] -= s;
+        for (int jj = tid; jj < nj; jj += 256) {                                        // z_J -= E w
+            const int g = J[jj];
+            const double sj = dot_strided(E + jj, ldJ, w, r);
+            zc[g] -= sj;
         }
         for (int b = tid; b < r; b += 256) zc[rg[b]] = w[b];
         __syncthreads();
@@ -80,6 +89,7 @@ __global__ void __launch_bounds__(256) k_solve_fwd(SweepArgs a, const int* __res
 template <typename TT>
 __global__ void __launch_bounds__(256) k_solve_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
+    extern __shared__ double zJ[];   // ldJ
     __shared__ double zR[kMaxBox];
     __shared__ double part[4][kMaxBox];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
@@ -97,15 +107,16 @@ __global__ void __launch_bounds__(256) k_solve_bwd(SweepArgs a, const int* __res
     for (int i = tid; i < r; i += 256) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     const int wv = tid >> 6, lane = tid & 63;
+    const int q4 = (nj + 3) / 4;   // J entries per wave
     for (int h = 0; h < nrhs; ++h) {
         double* zc = z + (int64_t)h * ld;
-        // z_R -= G z_J : wave wv sums over jj = wv, wv+4, ...; lanes over rows b
+        for (int jj = tid; jj < nj; jj += 256) zJ[jj] = zc[J[jj]];
+        __syncthreads();
+        // z_R -= G z_J : wave wv takes a contiguous quarter of J, lanes take rows b
+        const int j0 = wv * q4, j1 = min(nj, j0 + q4);
         for (int b0 = 0; b0 < r; b0 += 64) {
-            int b = b0 + lane;
-            double s = 0.0;
-            if (b < r)
-                for (int jj = wv; jj < nj; jj += 4) s += (double)G[b + (int64_t)jj * nmax] * zc[J[jj]];
-            if (b < r) part[wv][b] = s;
+            const int b = b0 + lane;
+            if (b < r) part[wv][b] = j1 > j0 ? dot_strided(G + b + (int64_t)j0 * nmax, nmax, zJ + j0, j1 - j0) : 0.0;
         }
         __syncthreads();
         for (int b = tid; b < r; b += 256) {
@@ -114,11 +125,7 @@ __global__ void __launch_bounds__(256) k_solve_bwd(SweepArgs a, const int* __res
             zc[rg[b]] = v;
         }
         __syncthreads();
-        for (int q = tid; q < k; q += 256) {
-            double s = 0.0;
-            for (int b = 0; b < r; ++b) s += (double)T[q + (int64_t)b * nmax] * zR[b];
-            zc[sg[q]] -= s;
-        }
+        for (int q = tid; q < k; q += 256) zc[sg[q]] -= dot_strided(T + q, nmax, zR, r);   // z_S -= T z_R
         __syncthreads();
     }
 }
@@ -240,8 +247,9 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
                       hipStream_t s) {
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
-    if (use32) k_solve_bwd<float><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
-    else k_solve_bwd<double><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+    const size_t lds = sizeof(double) * (size_t)L.ldJ;
+    if (use32) k_solve_bwd<float><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
+    else k_solve_bwd<double><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
 }
 
 void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
@@ -265,16 +273,24 @@ __global__ void k_gather_top(const int* __restrict__ idx, int64_t ntop, const do
     tmp[e] = z[h * ld + idx[i]];
 }
 
+// z[idx[i]] = sum_j M[i][j] tmp[j]: 64 rows per workgroup, one lane per row, the four
+// waves take quarters of j and add their partial sums in LDS.
 template <typename TT>
-__global__ void k_top_gemv(const int* __restrict__ idx, int64_t ntop, const TT* __restrict__ M,
-                           const double* __restrict__ tmp, int nrhs, double* __restrict__ z, int64_t ld) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int h = blockIdx.y;
-    if (i >= ntop) return;
+__global__ void __launch_bounds__(256) k_top_gemv(const int* __restrict__ idx, int64_t ntop, const TT* __restrict__ M,
+                                                  const double* __restrict__ tmp, int nrhs, double* __restrict__ z,
+                                                  int64_t ld) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int h = blockIdx.y;
     const double* x = tmp + (int64_t)h * ntop;
+    const int64_t q4 = (ntop + 3) / 4;
+    const int64_t j0 = wv * q4, j1 = j0 + q4 < ntop ? j0 + q4 : ntop;
     double s = 0.0;
-    for (int64_t j = 0; j < ntop; ++j) s += (double)M[i + j * ntop] * x[j];
-    z[(int64_t)h * ld + idx[i]] = s;
+    if (i < ntop && j1 > j0) s = dot_strided(M + i + j0 * ntop, ntop, x + j0, (int)(j1 - j0));
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && i < ntop) z[(int64_t)h * ld + idx[i]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 void launch_top_apply(const int* top_idx, int64_t ntop, const double* M, const float* M32, double* z, int nrhs,
@@ -282,7 +298,7 @@ void launch_top_apply(const int* top_idx, int64_t ntop, const double* M, const f
     if (ntop <= 0) return;
     int64_t tot = ntop * nrhs;
     k_gather_top<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(top_idx, ntop, z, nrhs, ld, tmp);
-    dim3 grid((unsigned)((ntop + 255) / 256), nrhs);
+    dim3 grid((unsigned)((ntop + 63) / 64), nrhs);
     if (M32) k_top_gemv<float><<<grid, dim3(256), 0, s>>>(top_idx, ntop, M32, tmp, nrhs, z, ld);
     else k_top_gemv<double><<<grid, dim3(256), 0, s>>>(top_idx, ntop, M, tmp, nrhs, z, ld);
 }
