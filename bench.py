@@ -7,9 +7,11 @@ then rss_factor_destroy.  The headline runs the mixed-precision factor (FP32 Sch
 products, FP32 factor copy for the preconditioner); the FP64 factor is timed on the same
 inputs for comparison.  Solves/s (plain x = F^{-1} b) are timed separately.
 
-Prints one JSON line.  `roofline` is computed for the dominant kernel of the factor from
-the library's own HIP events (recorded on the launch stream around every launch of the
-timed steps) and the algorithmic flop / byte counts of the realized box sizes.
+Prints one JSON line.  `roofline` is computed for the dominant kernel of the factor (the Schur update k_schur)
+from the library's own HIP events (recorded on the launch stream around every launch of
+the timed steps) and the algorithmic flop / byte counts of the realized box sizes;
+`traffic` is the HBM bytes per launch measured with rocprofv3 counters (committed summary
+under profiles/, null once the kernel source differs from the one measured).
 `cpu_baseline` times the oracle on a bounded sample of the same workload (a corner
 sub-grid with the same h, weight, leaf size and tolerance) and scales it linearly in N
 (the method's cost is linear in N, Corollary 2).
@@ -56,35 +58,57 @@ def parse():
     return ap.parse_args()
 
 
-def dominant_roofline(info: dict, mixed: bool) -> dict:
-    """Roofline of the factor kernel with the largest total time."""
-    ph = info["phase_ms"]
-    launches = info["launches"]
-    lv = info["levels"]
-    flops = {"id": sum(l["flops_id"] for l in lv),
-             "elim": sum(l["flops_x"] + l["flops_lu"] + l["flops_g"] for l in lv),
-             "schur": sum(l["flops_schur"] for l in lv)}
-    name = max(flops, key=lambda k: ph[k])
-    t = ph[name] / 1e3
-    nl = max(launches[name], 1)
-    if name == "schur":
-        byts = sum(l["bytes_schur"] for l in lv)
-        ai = flops[name] / byts
-        peak_f = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
-        ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
-        if ai < ridge:
-            ach = byts / t / 1e9
-            return dict(kernel="schur", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=ach / HBM_PEAK_GBS, traffic=None, launches=nl, avg_launch_ms=ph[name] / nl,
-                        algorithmic_bytes_per_launch=byts / nl, arithmetic_intensity=ai)
-        ach = flops[name] / t / 1e12
-        return dict(kernel="schur", bound="mfma", achieved=ach, peak=peak_f, unit="TFLOP/s", frac=ach / peak_f,
-                    traffic=None, launches=nl, avg_launch_ms=ph[name] / nl,
-                    algorithmic_flops_per_launch=flops[name] / nl, arithmetic_intensity=ai)
-    ach = flops[name] / t / 1e12
-    return dict(kernel=name, bound="alu", achieved=ach, peak=FP64_PEAK_TFS, unit="TFLOP/s",
-                frac=ach / FP64_PEAK_TFS, traffic=None, launches=nl, avg_launch_ms=ph[name] / nl,
-                algorithmic_flops_per_launch=flops[name] / nl)
+SCHUR_SRC = os.path.join(ROOT, "paper_1609_08130_amd", "csrc", "rss_schur.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_schur_grid1024_tol1e-6_hbm_counters.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_schur launch from the committed counter summary, or None when the
+    kernel source changed after the counters were taken (its SHA-256 is recorded there)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip().strip("`")
+        if "=" in line and not line.startswith("|"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        want = vals["source_sha256"]
+        traffic = float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    have = hashlib.sha256(open(SCHUR_SRC, "rb").read()).hexdigest()
+    return traffic if have == want else None
+
+
+def dominant_roofline(infos: list, mixed: bool) -> dict:
+    """Roofline of k_schur, the factor kernel with the largest total time in the rocprofv3
+    trace of this workload.  Durations come from the library's HIP events around every
+    k_schur launch of the timed steps (on the launch stream); bytes and flops are the
+    algorithmic counts of the realized |J| and |R| of every box."""
+    t_ms = sum(i["phase_ms"]["schur"] for i in infos)
+    nl = max(sum(i["launches"]["schur"] for i in infos), 1)
+    byts = sum(sum(l["bytes_schur"] for l in i["levels"]) for i in infos)
+    flops = sum(sum(l["flops_schur"] for l in i["levels"]) for i in infos)
+    avg_ms = t_ms / nl
+    ai = flops / byts
+    peak_f = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
+    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = measured_traffic()
+    common = dict(kernel="k_schur<float>" if mixed else "k_schur<double>", launches=nl, avg_launch_ms=avg_ms,
+                  algorithmic_bytes_per_launch=byts / nl, algorithmic_flops_per_launch=flops / nl,
+                  arithmetic_intensity=ai)
+    if ai < ridge:
+        ach = (byts / nl) / (avg_ms / 1e3) / 1e9
+        return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    traffic=traffic, **common)
+    ach = (flops / nl) / (avg_ms / 1e3) / 1e12
+    return dict(bound="mfma", achieved=ach, peak=peak_f, unit="TFLOP/s", frac=ach / peak_f, traffic=traffic,
+                **common)
 
 
 def run_gpu(args, precision: str):
@@ -202,7 +226,7 @@ def main():
         sys.exit(2)
     mixed = run_gpu(args, "mixed")
     fp64 = None if args.no_fp64 else run_gpu(args, "fp64")
-    roof = dominant_roofline(mixed["info"], True)
+    roof = dominant_roofline(mixed["infos"], True)
     out = {
         "metric": "RS-S factor s + solves/s, N=1M 2D Laplace ε=1e-6, mixed vs FP64, one GPU",
         "value": 1e3 / mixed["ms_per_step"],
