@@ -27,7 +27,7 @@ struct SchurArgs {
 };
 
 template <typename TT>
-__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int tpd) {
+__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd) {
     constexpr int TM = 64, TK = 16;
     __shared__ TT As[TK][TM + 1];
     __shared__ TT Bs[TK][TM + 1];
@@ -38,8 +38,15 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     __shared__ int nS;
 
     const int tid = threadIdx.x;
-    const int c = boxes[blockIdx.y];
-    const int ti = blockIdx.x % tpd, tj = blockIdx.x / tpd;
+    // Workgroups are dealt to the 8 XCDs round-robin in launch order; id = x + 8 s puts all
+    // tiles of box x + 8 (s / tpd^2) on XCD x, so its X_JR and G stay in one L2.
+    const int ntile = tpd * tpd;
+    const int xcd = blockIdx.x & 7, sidx = blockIdx.x >> 3;
+    const int bi = xcd + 8 * (sidx / ntile);
+    if (bi >= nbox) return;
+    const int c = boxes[bi];
+    const int tile = sidx % ntile;
+    const int ti = tile % tpd, tj = tile / tpd;
     const int nj = a.nJ[c];
     if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
     const int n = a.cnt[c], k = a.krank[c], r = n - k;
@@ -143,14 +150,15 @@ void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mi
     SchurArgs a;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ; a.spos = L.spos;
-    int tpd = (maxJ + 63) / 64;
-    dim3 grid(tpd * tpd, nboxes), block(256);
+    const int tpd = (maxJ + 63) / 64;
+    const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);
+    dim3 grid((unsigned)nwg), block(256);
     if (mixed) {
         a.XJR = L.XJR32; a.G = L.G32;
-        k_schur<float><<<grid, block, 0, s>>>(a, boxes, tpd);
+        k_schur<float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
     } else {
         a.XJR = L.XJR; a.G = L.G;
-        k_schur<double><<<grid, block, 0, s>>>(a, boxes, tpd);
+        k_schur<double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
     }
 }
 
