@@ -53,6 +53,19 @@ struct ElimArgs {
 
 constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
 
+// Workgroups are dealt to the 8 XCDs round-robin in launch order.  With a grid of
+// 8 * ntile * ceil(nbox / 8) workgroups, id = x + 8 s takes box x + 8 (s / ntile) and
+// tile s % ntile, so all tiles of a box (and its one-workgroup kernels, launched with
+// id = box) run on XCD x and share its L2.
+__device__ inline bool xcd_tile(int ntile, int nbox, int& bi, int& tile) {
+    const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
+    bi = x + 8 * (s / ntile);
+    tile = s % ntile;
+    return bi < nbox;
+}
+
+static inline unsigned xcd_grid(int ntile, int nbox) { return (unsigned)(8 * ntile * ((nbox + 7) / 8)); }
+
 // Per-workgroup tables of box c in LDS.
 struct ElimShared {
     int sp[kMaxBox], rp[kMaxBox];   // B positions of S and R
@@ -653,12 +666,14 @@ __global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict_
 // ---- split path ---------------------------------------------------------------------------
 // grid (row tiles of [J; R], boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw]
 template <int NTH>
-__global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int mixed,
-                                                   double* __restrict__ work, int tsz, int tw) {
+__global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
+                                                   int mixed, double* __restrict__ work, int tsz, int tw) {
     extern __shared__ double dyn[];
     __shared__ ElimShared sh;
     const int tid = threadIdx.x;
-    const int c = boxes[blockIdx.y];
+    int bi, tile;
+    if (!xcd_tile(ntile, nbox, bi, tile)) return;
+    const int c = boxes[bi];
     const int n = a.cnt[c];
     const int k = a.krank[c];
     const int r = n - k;
@@ -669,13 +684,13 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     elim_setup<NTH>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
-    const int r0 = blockIdx.x * tw;
+    const int r0 = tile * tw;
     if (r0 >= nj + r) return;
     const int tr = min(tw, nj + r - r0);
     for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
-    double* Y = work + (int64_t)blockIdx.y * nmax * nmax;
+    double* Y = work + (int64_t)bi * nmax * nmax;
     elim_rows_tile<NTH>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
 }
 
@@ -720,11 +735,13 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
 
 // grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw] | tX[nmax tw]
 template <int NTH, int HB>
-__global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int mixed, int* flag,
-                                                int tsz, int tw) {
+__global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
+                                                int mixed, int* flag, int tsz, int tw) {
     extern __shared__ double dyn[];
     __shared__ ElimShared sh;
-    const int c = boxes[blockIdx.y];
+    int bi, tile;
+    if (!xcd_tile(ntile, nbox, bi, tile)) return;
+    const int c = boxes[bi];
     const int n = a.cnt[c];
     const int k = a.krank[c];
     const int r = n - k;
@@ -737,7 +754,7 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     elim_setup<NTH>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
-    const int c0 = blockIdx.x * tw;
+    const int c0 = tile * tw;
     if (c0 >= nj) return;
     double* G = a.G + (int64_t)c * nmax * ldJ;
     float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
@@ -791,8 +808,9 @@ int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double*
         if (twr == 0 || twg == 0) return -1;
         const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
         set_lds(k_elim_rows<256>, lr);
-        k_elim_rows<256><<<dim3((unsigned)((L.ldJ + L.nmax + twr - 1) / twr), nboxes), dim3(256), lr, s>>>(
-            a, boxes, mixed, work, (int)tsz, twr);
+        const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
+        k_elim_rows<256><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
+                                                                           (int)tsz, twr);
         const size_t base = tsz + 4 * nm;
         const bool xl = D * (base + nm * nm) <= lim;
         const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
@@ -813,16 +831,17 @@ int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double*
             set_lds(k_elim_inv<false, 1024>, li);
             k_elim_inv<false, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         }
-        const dim3 gg((unsigned)((L.ldJ + twg - 1) / twg), nboxes);
+        const int ntg = (L.ldJ + twg - 1) / twg;
+        const dim3 gg(xcd_grid(ntg, nboxes));
         if (L.nmax <= 64) {
             set_lds(k_elim_g<256, 1>, lg);
-            k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
+            k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
         } else if (L.nmax <= 128) {
             set_lds(k_elim_g<256, 2>, lg);
-            k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
+            k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
         } else {
             set_lds(k_elim_g<256, 4>, lg);
-            k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, mixed, flag, (int)tsz, twg);
+            k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
         }
         return 3;
     }
