@@ -108,18 +108,26 @@ void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double 
 // ------------------------------------------------------------------------------------
 // Leaf store: A(B_a, B_b) = diag on coincident DOFs, w K(x_i - x_j) otherwise.
 // One block per (box a, neighbour slot).  flag |= 2 on duplicate points.
+// The kernel is symmetric (K(x - y) = K(y - x), exactly in floating point since the
+// differences only change sign), so A(B_b, B_a) = A(B_a, B_b)^T: one workgroup per box a
+// and per offset of the self block or the 12 offsets (dx, dy) with dy > 0 or (dy = 0,
+// dx > 0).  Each 64 x 64 tile is evaluated once into LDS and written to both blocks,
+// coalesced in both orientations.
 __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, const int* __restrict__ cnt,
                                                     const int* __restrict__ gidx, const double* __restrict__ pts,
                                                     int nb, int nmax, double coef, double diag, int* flag) {
     __shared__ double xa[kMaxBox], ya[kMaxBox], xb[kMaxBox], yb[kMaxBox];
     __shared__ int ga[kMaxBox], gb[kMaxBox];
-    int a = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
-    int dx = o % 5 - 2, dy = o / 5 - 2;
-    int ax = a % nb, ay = a / nb;
-    int bx = ax + dx, by = ay + dy;
+    __shared__ double tile[64][65];
+    const int a = blockIdx.x / 13, oi = blockIdx.x % 13;
+    // oi = 0: self; oi = 1..12: the offsets after (0, 0) in row-major order of the 5x5 window
+    const int o = 12 + oi;
+    const int dx = o % 5 - 2, dy = o / 5 - 2;
+    const int ax = a % nb, ay = a / nb;
+    const int bx = ax + dx, by = ay + dy;
     if (bx < 0 || by < 0 || bx >= nb || by >= nb) return;
-    int b = bx + nb * by;
-    int na = cnt[a], nbb = cnt[b];
+    const int b = bx + nb * by;
+    const int na = cnt[a], nbb = cnt[b];
     for (int i = threadIdx.x; i < na; i += blockDim.x) {
         int g = gidx[(int64_t)a * nmax + i];
         ga[i] = g; xa[i] = pts[2 * (int64_t)g]; ya[i] = pts[2 * (int64_t)g + 1];
@@ -129,26 +137,44 @@ __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, 
         gb[i] = g; xb[i] = pts[2 * (int64_t)g]; yb[i] = pts[2 * (int64_t)g + 1];
     }
     __syncthreads();
-    double* blk = store + ((int64_t)a * kNbr + o) * nmax * nmax;
-    int tot = na * nbb;
+    double* blk_ab = store + ((int64_t)a * kNbr + o) * nmax * nmax;                  // A(B_a, B_b)
+    double* blk_ba = store + ((int64_t)b * kNbr + (24 - o)) * nmax * nmax;           // A(B_b, B_a)
+    const bool self = oi == 0;
     bool dup = false;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        int i = e % na, j = e / na;
-        double v;
-        if (ga[i] == gb[j]) {
-            v = diag;
-        } else {
-            v = kernel_entry(xa[i], ya[i], xb[j], yb[j], coef);
-            dup |= (xa[i] == xb[j] && ya[i] == yb[j]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i0 = 0; i0 < na; i0 += 64)
+        for (int j0 = 0; j0 < nbb; j0 += 64) {
+            const int ti = min(64, na - i0), tj = min(64, nbb - j0);
+            // rows i0 + lane, columns j0 + wv + 4 t
+            for (int jj = wv; jj < tj; jj += 4) {
+                const int j = j0 + jj;
+                double v = 0.0;
+                if (lane < ti) {
+                    const int i = i0 + lane;
+                    if (ga[i] == gb[j]) {
+                        v = diag;
+                    } else {
+                        v = kernel_entry(xa[i], ya[i], xb[j], yb[j], coef);
+                        dup |= (xa[i] == xb[j] && ya[i] == yb[j]);
+                    }
+                    blk_ab[i + (int64_t)j * nmax] = v;
+                }
+                tile[jj][lane] = v;
+            }
+            if (!self) {
+                __syncthreads();
+                // A(B_b, B_a)(j, i) = A(B_a, B_b)(i, j): rows j0 + lane, columns i0 + wv + 4 t
+                for (int ii = wv; ii < ti; ii += 4)
+                    if (lane < tj) blk_ba[(j0 + lane) + (int64_t)(i0 + ii) * nmax] = tile[lane][ii];
+                __syncthreads();
+            }
         }
-        blk[i + (int64_t)j * nmax] = v;
-    }
     if (dup) atomicOr(flag, 2);
 }
 
 void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag, hipStream_t s) {
-    k_leaf_store<<<dim3(L.nbox * kNbr), dim3(256), 0, s>>>(L.store, L.cnt, L.gidx, pts, L.nb, L.nmax, kp.coef,
-                                                            kp.diag, flag);
+    k_leaf_store<<<dim3(L.nbox * 13), dim3(256), 0, s>>>(L.store, L.cnt, L.gidx, pts, L.nb, L.nmax, kp.coef,
+                                                          kp.diag, flag);
 }
 
 // ------------------------------------------------------------------------------------
