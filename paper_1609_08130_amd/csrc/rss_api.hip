@@ -153,6 +153,50 @@ T* h2d(rss_factor f, const std::vector<T>& h, hipStream_t s) {
     return d;
 }
 
+// Several box lists in one device allocation and one copy; returns a pointer per list.
+std::vector<int*> h2d_lists(rss_factor f, const std::vector<std::vector<int>>& lists, hipStream_t s) {
+    std::vector<int> all;
+    std::vector<size_t> off;
+    for (auto& v : lists) {
+        off.push_back(all.size());
+        all.insert(all.end(), v.begin(), v.end());
+    }
+    int* d = dalloc<int>(f, std::max<size_t>(all.size(), 1));
+    if (!all.empty()) HIPCHK(hipMemcpyAsync(d, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    std::vector<int*> ptrs;
+    for (size_t o : off) ptrs.push_back(d + o);
+    return ptrs;
+}
+
+// Several device int arrays copied through pinned host memory with one synchronization.
+std::vector<std::vector<int>> d2h_many(rss_factor f, const std::vector<std::pair<const int*, size_t>>& src,
+                                       hipStream_t s) {
+    size_t tot = 0;
+    for (auto& p : src) tot += p.second;
+    const size_t bytes = std::max<size_t>(tot, 1) * sizeof(int);
+    if (bytes > f->hpin_bytes) {
+        if (f->hpin) (void)hipHostFree(f->hpin);
+        f->hpin = nullptr;
+        f->hpin_bytes = 0;
+        HIPCHK(hipHostMalloc(&f->hpin, bytes));
+        f->hpin_bytes = bytes;
+    }
+    int* h = (int*)f->hpin;
+    size_t o = 0;
+    for (auto& p : src) {
+        if (p.second) HIPCHK(hipMemcpyAsync(h + o, p.first, p.second * sizeof(int), hipMemcpyDeviceToHost, s));
+        o += p.second;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<std::vector<int>> out;
+    o = 0;
+    for (auto& p : src) {
+        out.emplace_back(h + o, h + o + p.second);
+        o += p.second;
+    }
+    return out;
+}
+
 int colour_of(int b, int nb) { return (b % nb) % 3 + 3 * ((b / nb) % 3); }
 
 __global__ void k_init_active(const int* cnt, int* nact, int* apos, int nbox, int nmax) {
@@ -232,6 +276,9 @@ void destroy_all(rss_factor f) {
     (void)hipDeviceSynchronize();
     for (void* p : f->allocs) release_block(p);
     f->allocs.clear();
+    if (f->hpin) (void)hipHostFree(f->hpin);
+    f->hpin = nullptr;
+    f->hpin_bytes = 0;
 }
 
 // phase indices of rss_factor_s::phase_ms
@@ -341,7 +388,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (int b = 0; b < L.nbox; ++b) L.colour_boxes[colour_of(b, nb)].push_back(b);
         size_t maxc = 0;
         for (auto& v : L.colour_boxes) maxc = std::max(maxc, v.size());
-        for (auto& v : L.colour_boxes) L.d_colour_boxes.push_back(h2d(f, v, s));
+        L.d_colour_boxes = h2d_lists(f, L.colour_boxes, s);
         alloc_level_records(f, L, mixed);
         size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc));
         if (need > work_n) {
@@ -369,7 +416,9 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             f->kernel_launches[PH_ELIM] += ne;
             f->kernel_launches[PH_SCHUR] += 1;
         }
-        HIPCHK(hipStreamSynchronize(s));
+        // flag, statistics and solve schedule: one synchronization
+        const size_t nbx = (size_t)L.nbox;
+        auto hv = d2h_many(f, {{f->flag, 1}, {L.cnt, nbx}, {L.krank, nbx}, {L.nJ, nbx}, {L.mrows, nbx}}, s);
         double lv_id = 0, lv_elim = 0, lv_schur = 0;
         for (size_t i = 1; i < ev.size(); i += 3) {
             lv_id += ev_ms(ev[i - 1], ev[i]);
@@ -379,20 +428,16 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         f->phase_ms[PH_ID] += lv_id;
         f->phase_ms[PH_ELIM] += lv_elim;
         f->phase_ms[PH_SCHUR] += lv_schur;
-        int flag = 0;
-        HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
-        if (flag & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
-
-        // statistics and solve schedule
-        L.h_cnt = d2h(L.cnt, L.nbox, s);
-        L.h_k = d2h(L.krank, L.nbox, s);
-        std::vector<int> hJ = d2h(L.nJ, L.nbox, s);
-        std::vector<int> hm = d2h(L.mrows, L.nbox, s);
+        if (hv[0][0] & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
+        L.h_cnt = std::move(hv[1]);
+        L.h_k = std::move(hv[2]);
+        std::vector<int> hJ = std::move(hv[3]);
+        std::vector<int> hm = std::move(hv[4]);
         L.rec_boxes.assign(9, {});
         for (int col = 0; col < 9; ++col)
             for (int b : L.colour_boxes[col])
                 if (hJ[b] > 0) L.rec_boxes[col].push_back(b);
-        for (auto& v : L.rec_boxes) L.d_rec_boxes.push_back(h2d(f, v, s));
+        L.d_rec_boxes = h2d_lists(f, L.rec_boxes, s);
         rss::LevelStats st;
         st.depth = L.t; st.boxes = L.nbox; st.nmax = L.nmax;
         st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur;

@@ -117,6 +117,8 @@ struct rss_factor_s {
     size_t work_elems = 0;
     int* flag = nullptr;            // device error flags
     std::vector<void*> allocs;
+    void* hpin = nullptr;          // pinned host staging for small device-to-host copies
+    size_t hpin_bytes = 0;
     std::vector<rss::LevelStats> stats;
     std::vector<double> phase_ms;   // tree, leaf store, id, elim, schur, transition, top, total
     std::vector<int> kernel_launches;
