@@ -14,12 +14,10 @@
 // Schur kernel.  J lists S first, then the active DOFs of the adjacent boxes in
 // ascending box index.
 //
-// Two launch shapes compute the same values in the same order:
-//  - fused (many boxes in the colour): one workgroup per box does everything;
-//  - split (few boxes, the upper levels): k_elim_rows forms X_JR and
-//    Y_RR = A_RR - A_RS T tile by tile over many workgroups per box, k_elim_inv forms
-//    X_RR = Y_RR - T^T Z_S and its inverse (one workgroup per box), and k_elim_g forms G
-//    tile by tile over many workgroups per box.
+// Three launches per colour: k_elim_rows forms X_JR and Y_RR = A_RR - A_RS T tile by
+// tile over many workgroups per box, k_elim_inv forms X_RR = Y_RR - T^T Z_S and its
+// inverse (one workgroup per box), and k_elim_g forms G tile by tile over many
+// workgroups per box.
 #include "rss_internal.h"
 
 namespace rss {
@@ -65,6 +63,25 @@ __device__ inline bool xcd_tile(int ntile, int nbox, int& bi, int& tile) {
 }
 
 static inline unsigned xcd_grid(int ntile, int nbox) { return (unsigned)(8 * ntile * ((nbox + 7) / 8)); }
+
+// dst(e) = src(e) for e < total, NTH threads, each issuing U loads before the first
+// store so that U global loads per thread are in flight at a time.
+template <int NTH, int U = 8, typename Load, typename Store>
+__device__ inline void stage_batched(int total, Load load, Store store) {
+    for (int e0 = threadIdx.x; e0 < total; e0 += NTH * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NTH;
+            v[u] = e < total ? load(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NTH;
+            if (e < total) store(e, v[u]);
+        }
+    }
+}
 
 // Per-workgroup tables of box c in LDS.
 struct ElimShared {
@@ -158,11 +175,14 @@ __device__ void elim_rows_tile(ElimShared& sh, const ElimArgs& a, int c, int k, 
     }
     __syncthreads();
     // tA[i + tw col]: line i of the tile at B position (col < k ? sp[col] : rp[col - k])
-    for (int e = tid; e < tr * n; e += NTH) {
-        int i = e % tr, col = e / tr;
-        int pos = col < k ? sh.sp[col] : sh.rp[col - k];
-        tA[i + tw * col] = sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
-    }
+    stage_batched<NTH>(
+        tr * n,
+        [&](int e) {
+            const int i = e % tr, col = e / tr;
+            const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
+            return sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
+        },
+        [&](int e, double v) { tA[(e % tr) + tw * (e / tr)] = v; });
     __syncthreads();
     const int i = tid & 31, bg = tid >> 5;
     if (i < tr) {
@@ -225,10 +245,9 @@ __device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int
     }
     __syncthreads();
     // tA[pos + nmax jp] = A(B_c position pos, J column c0 + jp)
-    for (int e = tid; e < tc * n; e += NTH) {
-        int pos = e % n, jp = e / n;
-        tA[pos + nmax * jp] = sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax];
-    }
+    stage_batched<NTH>(
+        tc * n, [&](int e) { const int pos = e % n, jp = e / n; return sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax]; },
+        [&](int e, double v) { tA[(e % n) + nmax * (e / n)] = v; });
     __syncthreads();
     // X_RJ[b][jp] = A(rp[b], jp) - sum_q T[q][b] A(sp[q], jp), q ascending
     for (int b = lane; b < r; b += 64) {
@@ -257,10 +276,9 @@ __device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int
         const int qn = min(qc, r - q0);
         const double* W = Xi + (int64_t)q0 * nmax;
         if (!xi_lds) {
-            for (int e = tid; e < r * qn; e += NTH) {
-                int b = e % r, qq = e / r;
-                tA[b + nmax * qq] = W[b + (int64_t)qq * nmax];
-            }
+            stage_batched<NTH>(
+                r * qn, [&](int e) { return W[(e % r) + (int64_t)(e / r) * nmax]; },
+                [&](int e, double v) { tA[(e % r) + nmax * (e / r)] = v; });
             __syncthreads();
             W = tA;
         }
@@ -613,57 +631,7 @@ __device__ bool elim_xrr_inverse(ElimShared& sh, const ElimArgs& a, int c, int k
     return true;
 }
 
-// Dynamic LDS: Ts[tsz] | Xs[nmax^2] (when XLDS) | tA[nmax tw] | tX[nmax tw]
-template <bool XLDS, int NTH>
-__global__ void __launch_bounds__(NTH) k_elim(ElimArgs a, const int* __restrict__ boxes, int mixed,
-                                              double* __restrict__ work, int* flag, int tsz, int tw) {
-    extern __shared__ double dyn[];
-    __shared__ ElimShared sh;
-    __shared__ int colswap[kMaxBox];
-    __shared__ int piv_idx;
-    __shared__ double piv_val;
-    const int tid = threadIdx.x;
-    const int c = boxes[blockIdx.x];
-    const int n = a.cnt[c];
-    const int k = a.krank[c];
-    const int r = n - k;
-    if (n == 0 || r == 0) {
-        if (tid == 0) a.nJ[c] = 0;
-        return;
-    }
-    const int nmax = a.nmax, ldJ = a.ldJ;
-    const int64_t bsz = (int64_t)nmax * nmax;
-    double* Ts = dyn;
-    double* Xs = XLDS ? dyn + tsz : work + (int64_t)blockIdx.x * bsz;
-    double* tA = dyn + tsz + (XLDS ? bsz : 0);
-    double* tX = tA + (int64_t)nmax * tw;
-    elim_setup<NTH>(sh, a, c, k, r, Ts);
-    __syncthreads();
-    const int nj = sh.joff[sh.nN];
-    for (int jj = tid; jj < nj; jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
-    double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
-    float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
-    for (int r0 = 0; r0 < nj; r0 += tw)
-        elim_rows_tile<NTH>(sh, a, c, k, r, nj, r0, min(tw, nj - r0), tw, Ts, tA, XJR, XJR32, nullptr);
-    // the tile buffers (2 nmax tw >= 4 nmax doubles) are free here: Z_S when it fits, then
-    // the inversion's scratch
-    double* xsr = (k * r <= 2 * nmax * tw) ? tA : nullptr;
-    if (!elim_xrr_inverse<NTH>(sh, a, c, k, r, nj, Ts, nullptr, Xs, xsr, mixed, colswap, tA, piv_idx, piv_val)) {
-        if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
-        return;
-    }
-    double* G = a.G + (int64_t)c * nmax * ldJ;
-    float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
-    for (int c0 = 0; c0 < nj; c0 += tw)
-        elim_g_tile<NTH, kMaxBox / 64>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, Xs, XLDS, G, G32);
-    if (tid == 0) {
-        a.nJ[c] = nj;
-        a.nact[c] = k;
-    }
-    for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
-}
-
-// ---- split path ---------------------------------------------------------------------------
+// ---- the three launches of a colour ------------------------------------------------------
 // grid (row tiles of [J; R], boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw]
 template <int NTH>
 __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
@@ -762,9 +730,6 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
                          G32);
 }
 
-// Colours with fewer boxes than this take the split path.
-constexpr int kElimSplitBelow = 1 << 30;
-
 static int g_max_lds = -1;
 
 int elim_lds_limit() {
@@ -803,73 +768,46 @@ int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double*
             if (D * (fixed + bufs * nm * tw) <= lim) return tw;
         return 0;
     };
-    if (nboxes < kElimSplitBelow) {
-        const int twr = tile_w(tsz, 1), twg = tile_w(tsz, 2);
-        if (twr == 0 || twg == 0) return -1;
-        const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
-        set_lds(k_elim_rows<256>, lr);
-        const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
-        k_elim_rows<256><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
-                                                                           (int)tsz, twr);
-        const size_t base = tsz + 4 * nm;
-        const bool xl = D * (base + nm * nm) <= lim;
-        const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
-        const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
-        // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
-        if (nboxes >= 256) {
-            if (xl) {
-                set_lds(k_elim_inv<true, 256>, li);
-                k_elim_inv<true, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
-            } else {
-                set_lds(k_elim_inv<false, 256>, li);
-                k_elim_inv<false, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
-            }
-        } else if (xl) {
-            set_lds(k_elim_inv<true, 1024>, li);
-            k_elim_inv<true, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+    const int twr = tile_w(tsz, 1), twg = tile_w(tsz, 2);
+    if (twr == 0 || twg == 0) return -1;
+    const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
+    set_lds(k_elim_rows<256>, lr);
+    const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
+    k_elim_rows<256><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
+                                                                       (int)tsz, twr);
+    const size_t base = tsz + 4 * nm;
+    const bool xl = D * (base + nm * nm) <= lim;
+    const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
+    const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
+    // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
+    if (nboxes >= 256) {
+        if (xl) {
+            set_lds(k_elim_inv<true, 256>, li);
+            k_elim_inv<true, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         } else {
-            set_lds(k_elim_inv<false, 1024>, li);
-            k_elim_inv<false, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+            set_lds(k_elim_inv<false, 256>, li);
+            k_elim_inv<false, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         }
-        const int ntg = (L.ldJ + twg - 1) / twg;
-        const dim3 gg(xcd_grid(ntg, nboxes));
-        if (L.nmax <= 64) {
-            set_lds(k_elim_g<256, 1>, lg);
-            k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
-        } else if (L.nmax <= 128) {
-            set_lds(k_elim_g<256, 2>, lg);
-            k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
-        } else {
-            set_lds(k_elim_g<256, 4>, lg);
-            k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
-        }
-        return 3;
-    }
-    // a large workgroup per box while the colour has fewer boxes than the chip has CUs x 2
-    const bool big = nboxes < 512;
-    const int twx = tile_w(tsz + nm * nm, 2);
-    if (twx > 0) {
-        const size_t l = D * (tsz + nm * nm + 2 * nm * twx);
-        if (big) {
-            set_lds(k_elim<true, 1024>, l);
-            k_elim<true, 1024><<<dim3(nboxes), dim3(1024), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, twx);
-        } else {
-            set_lds(k_elim<true, 256>, l);
-            k_elim<true, 256><<<dim3(nboxes), dim3(256), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, twx);
-        }
-        return 1;
-    }
-    const int tw = tile_w(tsz, 2);
-    if (tw == 0) return -1;
-    const size_t l = D * (tsz + 2 * nm * tw);
-    if (big) {
-        set_lds(k_elim<false, 1024>, l);
-        k_elim<false, 1024><<<dim3(nboxes), dim3(1024), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, tw);
+    } else if (xl) {
+        set_lds(k_elim_inv<true, 1024>, li);
+        k_elim_inv<true, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
     } else {
-        set_lds(k_elim<false, 256>, l);
-        k_elim<false, 256><<<dim3(nboxes), dim3(256), l, s>>>(a, boxes, mixed, work, flag, (int)tsz, tw);
+        set_lds(k_elim_inv<false, 1024>, li);
+        k_elim_inv<false, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
     }
-    return 1;
+    const int ntg = (L.ldJ + twg - 1) / twg;
+    const dim3 gg(xcd_grid(ntg, nboxes));
+    if (L.nmax <= 64) {
+        set_lds(k_elim_g<256, 1>, lg);
+        k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+    } else if (L.nmax <= 128) {
+        set_lds(k_elim_g<256, 2>, lg);
+        k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+    } else {
+        set_lds(k_elim_g<256, 4>, lg);
+        k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+    }
+    return 3;
 }
 
 }  // namespace rss

@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
     __shared__ ORing oring;
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
     __shared__ double colx[kMaxBox], coly[kMaxBox];
+    __shared__ const double* rowsrc[kChunk];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.y];
     const int sl = blockIdx.x % nslice;
@@ -237,24 +238,49 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
     for (int r0 = r_begin; r0 < r_end; r0 += kChunk) {
         const int rows = min(kChunk, r_end - r0);
         __syncthreads();
-        for (int idx = tid; idx < kChunk * ld; idx += NTH) {
-            int i = idx % kChunk, q = idx / kChunk;
-            double v = 0.0;
-            if (i < rows && q < n) {
-                int row = r0 + i;
-                if (row < mO) {
-                    int o = 0;
-                    while (oring.beg[o + 1] <= row) ++o;
-                    v = oring.base[o][oring.ap[o][row - oring.beg[o]] + (int64_t)q * nmax];
-                } else {
-#pragma clang fp contract(off)
-                    int pp = row - mO;
-                    double dx = pxs[pp] - colx[q];
-                    double dy = pys[pp] - coly[q];
-                    v = kp.coef * log(dx * dx + dy * dy);
-                }
+        // source row of each chunk line (one lookup per line), then the chunk with GU
+        // loads in flight per thread
+        constexpr int GU = 4;
+        if (tid < kChunk) {
+            const double* src = nullptr;
+            const int row = r0 + tid;
+            if (tid < rows && row < mO) {
+                int o = 0;
+                while (oring.beg[o + 1] <= row) ++o;
+                src = oring.base[o] + oring.ap[o][row - oring.beg[o]];
             }
-            Ms[i * ld + q] = v;
+            rowsrc[tid] = src;
+        }
+        __syncthreads();
+        for (int idx0 = tid; idx0 < kChunk * ld; idx0 += NTH * GU) {
+            double v[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int idx = idx0 + u * NTH;
+                const int i = idx & (kChunk - 1), q = idx / kChunk;
+                const double* src = rowsrc[i];
+                v[u] = (idx < kChunk * ld && i < rows && q < n && src) ? src[(int64_t)q * nmax] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int idx = idx0 + u * NTH;
+                const int i = idx & (kChunk - 1), q = idx / kChunk;
+                // proxy entries are written by the loop below, not here
+                const bool proxy = i < rows && q < n && !rowsrc[i];
+                if (idx < kChunk * ld && !proxy) Ms[i * ld + q] = v[u];
+            }
+        }
+        // proxy rows (the last rows of M) from the kernel
+        if (r0 + rows > mO) {
+            const int i0 = max(0, mO - r0);
+            for (int idx = tid; idx < (rows - i0) * n; idx += NTH) {
+#pragma clang fp contract(off)
+                const int i = i0 + idx % (rows - i0), q = idx / (rows - i0);
+                const int pp = r0 + i - mO;
+                const double dx = pxs[pp] - colx[q];
+                const double dy = pys[pp] - coly[q];
+                Ms[i * ld + q] = kp.coef * log(dx * dx + dy * dy);
+            }
         }
         __syncthreads();
         for (int i = 0; i < rows; ++i) {

@@ -101,15 +101,24 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     const int row0 = ti * TM, col0 = tj * TM;
     for (int k0 = 0; k0 < r; k0 += TK) {
         __syncthreads();
-        for (int e = tid; e < TM * TK; e += 256) {
-            int i = e % TM, kk = e / TM;
-            int row = row0 + i, kc = k0 + kk;
-            As[kk][i] = (row < nj && kc < r) ? XJR[row + (int64_t)kc * ldJ] : (TT)0;
+        // all loads of the slab are issued before the first store to LDS
+        constexpr int PER = TM * TK / 256;
+        TT va[PER], vb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            const int i = e % TM, kk = e / TM;
+            const int row = row0 + i, kc = k0 + kk;
+            va[u] = (row < nj && kc < r) ? XJR[row + (int64_t)kc * ldJ] : (TT)0;
+            const int kb = e % TK, j = e / TK;
+            const int col = col0 + j, kc2 = k0 + kb;
+            vb[u] = (col < nj && kc2 < r) ? G[kc2 + (int64_t)col * nmax] : (TT)0;
         }
-        for (int e = tid; e < TM * TK; e += 256) {
-            int kk = e % TK, j = e / TK;
-            int col = col0 + j, kc = k0 + kk;
-            Bs[kk][j] = (col < nj && kc < r) ? G[kc + (int64_t)col * nmax] : (TT)0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            As[e / TM][e % TM] = va[u];
+            Bs[e % TK][e / TK] = vb[u];
         }
         __syncthreads();
 #pragma unroll
