@@ -115,10 +115,9 @@ __device__ void elim_setup(ElimShared& sh, const ElimArgs& a, int c, int k, int 
         sh.srcpos[tid] = in ? a.nact[ox + nb * oy] : 0;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
-    for (int e = tid; e < k * r; e += NTH) {
-        int q = e % k, b = e / k;
-        Ts[b + r * q] = Tg[q + (int64_t)b * nmax];
-    }
+    stage_batched<NTH>(
+        k * r, [&](int e) { return Tg[(e % k) + (int64_t)(e / k) * nmax]; },
+        [&](int e, double v) { Ts[(e / k) + r * (e % k)] = v; });
     __syncthreads();
     if (tid == 0) {
         int cntN = 0;
