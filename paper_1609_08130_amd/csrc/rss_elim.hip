@@ -495,35 +495,48 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
             fv[h] = (i == j || i >= r) ? 0.0 : cb[i == p ? j : i];   // column j after the interchange
         }
         const int jl = j & 63, jh = j >> 6, pl = p & 63, ph = p >> 6;
-        bool isj[RB], isp[RB];
+        // old rows j and p of this wave's columns, from the lanes that hold them (the slots
+        // jh, ph are wave-uniform)
+        double rj[CB], rp[CB], xj[CB];
 #pragma unroll
         for (int h = 0; h < RB; ++h) {
-            isj[h] = lane + 64 * h == j;
-            isp[h] = lane + 64 * h == p;
+            if (h == jh) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) rj[c] = lane_read(x[h][c], jl);
+            }
+            if (h == ph) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) rp[c] = lane_read(x[h][c], pl);
+            }
         }
-        // rows and columns >= r hold values that are never read back, so they are updated
-        // without bounds tests; rows j and p come from the lanes that hold them
+        // rank-one update of every element (rows and columns >= r hold values that are
+        // never read back, so no bounds tests), then the rows p and j and the column j,
+        // whose new values follow other rules, are overwritten
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int l = wv + NW * c;
-            double rj = 0.0, rp = 0.0;   // old rows j and p of column l
+            xj[c] = rp[c] * rinv;   // new pivot row
 #pragma unroll
-            for (int h = 0; h < RB; ++h) {
-                if (h == jh) rj = lane_read(x[h][c], jl);
-                if (h == ph) rp = lane_read(x[h][c], pl);
+            for (int h = 0; h < RB; ++h) x[h][c] -= fv[h] * xj[c];
+        }
+#pragma unroll
+        for (int h = 0; h < RB; ++h)
+            if (h == ph && lane == pl) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) x[h][c] = rj[c] - fv[h] * xj[c];   // old row j moves to row p
             }
-            if (l == j) {
-                const double xjl = rinv;
 #pragma unroll
-                for (int h = 0; h < RB; ++h) x[h][c] = isj[h] ? xjl : -fv[h] * xjl;
-            } else {
-                const double xjl = rp * rinv;
+        for (int h = 0; h < RB; ++h)
+            if (h == jh && lane == jl) {
 #pragma unroll
-                for (int h = 0; h < RB; ++h) {
-                    const double v = (isp[h] ? rj : x[h][c]) - fv[h] * xjl;
-                    x[h][c] = isj[h] ? xjl : v;
+                for (int c = 0; c < CB; ++c) x[h][c] = xj[c];
+            }
+        if (wv == j % NW) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c == cj) {
+#pragma unroll
+                    for (int h = 0; h < RB; ++h) x[h][c] = (lane + 64 * h == j) ? rinv : -fv[h] * rinv;
                 }
-            }
         }
     }
     // undo the row interchanges on the columns: final position of each column
