@@ -373,10 +373,34 @@ __device__ inline dd gram_entry(const double2* G, int nsl, int nmax, int64_t sst
     return acc;
 }
 
-// One workgroup per box, thread q owns column q.  Rows j < kc of R live in LDS (hi and lo
-// parts apart), later rows in the workspace.  nsl_fixed > 0: the slices are already summed
-// into slice 0 (nsl_fixed = 1); otherwise every entry is summed over the box's slices here.
-template <int NTH>
+// Sum of v over the SUB adjacent lanes of a column group, identical on all of them
+// (double-double addition is commutative bit for bit, so both orders agree).
+template <int SUB>
+__device__ inline dd group_sum_dd(dd v) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int o = 1; o < SUB; o <<= 1) {
+        const dd w = {__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)};
+        v = dd_add(v, w);
+    }
+    return v;
+}
+
+template <int SUB>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < SUB; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One workgroup per box; the SUB adjacent threads 4 q .. 4 q + SUB - 1 own column q and
+// split its dot products (every one of them then holds the same values).  Rows j < kc of
+// R live in LDS (hi and lo parts apart), later rows in the workspace; every thread of a
+// column writes the same value to the same entry, so each reads back only what it wrote
+// itself or what other columns wrote before a barrier.  nsl_fixed > 0: the slices are
+// already summed into slice 0 (nsl_fixed = 1); otherwise every entry is summed over the
+// box's slices here.
+template <int NTH, int SUB>
 __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, const int* __restrict__ nact,
                                                const int* __restrict__ boxes, int nb, int nmax, KernelParams kp,
                                                const double* __restrict__ gpart, int nslice, int slice_rows,
@@ -393,12 +417,13 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
     __shared__ double redv[2][NW];
     __shared__ int redi[2][NW];
     __shared__ unsigned long long smask[NW];
-    const int q = threadIdx.x;
-    const int wv = q >> 6, lane = q & 63;
+    const int tid = threadIdx.x;
+    const int q = tid / SUB, sub = tid % SUB;
+    const int wv = tid >> 6, lane = tid & 63;
     const int c = boxes[blockIdx.x];
     const int n = cnt[c];
     if (n == 0) {
-        if (q == 0) { krank[c] = 0; mrows[c] = 0; }
+        if (tid == 0) { krank[c] = 0; mrows[c] = 0; }
         return;
     }
     const int m = id_rows(nact, c, nb, kp.n_proxy);
@@ -435,7 +460,7 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
     for (int j = 0; j < kmax; ++j) {
         const int buf = j & 1;
         const double nu = done ? -1.0 : d.hi + d.lo;
-        if (q < n) { dh[buf][q] = d.hi; dl[buf][q] = d.lo; }
+        if (q < n && sub == 0) { dh[buf][q] = d.hi; dl[buf][q] = d.lo; }
         double wmax = wave_max_d(nu);
         if (lane == 0) redv[buf][wv] = wmax;
         __syncthreads();
@@ -462,25 +487,24 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
         // every thread forms r_jj itself (no extra barrier)
         const dd rjj = dd_sqrt({dh[buf][p], dl[buf][p]});
         if (q == p) {
-            piv[j] = p;
+            if (sub == 0) piv[j] = p;
             rput(j, p, rjj);
             done = true;
         }
         if (!done) {
-            // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2.  The sum runs in four
-            // partial sums while the load of G_pq is in flight.
+            // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2.  Thread sub of the
+            // column takes i = sub, sub + SUB, ... in two partial sums while the load of G_pq
+            // is in flight.
             const dd gpq = gram_entry(G, nsl, nmax, sstride, p, q);
-            dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0}, s2 = {0.0, 0.0}, s3 = {0.0, 0.0};
-            int i = 0;
-            for (; i + 3 < j; i += 4) {
+            dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+            int i = sub;
+            for (; i + SUB < j; i += 2 * SUB) {
                 s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
-                s1 = dd_add(s1, dd_mul(rget(i + 1, p), rget(i + 1, q)));
-                s2 = dd_add(s2, dd_mul(rget(i + 2, p), rget(i + 2, q)));
-                s3 = dd_add(s3, dd_mul(rget(i + 3, p), rget(i + 3, q)));
+                s1 = dd_add(s1, dd_mul(rget(i + SUB, p), rget(i + SUB, q)));
             }
-            for (; i < j; ++i) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
-            const dd acc = dd_sub(gpq, dd_add(dd_add(s0, s1), dd_add(s2, s3)));
-            const dd rjq = dd_div(acc, rjj);
+            if (i < j) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+            const dd sum = group_sum_dd<SUB>(dd_add(s0, s1));
+            const dd rjq = dd_div(dd_sub(gpq, sum), rjj);
             rput(j, q, rjq);
             d = dd_sub(d, dd_mul(rjq, rjq));
         }
@@ -490,30 +514,32 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
     // ---- sorted sets and T = R11^{-1} R12 (FP64 back substitution) ----------------------
     __syncthreads();
     const bool isS = (q < n) && done;
-    const unsigned long long mask = __ballot(isS);
+    const unsigned long long mask = __ballot(isS && sub == 0);
     if (lane == 0) smask[wv] = mask;
     __syncthreads();
     int below = 0;
     for (int w = 0; w < wv; ++w) below += __popcll(smask[w]);
     const int srank = below + __popcll(mask & ((1ull << lane) - 1ull));
-    if (isS) srank_s[q] = srank;
+    if (isS && sub == 0) srank_s[q] = srank;
     __syncthreads();
-    if (q == 0) { krank[c] = k; mrows[c] = m; }
+    if (tid == 0) { krank[c] = k; mrows[c] = m; }
     const int64_t boff = (int64_t)c * nmax;
     double* Tb = Tout + (int64_t)c * nmax * nmax;
     if (q < n) {
         if (isS) {
-            spos[boff + srank] = q;
+            if (sub == 0) spos[boff + srank] = q;
         } else {
             const int rr = q - srank;
-            rpos[boff + rr] = q;
-            // in place in column q of R: R[a][q] <- t_a, last row first
+            if (sub == 0) rpos[boff + rr] = q;
+            // in place in column q of R: R[a][q] <- t_a, last row first; the sum over b is
+            // split over the column's threads
             for (int a = k - 1; a >= 0; --a) {
-                double acc = rhi(a, q);
-                for (int b = a + 1; b < k; ++b) acc -= rhi(a, piv[b]) * rhi(b, q);
+                double part = 0.0;
+                for (int b = a + 1 + sub; b < k; b += SUB) part += rhi(a, piv[b]) * rhi(b, q);
+                const double acc = rhi(a, q) - group_sum<SUB>(part);
                 rset_hi(a, q, acc / rhi(a, piv[a]));
             }
-            for (int a = 0; a < k; ++a) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = rhi(a, q);
+            for (int a = sub; a < k; a += SUB) Tb[srank_s[piv[a]] + (int64_t)rr * nmax] = rhi(a, q);
         }
     }
 }
@@ -525,15 +551,15 @@ static void gram_launch(const Level& L, const int* boxes, int nboxes, const doub
         L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart, g.nsl, g.slice_rows);
 }
 
-template <int NTH>
+template <int NTH, int SUB>
 static void pchol_launch(const Level& L, const int* boxes, int nboxes, const KernelParams& kp, double* gpart,
                          const GramPlan& g, int nsl_fixed, double* rwork, hipStream_t s) {
     // many boxes: occupancy hides the workspace latency better than LDS rows would
     const int kc = nboxes >= 512 ? 0 : pchol_lds_rows(L.nmax);
     const size_t lds = sizeof(double) * 2 * (size_t)kc * L.nmax;
-    k_pchol<NTH><<<dim3(nboxes), dim3(NTH), lds, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, g.nsl,
-                                                     g.slice_rows, nsl_fixed, rwork, kc, L.krank, L.spos, L.rpos,
-                                                     L.T, L.mrows);
+    k_pchol<NTH, SUB><<<dim3(nboxes), dim3(NTH), lds, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, g.nsl,
+                                                          g.slice_rows, nsl_fixed, rwork, kc, L.krank, L.spos,
+                                                          L.rpos, L.T, L.mrows);
 }
 
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
@@ -556,9 +582,16 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
         nsl_fixed = 1;
         ++launches;
     }
-    if (L.nmax <= 64) pchol_launch<64>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
-    else if (L.nmax <= 128) pchol_launch<128>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
-    else pchol_launch<256>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    // many boxes: one thread per column; few boxes: four threads per column
+    if (nboxes >= 512) {
+        if (L.nmax <= 64) pchol_launch<64, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+        else if (L.nmax <= 128) pchol_launch<128, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+        else pchol_launch<256, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    } else {
+        if (L.nmax <= 64) pchol_launch<256, 4>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+        else if (L.nmax <= 128) pchol_launch<512, 4>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+        else pchol_launch<1024, 4>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
+    }
     return launches;
 }
 
