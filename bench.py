@@ -42,11 +42,11 @@ FP32_PEAK_TFS = 157.3       # MI355X FP32 (vector and matrix)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1024, help="grid side (N = n^2)")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--solves", type=int, default=20, help="solves timed for solves/s")
+    ap.add_argument("--solves", type=int, default=100, help="solves timed for solves/s")
     ap.add_argument("--rtol", type=float, default=1e-10, help="GMRES relative residual target")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")

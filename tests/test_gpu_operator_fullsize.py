@@ -69,11 +69,12 @@ def _colour0_leaf_sample(F, pts, prm, count):
         assert np.array_equal(Sg, B[s]) and np.array_equal(Rg, B[r]), b
 
 
-@pytest.mark.parametrize("n,precision", [(512, "mixed"), (1024, "mixed"), (1024, "fp64")])
-def test_full_size_properties(rss, n, precision):
+@pytest.mark.parametrize("n,precision,tol", [(512, "mixed", 1e-6), (1024, "mixed", 1e-6), (1024, "fp64", 1e-6),
+                                             (1024, "mixed", 1e-3), (1024, "mixed", 1e-9)])
+def test_full_size_properties(rss, n, precision, tol):
     pts = W.grid_points(n)
-    prm = W.problem(n, 1e-6)
-    say(f"[fullsize] n={n} precision={precision} factor")
+    prm = W.problem(n, tol)
+    say(f"[fullsize] n={n} precision={precision} tol={tol} factor")
     F = _factor(rss, pts, prm, precision)
     _colour0_leaf_sample(F, pts, prm, 6)
     b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
