@@ -48,8 +48,8 @@ __device__ inline double dot_strided(const TT* __restrict__ M, int64_t stride, c
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-template <typename TT>
-__global__ void __launch_bounds__(256) k_solve_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
+template <typename TT, int NTH>
+__global__ void __launch_bounds__(NTH) k_solve_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
     __shared__ double zS[kMaxBox], zR[kMaxBox], w[kMaxBox];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
@@ -64,34 +64,35 @@ __global__ void __launch_bounds__(256) k_solve_fwd(SweepArgs a, const int* __res
     const TT* Xi = (const TT*)a.Xinv + c * bsz;
     const TT* E = (const TT*)a.XJR + (int64_t)c * ldJ * nmax;
     const int* J = a.Jg + (int64_t)c * ldJ;
-    for (int i = tid; i < k; i += 256) sg[i] = a.Sg[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += 256) rg[i] = a.Rg[(int64_t)c * nmax + i];
+    for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     for (int h = 0; h < nrhs; ++h) {
         double* zc = z + (int64_t)h * ld;
-        for (int i = tid; i < k; i += 256) zS[i] = zc[sg[i]];
-        for (int i = tid; i < r; i += 256) zR[i] = zc[rg[i]];
+        for (int i = tid; i < k; i += NTH) zS[i] = zc[sg[i]];
+        for (int i = tid; i < r; i += NTH) zR[i] = zc[rg[i]];
         __syncthreads();
-        for (int b = tid; b < r; b += 256) zR[b] -= dot_strided(T + (int64_t)b * nmax, 1, zS, k);   // z_R -= T^T z_S
+        for (int b = tid; b < r; b += NTH) zR[b] -= dot_strided(T + (int64_t)b * nmax, 1, zS, k);   // z_R -= T^T z_S
         __syncthreads();
-        for (int b = tid; b < r; b += 256) w[b] = dot_strided(Xi + b, nmax, zR, r);   // X_RR^{-1} z_R
+        for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Xi + b, nmax, zR, r);   // X_RR^{-1} z_R
         __syncthreads();
-        for (int jj = tid; jj < nj; jj += 256) {                                        // z_J -= E w
+        for (int jj = tid; jj < nj; jj += NTH) {                                        // z_J -= E w
             const int g = J[jj];
             const double sj = dot_strided(E + jj, ldJ, w, r);
             zc[g] -= sj;
         }
-        for (int b = tid; b < r; b += 256) zc[rg[b]] = w[b];
+        for (int b = tid; b < r; b += NTH) zc[rg[b]] = w[b];
         __syncthreads();
     }
 }
 
-template <typename TT>
-__global__ void __launch_bounds__(256) k_solve_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
+template <typename TT, int NTH>
+__global__ void __launch_bounds__(NTH) k_solve_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
+    constexpr int NW = NTH / 64;
     extern __shared__ double zJ[];   // ldJ
     __shared__ double zR[kMaxBox];
-    __shared__ double part[4][kMaxBox];
+    __shared__ double part[NW][kMaxBox];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -103,29 +104,32 @@ __global__ void __launch_bounds__(256) k_solve_bwd(SweepArgs a, const int* __res
     const TT* T = (const TT*)a.T + c * bsz;
     const TT* G = (const TT*)a.G + (int64_t)c * nmax * ldJ;
     const int* J = a.Jg + (int64_t)c * ldJ;
-    for (int i = tid; i < k; i += 256) sg[i] = a.Sg[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += 256) rg[i] = a.Rg[(int64_t)c * nmax + i];
+    for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     const int wv = tid >> 6, lane = tid & 63;
-    const int q4 = (nj + 3) / 4;   // J entries per wave
+    const int q4 = (nj + NW - 1) / NW;   // J entries per wave
     for (int h = 0; h < nrhs; ++h) {
         double* zc = z + (int64_t)h * ld;
-        for (int jj = tid; jj < nj; jj += 256) zJ[jj] = zc[J[jj]];
+        for (int jj = tid; jj < nj; jj += NTH) zJ[jj] = zc[J[jj]];
         __syncthreads();
-        // z_R -= G z_J : wave wv takes a contiguous quarter of J, lanes take rows b
+        // z_R -= G z_J : wave wv takes a contiguous 1/NW of J, lanes take rows b
         const int j0 = wv * q4, j1 = min(nj, j0 + q4);
         for (int b0 = 0; b0 < r; b0 += 64) {
             const int b = b0 + lane;
             if (b < r) part[wv][b] = j1 > j0 ? dot_strided(G + b + (int64_t)j0 * nmax, nmax, zJ + j0, j1 - j0) : 0.0;
         }
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {
-            double v = zc[rg[b]] - (part[0][b] + part[1][b] + part[2][b] + part[3][b]);
+        for (int b = tid; b < r; b += NTH) {
+            double sp = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) sp += part[w][b];
+            double v = zc[rg[b]] - sp;
             zR[b] = v;
             zc[rg[b]] = v;
         }
         __syncthreads();
-        for (int q = tid; q < k; q += 256) zc[sg[q]] -= dot_strided(T + q, nmax, zR, r);   // z_S -= T z_R
+        for (int q = tid; q < k; q += NTH) zc[sg[q]] -= dot_strided(T + q, nmax, zR, r);   // z_S -= T z_R
         __syncthreads();
     }
 }
@@ -239,8 +243,14 @@ void launch_solve_fwd(const Level& L, const int* boxes, int nboxes, double* z, i
                       hipStream_t s) {
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
-    if (use32) k_solve_fwd<float><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
-    else k_solve_fwd<double><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+    // few boxes: a large workgroup per box keeps more loads of the record in flight
+    if (nboxes < 256) {
+        if (use32) k_solve_fwd<float, 1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
+        else k_solve_fwd<double, 1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
+    } else {
+        if (use32) k_solve_fwd<float, 256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+        else k_solve_fwd<double, 256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+    }
 }
 
 void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld, int use32,
@@ -248,8 +258,13 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
     const size_t lds = sizeof(double) * (size_t)L.ldJ;
-    if (use32) k_solve_bwd<float><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
-    else k_solve_bwd<double><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
+    if (nboxes < 256) {
+        if (use32) k_solve_bwd<float, 1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
+        else k_solve_bwd<double, 1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
+    } else {
+        if (use32) k_solve_bwd<float, 256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
+        else k_solve_bwd<double, 256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
+    }
 }
 
 void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
