@@ -99,7 +99,8 @@ def dominant_roofline(infos: list, mixed: bool) -> dict:
     peak_f = FP32_PEAK_TFS if mixed else FP64_PEAK_TFS
     ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
     traffic = measured_traffic()
-    common = dict(kernel="k_schur<float>" if mixed else "k_schur<double>", launches=nl, avg_launch_ms=avg_ms,
+    common = dict(kernel="k_schur<float, float>" if mixed else "k_schur<double, double>", launches=nl,
+                  avg_launch_ms=avg_ms,
                   algorithmic_bytes_per_launch=byts / nl, algorithmic_flops_per_launch=flops / nl,
                   arithmetic_intensity=ai)
     if ai < ridge:

@@ -65,9 +65,13 @@ typedef struct {
     double   root_lo[2];    /* lower corner of the root box */
     double   root_side;     /* side of the root box; <= 0: bounding square of the points */
     int32_t  precision;     /* rss_precision: RSS_MIXED computes the Schur-complement
-                               products in FP32 and keeps an FP32 copy of the factor
-                               for rss_solve; the ID, the LU factors and the block store
-                               stay FP64 */
+                               products in FP32, keeps an FP32 copy of the factor for
+                               rss_solve and, when tol >= 16 * 2^-24 (~9.5e-7), keeps the
+                               block store (the current A_{B_a,B_b} blocks) in FP32; the
+                               ID (double-double Gram and pivoted Cholesky), the
+                               eliminations, the LU factors and the FP64 records stay
+                               FP64.  The factor is then accurate to ~1e-7; rss_gmres
+                               refines to any rtol */
 } rss_params;
 
 /* Fill *p with the defaults: dim 2, diag 1, weight 1, tol 1e-6, leaf 64, 16 proxies at

@@ -218,7 +218,7 @@ void alloc_level_lists(rss_factor f, rss::Level& L) {
     L.gidx = dalloc<int>(f, (size_t)L.nbox * L.nmax);
     L.nact = dalloc<int>(f, L.nbox);
     L.apos = dalloc<int>(f, (size_t)L.nbox * L.nmax);
-    L.store = dalloc<double>(f, (size_t)L.nbox * rss::kNbr * L.nmax * L.nmax);
+    L.store = dalloc<unsigned char>(f, L.store_bytes());
 }
 
 void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
@@ -247,7 +247,7 @@ void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
 }
 
 void free_store(rss_factor f, rss::Level& L) {
-    dfree(f, L.store, sizeof(double) * (size_t)L.nbox * rss::kNbr * L.nmax * L.nmax);
+    dfree(f, L.store, L.store_bytes());
     L.store = nullptr;
 }
 
@@ -350,6 +350,9 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     L.t = depth; L.nb = 1 << depth; L.nbox = L.nb * L.nb;
     L.nmax = std::max(maxcount, 1);
     L.ldJ = 9 * L.nmax;
+    // FP32 store in mixed precision when its rounding (u32 = 2^-24) sits at least 16x below
+    // the ID tolerance; tighter tolerances keep an FP64 store (the Schur products stay FP32)
+    L.store32 = (p.precision == RSS_MIXED && p.tol >= 16.0 * 0x1.0p-24) ? 1 : 0;
     alloc_level_lists(f, L);
     rss::launch_leaf_lists(f->pts, f->n, depth, lo_x, lo_y, side, L.cnt, L.gidx, L.nmax, L.nbox, s);
     check_launch();
@@ -453,7 +456,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             st.flops_lu += 2.0 / 3.0 * r * r * r;
             st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
             st.flops_schur += 2.0 * J * J * r;
-            st.bytes_schur += 16.0 * J * J + (mixed ? 4.0 : 8.0) * 2.0 * J * r;
+            st.bytes_schur += (L.store32 ? 8.0 : 16.0) * J * J + (mixed ? 4.0 : 8.0) * 2.0 * J * r;
             st.bytes_solve64 += 8.0 * (2.0 * J * r + 2.0 * k * r + r * r);
             st.bytes_solve32 += 4.0 * (2.0 * J * r + 2.0 * k * r + r * r);
         }
@@ -478,7 +481,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         P.gidx = dalloc<int>(f, (size_t)P.nbox * P.nmax);
         P.nact = dalloc<int>(f, P.nbox);
         P.apos = dalloc<int>(f, (size_t)P.nbox * P.nmax);
-        P.store = dalloc<double>(f, (size_t)P.nbox * rss::kNbr * P.nmax * P.nmax);
+        P.store32 = L.store32;
+        P.store = dalloc<unsigned char>(f, P.store_bytes());
         int* pmap = dalloc<int>(f, (size_t)P.nbox * P.nmax);
         rss::launch_parent_lists(L, P, pmap, s);
         check_launch();

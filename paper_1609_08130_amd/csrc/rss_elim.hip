@@ -23,7 +23,7 @@
 namespace rss {
 
 struct ElimArgs {
-    double* store;
+    const void* store;   // FP64 or FP32 entries (the kernels' ST)
     int nb, nmax, ldJ;
     const int* cnt;
     const int* gidx;
@@ -83,22 +83,23 @@ __device__ inline void stage_batched(int total, Load load, Store store) {
     }
 }
 
-// Per-workgroup tables of box c in LDS.
+// Per-workgroup tables of box c in LDS (ST: entry type of the block store).
+template <typename ST>
 struct ElimShared {
     int sp[kMaxBox], rp[kMaxBox];   // B positions of S and R
-    const double* blk_nc[8];        // A(B_o, B_c) of the adjacent boxes o
-    const double* blk_cn[8];        // A(B_c, B_o)
+    const ST* blk_nc[8];            // A(B_o, B_c) of the adjacent boxes o
+    const ST* blk_cn[8];            // A(B_c, B_o)
     const int* nap[8];              // active positions of o
     int nbox[8];
     int joff[9];                    // J segments: [0, k) is S, then one per adjacent box
     int nN;
-    const double* srcp[kTileMax];   // source block and row/column of each tile line
+    const ST* srcp[kTileMax];       // source block and row/column of each tile line
     int srcpos[kTileMax];
 };
 
 // sp, rp, the adjacent-box tables and T (Ts[b + r q] = T[q][b]).  The caller synchronizes.
-template <int NTH>
-__device__ void elim_setup(ElimShared& sh, const ElimArgs& a, int c, int k, int r, double* Ts) {
+template <int NTH, typename ST>
+__device__ void elim_setup(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, double* Ts) {
     const int tid = threadIdx.x, nmax = a.nmax, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
     for (int i = tid; i < k; i += NTH) sh.sp[i] = a.spos[(int64_t)c * nmax + i];
@@ -127,8 +128,8 @@ __device__ void elim_setup(ElimShared& sh, const ElimArgs& a, int c, int k, int 
             if (o < 0) continue;
             const int tt = t < 4 ? t : t + 1;
             const int dx = tt % 3 - 1, dy = tt / 3 - 1;
-            sh.blk_nc[cntN] = a.store + ((int64_t)o * kNbr + nbr_slot(-dx, -dy)) * bsz;   // A(B_o, B_c)
-            sh.blk_cn[cntN] = a.store + ((int64_t)c * kNbr + nbr_slot(dx, dy)) * bsz;     // A(B_c, B_o)
+            sh.blk_nc[cntN] = (const ST*)a.store + ((int64_t)o * kNbr + nbr_slot(-dx, -dy)) * bsz;   // A(B_o, B_c)
+            sh.blk_cn[cntN] = (const ST*)a.store + ((int64_t)c * kNbr + nbr_slot(dx, dy)) * bsz;     // A(B_c, B_o)
             sh.nap[cntN] = a.apos + (int64_t)o * nmax;
             sh.nbox[cntN] = o;
             sh.joff[cntN + 1] = sh.joff[cntN] + sh.srcpos[t];
@@ -139,7 +140,8 @@ __device__ void elim_setup(ElimShared& sh, const ElimArgs& a, int c, int k, int 
 }
 
 // Global index of J entry jj.
-__device__ inline int j_global(const ElimShared& sh, const ElimArgs& a, int c, int jj, int k) {
+template <typename ST>
+__device__ inline int j_global(const ElimShared<ST>& sh, const ElimArgs& a, int c, int jj, int k) {
     if (jj < k) return a.gidx[(int64_t)c * a.nmax + sh.sp[jj]];
     int i = 0;
     while (sh.joff[i + 1] <= jj) ++i;
@@ -150,13 +152,13 @@ __device__ inline int j_global(const ElimShared& sh, const ElimArgs& a, int c, i
 // FP32 copy when XJR32 != nullptr), rows past J give Y_RR = A_RR - A_RS T (into Y, ld nmax).
 // tA: tw x n.  Thread t takes row t % 32 of the tile and, per pass, 8 columns of R spaced
 // NTH / 32 apart, so each A(i, S_q) read from LDS serves 8 products.
-template <int NTH>
-__device__ void elim_rows_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
+template <int NTH, typename ST>
+__device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
                                int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
     constexpr int BG = NTH / 32;   // column groups
     const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int n = k + r;
-    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    const ST* Acc = (const ST*)a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
     if (tid < tr) {
         const int jj = r0 + tid;
         if (jj < k) {
@@ -179,7 +181,7 @@ __device__ void elim_rows_tile(ElimShared& sh, const ElimArgs& a, int c, int k, 
         [&](int e) {
             const int i = e % tr, col = e / tr;
             const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
-            return sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
+            return (double)sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
         },
         [&](int e, double v) { tA[(e % tr) + tw * (e / tr)] = v; });
     __syncthreads();
@@ -220,8 +222,8 @@ __device__ void elim_rows_tile(ElimShared& sh, const ElimArgs& a, int c, int k, 
 // in LDS (xi_lds); otherwise it is staged through tA, tw columns at a time.  Thread t
 // takes rows b = t % 64 + 64 h (h < HB, r <= 64 HB) of the result and the columns
 // t / 64 + NW v of the tile.
-template <int NTH, int HB>
-__device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int c0, int tc, int tw,
+template <int NTH, int HB, typename ST>
+__device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int c0, int tc, int tw,
                             const double* Ts, double* tA, double* tX, const double* Xi, bool xi_lds, double* G,
                             float* G32) {
     constexpr int NW = NTH / 64;
@@ -229,7 +231,7 @@ __device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int
     const int tid = threadIdx.x, nmax = a.nmax;
     const int n = k + r;
     const int lane = tid & 63, jg = tid >> 6;
-    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    const ST* Acc = (const ST*)a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
     if (tid < tc) {
         const int jj = c0 + tid;
         if (jj < k) {
@@ -245,7 +247,7 @@ __device__ void elim_g_tile(ElimShared& sh, const ElimArgs& a, int c, int k, int
     __syncthreads();
     // tA[pos + nmax jp] = A(B_c position pos, J column c0 + jp)
     stage_batched<NTH>(
-        tc * n, [&](int e) { const int pos = e % n, jp = e / n; return sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax]; },
+        tc * n, [&](int e) { const int pos = e % n, jp = e / n; return (double)sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax]; },
         [&](int e, double v) { tA[(e % n) + nmax * (e / n)] = v; });
     __syncthreads();
     // X_RJ[b][jp] = A(rp[b], jp) - sum_q T[q][b] A(sp[q], jp), q ascending
@@ -574,16 +576,15 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
     return true;
 }
 
-// X_RR = Y_RR - T^T Z_S (Y_RR read from Yg or, in the fused kernel, formed from the store),
+// X_RR = Y_RR - T^T Z_S (Y_RR read from Yg, formed by the row tiles),
 // then its inverse, log|det| and the per-box records.  Returns false when X_RR is singular.
-template <int NTH>
-__device__ bool elim_xrr_inverse(ElimShared& sh, const ElimArgs& a, int c, int k, int r, int nj, const double* Ts,
+template <int NTH, typename ST>
+__device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int nj, const double* Ts,
                                  const double* Yg, double* Xs, double* xsr, int mixed, int* colswap, double* sc,
                                  int& piv_idx, double& piv_val) {
     const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int64_t bsz = (int64_t)nmax * nmax;
     const double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
-    const double* Acc = a.store + ((int64_t)c * kNbr + 12) * bsz;
     double* XRR = a.XRR + (int64_t)c * bsz;
     // Z_S = rows S of X_JR, staged in LDS (xsr[q + k b2]) when a buffer is given
     const double* zs = XJR;
@@ -599,13 +600,7 @@ __device__ bool elim_xrr_inverse(ElimShared& sh, const ElimArgs& a, int c, int k
     }
     for (int e = tid; e < r * r; e += NTH) {
         int b = e % r, b2 = e / r;
-        double v;
-        if (Yg) {
-            v = Yg[b + (int64_t)b2 * nmax];
-        } else {
-            v = Acc[sh.rp[b] + (int64_t)sh.rp[b2] * nmax];
-            for (int q = 0; q < k; ++q) v -= Acc[sh.rp[b] + (int64_t)sh.sp[q] * nmax] * Ts[b2 + r * q];
-        }
+        double v = Yg[b + (int64_t)b2 * nmax];
         for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * zs[q + (int64_t)b2 * ldz];
         XRR[b + (int64_t)b2 * nmax] = v;
         Xs[b + b2 * nmax] = v;
@@ -645,11 +640,11 @@ __device__ bool elim_xrr_inverse(ElimShared& sh, const ElimArgs& a, int c, int k
 
 // ---- the three launches of a colour ------------------------------------------------------
 // grid (row tiles of [J; R], boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw]
-template <int NTH>
+template <int NTH, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
                                                    int mixed, double* __restrict__ work, int tsz, int tw) {
     extern __shared__ double dyn[];
-    __shared__ ElimShared sh;
+    __shared__ ElimShared<ST> sh;
     const int tid = threadIdx.x;
     int bi, tile;
     if (!xcd_tile(ntile, nbox, bi, tile)) return;
@@ -661,7 +656,7 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     const int nmax = a.nmax, ldJ = a.ldJ;
     double* Ts = dyn;
     double* tA = dyn + tsz;
-    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
     const int r0 = tile * tw;
@@ -671,16 +666,16 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
     double* Y = work + (int64_t)bi * nmax * nmax;
-    elim_rows_tile<NTH>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
+    elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
 }
 
 // grid (boxes).  Dynamic LDS: Ts[tsz] | sc[4 nmax] | Z_S[tsz] (when use_zs) | Xs[nmax^2]
 // (when XLDS; else X_RR is inverted in place of Y_RR in the workspace)
-template <bool XLDS, int NTH>
+template <bool XLDS, int NTH, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restrict__ boxes, int mixed,
                                                   double* __restrict__ work, int* flag, int tsz, int use_zs) {
     extern __shared__ double dyn[];
-    __shared__ ElimShared sh;
+    __shared__ ElimShared<ST> sh;
     __shared__ int colswap[kMaxBox];
     __shared__ int piv_idx;
     __shared__ double piv_val;
@@ -699,10 +694,10 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     double* xsr = use_zs ? sc + 4 * nmax : nullptr;
     double* Y = work + (int64_t)blockIdx.x * nmax * nmax;
     double* Xs = XLDS ? sc + 4 * nmax + (use_zs ? tsz : 0) : Y;
-    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
-    if (!elim_xrr_inverse<NTH>(sh, a, c, k, r, nj, Ts, Y, Xs, xsr, mixed, colswap, sc, piv_idx, piv_val)) {
+    if (!elim_xrr_inverse<NTH, ST>(sh, a, c, k, r, nj, Ts, Y, Xs, xsr, mixed, colswap, sc, piv_idx, piv_val)) {
         if (tid == 0) { atomicOr(flag, 4); a.nJ[c] = 0; }
         return;
     }
@@ -714,11 +709,11 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
 }
 
 // grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw] | tX[nmax tw]
-template <int NTH, int HB>
+template <int NTH, int HB, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
                                                 int mixed, int* flag, int tsz, int tw) {
     extern __shared__ double dyn[];
-    __shared__ ElimShared sh;
+    __shared__ ElimShared<ST> sh;
     int bi, tile;
     if (!xcd_tile(ntile, nbox, bi, tile)) return;
     const int c = boxes[bi];
@@ -731,14 +726,14 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     double* Ts = dyn;
     double* tA = dyn + tsz;
     double* tX = tA + (int64_t)nmax * tw;
-    elim_setup<NTH>(sh, a, c, k, r, Ts);
+    elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
     const int c0 = tile * tw;
     if (c0 >= nj) return;
     double* G = a.G + (int64_t)c * nmax * ldJ;
     float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
-    elim_g_tile<NTH, HB>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz, false, G,
+    elim_g_tile<NTH, HB, ST>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz, false, G,
                          G32);
 }
 
@@ -761,7 +756,9 @@ static void set_lds(K kernel, size_t bytes) {
     hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, hipStream_t s) {
+template <typename ST>
+static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
+                         hipStream_t s) {
     if (nboxes <= 0) return 0;
     ElimArgs a;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
@@ -783,9 +780,9 @@ int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double*
     const int twr = tile_w(tsz, 1), twg = tile_w(tsz, 2);
     if (twr == 0 || twg == 0) return -1;
     const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
-    set_lds(k_elim_rows<256>, lr);
+    set_lds(k_elim_rows<256, ST>, lr);
     const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
-    k_elim_rows<256><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
+    k_elim_rows<256, ST><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
                                                                        (int)tsz, twr);
     const size_t base = tsz + 4 * nm;
     const bool xl = D * (base + nm * nm) <= lim;
@@ -794,32 +791,37 @@ int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double*
     // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
     if (nboxes >= 256) {
         if (xl) {
-            set_lds(k_elim_inv<true, 256>, li);
-            k_elim_inv<true, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+            set_lds(k_elim_inv<true, 256, ST>, li);
+            k_elim_inv<true, 256, ST><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         } else {
-            set_lds(k_elim_inv<false, 256>, li);
-            k_elim_inv<false, 256><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+            set_lds(k_elim_inv<false, 256, ST>, li);
+            k_elim_inv<false, 256, ST><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
         }
     } else if (xl) {
-        set_lds(k_elim_inv<true, 1024>, li);
-        k_elim_inv<true, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+        set_lds(k_elim_inv<true, 1024, ST>, li);
+        k_elim_inv<true, 1024, ST><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
     } else {
-        set_lds(k_elim_inv<false, 1024>, li);
-        k_elim_inv<false, 1024><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
+        set_lds(k_elim_inv<false, 1024, ST>, li);
+        k_elim_inv<false, 1024, ST><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
     }
     const int ntg = (L.ldJ + twg - 1) / twg;
     const dim3 gg(xcd_grid(ntg, nboxes));
     if (L.nmax <= 64) {
-        set_lds(k_elim_g<256, 1>, lg);
-        k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        set_lds(k_elim_g<256, 1, ST>, lg);
+        k_elim_g<256, 1, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
     } else if (L.nmax <= 128) {
-        set_lds(k_elim_g<256, 2>, lg);
-        k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        set_lds(k_elim_g<256, 2, ST>, lg);
+        k_elim_g<256, 2, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
     } else {
-        set_lds(k_elim_g<256, 4>, lg);
-        k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        set_lds(k_elim_g<256, 4, ST>, lg);
+        k_elim_g<256, 4, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
     }
     return 3;
+}
+
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, hipStream_t s) {
+    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, s)
+                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, s);
 }
 
 }  // namespace rss

@@ -139,14 +139,16 @@ size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes) {
     return slices * nn * 2 + nboxes * nn * 2;
 }
 
+template <typename ST>
 struct ORing {
-    const double* base[16];
+    const ST* base[16];
     const int* ap[16];
     int beg[17];
     int cnt;
 };
 
-__device__ inline void build_oring(ORing& o, const double* store, const int* nact, const int* apos, int c, int nb,
+template <typename ST>
+__device__ inline void build_oring(ORing<ST>& o, const ST* store, const int* nact, const int* apos, int c, int nb,
                                    int nmax) {
     const int64_t bsz = (int64_t)nmax * nmax;
     const int cx = c % nb, cy = c / nb;
@@ -168,8 +170,8 @@ __device__ inline void build_oring(ORing& o, const double* store, const int* nac
 
 // ---- 1. partial Gram matrices -------------------------------------------------------------
 // grid (slices x tile groups, boxes); thread owns TPT 2x2 tiles of the upper triangle of G.
-template <int NTH, int TPT>
-__global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, int nb, int nmax,
+template <int NTH, int TPT, typename ST>
+__global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int nb, int nmax,
                                               const int* __restrict__ cnt, const int* __restrict__ gidx,
                                               const int* __restrict__ nact, const int* __restrict__ apos,
                                               const int* __restrict__ boxes, const double* __restrict__ pts,
@@ -177,10 +179,10 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
                                               double* __restrict__ gpart, int nslice, int slice_rows) {
 #pragma clang fp contract(off)
     extern __shared__ double Ms[];   // kChunk x (nmax + 1)
-    __shared__ ORing oring;
+    __shared__ ORing<ST> oring;
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
     __shared__ double colx[kMaxBox], coly[kMaxBox];
-    __shared__ const double* rowsrc[kChunk];
+    __shared__ const ST* rowsrc[kChunk];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.y];
     const int sl = blockIdx.x % nslice;
@@ -242,7 +244,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
         // loads in flight per thread
         constexpr int GU = 4;
         if (tid < kChunk) {
-            const double* src = nullptr;
+            const ST* src = nullptr;
             const int row = r0 + tid;
             if (tid < rows && row < mO) {
                 int o = 0;
@@ -258,8 +260,8 @@ __global__ void __launch_bounds__(NTH) k_gram(const double* __restrict__ store, 
             for (int u = 0; u < GU; ++u) {
                 const int idx = idx0 + u * NTH;
                 const int i = idx & (kChunk - 1), q = idx / kChunk;
-                const double* src = rowsrc[i];
-                v[u] = (idx < kChunk * ld && i < rows && q < n && src) ? src[(int64_t)q * nmax] : 0.0;
+                const ST* src = rowsrc[i];
+                v[u] = (idx < kChunk * ld && i < rows && q < n && src) ? (double)src[(int64_t)q * nmax] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
@@ -547,8 +549,15 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
 template <int NTH, int TPT>
 static void gram_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                         const KernelParams& kp, double* gpart, const GramPlan& g, size_t lds, hipStream_t s) {
-    k_gram<NTH, TPT><<<dim3(g.nsl * g.groups, nboxes), dim3(NTH), lds, s>>>(
-        L.store, L.nb, L.nmax, L.cnt, L.gidx, L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart, g.nsl, g.slice_rows);
+    const dim3 grid(g.nsl * g.groups, nboxes);
+    if (L.store32)
+        k_gram<NTH, TPT, float><<<grid, dim3(NTH), lds, s>>>((const float*)L.store, L.nb, L.nmax, L.cnt, L.gidx,
+                                                              L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart,
+                                                              g.nsl, g.slice_rows);
+    else
+        k_gram<NTH, TPT, double><<<grid, dim3(NTH), lds, s>>>((const double*)L.store, L.nb, L.nmax, L.cnt, L.gidx,
+                                                               L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart,
+                                                               g.nsl, g.slice_rows);
 }
 
 template <int NTH, int SUB>

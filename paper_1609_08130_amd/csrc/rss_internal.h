@@ -37,7 +37,9 @@ struct Level {
     int t = 0, nb = 0, nbox = 0;
     int nmax = 0;        // max |B| at level start; leading dimension of store blocks
     int ldJ = 0;         // 9 * nmax: capacity of J lists
-    double* store = nullptr;   // nbox * 25 * nmax * nmax
+    void* store = nullptr;     // nbox * 25 * nmax * nmax entries: FP64, or FP32 when store32
+    int store32 = 0;           // mixed precision: the block store holds FP32 entries
+    size_t store_bytes() const { return (size_t)nbox * kNbr * nmax * nmax * (store32 ? 4 : 8); }
     int* cnt = nullptr;        // |B| at level start
     int* gidx = nullptr;       // nbox * nmax global DOF indices (ascending)
     int* nact = nullptr;       // current active count

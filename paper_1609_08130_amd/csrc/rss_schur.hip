@@ -7,14 +7,15 @@
 // the store.  Boxes of one colour have disjoint neighbourhoods, so no two workgroups of
 // a launch write the same entry and no atomics are needed.
 //
-// TT = double: FP64 products.  TT = float: the products of the FP32 copies of X_JR and G
-// are accumulated in FP32 and subtracted from the FP64 store.
+// TT = double: FP64 products subtracted from the FP64 store.  TT = float (mixed
+// precision): the products of the FP32 copies of X_JR and G are accumulated in FP32 and
+// subtracted from the store of entry type ST (FP32 in mixed factorizations).
 #include "rss_internal.h"
 
 namespace rss {
 
 struct SchurArgs {
-    double* store;
+    void* store;   // entries of type ST
     int nb, nmax, ldJ;
     const int* cnt;
     const int* nact;
@@ -26,7 +27,7 @@ struct SchurArgs {
     const void* G;
 };
 
-template <typename TT>
+template <typename TT, typename ST>
 __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd) {
     constexpr int TM = 64, TK = 16;
     __shared__ TT As[TK][TM + 1];
@@ -148,8 +149,8 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
             if (sa < 0) continue;
             int abox = slot_box[sa];
             int dx = (bbox % nb) - (abox % nb), dy = (bbox / nb) - (abox / nb);
-            double* blk = a.store + ((int64_t)abox * kNbr + nbr_slot(dx, dy)) * bsz;
-            blk[rpos_[i] + (int64_t)cpos_[j] * nmax] -= (double)acc[u][v];
+            ST* blk = (ST*)a.store + ((int64_t)abox * kNbr + nbr_slot(dx, dy)) * bsz;
+            blk[rpos_[i] + (int64_t)cpos_[j] * nmax] -= (ST)acc[u][v];
         }
     }
 }
@@ -164,10 +165,11 @@ void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mi
     dim3 grid((unsigned)nwg), block(256);
     if (mixed) {
         a.XJR = L.XJR32; a.G = L.G32;
-        k_schur<float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
+        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
+        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
     } else {
         a.XJR = L.XJR; a.G = L.G;
-        k_schur<double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
+        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
     }
 }
 

@@ -113,7 +113,8 @@ void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double 
 // and per offset of the self block or the 12 offsets (dx, dy) with dy > 0 or (dy = 0,
 // dx > 0).  Each 64 x 64 tile is evaluated once into LDS and written to both blocks,
 // coalesced in both orientations.
-__global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, const int* __restrict__ cnt,
+template <typename ST>
+__global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, const int* __restrict__ cnt,
                                                     const int* __restrict__ gidx, const double* __restrict__ pts,
                                                     int nb, int nmax, double coef, double diag, int* flag) {
     __shared__ double xa[kMaxBox], ya[kMaxBox], xb[kMaxBox], yb[kMaxBox];
@@ -137,8 +138,8 @@ __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, 
         gb[i] = g; xb[i] = pts[2 * (int64_t)g]; yb[i] = pts[2 * (int64_t)g + 1];
     }
     __syncthreads();
-    double* blk_ab = store + ((int64_t)a * kNbr + o) * nmax * nmax;                  // A(B_a, B_b)
-    double* blk_ba = store + ((int64_t)b * kNbr + (24 - o)) * nmax * nmax;           // A(B_b, B_a)
+    ST* blk_ab = store + ((int64_t)a * kNbr + o) * nmax * nmax;                  // A(B_a, B_b)
+    ST* blk_ba = store + ((int64_t)b * kNbr + (24 - o)) * nmax * nmax;           // A(B_b, B_a)
     const bool self = oi == 0;
     bool dup = false;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, 
                         v = kernel_entry(xa[i], ya[i], xb[j], yb[j], coef);
                         dup |= (xa[i] == xb[j] && ya[i] == yb[j]);
                     }
-                    blk_ab[i + (int64_t)j * nmax] = v;
+                    blk_ab[i + (int64_t)j * nmax] = (ST)v;
                 }
                 tile[jj][lane] = v;
             }
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, 
                 __syncthreads();
                 // A(B_b, B_a)(j, i) = A(B_a, B_b)(i, j): rows j0 + lane, columns i0 + wv + 4 t
                 for (int ii = wv; ii < ti; ii += 4)
-                    if (lane < tj) blk_ba[(j0 + lane) + (int64_t)(i0 + ii) * nmax] = tile[lane][ii];
+                    if (lane < tj) blk_ba[(j0 + lane) + (int64_t)(i0 + ii) * nmax] = (ST)tile[lane][ii];
                 __syncthreads();
             }
         }
@@ -173,8 +174,12 @@ __global__ void __launch_bounds__(256) k_leaf_store(double* __restrict__ store, 
 }
 
 void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag, hipStream_t s) {
-    k_leaf_store<<<dim3(L.nbox * 13), dim3(256), 0, s>>>(L.store, L.cnt, L.gidx, pts, L.nb, L.nmax, kp.coef,
-                                                          kp.diag, flag);
+    if (L.store32)
+        k_leaf_store<float><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((float*)L.store, L.cnt, L.gidx, pts, L.nb,
+                                                                    L.nmax, kp.coef, kp.diag, flag);
+    else
+        k_leaf_store<double><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((double*)L.store, L.cnt, L.gidx, pts, L.nb,
+                                                                     L.nmax, kp.coef, kp.diag, flag);
 }
 
 // ------------------------------------------------------------------------------------
@@ -242,8 +247,9 @@ void launch_parent_counts(const Level& C, Level& P, hipStream_t s) {
     k_parent_counts<<<dim3((P.nbox + 255) / 256), dim3(256), 0, s>>>(C.nact, C.nb, P.cnt, P.nb);
 }
 
-__global__ void __launch_bounds__(256) k_parent_store(const double* __restrict__ cstore, int cnb, int cnmax,
-                                                      double* __restrict__ pstore, const int* __restrict__ pcnt,
+template <typename ST>
+__global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cstore, int cnb, int cnmax,
+                                                      ST* __restrict__ pstore, const int* __restrict__ pcnt,
                                                       const int* __restrict__ pgidx, const int* __restrict__ pmap,
                                                       int pnb, int pnmax, const double* __restrict__ pts,
                                                       double coef) {
@@ -267,7 +273,7 @@ __global__ void __launch_bounds__(256) k_parent_store(const double* __restrict__
         xq[i] = pts[2 * (int64_t)g]; yq[i] = pts[2 * (int64_t)g + 1];
     }
     __syncthreads();
-    double* blk = pstore + ((int64_t)P * kNbr + o) * pnmax * pnmax;
+    ST* blk = pstore + ((int64_t)P * kNbr + o) * pnmax * pnmax;
     int tot = np * nq;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         int i = e % np, j = e / np;
@@ -279,19 +285,23 @@ __global__ void __launch_bounds__(256) k_parent_store(const double* __restrict__
         double v;
         if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
             int a = ax + cnb * ay;
-            const double* cb = cstore + ((int64_t)a * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
+            const ST* cb = cstore + ((int64_t)a * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
             v = cb[pa + (int64_t)qb * cnmax];
         } else {
             v = kernel_entry(xp[i], yp[i], xq[j], yq[j], coef);
         }
-        blk[i + (int64_t)j * pnmax] = v;
+        blk[i + (int64_t)j * pnmax] = (ST)v;
     }
 }
 
 void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
                          const KernelParams& kp, hipStream_t s) {
-    k_parent_store<<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(C.store, C.nb, C.nmax, P.store, P.cnt, P.gidx, pmap,
-                                                             P.nb, P.nmax, pts, kp.coef);
+    if (C.store32)
+        k_parent_store<float><<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(
+            (const float*)C.store, C.nb, C.nmax, (float*)P.store, P.cnt, P.gidx, pmap, P.nb, P.nmax, pts, kp.coef);
+    else
+        k_parent_store<double><<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(
+            (const double*)C.store, C.nb, C.nmax, (double*)P.store, P.cnt, P.gidx, pmap, P.nb, P.nmax, pts, kp.coef);
 }
 
 // ------------------------------------------------------------------------------------
@@ -328,7 +338,8 @@ void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hip
     k_top_lists<<<dim3(1), dim3(1024), 0, s>>>(L.nact, L.apos, L.gidx, L.nbox, L.nmax, top_idx, tmap);
 }
 
-__global__ void k_top_assemble(const double* __restrict__ store, int nb, int nmax, const int* __restrict__ tmap,
+template <typename ST>
+__global__ void k_top_assemble(const ST* __restrict__ store, int nb, int nmax, const int* __restrict__ tmap,
                                const int* __restrict__ top_idx, int64_t ntop, const double* __restrict__ pts,
                                double coef, double* __restrict__ A) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,7 +350,7 @@ __global__ void k_top_assemble(const double* __restrict__ store, int nb, int nma
     int dx = b % nb - a % nb, dy = b / nb - a / nb;
     double v;
     if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
-        v = store[((int64_t)a * kNbr + nbr_slot(dx, dy)) * nmax * nmax + pa + (int64_t)qb * nmax];
+        v = (double)store[((int64_t)a * kNbr + nbr_slot(dx, dy)) * nmax * nmax + pa + (int64_t)qb * nmax];
     } else {
         int gi = top_idx[i], gj = top_idx[j];
         v = kernel_entry(pts[2 * (int64_t)gi], pts[2 * (int64_t)gi + 1], pts[2 * (int64_t)gj],
@@ -351,8 +362,13 @@ __global__ void k_top_assemble(const double* __restrict__ store, int nb, int nma
 void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, int64_t ntop, const double* pts,
                          const KernelParams& kp, double* A, hipStream_t s) {
     int64_t tot = ntop * ntop;
-    k_top_assemble<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(L.store, L.nb, L.nmax, tmap, top_idx,
-                                                                            ntop, pts, kp.coef, A);
+    const dim3 g((unsigned)((tot + 255) / 256));
+    if (L.store32)
+        k_top_assemble<float><<<g, dim3(256), 0, s>>>((const float*)L.store, L.nb, L.nmax, tmap, top_idx, ntop, pts,
+                                                      kp.coef, A);
+    else
+        k_top_assemble<double><<<g, dim3(256), 0, s>>>((const double*)L.store, L.nb, L.nmax, tmap, top_idx, ntop,
+                                                       pts, kp.coef, A);
 }
 
 }  // namespace rss
