@@ -642,7 +642,7 @@ __device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, i
 // grid (row tiles of [J; R], boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw]
 template <int NTH, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
-                                                   int mixed, double* __restrict__ work, int tsz, int tw) {
+                                                   int mixed, double* __restrict__ work, int tsz, int tw, int tpw) {
     extern __shared__ double dyn[];
     __shared__ ElimShared<ST> sh;
     const int tid = threadIdx.x;
@@ -659,14 +659,16 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
-    const int r0 = tile * tw;
-    if (r0 >= nj + r) return;
-    const int tr = min(tw, nj + r - r0);
-    for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
     double* Y = work + (int64_t)bi * nmax * nmax;
-    elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
+    for (int t = tile * tpw; t < (tile + 1) * tpw; ++t) {   // tpw consecutive tiles share the setup
+        const int r0 = t * tw;
+        if (r0 >= nj + r) break;
+        const int tr = min(tw, nj + r - r0);
+        for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+        elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
+    }
 }
 
 // grid (boxes).  Dynamic LDS: Ts[tsz] | sc[4 nmax] | Z_S[tsz] (when use_zs) | Xs[nmax^2]
@@ -711,7 +713,7 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
 // grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw] | tX[nmax tw]
 template <int NTH, int HB, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
-                                                int mixed, int* flag, int tsz, int tw) {
+                                                int mixed, int* flag, int tsz, int tw, int tpw) {
     extern __shared__ double dyn[];
     __shared__ ElimShared<ST> sh;
     int bi, tile;
@@ -729,13 +731,20 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
-    const int c0 = tile * tw;
-    if (c0 >= nj) return;
     double* G = a.G + (int64_t)c * nmax * ldJ;
     float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
-    elim_g_tile<NTH, HB, ST>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz, false, G,
-                         G32);
+    for (int t = tile * tpw; t < (tile + 1) * tpw; ++t) {   // tpw consecutive tiles share the setup
+        const int c0 = t * tw;
+        if (c0 >= nj) break;
+        elim_g_tile<NTH, HB, ST>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz,
+                                 false, G, G32);
+    }
 }
+
+// Tiles of one box handled in turn by one workgroup of the row and column tile kernels:
+// several when the launch has work groups to spare (the per-box setup is then paid once
+// for them), one otherwise so that small colours still spread over all compute units.
+static int tiles_per_wg(int ntile, int nboxes) { return nboxes >= 1024 ? min(ntile, 4) : 1; }
 
 static int g_max_lds = -1;
 
@@ -782,8 +791,9 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
     set_lds(k_elim_rows<256, ST>, lr);
     const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
-    k_elim_rows<256, ST><<<dim3(xcd_grid(ntr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, ntr, mixed, work,
-                                                                       (int)tsz, twr);
+    const int pr = tiles_per_wg(ntr, nboxes), gr = (ntr + pr - 1) / pr;
+    k_elim_rows<256, ST><<<dim3(xcd_grid(gr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, gr, mixed, work,
+                                                                      (int)tsz, twr, pr);
     const size_t base = tsz + 4 * nm;
     const bool xl = D * (base + nm * nm) <= lim;
     const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
@@ -805,16 +815,17 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
         k_elim_inv<false, 1024, ST><<<dim3(nboxes), dim3(1024), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
     }
     const int ntg = (L.ldJ + twg - 1) / twg;
-    const dim3 gg(xcd_grid(ntg, nboxes));
+    const int pg = tiles_per_wg(ntg, nboxes), gt = (ntg + pg - 1) / pg;
+    const dim3 gg(xcd_grid(gt, nboxes));
     if (L.nmax <= 64) {
         set_lds(k_elim_g<256, 1, ST>, lg);
-        k_elim_g<256, 1, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        k_elim_g<256, 1, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
     } else if (L.nmax <= 128) {
         set_lds(k_elim_g<256, 2, ST>, lg);
-        k_elim_g<256, 2, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        k_elim_g<256, 2, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
     } else {
         set_lds(k_elim_g<256, 4, ST>, lg);
-        k_elim_g<256, 4, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, ntg, mixed, flag, (int)tsz, twg);
+        k_elim_g<256, 4, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
     }
     return 3;
 }
