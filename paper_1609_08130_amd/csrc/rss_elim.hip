@@ -425,14 +425,17 @@ __device__ inline double lane_read(double v, int ln) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Register-resident variant of gj_inverse (same pivots, same arithmetic per element):
-// thread (wave w, lane) holds X[lane + 64 h][w + NW c] for h < RB, c < CB, which covers
-// r <= 64 RB and r <= NW CB.  One barrier per step: the wave that owns column j picks the
-// pivot (maximum of |x| as an unsigned 64-bit key, lowest row among equal keys) and
-// publishes column j and the pivot row index; every wave reads rows j and p of its own
-// columns from the lanes that hold them.  Column j goes through a buffer of two halves
-// used in alternate steps, so no second barrier is needed.  The result is written back to
-// Xs with the column interchanges undone.  sc: 4 * ldx doubles of LDS.
+// Register-resident variant of gj_inverse: thread (wave w, lane) holds X[lane + 64 h][w + NW c]
+// for h < RB, c < CB, which covers r <= 64 RB and r <= NW CB.  The pivot rows are not
+// interchanged: step j takes as pivot the unused row p of largest |x_pj| (an unsigned 64-bit
+// key, lowest row among equal keys), scales row p, subtracts its multiples from every other
+// row and replaces column j; the per-step arithmetic of each element is that of the
+// interchanging form.  At the end row p_j of the array holds row j of the interchanging form,
+// and the column interchanges of that form (the transposition of j with the position row p_j
+// had reached there) are undone on the way out.  One barrier per step: the wave that owns
+// column j picks the pivot and publishes column j, which goes through a buffer of two halves
+// used in alternate steps; every wave reads row p of its own columns from the lane holding it.
+// sc: 4 * ldx doubles of LDS.
 template <int NTH, int RB, int CB>
 __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double* sc, double& ld_sum, int& sgn) {
     constexpr int NW = NTH / 64;
@@ -440,7 +443,6 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
     const int wv = tid >> 6, lane = tid & 63;
     double* colj = sc;                  // two halves of ldx
     double* pivs = sc + 2 * ldx;
-    int* dest = (int*)(sc + 3 * ldx);   // ldx doubles hold 2 ldx >= r ints
     double x[RB][CB];
 #pragma unroll
     for (int h = 0; h < RB; ++h)
@@ -449,6 +451,7 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
             const int i = lane + 64 * h, l = wv + NW * c;
             x[h][c] = (i < r && l < r) ? Xs[i + l * ldx] : 0.0;
         }
+    unsigned used = 0;   // bit h: row lane + 64 h has been a pivot row
     for (int j = 0; j < r; ++j) {
         double* cb = colj + (j & 1) * ldx;
         const int cj = j / NW;
@@ -463,7 +466,8 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
                     if (c == cj) v = x[h][c];
                 const int i = lane + 64 * h;
                 if (i < r) cb[i] = v;
-                const unsigned long long key = (i >= j && i < r) ? (unsigned long long)__double_as_longlong(fabs(v)) : 0ull;
+                const bool cand = i < r && !((used >> h) & 1u);
+                const unsigned long long key = cand ? (unsigned long long)__double_as_longlong(fabs(v)) : 0ull;
                 if (key > kb) { kb = key; hb = h; }
             }
             unsigned long long km = kb;
@@ -490,67 +494,65 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
         if (!(fabs(d) > 0.0)) return false;
         if (tid == 0) pivs[j] = d;
         const double rinv = 1.0 / d;
+        const int pl = p & 63, ph = p >> 6;
         double fv[RB];
 #pragma unroll
         for (int h = 0; h < RB; ++h) {
             const int i = lane + 64 * h;
-            fv[h] = (i == j || i >= r) ? 0.0 : cb[i == p ? j : i];   // column j after the interchange
+            fv[h] = (i == p || i >= r) ? 0.0 : cb[i];
         }
-        const int jl = j & 63, jh = j >> 6, pl = p & 63, ph = p >> 6;
-        // old rows j and p of this wave's columns, from the lanes that hold them (the slots
-        // jh, ph are wave-uniform)
-        double rj[CB], rp[CB], xj[CB];
+        // new pivot row, from the lane that holds row p (slot ph is wave-uniform)
+        double xj[CB];
 #pragma unroll
-        for (int h = 0; h < RB; ++h) {
-            if (h == jh) {
-#pragma unroll
-                for (int c = 0; c < CB; ++c) rj[c] = lane_read(x[h][c], jl);
-            }
+        for (int h = 0; h < RB; ++h)
             if (h == ph) {
 #pragma unroll
-                for (int c = 0; c < CB; ++c) rp[c] = lane_read(x[h][c], pl);
+                for (int c = 0; c < CB; ++c) xj[c] = lane_read(x[h][c], pl) * rinv;
             }
-        }
-        // rank-one update of every element (rows and columns >= r hold values that are
-        // never read back, so no bounds tests), then the rows p and j and the column j,
-        // whose new values follow other rules, are overwritten
+        // every row but p (rows and columns >= r hold values that are never read back)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            xj[c] = rp[c] * rinv;   // new pivot row
+        for (int c = 0; c < CB; ++c)
 #pragma unroll
             for (int h = 0; h < RB; ++h) x[h][c] -= fv[h] * xj[c];
-        }
 #pragma unroll
         for (int h = 0; h < RB; ++h)
             if (h == ph && lane == pl) {
 #pragma unroll
-                for (int c = 0; c < CB; ++c) x[h][c] = rj[c] - fv[h] * xj[c];   // old row j moves to row p
-            }
-#pragma unroll
-        for (int h = 0; h < RB; ++h)
-            if (h == jh && lane == jl) {
-#pragma unroll
                 for (int c = 0; c < CB; ++c) x[h][c] = xj[c];
+                used |= 1u << h;
             }
         if (wv == j % NW) {
 #pragma unroll
             for (int c = 0; c < CB; ++c)
                 if (c == cj) {
 #pragma unroll
-                    for (int h = 0; h < RB; ++h) x[h][c] = (lane + 64 * h == j) ? rinv : -fv[h] * rinv;
+                    for (int h = 0; h < RB; ++h) x[h][c] = (lane + 64 * h == p) ? rinv : -fv[h] * rinv;
                 }
         }
     }
-    // undo the row interchanges on the columns: final position of each column
+    // Logical rows and column interchanges of the interchanging form: it would have moved
+    // row p_j to position j by exchanging positions j and q_j; the columns are exchanged
+    // back in reverse order.
     __syncthreads();
+    int* lpos = (int*)colj;      // physical row -> logical position
+    int* physat = lpos + ldx;    // logical position -> physical row
+    int* orig = physat + ldx;    // orig[pos] = column now at position pos
+    int* dest = (int*)(sc + 3 * ldx);
     if (tid == 0) {
-        int* orig = dest + r;   // orig[pos] = column now at position pos
+        for (int i = 0; i < r; ++i) { lpos[i] = i; physat[i] = i; }
+        for (int jj = 0; jj < r; ++jj) {
+            const int q = lpos[colswap[jj]];
+            colswap[jj] = q;
+            const int a0 = physat[jj], a1 = physat[q];
+            physat[jj] = a1; physat[q] = a0;
+            lpos[a1] = jj; lpos[a0] = q;
+        }
         for (int l = 0; l < r; ++l) orig[l] = l;
-        for (int j = r - 1; j >= 0; --j) {
-            const int p = colswap[j];
-            const int t0 = orig[j];
-            orig[j] = orig[p];
-            orig[p] = t0;
+        for (int jj = r - 1; jj >= 0; --jj) {
+            const int q = colswap[jj];
+            const int t0 = orig[jj];
+            orig[jj] = orig[q];
+            orig[q] = t0;
         }
         for (int q = 0; q < r; ++q) dest[orig[q]] = q;
     }
@@ -560,8 +562,9 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int i = lane + 64 * h, l = wv + NW * c;
-            if (i < r && l < r) Xs[i + dest[l] * ldx] = x[h][c];
+            if (i < r && l < r) Xs[lpos[i] + dest[l] * ldx] = x[h][c];
         }
+    __syncthreads();
     // log|det| and sign, summed in pivot order
     for (int i = tid; i < r; i += NTH) colj[i] = log(fabs(pivs[i]));
     __syncthreads();

@@ -34,9 +34,10 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     __shared__ TT Bs[TK][TM + 1];
     __shared__ int rslot[TM], rpos_[TM], cslot[TM], cpos_[TM];
     __shared__ int slot_box[9];
+    __shared__ int slot_nact[9];
     __shared__ int joff[10];
     __shared__ int jslot[9];
-    __shared__ int nS;
+    __shared__ int64_t blkoff[81];   // [row slot * 9 + column slot]: first entry of that block
 
     const int tid = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin in launch order; id = x + 8 s puts all
@@ -51,29 +52,59 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     const int nj = a.nJ[c];
     if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
     const int n = a.cnt[c], k = a.krank[c], r = n - k;
+    if (r <= 0) return;
     const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
     const int cx = c % nb, cy = c / nb;
+    const int row0 = ti * TM, col0 = tj * TM;
+    const TT* XJR = (const TT*)a.XJR + (int64_t)c * ldJ * nmax;
+    const TT* G = (const TT*)a.G + (int64_t)c * nmax * ldJ;
+    // slab k0 of X_JR (rows row0..) and G (columns col0..) into registers; the loads of
+    // the first slab are in flight during the set-up below, those of slab s + 1 during
+    // the products of slab s
+    constexpr int PER = TM * TK / 256;
+    TT va[PER], vb[PER];
+    auto load_slab = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            const int i = e % TM, kk = e / TM;
+            const int row = row0 + i, kc = k0 + kk;
+            va[u] = (row < nj && kc < r) ? XJR[row + (int64_t)kc * ldJ] : (TT)0;
+            const int kb = e % TK, j = e / TK;
+            const int col = col0 + j, kc2 = k0 + kb;
+            vb[u] = (col < nj && kc2 < r) ? G[kc2 + (int64_t)col * nmax] : (TT)0;
+        }
+    };
+    load_slab(0);
+    if (tid < 9) {
+        // slot s = (dy + 1) 3 + (dx + 1) of the 3x3 neighbourhood; the active counts are
+        // loaded by nine threads at once
+        const int ox = cx + tid % 3 - 1, oy = cy + tid / 3 - 1;
+        const int box = (ox < 0 || oy < 0 || ox >= nb || oy >= nb) ? -1 : ox + nb * oy;
+        slot_box[tid] = box;
+        slot_nact[tid] = box < 0 ? 0 : a.nact[box];
+    }
+    __syncthreads();
     if (tid == 0) {
         // J segments: S of c (slot 4), then adjacent boxes in ascending index
-        int cntS = 0;
         joff[0] = 0;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                int s = (dy + 1) * 3 + (dx + 1);
-                int ox = cx + dx, oy = cy + dy;
-                slot_box[s] = (ox < 0 || oy < 0 || ox >= nb || oy >= nb) ? -1 : ox + nb * oy;
-            }
         jslot[0] = 4;
         joff[1] = k;
-        cntS = 1;
+        int cntS = 1;
         for (int s = 0; s < 9; ++s) {
             if (s == 4 || slot_box[s] < 0) continue;
             jslot[cntS] = s;
-            joff[cntS + 1] = joff[cntS] + a.nact[slot_box[s]];
+            joff[cntS + 1] = joff[cntS] + slot_nact[s];
             ++cntS;
         }
-        nS = cntS;
+    } else if (tid >= 64 && tid < 64 + 81) {
+        // block (row box of slot sa, column box of slot sb): offset (sb - sa) in the 3x3 grid
+        const int sa = (tid - 64) / 9, sb = (tid - 64) % 9;
+        const int abox = slot_box[sa];
+        blkoff[tid - 64] = (abox < 0 || slot_box[sb] < 0)
+                               ? (int64_t)-1
+                               : ((int64_t)abox * kNbr + nbr_slot(sb % 3 - sa % 3, sb / 3 - sa / 3)) * bsz;
     }
     __syncthreads();
     if (tid < 2 * TM) {
@@ -91,30 +122,14 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         if (tid < TM) { rslot[i] = sl; rpos_[i] = ps; }
         else { cslot[i] = sl; cpos_[i] = ps; }
     }
-    const TT* XJR = (const TT*)a.XJR + (int64_t)c * ldJ * nmax;
-    const TT* G = (const TT*)a.G + (int64_t)c * nmax * ldJ;
     const int tx = tid & 15, ty = tid >> 4;
     TT acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0;
-    const int row0 = ti * TM, col0 = tj * TM;
     for (int k0 = 0; k0 < r; k0 += TK) {
         __syncthreads();
-        // all loads of the slab are issued before the first store to LDS
-        constexpr int PER = TM * TK / 256;
-        TT va[PER], vb[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = tid + 256 * u;
-            const int i = e % TM, kk = e / TM;
-            const int row = row0 + i, kc = k0 + kk;
-            va[u] = (row < nj && kc < r) ? XJR[row + (int64_t)kc * ldJ] : (TT)0;
-            const int kb = e % TK, j = e / TK;
-            const int col = col0 + j, kc2 = k0 + kb;
-            vb[u] = (col < nj && kc2 < r) ? G[kc2 + (int64_t)col * nmax] : (TT)0;
-        }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + 256 * u;
@@ -122,6 +137,7 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
             Bs[e % TK][e / TK] = vb[u];
         }
         __syncthreads();
+        if (k0 + TK < r) load_slab(k0 + TK);
 #pragma unroll
         for (int kk = 0; kk < TK; ++kk) {
             TT av[4], bv[4];
@@ -135,24 +151,34 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
                 for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
         }
     }
-    __syncthreads();
+    // read-modify-write of the 16 entries: all loads are issued, without branches, before
+    // the first store; an entry outside J reads entry 0 of the store and is not written
+    ST* st = (ST*)a.store;
+    auto entry = [&](int u, int v) -> int64_t {
+        const int i = tx + 16 * u, j = ty + 16 * v;
+        const int sa = rslot[i], sb = cslot[j];
+        const bool in = (sa | sb) >= 0;
+        const int64_t e = blkoff[in ? sa * 9 + sb : 0] + rpos_[i] + (int64_t)cpos_[j] * nmax;
+        return in ? e : (int64_t)-1;
+    };
+    ST old[4][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        int j = ty + 16 * v;
-        int sb = cslot[j];
-        if (sb < 0) continue;
-        int bbox = slot_box[sb];
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) old[u][v] = st[max(entry(u, v), (int64_t)0)];
+    // keep every load here, ahead of the stores (the compiler would otherwise move a load
+    // into the conditional store below and wait for it there)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) asm volatile("" ::"v"(old[u][v]));
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            int i = tx + 16 * u;
-            int sa = rslot[i];
-            if (sa < 0) continue;
-            int abox = slot_box[sa];
-            int dx = (bbox % nb) - (abox % nb), dy = (bbox / nb) - (abox / nb);
-            ST* blk = (ST*)a.store + ((int64_t)abox * kNbr + nbr_slot(dx, dy)) * bsz;
-            blk[rpos_[i] + (int64_t)cpos_[j] * nmax] -= (ST)acc[u][v];
+            const int64_t e = entry(u, v);
+            if (e >= 0) st[e] = old[u][v] - (ST)acc[u][v];
         }
-    }
 }
 
 void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s) {
