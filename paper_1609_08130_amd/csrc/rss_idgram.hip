@@ -15,6 +15,7 @@
 // The ID input of box c is M = [A(O, B_c); w K(Gamma, B_c)] (O = boxes at Chebyshev
 // distance 2, Gamma = n_p proxy points on the circle of radius proxy_radius * side).
 #include <algorithm>
+#include <type_traits>
 
 #include "rss_internal.h"
 
@@ -103,7 +104,7 @@ constexpr int kChunk = 32;        // rows staged in LDS at a time
 // that the colour still spreads over the whole chip.  The partial Gram matrices of the
 // slices are then summed by k_gram_reduce.
 struct GramPlan {
-    int slice_rows, nsl, groups, tpt;
+    int slice_rows, nsl, groups, tpt, nth;
 };
 
 static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes) {
@@ -111,10 +112,22 @@ static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes) {
     const int nt = (nmax + 1) / 2, ntiles = nt * (nt + 1) / 2;
     GramPlan g;
     if (nboxes >= 512) {
+        // fewest tile slots (idle threads) over 192- and 256-thread workgroups with 3, 5 or
+        // 9 tiles per thread, the fewer tiles per thread on a tie
         g.slice_rows = 256;
-        g.tpt = ntiles <= 3 * 256 ? 3 : ntiles <= 5 * 256 ? 5 : 9;
-        g.groups = (ntiles + 9 * 256 - 1) / (9 * 256);
+        int best = 1 << 30;
+        for (int tpt : {3, 5, 9})
+            for (int nth : {192, 256}) {
+                const int groups = (ntiles + nth * tpt - 1) / (nth * tpt);
+                if (groups * nth * tpt < best) {
+                    best = groups * nth * tpt;
+                    g.tpt = tpt;
+                    g.nth = nth;
+                    g.groups = groups;
+                }
+            }
     } else {
+        g.nth = 256;
         g.tpt = 1;
         g.groups = (ntiles + 255) / 256;
         g.slice_rows = 128;
@@ -147,28 +160,74 @@ struct ORing {
     int cnt;
 };
 
+// Offset (dx, dy) of ring slot s: the 16 offsets at distance 2 in ascending (dy, dx) order
+// (5 on the row dy = -2, then pairs dx = -2, 2 on the rows -1, 0, 1, then 5 on dy = 2).
+__device__ inline void ring_offset(int s, int& dx, int& dy) {
+    if (s < 5) { dx = s - 2; dy = -2; }
+    else if (s < 11) { dy = (s - 5) / 2 - 1; dx = ((s - 5) & 1) ? 2 : -2; }
+    else { dx = s - 13; dy = 2; }
+}
+
+// Threads 0..15 look up one ring slot each (the active counts load in parallel); after a
+// barrier, thread 0 lists the boxes that exist in ring order.  Ends with a barrier.
 template <typename ST>
-__device__ inline void build_oring(ORing<ST>& o, const ST* store, const int* nact, const int* apos, int c, int nb,
-                                   int nmax) {
+__device__ inline void build_oring(ORing<ST>& o, int* ring_box, int* ring_nact, const ST* store, const int* nact,
+                                   const int* apos, int c, int nb, int nmax) {
     const int64_t bsz = (int64_t)nmax * nmax;
-    const int cx = c % nb, cy = c / nb;
-    int cntO = 0;
-    o.beg[0] = 0;
-    for (int dy = -2; dy <= 2; ++dy)
-        for (int dx = -2; dx <= 2; ++dx) {
-            if (max(abs(dx), abs(dy)) != 2) continue;
-            int ox = cx + dx, oy = cy + dy;
-            if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
-            int ob = ox + nb * oy;
+    const int tid = threadIdx.x;
+    if (tid < 16) {
+        int dx, dy;
+        ring_offset(tid, dx, dy);
+        const int ox = c % nb + dx, oy = c / nb + dy;
+        const bool in = ox >= 0 && oy >= 0 && ox < nb && oy < nb;
+        ring_box[tid] = in ? ox + nb * oy : -1;
+        ring_nact[tid] = in ? nact[ox + nb * oy] : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int cntO = 0;
+        o.beg[0] = 0;
+        for (int s = 0; s < 16; ++s) {
+            const int ob = ring_box[s];
+            if (ob < 0) continue;
+            int dx, dy;
+            ring_offset(s, dx, dy);
             o.base[cntO] = store + ((int64_t)ob * kNbr + nbr_slot(-dx, -dy)) * bsz;   // block (o, c)
             o.ap[cntO] = apos + (int64_t)ob * nmax;
-            o.beg[cntO + 1] = o.beg[cntO] + nact[ob];
+            o.beg[cntO + 1] = o.beg[cntO] + ring_nact[s];
             ++cntO;
         }
-    o.cnt = cntO;
+        o.cnt = cntO;
+    }
+    __syncthreads();
 }
 
 // ---- 1. partial Gram matrices -------------------------------------------------------------
+// One row of M into the thread's TPT 2x2 tiles: compensated accumulation of each product
+// (TwoSum into s, its error into e); TWOPROD adds the product's own rounding error.
+template <int TPT, bool TWOPROD>
+__device__ inline void gram_row(const double* row, const int (&tp)[TPT], const int (&tq)[TPT], double (&s)[TPT][4],
+                                double (&e)[TPT][4]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+        if (tp[u] < 0) continue;
+        const double a0 = row[tp[u]], a1 = row[tp[u] + 1];
+        const double b0 = row[tq[u]], b1 = row[tq[u] + 1];
+        const double aa[4] = {a0, a0, a1, a1};
+        const double bb[4] = {b0, b1, b0, b1};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double p = aa[v] * bb[v];
+            double sn, te;
+            two_sum(s[u][v], p, sn, te);
+            s[u][v] = sn;
+            if constexpr (TWOPROD) e[u][v] += te + fma(aa[v], bb[v], -p);
+            else e[u][v] += te;
+        }
+    }
+}
+
 // grid (slices x tile groups, boxes); thread owns TPT 2x2 tiles of the upper triangle of G.
 template <int NTH, int TPT, typename ST>
 __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int nb, int nmax,
@@ -180,6 +239,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
 #pragma clang fp contract(off)
     extern __shared__ double Ms[];   // kChunk x (nmax + 1)
     __shared__ ORing<ST> oring;
+    __shared__ int ring_box[16], ring_nact[16];
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
     __shared__ double colx[kMaxBox], coly[kMaxBox];
     __shared__ const ST* rowsrc[kChunk];
@@ -189,7 +249,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     const int grp = blockIdx.x / nslice;
     const int n = cnt[c];
     if (n == 0) return;
-    if (tid == 0) build_oring(oring, store, nact, apos, c, nb, nmax);
+    build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax);
     {
 #pragma clang fp contract(off)
         const int cx = c % nb, cy = c / nb;
@@ -285,28 +345,12 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
             }
         }
         __syncthreads();
-        for (int i = 0; i < rows; ++i) {
-            const double* row = Ms + i * ld;
-#pragma unroll
-            for (int u = 0; u < TPT; ++u) {
-                if (tp[u] < 0) continue;
-                const double a0 = row[tp[u]], a1 = row[tp[u] + 1];
-                const double b0 = row[tq[u]], b1 = row[tq[u] + 1];
-                const double av[4] = {a0 * b0, a0 * b1, a1 * b0, a1 * b1};
-                const double aa[4] = {a0, a0, a1, a1};
-                const double bb[4] = {b0, b1, b0, b1};
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    // compensated accumulation of the product aa*bb (TwoProd + TwoSum)
-                    const double p = av[v];
-                    const double pe = fma(aa[v], bb[v], -p);
-                    double sn, te;
-                    two_sum(s[u][v], p, sn, te);
-                    s[u][v] = sn;
-                    e[u][v] += te + pe;
-                }
-            }
-        }
+        // Rows copied from an FP32 store hold FP32 values, whose products are exact in FP64:
+        // their rounding error term is zero and is not formed (the sums are unchanged).
+        const int exact_end = std::is_same<ST, float>::value ? min(max(mO - r0, 0), rows) : 0;
+        int i = 0;
+        for (; i < exact_end; ++i) gram_row<TPT, false>(Ms + i * ld, tp, tq, s, e);
+        for (; i < rows; ++i) gram_row<TPT, true>(Ms + i * ld, tp, tq, s, e);
     }
     // write the slice's partial Gram (upper triangle, double-double)
     double2* G = (double2*)gpart + ((int64_t)blockIdx.y * nslice + sl) * nmax * nmax;
@@ -396,7 +440,9 @@ __device__ inline double group_sum(double v) {
 }
 
 // One workgroup per box; the SUB adjacent threads 4 q .. 4 q + SUB - 1 own column q and
-// split its dot products (every one of them then holds the same values).  Rows j < kc of
+// split its dot products (every one of them then holds the same values).  The pivot of a
+// step is chosen by every wave from the trailing norms in LDS, so that one barrier per
+// step suffices.  Rows j < kc of
 // R live in LDS (hi and lo parts apart), later rows in the workspace; every thread of a
 // column writes the same value to the same entry, so each reads back only what it wrote
 // itself or what other columns wrote before a barrier.  nsl_fixed > 0: the slices are
@@ -412,12 +458,12 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
                                                int* __restrict__ mrows) {
 #pragma clang fp contract(off)
     constexpr int NW = NTH / 64;
+    constexpr int NQ = NTH / SUB;    // columns the workgroup can hold (n <= NQ)
     extern __shared__ double rl[];   // Rh[kc * nmax] | Rl[kc * nmax]
-    __shared__ int piv[kMaxBox];
-    __shared__ int srank_s[kMaxBox];
-    __shared__ double dh[2][kMaxBox], dl[2][kMaxBox];   // trailing norms^2, by step parity
-    __shared__ double redv[2][NW];
-    __shared__ int redi[2][NW];
+    __shared__ int piv[NQ];
+    __shared__ int srank_s[NQ];
+    __shared__ double dh[2][NQ], dl[2][NQ];   // trailing norms^2, by step parity
+    __shared__ double nuv[2][NQ];             // their sum (-1: column done)
     __shared__ unsigned long long smask[NW];
     const int tid = threadIdx.x;
     const int q = tid / SUB, sub = tid % SUB;
@@ -461,14 +507,16 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
         const int buf = j & 1;
-        const double nu = done ? -1.0 : d.hi + d.lo;
-        if (q < n && sub == 0) { dh[buf][q] = d.hi; dl[buf][q] = d.lo; }
-        double wmax = wave_max_d(nu);
-        if (lane == 0) redv[buf][wv] = wmax;
+        if (q < n && sub == 0) {
+            dh[buf][q] = d.hi;
+            dl[buf][q] = d.lo;
+            nuv[buf][q] = done ? -1.0 : d.hi + d.lo;
+        }
         __syncthreads();
-        double numax = redv[buf][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) numax = fmax(numax, redv[buf][w]);
+        // largest trailing norm, then the lowest column within tau rnorm0 of it
+        double wm = -1.0;
+        for (int t = lane; t < n; t += 64) wm = fmax(wm, nuv[buf][t]);
+        const double numax = wave_max_d(wm);
         const double mu = sqrt(fmax(numax, 0.0));
         if (!(numax == numax)) break;
         if (j == 0) {
@@ -478,13 +526,15 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
             break;
         }
         const double thr = mu - kp.tau * rnorm0;
-        int cand = (!done && nu >= 0.0 && sqrt(nu) >= thr) ? q : (1 << 30);
-        int wmin = wave_min_i(cand);
-        if (lane == 0) redi[buf][wv] = wmin;
-        __syncthreads();
-        int p = redi[buf][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) p = min(p, redi[buf][w]);
+        int p = 1 << 30;
+        for (int t0 = 0; t0 < n; t0 += 64) {
+            const double nu = t0 + lane < n ? nuv[buf][t0 + lane] : -1.0;
+            const unsigned long long b = __ballot(nu >= 0.0 && sqrt(nu) >= thr);
+            if (b) {
+                p = t0 + __ffsll((long long)b) - 1;
+                break;
+            }
+        }
         if (p >= n) break;
         // every thread forms r_jj itself (no extra barrier)
         const dd rjj = dd_sqrt({dh[buf][p], dl[buf][p]});
@@ -581,8 +631,11 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
     const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 1);
     int launches = 2;
     if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else if (g.tpt == 3 && g.nth == 192) gram_launch<192, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3) gram_launch<256, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else if (g.tpt == 5 && g.nth == 192) gram_launch<192, 5>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 5) gram_launch<256, 5>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    else if (g.nth == 192) gram_launch<192, 9>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else gram_launch<256, 9>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     int nsl_fixed = 0;
     if (g.groups > 1 || g.slice_rows < 256) {
