@@ -64,21 +64,34 @@ __device__ inline bool xcd_tile(int ntile, int nbox, int& bi, int& tile) {
 
 static inline unsigned xcd_grid(int ntile, int nbox) { return (unsigned)(8 * ntile * ((nbox + 7) / 8)); }
 
-// dst(e) = src(e) for e < total, NTH threads, each issuing U loads before the first
-// store so that U global loads per thread are in flight at a time.
+// dst(i, j) = src(i, j) for i < rows, j < cols, taken in the order e = i + rows j: thread t
+// handles e = t, t + NTH, ... and issues U loads before its first store.  The (i, j) of
+// successive elements advance by the fixed step (NTH % rows, NTH / rows), so no division
+// is done per element.
 template <int NTH, int U = 8, typename Load, typename Store>
-__device__ inline void stage_batched(int total, Load load, Store store) {
+__device__ inline void stage2d(int rows, int cols, Load load, Store store) {
+    const int total = rows * cols;
+    if (total <= 0) return;
+    const int di = NTH % rows, dj = NTH / rows;
+    int i = threadIdx.x % rows, j = threadIdx.x / rows;
+    auto advance = [&](int& a, int& b) {
+        a += di;
+        b += dj;
+        if (a >= rows) { a -= rows; ++b; }
+    };
     for (int e0 = threadIdx.x; e0 < total; e0 += NTH * U) {
         double v[U];
+        const int i0 = i, j0 = j;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * NTH;
-            v[u] = e < total ? load(e) : 0.0;
+            v[u] = e0 + u * NTH < total ? load(i, j) : 0.0;
+            advance(i, j);
         }
+        int a = i0, b = j0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * NTH;
-            if (e < total) store(e, v[u]);
+            if (e0 + u * NTH < total) store(a, b, v[u]);
+            advance(a, b);
         }
     }
 }
@@ -116,9 +129,8 @@ __device__ void elim_setup(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, 
         sh.srcpos[tid] = in ? a.nact[ox + nb * oy] : 0;
     }
     const double* Tg = a.T + (int64_t)c * bsz;
-    stage_batched<NTH>(
-        k * r, [&](int e) { return Tg[(e % k) + (int64_t)(e / k) * nmax]; },
-        [&](int e, double v) { Ts[(e / k) + r * (e % k)] = v; });
+    stage2d<NTH>(
+        k, r, [&](int q, int b) { return Tg[q + (int64_t)b * nmax]; }, [&](int q, int b, double v) { Ts[b + r * q] = v; });
     __syncthreads();
     if (tid == 0) {
         int cntN = 0;
@@ -176,14 +188,13 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
     }
     __syncthreads();
     // tA[i + tw col]: line i of the tile at B position (col < k ? sp[col] : rp[col - k])
-    stage_batched<NTH>(
-        tr * n,
-        [&](int e) {
-            const int i = e % tr, col = e / tr;
+    stage2d<NTH>(
+        tr, n,
+        [&](int i, int col) {
             const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
             return (double)sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
         },
-        [&](int e, double v) { tA[(e % tr) + tw * (e / tr)] = v; });
+        [&](int i, int col, double v) { tA[i + tw * col] = v; });
     __syncthreads();
     const int i = tid & 31, bg = tid >> 5;
     if (i < tr) {
@@ -245,21 +256,25 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
         }
     }
     __syncthreads();
-    // tA[pos + nmax jp] = A(B_c position pos, J column c0 + jp)
-    stage_batched<NTH>(
-        tc * n, [&](int e) { const int pos = e % n, jp = e / n; return (double)sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax]; },
-        [&](int e, double v) { tA[(e % n) + nmax * (e / n)] = v; });
+    // tA[rho + nmax jp] = A(B_c position of rho, J column c0 + jp), rows in the order S, R
+    // (rho < k: sp[rho]; else rp[rho - k])
+    stage2d<NTH>(
+        n, tc,
+        [&](int rho, int jp) {
+            const int pos = rho < k ? sh.sp[rho] : sh.rp[rho - k];
+            return (double)sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax];
+        },
+        [&](int rho, int jp, double v) { tA[rho + nmax * jp] = v; });
     __syncthreads();
     // X_RJ[b][jp] = A(rp[b], jp) - sum_q T[q][b] A(sp[q], jp), q ascending
     for (int b = lane; b < r; b += 64) {
         double v[VC];
 #pragma unroll
-        for (int u = 0; u < VC; ++u) v[u] = tA[sh.rp[b] + nmax * min(jg + NW * u, tc - 1)];
+        for (int u = 0; u < VC; ++u) v[u] = tA[k + b + nmax * min(jg + NW * u, tc - 1)];
         for (int q = 0; q < k; ++q) {
             const double t = Ts[b + r * q];
-            const int sq = sh.sp[q];
 #pragma unroll
-            for (int u = 0; u < VC; ++u) v[u] -= t * tA[sq + nmax * min(jg + NW * u, tc - 1)];
+            for (int u = 0; u < VC; ++u) v[u] -= t * tA[q + nmax * min(jg + NW * u, tc - 1)];
         }
 #pragma unroll
         for (int u = 0; u < VC; ++u)
@@ -277,9 +292,9 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
         const int qn = min(qc, r - q0);
         const double* W = Xi + (int64_t)q0 * nmax;
         if (!xi_lds) {
-            stage_batched<NTH>(
-                r * qn, [&](int e) { return W[(e % r) + (int64_t)(e / r) * nmax]; },
-                [&](int e, double v) { tA[(e % r) + nmax * (e / r)] = v; });
+            stage2d<NTH>(
+                r, qn, [&](int b, int q) { return W[b + (int64_t)q * nmax]; },
+                [&](int b, int q, double v) { tA[b + nmax * q] = v; });
             __syncthreads();
             W = tA;
         }
