@@ -117,9 +117,11 @@ template <typename ST>
 __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, const int* __restrict__ cnt,
                                                     const int* __restrict__ gidx, const double* __restrict__ pts,
                                                     int nb, int nmax, double coef, double diag, int* flag) {
-    __shared__ double xa[kMaxBox], ya[kMaxBox], xb[kMaxBox], yb[kMaxBox];
-    __shared__ int ga[kMaxBox], gb[kMaxBox];
-    __shared__ double tile[64][65];
+    // the row point of a thread comes from registers, the column points (the same for the
+    // whole wave) from LDS; the transposing tile holds entries in the store's type
+    __shared__ double xb[kMaxBox], yb[kMaxBox];
+    __shared__ int gb[kMaxBox];
+    __shared__ ST tile[64][65];
     const int a = blockIdx.x / 13, oi = blockIdx.x % 13;
     // oi = 0: self; oi = 1..12: the offsets after (0, 0) in row-major order of the 5x5 window
     const int o = 12 + oi;
@@ -129,10 +131,6 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
     if (bx < 0 || by < 0 || bx >= nb || by >= nb) return;
     const int b = bx + nb * by;
     const int na = cnt[a], nbb = cnt[b];
-    for (int i = threadIdx.x; i < na; i += blockDim.x) {
-        int g = gidx[(int64_t)a * nmax + i];
-        ga[i] = g; xa[i] = pts[2 * (int64_t)g]; ya[i] = pts[2 * (int64_t)g + 1];
-    }
     for (int i = threadIdx.x; i < nbb; i += blockDim.x) {
         int g = gidx[(int64_t)b * nmax + i];
         gb[i] = g; xb[i] = pts[2 * (int64_t)g]; yb[i] = pts[2 * (int64_t)g + 1];
@@ -143,22 +141,30 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
     const bool self = oi == 0;
     bool dup = false;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i0 = 0; i0 < na; i0 += 64)
+    for (int i0 = 0; i0 < na; i0 += 64) {
+        const int ti = min(64, na - i0);
+        int gi = -1;
+        double xi = 0.0, yi = 0.0;
+        if (lane < ti) {
+            gi = gidx[(int64_t)a * nmax + i0 + lane];
+            xi = pts[2 * (int64_t)gi];
+            yi = pts[2 * (int64_t)gi + 1];
+        }
         for (int j0 = 0; j0 < nbb; j0 += 64) {
-            const int ti = min(64, na - i0), tj = min(64, nbb - j0);
+            const int tj = min(64, nbb - j0);
             // rows i0 + lane, columns j0 + wv + 4 t
             for (int jj = wv; jj < tj; jj += 4) {
                 const int j = j0 + jj;
-                double v = 0.0;
+                ST v = (ST)0;
                 if (lane < ti) {
                     const int i = i0 + lane;
-                    if (ga[i] == gb[j]) {
-                        v = diag;
+                    if (gi == gb[j]) {
+                        v = (ST)diag;
                     } else {
-                        v = kernel_entry(xa[i], ya[i], xb[j], yb[j], coef);
-                        dup |= (xa[i] == xb[j] && ya[i] == yb[j]);
+                        v = (ST)kernel_entry(xi, yi, xb[j], yb[j], coef);
+                        dup |= (xi == xb[j] && yi == yb[j]);
                     }
-                    blk_ab[i + (int64_t)j * nmax] = (ST)v;
+                    blk_ab[i + (int64_t)j * nmax] = v;
                 }
                 tile[jj][lane] = v;
             }
@@ -166,10 +172,11 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
                 __syncthreads();
                 // A(B_b, B_a)(j, i) = A(B_a, B_b)(i, j): rows j0 + lane, columns i0 + wv + 4 t
                 for (int ii = wv; ii < ti; ii += 4)
-                    if (lane < tj) blk_ba[(j0 + lane) + (int64_t)(i0 + ii) * nmax] = (ST)tile[lane][ii];
+                    if (lane < tj) blk_ba[(j0 + lane) + (int64_t)(i0 + ii) * nmax] = tile[lane][ii];
                 __syncthreads();
             }
         }
+    }
     if (dup) atomicOr(flag, 2);
 }
 
