@@ -212,8 +212,9 @@ __device__ inline void gram_row(const double* row, const int (&tp)[TPT], const i
 #pragma unroll
     for (int u = 0; u < TPT; ++u) {
         if (tp[u] < 0) continue;
-        const double a0 = row[tp[u]], a1 = row[tp[u] + 1];
-        const double b0 = row[tq[u]], b1 = row[tq[u] + 1];
+        const double2 ap = *(const double2*)(row + tp[u]);
+        const double2 bq = *(const double2*)(row + tq[u]);
+        const double a0 = ap.x, a1 = ap.y, b0 = bq.x, b1 = bq.y;
         const double aa[4] = {a0, a0, a1, a1};
         const double bb[4] = {b0, b1, b0, b1};
 #pragma unroll
@@ -237,7 +238,10 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
                                               const double* __restrict__ ptmpl, KernelParams kp, int t,
                                               double* __restrict__ gpart, int nslice, int slice_rows) {
 #pragma clang fp contract(off)
-    extern __shared__ double Ms[];   // kChunk x (nmax + 1)
+    // kChunk rows of M, leading dimension nmax + 2: even, so that the column pairs of a
+    // 2x2 tile are 16-byte aligned and read as one double2
+    extern __shared__ double2 Ms2[];
+    double* Ms = (double*)Ms2;
     __shared__ ORing<ST> oring;
     __shared__ int ring_box[16], ring_nact[16];
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
@@ -273,7 +277,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     const int r_begin = sl * slice_rows;
     if (r_begin >= m) return;
     const int r_end = min(m, r_begin + slice_rows);
-    const int ld = nmax + 1;
+    const int ld = nmax + 2;
     const int nt = (n + 1) >> 1;                  // 2x2 tiles per dimension
     const int ntiles = nt * (nt + 1) / 2;
     if (grp * NTH * TPT >= ntiles) return;        // this box has no tiles in the group
@@ -600,6 +604,11 @@ template <int NTH, int TPT>
 static void gram_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                         const KernelParams& kp, double* gpart, const GramPlan& g, size_t lds, hipStream_t s) {
     const dim3 grid(g.nsl * g.groups, nboxes);
+    // the chunk exceeds the default 64 KB of dynamic LDS only for nmax > 254
+    if (L.store32)
+        hipFuncSetAttribute((const void*)k_gram<NTH, TPT, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    else
+        hipFuncSetAttribute((const void*)k_gram<NTH, TPT, double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (L.store32)
         k_gram<NTH, TPT, float><<<grid, dim3(NTH), lds, s>>>((const float*)L.store, L.nb, L.nmax, L.cnt, L.gidx,
                                                               L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart,
@@ -628,7 +637,7 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
     const size_t nn = (size_t)L.nmax * L.nmax;
     double* gpart = work;
     double* rwork = work + (size_t)nboxes * g.nsl * nn * 2;
-    const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 1);
+    const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 2);
     int launches = 2;
     if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3 && g.nth == 192) gram_launch<192, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
