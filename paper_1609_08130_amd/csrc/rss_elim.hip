@@ -450,22 +450,16 @@ __device__ inline double lane_read(double v, int ln) {
 // had reached there) are undone on the way out.  One barrier per step: the wave that owns
 // column j picks the pivot and publishes column j, which goes through a buffer of two halves
 // used in alternate steps; every wave reads row p of its own columns from the lane holding it.
+// x holds the matrix on entry (zero outside r x r); the inverse is written to Xs (ld ldx).
 // sc: 4 * ldx doubles of LDS.
 template <int NTH, int RB, int CB>
-__device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double* sc, double& ld_sum, int& sgn) {
+__device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, int r, int* colswap, double* sc,
+                               double& ld_sum, int& sgn) {
     constexpr int NW = NTH / 64;
     const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
     double* colj = sc;                  // two halves of ldx
     double* pivs = sc + 2 * ldx;
-    double x[RB][CB];
-#pragma unroll
-    for (int h = 0; h < RB; ++h)
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int i = lane + 64 * h, l = wv + NW * c;
-            x[h][c] = (i < r && l < r) ? Xs[i + l * ldx] : 0.0;
-        }
     unsigned used = 0;   // bit h: row lane + 64 h has been a pivot row
     for (int j = 0; j < r; ++j) {
         double* cb = colj + (j & 1) * ldx;
@@ -594,6 +588,44 @@ __device__ bool gj_inverse_reg(double* Xs, int ldx, int r, int* colswap, double*
     return true;
 }
 
+// X_RR = Y_RR - T^T Z_S straight into the registers of gj_inverse_reg (thread (wave w, lane)
+// forms X[lane + 64 h][w + NW c], reading T for its rows and Z_S for its columns once per q),
+// also written to XRR; then the inverse into Xs.
+template <int NTH, int RB, int CB>
+__device__ bool xrr_gj_reg(const double* Yg, int nmax, const double* Ts, const double* zs, int ldz, int k, int r,
+                           double* XRR, double* Xs, int* colswap, double* sc, double& ld_sum, int& sgn) {
+    constexpr int NW = NTH / 64;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double x[RB][CB];
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = lane + 64 * h, l = wv + NW * c;
+            x[h][c] = (i < r && l < r) ? Yg[i + (int64_t)l * nmax] : 0.0;
+        }
+    for (int q = 0; q < k; ++q) {
+        double t[RB], z[CB];
+#pragma unroll
+        for (int h = 0; h < RB; ++h) t[h] = Ts[min(lane + 64 * h, r - 1) + r * q];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) z[c] = zs[q + (int64_t)min(wv + NW * c, r - 1) * ldz];
+#pragma unroll
+        for (int h = 0; h < RB; ++h)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) x[h][c] -= t[h] * z[c];
+    }
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = lane + 64 * h, l = wv + NW * c;
+            if (i < r && l < r) XRR[i + (int64_t)l * nmax] = x[h][c];
+            else x[h][c] = 0.0;
+        }
+    return gj_inverse_reg<NTH, RB, CB>(x, Xs, nmax, r, colswap, sc, ld_sum, sgn);
+}
+
 // X_RR = Y_RR - T^T Z_S (Y_RR read from Yg, formed by the row tiles),
 // then its inverse, log|det| and the per-box records.  Returns false when X_RR is singular.
 template <int NTH, typename ST>
@@ -616,24 +648,40 @@ __device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, i
         zs = xsr;
         ldz = k;
     }
-    for (int e = tid; e < r * r; e += NTH) {
-        int b = e % r, b2 = e / r;
-        double v = Yg[b + (int64_t)b2 * nmax];
-        for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * zs[q + (int64_t)b2 * ldz];
-        XRR[b + (int64_t)b2 * nmax] = v;
-        Xs[b + b2 * nmax] = v;
-    }
-    __syncthreads();
     double ld_sum;
     int sgn;
     bool ok;
-    if constexpr (NTH == 1024) {
-        if (r <= 64) ok = gj_inverse_reg<NTH, 1, 4>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
-        else if (r <= 128) ok = gj_inverse_reg<NTH, 2, 8>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
-        else ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+    // Large workgroups (few boxes): X_RR formed in the registers of the register Gauss-Jordan
+    // when 64 RB rows and 16 CB columns cover r.  Otherwise X_RR goes through Xs, then to
+    // the register form (r <= 64, 256 threads) or the LDS form.
+    if (NTH == 1024 && r <= 128) {
+        if constexpr (NTH == 1024) {
+            if (r <= 64) ok = xrr_gj_reg<NTH, 1, 4>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
+            else if (r <= 96) ok = xrr_gj_reg<NTH, 2, 6>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
+            else ok = xrr_gj_reg<NTH, 2, 8>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
+        }
     } else {
-        if (r <= 64) ok = gj_inverse_reg<NTH, 1, 16>(Xs, nmax, r, colswap, sc, ld_sum, sgn);
-        else ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+        for (int e = tid; e < r * r; e += NTH) {
+            int b = e % r, b2 = e / r;
+            double v = Yg[b + (int64_t)b2 * nmax];
+            for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * zs[q + (int64_t)b2 * ldz];
+            XRR[b + (int64_t)b2 * nmax] = v;
+            Xs[b + b2 * nmax] = v;
+        }
+        __syncthreads();
+        if (NTH == 256 && r <= 64) {
+            constexpr int CB = NTH / 16;   // 16 columns per thread at 256 threads
+            double x[1][CB];
+            const int wv = tid >> 6, lane = tid & 63;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int l = wv + (NTH / 64) * c;
+                x[0][c] = (lane < r && l < r) ? Xs[lane + l * nmax] : 0.0;
+            }
+            ok = gj_inverse_reg<NTH, 1, CB>(x, Xs, nmax, r, colswap, sc, ld_sum, sgn);
+        } else {
+            ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+        }
     }
     if (!ok) return false;
     if (tid == 0) {
