@@ -67,3 +67,26 @@ def problem(n: int, tol: float = 1e-6, leaf_size: int = 64, n_proxy: int = 16,
     """Parameter dictionary for the 2D Laplace grid problem of side n."""
     return dict(dim=2, diag=1.0, weight=laplace2d_weight(n), tol=tol, leaf_size=leaf_size,
                 n_proxy=n_proxy, proxy_radius=proxy_radius, root_lo=(0.0, 0.0), root_side=1.0)
+
+
+def laplace2d_cell_self_term(n: int) -> float:
+    """Integral of K(z) = -(1/(2 pi)) log|z| over one grid cell [-h/2, h/2]^2, h = 1/n.
+
+    This is the diagonal entry of the first-kind system of Example 1 (Section 4.1), where
+    the paper approximates the same integral by adaptive quadrature.  Closed form: by the
+    eight-fold symmetry of the square, in polar coordinates over the triangle
+    0 <= theta <= pi/4, 0 <= r <= a / cos(theta) (a = h/2),
+      int_square log(x^2 + y^2) = 8 a^2 (log a + log(2)/2 - 3/2 + pi/4),
+    and K = -(1/(4 pi)) log(x^2 + y^2).
+    """
+    a = 0.5 / float(n)
+    return -(8.0 * a * a / (4.0 * np.pi)) * (np.log(a) + 0.5 * np.log(2.0) - 1.5 + 0.25 * np.pi)
+
+
+def problem_first_kind(n: int, tol: float = 1e-6, leaf_size: int = 64, n_proxy: int = 16,
+                       proxy_radius: float = 1.25) -> dict:
+    """The first-kind volume integral equation of Example 1 (Section 4.1) on the n x n grid:
+    A_ij = h^2 K(x_i - x_j) for i != j and A_ii = the integral of K over one cell."""
+    d = problem(n, tol, leaf_size, n_proxy, proxy_radius)
+    d["diag"] = laplace2d_cell_self_term(n)
+    return d

@@ -1,0 +1,65 @@
+"""Example 1 of Section 4.1 (first-kind equation on the unit square) on the GPU: parity
+with the oracle on the small grid, and e_a, e_s, n_i at the paper's smallest size
+(N = 512^2) against its RS-S accuracy table (order of magnitude: the paper used
+n_occ = 256, 64 proxies and CG; here leaf 64, 16 proxies and GMRES)."""
+import numpy as np
+import pytest
+
+from oracle import rss_oracle as O
+from paper_1609_08130_amd import workloads as W
+from tests.example1_util import paper_row, power_norm
+from tests.parity_util import say
+from tests.test_gpu_parity import _compare, _gpu_factor
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08130_amd import rss as mod
+    return mod
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_parity_first_kind_grid64(rss, tol):
+    n = 64
+    _compare(rss, f"first_kind_grid64_tol{tol}", W.grid_points(n), O.Params(**W.problem_first_kind(n, tol)))
+
+
+@pytest.mark.parametrize("n,tol,precision", [(512, 1e-6, "fp64"), (512, 1e-6, "mixed"), (1024, 1e-6, "mixed")])
+def test_first_kind_accuracy_against_paper(rss, n, tol, precision):
+    say(f"[example1] N={n * n} tol={tol} precision={precision}")
+    p = O.Params(**W.problem_first_kind(n, tol))
+    F = _gpu_factor(rss, W.grid_points(n), p, precision)
+    use32 = precision == "mixed"
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    x0 = torch.randn(n * n, generator=gen, dtype=torch.float64).cuda()
+    tn = lambda t: float(torch.linalg.norm(t))
+    nA = power_norm(F.matvec, x0, norm=tn)
+    e_a = power_norm(lambda v: F.matvec(v) - F.apply(v), x0, norm=tn) / nA
+    e_s = power_norm(lambda v: v - F.matvec(F.solve(v, use_fp32=use32)), x0, norm=tn)
+    x = torch.randn(n * n, generator=gen, dtype=torch.float64).cuda()
+    b = F.matvec(x)
+    _, n_i, relres = F.gmres(b, rtol=1e-12, maxit=50, use_fp32=use32)
+    F.close()
+    ref = paper_row(tol, n)
+    say(f"[example1] N={n * n} tol={tol} {precision}: e_a={e_a:.2e} e_s={e_s:.2e} n_i={n_i} relres={relres:.1e} "
+        f"(paper RS-S: {ref['e_a']:.1e} {ref['e_s']:.1e} {ref['n_i']})")
+    assert relres <= 1e-12
+    assert e_a <= 10 * tol
+    assert ref["e_a"] / 100 <= e_a <= ref["e_a"] * 100
+    assert e_s <= ref["e_s"] * 100
+    assert n_i <= ref["n_i"] + 3
+
+
+def test_first_kind_tol1e9_exceeds_box_limit(rss):
+    # At tol 1e-9 the first-kind system of N = 512^2 needs more than 256 active DOFs in a
+    # box of the upper levels, beyond this build's per-box limit: a clean error, no factor.
+    n = 512
+    say(f"[example1] N={n * n} tol=1e-9: expecting RSS_E_UNSUPPORTED")
+    with pytest.raises(rss.RSSError) as ei:
+        _gpu_factor(rss, W.grid_points(n), O.Params(**W.problem_first_kind(n, 1e-9)), "fp64")
+    assert ei.value.status == 5
