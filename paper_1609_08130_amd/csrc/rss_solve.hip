@@ -31,12 +31,19 @@ struct SweepArgs {
     const double* XRR;
 };
 
-// sum_{t < cnt} M[t * stride] v[t] in eight partial sums, so that eight loads of M are in
-// flight at a time.
+// sum_{t < cnt} M[t * stride] v[t] in eight partial sums, with sixteen loads of M in
+// flight at a time (eight for the tail).
 template <typename TT>
 __device__ inline double dot_strided(const TT* __restrict__ M, int64_t stride, const double* v, int cnt) {
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int t = 0;
+    for (; t + 16 <= cnt; t += 16) {
+        TT m[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) m[u] = M[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s[u & 7] += (double)m[u] * v[t + u];
+    }
     for (; t + 8 <= cnt; t += 8) {
         TT m[8];
 #pragma unroll
