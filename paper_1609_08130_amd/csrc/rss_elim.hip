@@ -97,6 +97,8 @@ __device__ inline void stage2d(int rows, int cols, Load load, Store store) {
 }
 
 // Per-workgroup tables of box c in LDS (ST: entry type of the block store).
+typedef double f64x4 __attribute__((ext_vector_type(4)));   // accumulator of one FP64 MFMA block
+
 template <typename ST>
 struct ElimShared {
     int sp[kMaxBox], rp[kMaxBox];   // B positions of S and R
@@ -281,12 +283,17 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
             if (jg + NW * u < tc) tX[b + nmax * (jg + NW * u)] = v[u];
     }
     __syncthreads();
-    // G = X_RR^{-1} X_RJ, q ascending; rows b = lane + 64 h
-    double acc[HB][VC];
+    // G = X_RR^{-1} X_RJ on the FP64 matrix cores: 16 x 16 blocks of G dealt to the waves,
+    // one v_mfma_f64_16x16x4 per 4 values of q.  Operand layout of the instruction: lane l
+    // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16]
+    // for v < 4.
+    constexpr int MB = 2 * HB;   // blocks per wave: r <= 64 HB rows, <= 32 columns, 4 waves
+    static_assert(NW == 4 && kTileMax <= 32, "block count per wave assumes 4 waves and <= 32 columns");
+    const int nrb = (r + 15) / 16, nblk = nrb * ((tc + 15) / 16);
+    const int l16 = lane & 15, l4 = lane >> 4;
+    f64x4 acc[MB];
 #pragma unroll
-    for (int h = 0; h < HB; ++h)
-#pragma unroll
-        for (int u = 0; u < VC; ++u) acc[h][u] = 0.0;
+    for (int m = 0; m < MB; ++m) acc[m] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int qc = xi_lds ? r : tw;
     for (int q0 = 0; q0 < r; q0 += qc) {
         const int qn = min(qc, r - q0);
@@ -298,30 +305,32 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
             __syncthreads();
             W = tA;
         }
-        for (int qq = 0; qq < qn; ++qq) {
-            double x[VC];
 #pragma unroll
-            for (int u = 0; u < VC; ++u) x[u] = tX[(q0 + qq) + nmax * min(jg + NW * u, tc - 1)];
-#pragma unroll
-            for (int h = 0; h < HB; ++h) {
-                if (64 * h >= r) break;
-                const double w = W[min(lane + 64 * h, r - 1) + nmax * qq];
-#pragma unroll
-                for (int u = 0; u < VC; ++u) acc[h][u] += w * x[u];
+        for (int m = 0; m < MB; ++m) {
+            const int blk = jg + NW * m;
+            if (blk >= nblk) break;
+            const int row = (blk % nrb) * 16 + l16, col = (blk / nrb) * 16 + l16;
+            for (int qq = 0; qq < qn; qq += 4) {
+                const int kk = qq + l4;
+                const double av = (row < r && kk < qn) ? W[row + nmax * kk] : 0.0;
+                const double bv = (kk < qn && col < tc) ? tX[(q0 + kk) + nmax * col] : 0.0;
+                acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
             }
         }
         if (!xi_lds) __syncthreads();
     }
 #pragma unroll
-    for (int h = 0; h < HB; ++h) {
-        const int b = lane + 64 * h;
-        if (b >= r) break;
+    for (int m = 0; m < MB; ++m) {
+        const int blk = jg + NW * m;
+        if (blk >= nblk) break;
+        const int col = (blk / nrb) * 16 + l16;
 #pragma unroll
-        for (int u = 0; u < VC; ++u) {
-            const int jp = jg + NW * u;
-            if (jp >= tc) continue;
-            G[b + (int64_t)(c0 + jp) * nmax] = acc[h][u];
-            if (G32) G32[b + (int64_t)(c0 + jp) * nmax] = (float)acc[h][u];
+        for (int v = 0; v < 4; ++v) {
+            const int b = (blk % nrb) * 16 + l4 + 4 * v;
+            if (b < r && col < tc) {
+                G[b + (int64_t)(c0 + col) * nmax] = acc[m][v];
+                if (G32) G32[b + (int64_t)(c0 + col) * nmax] = (float)acc[m][v];
+            }
         }
     }
     __syncthreads();
