@@ -164,12 +164,10 @@ __device__ inline int j_global(const ElimShared<ST>& sh, const ElimArgs& a, int 
 
 // Rows [r0, r0 + tr) of E = [J; R] against the columns R: rows of J give X_JR (and its
 // FP32 copy when XJR32 != nullptr), rows past J give Y_RR = A_RR - A_RS T (into Y, ld nmax).
-// tA: tw x n.  Thread t takes row t % 32 of the tile and, per pass, 8 columns of R spaced
-// NTH / 32 apart, so each A(i, S_q) read from LDS serves 8 products.
+// tA: tw x n.
 template <int NTH, typename ST>
 __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
                                int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
-    constexpr int BG = NTH / 32;   // column groups
     const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int n = k + r;
     const ST* Acc = (const ST*)a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
@@ -198,31 +196,40 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
         },
         [&](int i, int col, double v) { tA[i + tw * col] = v; });
     __syncthreads();
-    const int i = tid & 31, bg = tid >> 5;
-    if (i < tr) {
-        const int row = r0 + i;
-        for (int b0 = bg; b0 < r; b0 += 8 * BG) {
-            double v[8];
+    // The transposed tile (r x tr) on the FP64 matrix cores, so that the 16 lanes of a
+    // result row hold 16 consecutive lines: D = A_(tile, R)^T - T^T A_(tile, S)^T with
+    // A = -T^T (A[b][q] = -Ts[b + r q]) and B[q][i] = tA[i + tw q]; D starts at the R
+    // columns of the tile.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+    // receives D[l / 16 + 4 v][l % 16].  16 x 16 blocks are dealt to the waves.
+    const int lane = tid & 63, wv = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int nrb = (r + 15) / 16, nblk = nrb * ((tr + 15) / 16);
+    for (int blk = wv; blk < nblk; blk += NTH / 64) {
+        const int rb = (blk % nrb) * 16, i = (blk / nrb) * 16 + l16;
+        f64x4 x;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int b = min(b0 + BG * u, r - 1);
-                v[u] = tA[i + tw * (k + b)];
-            }
-            for (int q = 0; q < k; ++q) {
-                const double x = tA[i + tw * q];
-                const double* tq = Ts + r * q;
+        for (int v = 0; v < 4; ++v) {
+            const int b = rb + l4 + 4 * v;
+            x[v] = (b < r && i < tr) ? tA[i + tw * (k + b)] : 0.0;
+        }
+        const int ar = rb + l16;
+        for (int q0 = 0; q0 < k; q0 += 4) {
+            const int q = q0 + l4;
+            const double av = (ar < r && q < k) ? -Ts[ar + r * q] : 0.0;
+            const double bv = (q < k && i < tr) ? tA[i + tw * q] : 0.0;
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x, 0, 0, 0);
+        }
+        if (i < tr) {
+            const int row = r0 + i;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] -= x * tq[min(b0 + BG * u, r - 1)];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int b = b0 + BG * u;
+            for (int v = 0; v < 4; ++v) {
+                const int b = rb + l4 + 4 * v;
                 if (b >= r) break;
                 if (row < nj) {
-                    XJR[row + (int64_t)b * ldJ] = v[u];
-                    if (XJR32) XJR32[row + (int64_t)b * ldJ] = (float)v[u];
+                    XJR[row + (int64_t)b * ldJ] = x[v];
+                    if (XJR32) XJR32[row + (int64_t)b * ldJ] = (float)x[v];
                 } else {
-                    Y[(row - nj) + (int64_t)b * nmax] = v[u];
+                    Y[(row - nj) + (int64_t)b * nmax] = x[v];
                 }
             }
         }
@@ -230,17 +237,14 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
     __syncthreads();
 }
 
-// Columns [c0, c0 + tc) of J: X_RJ = A_RJ - T^T A_SJ (tX, ld nmax), then
-// G = X_RR^{-1} X_RJ.  tA, tX: nmax x tw.  X_RR^{-1} (ld nmax) is read from Xi when it is
-// in LDS (xi_lds); otherwise it is staged through tA, tw columns at a time.  Thread t
-// takes rows b = t % 64 + 64 h (h < HB, r <= 64 HB) of the result and the columns
-// t / 64 + NW v of the tile.
+// Columns [c0, c0 + tc) of J: X_RJ = A_RJ - T^T A_SJ (tX, ld nmax + 1), then
+// G = X_RR^{-1} X_RJ.  tA, tX: (nmax + 1) x tw.  X_RR^{-1} (ld nmax) is read from Xi when
+// it is in LDS (xi_lds); otherwise it is staged through tA, tw columns at a time.  r <= 64 HB.
 template <int NTH, int HB, typename ST>
 __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int c0, int tc, int tw,
                             const double* Ts, double* tA, double* tX, const double* Xi, bool xi_lds, double* G,
                             float* G32) {
     constexpr int NW = NTH / 64;
-    constexpr int VC = (kTileMax + NW - 1) / NW;   // tile columns per thread
     const int tid = threadIdx.x, nmax = a.nmax;
     const int n = k + r;
     const int lane = tid & 63, jg = tid >> 6;
@@ -258,39 +262,55 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
         }
     }
     __syncthreads();
-    // tA[rho + nmax jp] = A(B_c position of rho, J column c0 + jp), rows in the order S, R
-    // (rho < k: sp[rho]; else rp[rho - k])
+    // tA[rho + ldt jp] = A(B_c position of rho, J column c0 + jp), rows in the order S, R
+    // (rho < k: sp[rho]; else rp[rho - k]); ldt = nmax + 1 is odd, so that 16 lanes reading
+    // one row of 16 columns hit 16 different banks
+    const int ldt = nmax + 1;
     stage2d<NTH>(
         n, tc,
         [&](int rho, int jp) {
             const int pos = rho < k ? sh.sp[rho] : sh.rp[rho - k];
             return (double)sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax];
         },
-        [&](int rho, int jp, double v) { tA[rho + nmax * jp] = v; });
+        [&](int rho, int jp, double v) { tA[rho + ldt * jp] = v; });
     __syncthreads();
-    // X_RJ[b][jp] = A(rp[b], jp) - sum_q T[q][b] A(sp[q], jp), q ascending
-    for (int b = lane; b < r; b += 64) {
-        double v[VC];
+    // Both products run transposed on the FP64 matrix cores (tc x r results, so that the 16
+    // lanes of a result row hold 16 consecutive rows of G): 16 x 16 blocks dealt to the
+    // waves, one v_mfma_f64_16x16x4 per 4 values of the inner index.  Operand layout of the
+    // instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+    // D[l / 16 + 4 v][l % 16] for v < 4.
+    constexpr int MB = 2 * HB;   // blocks per wave: r <= 64 HB, tc <= 32, 4 waves
+    static_assert(NW == 4 && kTileMax <= 32, "block count per wave assumes 4 waves and <= 32 columns");
+    const int ncb = (tc + 15) / 16, nblk = ncb * ((r + 15) / 16);
+    const int l16 = lane & 15, l4 = lane >> 4;
+    // X_RJ^T = A_RJ^T - A_SJ^T T: A[col][q] = tA[q + ldt col], B[q][b] = -Ts[b + r q], D
+    // starts at A_RJ^T; the result goes to tX[b + ldt col]
 #pragma unroll
-        for (int u = 0; u < VC; ++u) v[u] = tA[k + b + nmax * min(jg + NW * u, tc - 1)];
-        for (int q = 0; q < k; ++q) {
-            const double t = Ts[b + r * q];
+    for (int m = 0; m < MB; ++m) {
+        const int blk = jg + NW * m;
+        if (blk >= nblk) break;
+        const int cb = (blk % ncb) * 16, b = (blk / ncb) * 16 + l16;
+        f64x4 x;
 #pragma unroll
-            for (int u = 0; u < VC; ++u) v[u] -= t * tA[q + nmax * min(jg + NW * u, tc - 1)];
+        for (int v = 0; v < 4; ++v) {
+            const int col = cb + l4 + 4 * v;
+            x[v] = (b < r && col < tc) ? tA[k + b + ldt * col] : 0.0;
+        }
+        const int acol = cb + l16;
+        for (int q0 = 0; q0 < k; q0 += 4) {
+            const int q = q0 + l4;
+            const double av = (acol < tc && q < k) ? tA[q + ldt * acol] : 0.0;
+            const double bv = (q < k && b < r) ? -Ts[b + r * q] : 0.0;
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x, 0, 0, 0);
         }
 #pragma unroll
-        for (int u = 0; u < VC; ++u)
-            if (jg + NW * u < tc) tX[b + nmax * (jg + NW * u)] = v[u];
+        for (int v = 0; v < 4; ++v) {
+            const int col = cb + l4 + 4 * v;
+            if (b < r && col < tc) tX[b + ldt * col] = x[v];
+        }
     }
     __syncthreads();
-    // G = X_RR^{-1} X_RJ on the FP64 matrix cores: 16 x 16 blocks of G dealt to the waves,
-    // one v_mfma_f64_16x16x4 per 4 values of q.  Operand layout of the instruction: lane l
-    // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16]
-    // for v < 4.
-    constexpr int MB = 2 * HB;   // blocks per wave: r <= 64 HB rows, <= 32 columns, 4 waves
-    static_assert(NW == 4 && kTileMax <= 32, "block count per wave assumes 4 waves and <= 32 columns");
-    const int nrb = (r + 15) / 16, nblk = nrb * ((tc + 15) / 16);
-    const int l16 = lane & 15, l4 = lane >> 4;
+    // G^T = X_RJ^T X_RR^{-T}: A[col][q] = tX[q + ldt col], B[q][b] = X_RR^{-1}[b][q]
     f64x4 acc[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) acc[m] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -298,22 +318,24 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
     for (int q0 = 0; q0 < r; q0 += qc) {
         const int qn = min(qc, r - q0);
         const double* W = Xi + (int64_t)q0 * nmax;
+        int ldw = nmax;
         if (!xi_lds) {
             stage2d<NTH>(
                 r, qn, [&](int b, int q) { return W[b + (int64_t)q * nmax]; },
-                [&](int b, int q, double v) { tA[b + nmax * q] = v; });
+                [&](int b, int q, double v) { tA[b + ldt * q] = v; });
             __syncthreads();
             W = tA;
+            ldw = ldt;
         }
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
             const int blk = jg + NW * m;
             if (blk >= nblk) break;
-            const int row = (blk % nrb) * 16 + l16, col = (blk / nrb) * 16 + l16;
+            const int acol = (blk % ncb) * 16 + l16, b = (blk / ncb) * 16 + l16;
             for (int qq = 0; qq < qn; qq += 4) {
                 const int kk = qq + l4;
-                const double av = (row < r && kk < qn) ? W[row + nmax * kk] : 0.0;
-                const double bv = (kk < qn && col < tc) ? tX[(q0 + kk) + nmax * col] : 0.0;
+                const double av = (acol < tc && kk < qn) ? tX[(q0 + kk) + ldt * acol] : 0.0;
+                const double bv = (kk < qn && b < r) ? W[b + ldw * kk] : 0.0;
                 acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
             }
         }
@@ -323,10 +345,10 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
     for (int m = 0; m < MB; ++m) {
         const int blk = jg + NW * m;
         if (blk >= nblk) break;
-        const int col = (blk / nrb) * 16 + l16;
+        const int b = (blk / ncb) * 16 + l16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int b = (blk % nrb) * 16 + l4 + 4 * v;
+            const int col = (blk % ncb) * 16 + l4 + 4 * v;
             if (b < r && col < tc) {
                 G[b + (int64_t)(c0 + col) * nmax] = acc[m][v];
                 if (G32) G32[b + (int64_t)(c0 + col) * nmax] = (float)acc[m][v];
@@ -785,7 +807,7 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
 }
 
-// grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[nmax tw] | tX[nmax tw]
+// grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[(nmax + 1) tw] | tX[(nmax + 1) tw]
 template <int NTH, int HB, typename ST>
 __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
                                                 int mixed, int* flag, int tsz, int tw, int tpw) {
@@ -802,7 +824,7 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     const int64_t bsz = (int64_t)nmax * nmax;
     double* Ts = dyn;
     double* tA = dyn + tsz;
-    double* tX = tA + (int64_t)nmax * tw;
+    double* tX = tA + (int64_t)(nmax + 1) * tw;
     elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
     __syncthreads();
     const int nj = sh.joff[sh.nN];
@@ -861,9 +883,9 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
             if (D * (fixed + bufs * nm * tw) <= lim) return tw;
         return 0;
     };
-    const int twr = tile_w(tsz, 1), twg = tile_w(tsz, 2);
+    const int twr = tile_w(tsz, 1), twg = tile_w(tsz + 2 * kTileMax, 2);   // column tiles: ld nmax + 1
     if (twr == 0 || twg == 0) return -1;
-    const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * nm * twg);
+    const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * (nm + 1) * twg);
     set_lds(k_elim_rows<256, ST>, lr);
     const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
     const int pr = tiles_per_wg(ntr, nboxes), gr = (ntr + pr - 1) / pr;
