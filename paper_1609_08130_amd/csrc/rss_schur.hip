@@ -10,6 +10,8 @@
 // TT = double: FP64 products subtracted from the FP64 store.  TT = float (mixed
 // precision): the products of the FP32 copies of X_JR and G are accumulated in FP32 and
 // subtracted from the store of entry type ST (FP32 in mixed factorizations).
+#include <type_traits>
+
 #include "rss_internal.h"
 
 namespace rss {
@@ -26,6 +28,8 @@ struct SchurArgs {
     const void* XJR;
     const void* G;
 };
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));   // accumulator of one FP64 MFMA block
 
 template <typename TT, typename ST>
 __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd) {
@@ -122,12 +126,36 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         if (tid < TM) { rslot[i] = sl; rpos_[i] = ps; }
         else { cslot[i] = sl; cpos_[i] = ps; }
     }
+    // The 64 x 64 product, 16 entries per thread.  FP64 (TT = double): on the matrix cores,
+    // transposed (D[col][row] = sum_k G[k][col] X_JR[row][k]) so that the 16 lanes of a result
+    // row cover 16 consecutive J rows; wave w takes the 32 x 32 quadrant (rows 32 (w % 2),
+    // columns 32 (w / 2)) as 2 x 2 blocks of 16 x 16, one 16x16x4 MFMA per block and 4
+    // values of k, lane l supplying A[l % 16][l / 16] = G[k][col] and B[l / 16][l % 16] =
+    // X_JR[row][k] and receiving D[l / 16 + 4 v][l % 16] as value v.  FP32 (mixed): vector
+    // FMAs on a 4 x 4 register tile per thread (rows tx + 16 u, columns ty + 16 v), which
+    // measured faster here than the FP32 matrix-core form.
+    constexpr bool kMfma = std::is_same<TT, double>::value;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int qr = (wv & 1) * 32, qc = (wv >> 1) * 32;
     const int tx = tid & 15, ty = tid >> 4;
-    TT acc[4][4];
+    // entry e < 16 of the thread: tile row and column
+    auto erow = [&](int e) -> int {
+        if constexpr (kMfma) return qr + 16 * ((e >> 2) & 1) + l16;
+        else return tx + 16 * (e & 3);
+    };
+    auto ecol = [&](int e) -> int {
+        if constexpr (kMfma) return qc + 16 * (e >> 3) + l4 + 4 * (e & 3);
+        else return ty + 16 * (e >> 2);
+    };
+    f64x4 macc[2][2];   // [column block][row block] (matrix-core form)
+    TT vacc[16];        // [e] (vector form)
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int e = 0; e < 16; ++e) vacc[e] = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0;
+    for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) macc[ci][ri] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < r; k0 += TK) {
         __syncthreads();
 #pragma unroll
@@ -138,47 +166,61 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         }
         __syncthreads();
         if (k0 + TK < r) load_slab(k0 + TK);
+        if constexpr (kMfma) {
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            TT av[4], bv[4];
+            for (int kk = 0; kk < TK; kk += 4) {
+                double ga[2], xb[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[kk][tx + 16 * u];
+                for (int ci = 0; ci < 2; ++ci) ga[ci] = Bs[kk + l4][qc + 16 * ci + l16];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][ty + 16 * v];
+                for (int ri = 0; ri < 2; ++ri) xb[ri] = As[kk + l4][qr + 16 * ri + l16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+                    for (int ri = 0; ri < 2; ++ri)
+                        macc[ci][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[ci], xb[ri], macc[ci][ri], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < TK; ++kk) {
+                TT av[4], bv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) av[u] = As[kk][tx + 16 * u];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][ty + 16 * v];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) vacc[u + 4 * v] += av[u] * bv[v];
+            }
         }
     }
+    auto eval = [&](int e) -> TT {
+        if constexpr (kMfma) return macc[e >> 3][(e >> 2) & 1][e & 3];
+        else return vacc[e];
+    };
     // read-modify-write of the 16 entries: all loads are issued, without branches, before
     // the first store; an entry outside J reads entry 0 of the store and is not written
     ST* st = (ST*)a.store;
-    auto entry = [&](int u, int v) -> int64_t {
-        const int i = tx + 16 * u, j = ty + 16 * v;
+    auto entry = [&](int e) -> int64_t {
+        const int i = erow(e), j = ecol(e);
         const int sa = rslot[i], sb = cslot[j];
         const bool in = (sa | sb) >= 0;
-        const int64_t e = blkoff[in ? sa * 9 + sb : 0] + rpos_[i] + (int64_t)cpos_[j] * nmax;
-        return in ? e : (int64_t)-1;
+        const int64_t off = blkoff[in ? sa * 9 + sb : 0] + rpos_[i] + (int64_t)cpos_[j] * nmax;
+        return in ? off : (int64_t)-1;
     };
-    ST old[4][4];
+    ST old[16];
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) old[u][v] = st[max(entry(u, v), (int64_t)0)];
+    for (int e = 0; e < 16; ++e) old[e] = st[max(entry(e), (int64_t)0)];
     // keep every load here, ahead of the stores (the compiler would otherwise move a load
     // into the conditional store below and wait for it there)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int e = 0; e < 16; ++e) asm volatile("" ::"v"(old[e]));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) asm volatile("" ::"v"(old[u][v]));
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t e = entry(u, v);
-            if (e >= 0) st[e] = old[u][v] - (ST)acc[u][v];
-        }
+    for (int e = 0; e < 16; ++e) {
+        const int64_t off = entry(e);
+        if (off >= 0) st[off] = old[e] - (ST)eval(e);
+    }
 }
 
 void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s) {
