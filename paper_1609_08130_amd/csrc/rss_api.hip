@@ -146,10 +146,50 @@ std::vector<T> d2h(const T* d, size_t n, hipStream_t s) {
     return h;
 }
 
+// Everything queued on `s` has completed: blocks whose release was deferred go back to the
+// cache and the upload staging is free again.
+void after_sync(rss_factor f) {
+    for (auto& pb : f->pending_free) release_block(pb.first);
+    f->pending_free.clear();
+    f->hup_used = 0;
+}
+
+// Release a block once the work queued so far has completed (at the next after_sync).
+void defer_free(rss_factor f, void* p, size_t bytes) {
+    if (!p) return;
+    auto it = std::find(f->allocs.begin(), f->allocs.end(), p);
+    if (it != f->allocs.end()) f->allocs.erase(it);
+    f->bytes_device -= bytes;
+    f->pending_free.push_back({p, bytes});
+}
+
+// Copy host data to the device without waiting: the data goes through pinned staging that
+// stays untouched until the next synchronization (a full staging buffer forces one).
+void upload(rss_factor f, void* d, const void* h, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (f->hup_used + need > f->hup_bytes) {
+        HIPCHK(hipStreamSynchronize(s));
+        after_sync(f);
+        if (need > f->hup_bytes) {
+            if (f->hup) (void)hipHostFree(f->hup);
+            f->hup = nullptr;
+            f->hup_bytes = 0;
+            const size_t nb = std::max(need, (size_t)4 << 20);
+            HIPCHK(hipHostMalloc(&f->hup, nb));
+            f->hup_bytes = nb;
+        }
+    }
+    unsigned char* st = (unsigned char*)f->hup + f->hup_used;
+    std::memcpy(st, h, bytes);
+    f->hup_used += need;
+    HIPCHK(hipMemcpyAsync(d, st, bytes, hipMemcpyHostToDevice, s));
+}
+
 template <class T>
 T* h2d(rss_factor f, const std::vector<T>& h, hipStream_t s) {
     T* d = dalloc<T>(f, h.size());
-    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    upload(f, d, h.data(), h.size() * sizeof(T), s);
     return d;
 }
 
@@ -162,7 +202,7 @@ std::vector<int*> h2d_lists(rss_factor f, const std::vector<std::vector<int>>& l
         all.insert(all.end(), v.begin(), v.end());
     }
     int* d = dalloc<int>(f, std::max<size_t>(all.size(), 1));
-    if (!all.empty()) HIPCHK(hipMemcpyAsync(d, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    upload(f, d, all.data(), all.size() * sizeof(int), s);
     std::vector<int*> ptrs;
     for (size_t o : off) ptrs.push_back(d + o);
     return ptrs;
@@ -188,6 +228,7 @@ std::vector<std::vector<int>> d2h_many(rss_factor f, const std::vector<std::pair
         o += p.second;
     }
     HIPCHK(hipStreamSynchronize(s));
+    after_sync(f);
     std::vector<std::vector<int>> out;
     o = 0;
     for (auto& p : src) {
@@ -279,6 +320,11 @@ void destroy_all(rss_factor f) {
     if (f->hpin) (void)hipHostFree(f->hpin);
     f->hpin = nullptr;
     f->hpin_bytes = 0;
+    if (f->hup) (void)hipHostFree(f->hup);
+    f->hup = nullptr;
+    f->hup_bytes = f->hup_used = 0;
+    for (auto& pb : f->pending_free) release_block(pb.first);
+    f->pending_free.clear();
 }
 
 // phase indices of rss_factor_s::phase_ms
@@ -371,15 +417,12 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         tmpl[2 * i + 1] = std::sin(th);
     }
     double* ptmpl = h2d(f, tmpl, s);
-
-    HIPCHK(hipStreamSynchronize(s));
-    f->phase_ms[PH_TREE] += ev_ms(e0, e1);
-    f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
-    {
-        int flag = 0;
-        HIPCHK(hipMemcpy(&flag, f->flag, sizeof(int), hipMemcpyDeviceToHost));
-        if (flag & 2) fail(RSS_E_ARG, "duplicate points");
-    }
+    // The tree and leaf-store times and the duplicate-point flag (bit 2) are read at the
+    // first synchronization, after the first level; the level transitions likewise report
+    // their time at the synchronization after them.
+    bool first_sync = true;
+    hipEvent_t et_pend0 = nullptr, et_pend1 = nullptr;
+    std::vector<int> last_nact;   // active DOFs per box after the last skeletonized level
 
     const bool mixed = p.precision == RSS_MIXED;
     double* work = nullptr;
@@ -395,7 +438,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         alloc_level_records(f, L, mixed);
         size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc));
         if (need > work_n) {
-            if (work) dfree(f, work, work_n * sizeof(double));
+            if (work) defer_free(f, work, work_n * sizeof(double));
             work = dalloc<double>(f, need);
             work_n = need;
         }
@@ -421,7 +464,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         // flag, statistics and solve schedule: one synchronization
         const size_t nbx = (size_t)L.nbox;
-        auto hv = d2h_many(f, {{f->flag, 1}, {L.cnt, nbx}, {L.krank, nbx}, {L.nJ, nbx}, {L.mrows, nbx}}, s);
+        auto hv = d2h_many(f, {{f->flag, 1}, {L.cnt, nbx}, {L.krank, nbx}, {L.nJ, nbx}, {L.mrows, nbx}, {L.nact, nbx}},
+                           s);
         double lv_id = 0, lv_elim = 0, lv_schur = 0;
         for (size_t i = 1; i < ev.size(); i += 3) {
             lv_id += ev_ms(ev[i - 1], ev[i]);
@@ -431,11 +475,22 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         f->phase_ms[PH_ID] += lv_id;
         f->phase_ms[PH_ELIM] += lv_elim;
         f->phase_ms[PH_SCHUR] += lv_schur;
+        if (first_sync) {
+            first_sync = false;
+            f->phase_ms[PH_TREE] += ev_ms(e0, e1);
+            f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
+            if (hv[0][0] & 2) fail(RSS_E_ARG, "duplicate points");
+        }
+        if (et_pend0) {
+            f->phase_ms[PH_TRANS] += ev_ms(et_pend0, et_pend1);
+            et_pend0 = et_pend1 = nullptr;
+        }
         if (hv[0][0] & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
         L.h_cnt = std::move(hv[1]);
         L.h_k = std::move(hv[2]);
         std::vector<int> hJ = std::move(hv[3]);
         std::vector<int> hm = std::move(hv[4]);
+        last_nact = std::move(hv[5]);   // active DOFs per box after this level
         L.rec_boxes.assign(9, {});
         for (int col = 0; col < 9; ++col)
             for (int b : L.colour_boxes[col])
@@ -468,10 +523,16 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         hipEvent_t et0 = evs.rec(s);
         rss::Level P;
         P.t = L.t - 1; P.nb = L.nb / 2; P.nbox = P.nb * P.nb;
-        P.cnt = dalloc<int>(f, P.nbox);
-        rss::launch_parent_counts(L, P, s);
-        check_launch();
-        std::vector<int> pc = d2h(P.cnt, P.nbox, s);
+        // parent counts from the children's active counts, on the host (no synchronization)
+        std::vector<int> pc(P.nbox);
+        for (int py = 0; py < P.nb; ++py)
+            for (int px = 0; px < P.nb; ++px) {
+                int sum = 0;
+                for (int iy = 0; iy < 2; ++iy)
+                    for (int ix = 0; ix < 2; ++ix) sum += last_nact[(2 * px + ix) + L.nb * (2 * py + iy)];
+                pc[px + P.nb * py] = sum;
+            }
+        P.cnt = h2d(f, pc, s);
         int pmax = 1;
         for (int v : pc) pmax = std::max(pmax, v);
         if (pmax > rss::kMaxBox) fail(RSS_E_UNSUPPORTED, "a box holds " + std::to_string(pmax) +
@@ -489,21 +550,30 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         rss::launch_parent_store(L, P, pmap, f->pts, f->kp, s);
         check_launch();
         init_active(P, s);
-        hipEvent_t et1 = evs.rec(s);
-        HIPCHK(hipStreamSynchronize(s));
-        f->phase_ms[PH_TRANS] += ev_ms(et0, et1);
-        dfree(f, pmap, sizeof(int) * (size_t)P.nbox * P.nmax);
-        free_store(f, L);
+        et_pend0 = et0;
+        et_pend1 = evs.rec(s);
+        defer_free(f, pmap, sizeof(int) * (size_t)P.nbox * P.nmax);
+        defer_free(f, L.store, L.store_bytes());
+        L.store = nullptr;
         f->levels.push_back(std::move(L));
         L = std::move(P);
     }
     if (work) dfree(f, work, work_n * sizeof(double));
+    if (first_sync) {
+        // no skeletonized level (depth <= 1): the flag, the phase times and the active
+        // counts of the leaves are read here
+        auto hv = d2h_many(f, {{f->flag, 1}, {L.nact, (size_t)L.nbox}}, s);
+        first_sync = false;
+        f->phase_ms[PH_TREE] += ev_ms(e0, e1);
+        f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
+        if (hv[0][0] & 2) fail(RSS_E_ARG, "duplicate points");
+        last_nact = std::move(hv[1]);
+    }
 
     // top block
     hipEvent_t eT0 = evs.rec(s);
-    std::vector<int> hn = d2h(L.nact, L.nbox, s);
     int64_t ntop = 0;
-    for (int v : hn) ntop += v;
+    for (int v : last_nact) ntop += v;
     f->ntop = ntop;
     f->top_idx = dalloc<int>(f, ntop);
     int* tmap = dalloc<int>(f, ntop);
@@ -527,6 +597,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     }
     hipEvent_t eT1 = evs.rec(s);
     HIPCHK(hipStreamSynchronize(s));
+    after_sync(f);
     f->phase_ms[PH_TOP] += ev_ms(eT0, eT1);
     {
         int flag = 0;

@@ -484,8 +484,8 @@ __device__ inline double lane_read(double v, int ln) {
 // x holds the matrix on entry (zero outside r x r); the inverse is written to Xs (ld ldx).
 // sc: 4 * ldx doubles of LDS.
 template <int NTH, int RB, int CB>
-__device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, int r, int* colswap, double* sc,
-                               double& ld_sum, int& sgn) {
+__device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, float* Xs32, int r, int* colswap,
+                               double* sc, double& ld_sum, int& sgn) {
     constexpr int NW = NTH / 64;
     const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
@@ -570,50 +570,44 @@ __device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, int r, 
                 }
         }
     }
-    // Logical rows and column interchanges of the interchanging form: it would have moved
-    // row p_j to position j by exchanging positions j and q_j; the columns are exchanged
-    // back in reverse order.
+    // The interchanging form would have moved row p_j to position j (so its row j is row p_j
+    // of the array) and then moved column j of its result to column p_j: the product of
+    // its row transpositions, applied to the columns in reverse order, is the permutation
+    // j -> p_j itself.  So entry (i, l) of the array goes to (j with p_j = i, p_l).
     __syncthreads();
-    int* lpos = (int*)colj;      // physical row -> logical position
-    int* physat = lpos + ldx;    // logical position -> physical row
-    int* orig = physat + ldx;    // orig[pos] = column now at position pos
-    int* dest = (int*)(sc + 3 * ldx);
-    if (tid == 0) {
-        for (int i = 0; i < r; ++i) { lpos[i] = i; physat[i] = i; }
-        for (int jj = 0; jj < r; ++jj) {
-            const int q = lpos[colswap[jj]];
-            colswap[jj] = q;
-            const int a0 = physat[jj], a1 = physat[q];
-            physat[jj] = a1; physat[q] = a0;
-            lpos[a1] = jj; lpos[a0] = q;
-        }
-        for (int l = 0; l < r; ++l) orig[l] = l;
-        for (int jj = r - 1; jj >= 0; --jj) {
-            const int q = colswap[jj];
-            const int t0 = orig[jj];
-            orig[jj] = orig[q];
-            orig[q] = t0;
-        }
-        for (int q = 0; q < r; ++q) dest[orig[q]] = q;
-    }
+    int* lpos = (int*)colj;   // array row -> row of the inverse
+    for (int j = tid; j < r; j += NTH) lpos[colswap[j]] = j;
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < RB; ++h)
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int i = lane + 64 * h, l = wv + NW * c;
-            if (i < r && l < r) Xs[lpos[i] + dest[l] * ldx] = x[h][c];
+            if (i < r && l < r) {
+                Xs[lpos[i] + colswap[l] * ldx] = x[h][c];
+                if (Xs32) Xs32[lpos[i] + colswap[l] * ldx] = (float)x[h][c];
+            }
         }
-    __syncthreads();
-    // log|det| and sign, summed in pivot order
-    for (int i = tid; i < r; i += NTH) colj[i] = log(fabs(pivs[i]));
-    __syncthreads();
+    // log|det|: the sum of log|pivot| (wave 0, by lanes then across the wave); sign: the
+    // negative pivots and the parity of j -> p_j (number of inversions)
     ld_sum = 0.0;
     sgn = 1;
-    for (int i = 0; i < r; ++i) {
-        ld_sum += colj[i];
-        if (pivs[i] < 0) sgn = -sgn;
-        if (colswap[i] != i) sgn = -sgn;
+    if (wv == 0) {
+        double ls = 0.0;
+        int odd = 0;
+        for (int t = lane; t < r; t += 64) {
+            ls += log(fabs(pivs[t]));
+            const int pt = colswap[t];
+            int inv = pivs[t] < 0 ? 1 : 0;
+            for (int u = t + 1; u < r; ++u) inv += colswap[u] < pt ? 1 : 0;
+            odd ^= inv & 1;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            ls += __shfl_xor(ls, o, 64);
+            odd ^= __shfl_xor(odd, o, 64);
+        }
+        ld_sum = ls;
+        sgn = odd ? -1 : 1;
     }
     __syncthreads();
     return true;
@@ -621,10 +615,11 @@ __device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, int r, 
 
 // X_RR = Y_RR - T^T Z_S straight into the registers of gj_inverse_reg (thread (wave w, lane)
 // forms X[lane + 64 h][w + NW c], reading T for its rows and Z_S for its columns once per q),
-// also written to XRR; then the inverse into Xs.
+// also written to XRR; then the inverse straight into Xinv (and its FP32 copy).
 template <int NTH, int RB, int CB>
 __device__ bool xrr_gj_reg(const double* Yg, int nmax, const double* Ts, const double* zs, int ldz, int k, int r,
-                           double* XRR, double* Xs, int* colswap, double* sc, double& ld_sum, int& sgn) {
+                           double* XRR, double* Xinv, float* Xinv32, int* colswap, double* sc, double& ld_sum,
+                           int& sgn) {
     constexpr int NW = NTH / 64;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double x[RB][CB];
@@ -635,6 +630,7 @@ __device__ bool xrr_gj_reg(const double* Yg, int nmax, const double* Ts, const d
             const int i = lane + 64 * h, l = wv + NW * c;
             x[h][c] = (i < r && l < r) ? Yg[i + (int64_t)l * nmax] : 0.0;
         }
+#pragma unroll 2
     for (int q = 0; q < k; ++q) {
         double t[RB], z[CB];
 #pragma unroll
@@ -654,7 +650,7 @@ __device__ bool xrr_gj_reg(const double* Yg, int nmax, const double* Ts, const d
             if (i < r && l < r) XRR[i + (int64_t)l * nmax] = x[h][c];
             else x[h][c] = 0.0;
         }
-    return gj_inverse_reg<NTH, RB, CB>(x, Xs, nmax, r, colswap, sc, ld_sum, sgn);
+    return gj_inverse_reg<NTH, RB, CB>(x, Xinv, nmax, Xinv32, r, colswap, sc, ld_sum, sgn);
 }
 
 // X_RR = Y_RR - T^T Z_S (Y_RR read from Yg, formed by the row tiles),
@@ -682,14 +678,35 @@ __device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, i
     double ld_sum;
     int sgn;
     bool ok;
-    // Large workgroups (few boxes): X_RR formed in the registers of the register Gauss-Jordan
-    // when 64 RB rows and 16 CB columns cover r.  Otherwise X_RR goes through Xs, then to
-    // the register form (r <= 64, 256 threads) or the LDS form.
-    if (NTH == 1024 && r <= 128) {
+    // Register Gauss-Jordan when 64 RB rows and NW CB columns cover r (256 threads: r <= 64,
+    // X_RR through XRR; 1024 threads: r <= 128, X_RR formed in the registers); the inverse
+    // goes straight to Xinv.  Otherwise X_RR goes through Xs to the LDS form.
+    double* Xinv = a.Xinv + (int64_t)c * bsz;
+    float* Xinv32 = mixed ? a.Xinv32 + (int64_t)c * bsz : nullptr;
+    if ((NTH == 1024 && r <= 128) || (NTH == 256 && r <= 64)) {
         if constexpr (NTH == 1024) {
-            if (r <= 64) ok = xrr_gj_reg<NTH, 1, 4>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
-            else if (r <= 96) ok = xrr_gj_reg<NTH, 2, 6>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
-            else ok = xrr_gj_reg<NTH, 2, 8>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xs, colswap, sc, ld_sum, sgn);
+            if (r <= 64) ok = xrr_gj_reg<NTH, 1, 4>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xinv, Xinv32, colswap, sc, ld_sum, sgn);
+            else if (r <= 96) ok = xrr_gj_reg<NTH, 2, 6>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xinv, Xinv32, colswap, sc, ld_sum, sgn);
+            else ok = xrr_gj_reg<NTH, 2, 8>(Yg, nmax, Ts, zs, ldz, k, r, XRR, Xinv, Xinv32, colswap, sc, ld_sum, sgn);
+        } else if constexpr (NTH == 256) {
+            // X_RR element by element into XRR, then into the registers from there (the
+            // workgroup's own writes are visible to it after the barrier)
+            for (int e = tid; e < r * r; e += NTH) {
+                int b = e % r, b2 = e / r;
+                double v = Yg[b + (int64_t)b2 * nmax];
+                for (int q = 0; q < k; ++q) v -= Ts[b + r * q] * zs[q + (int64_t)b2 * ldz];
+                XRR[b + (int64_t)b2 * nmax] = v;
+            }
+            __syncthreads();
+            constexpr int CB = 16;
+            double x[1][CB];
+            const int wv = tid >> 6, lane = tid & 63;
+#pragma unroll
+            for (int cc = 0; cc < CB; ++cc) {
+                const int l = wv + 4 * cc;
+                x[0][cc] = (lane < r && l < r) ? XRR[lane + (int64_t)l * nmax] : 0.0;
+            }
+            ok = gj_inverse_reg<NTH, 1, CB>(x, Xinv, nmax, Xinv32, r, colswap, sc, ld_sum, sgn);
         }
     } else {
         for (int e = tid; e < r * r; e += NTH) {
@@ -700,30 +717,18 @@ __device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, i
             Xs[b + b2 * nmax] = v;
         }
         __syncthreads();
-        if (NTH == 256 && r <= 64) {
-            constexpr int CB = NTH / 16;   // 16 columns per thread at 256 threads
-            double x[1][CB];
-            const int wv = tid >> 6, lane = tid & 63;
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int l = wv + (NTH / 64) * c;
-                x[0][c] = (lane < r && l < r) ? Xs[lane + l * nmax] : 0.0;
+        ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
+        if (ok)
+            for (int e = tid; e < r * r; e += NTH) {
+                int b = e % r, b2 = e / r;
+                Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * nmax];
+                if (mixed) Xinv32[b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * nmax];
             }
-            ok = gj_inverse_reg<NTH, 1, CB>(x, Xs, nmax, r, colswap, sc, ld_sum, sgn);
-        } else {
-            ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
-        }
     }
     if (!ok) return false;
     if (tid == 0) {
         a.logdet_part[c] = ld_sum;
         a.sign_part[c] = sgn;
-    }
-    double* Xinv = a.Xinv + (int64_t)c * bsz;
-    for (int e = tid; e < r * r; e += NTH) {
-        int b = e % r, b2 = e / r;
-        Xinv[b + (int64_t)b2 * nmax] = Xs[b + b2 * nmax];
-        if (mixed) a.Xinv32[(int64_t)c * bsz + b + (int64_t)b2 * nmax] = (float)Xs[b + b2 * nmax];
     }
     if (mixed)
         for (int e = tid; e < k * r; e += NTH) {
@@ -892,7 +897,10 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     k_elim_rows<256, ST><<<dim3(xcd_grid(gr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, gr, mixed, work,
                                                                       (int)tsz, twr, pr);
     const size_t base = tsz + 4 * nm;
-    const bool xl = D * (base + nm * nm) <= lim;
+    // X_RR in LDS only for the LDS Gauss-Jordan: not when every r fits the register form
+    // (r <= nmax <= 64 with 256 threads, <= 128 with 1024)
+    const bool reg_only = nboxes >= 256 ? L.nmax <= 64 : L.nmax <= 128;
+    const bool xl = !reg_only && D * (base + nm * nm) <= lim;
     const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
     const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
     // many boxes: small workgroups, several per CU; few boxes: one large workgroup each

@@ -121,6 +121,9 @@ struct rss_factor_s {
     std::vector<void*> allocs;
     void* hpin = nullptr;          // pinned host staging for small device-to-host copies
     size_t hpin_bytes = 0;
+    void* hup = nullptr;           // pinned host staging of host-to-device uploads since the last sync
+    size_t hup_bytes = 0, hup_used = 0;
+    std::vector<std::pair<void*, size_t>> pending_free;   // released at the next synchronization
     std::vector<rss::LevelStats> stats;
     std::vector<double> phase_ms;   // tree, leaf store, id, elim, schur, transition, top, total
     std::vector<int> kernel_launches;
@@ -140,7 +143,6 @@ void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double 
                        int* fill, int* gidx, int nmax, int nbox, hipStream_t s);
 void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag,
                        hipStream_t s);
-void launch_parent_counts(const Level& C, Level& P, hipStream_t s);
 void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s);
 void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
                          const KernelParams& kp, hipStream_t s);

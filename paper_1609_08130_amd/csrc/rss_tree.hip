@@ -193,15 +193,6 @@ void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp
 // Level transition (Section 3.3, subsequent levels): B_P = union of the children's
 // active DOFs, ascending.  pmap[P*nmaxP + p] = (child slot << 16) | position of the DOF
 // in the child's level-start list (the child store is indexed by those positions).
-__global__ void k_parent_counts(const int* __restrict__ cnact, int cnb, int* pcnt, int pnb) {
-    int P = blockIdx.x * blockDim.x + threadIdx.x;
-    if (P >= pnb * pnb) return;
-    int px = P % pnb, py = P / pnb;
-    int s = 0;
-    for (int iy = 0; iy < 2; ++iy)
-        for (int ix = 0; ix < 2; ++ix) s += cnact[(2 * px + ix) + cnb * (2 * py + iy)];
-    pcnt[P] = s;
-}
 
 __global__ void __launch_bounds__(256) k_parent_lists(const int* __restrict__ cnact, const int* __restrict__ capos,
                                                       const int* __restrict__ cgidx, int cnb, int cnmax,
@@ -250,9 +241,6 @@ void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s) {
                                                       P.nmax);
 }
 
-void launch_parent_counts(const Level& C, Level& P, hipStream_t s) {
-    k_parent_counts<<<dim3((P.nbox + 255) / 256), dim3(256), 0, s>>>(C.nact, C.nb, P.cnt, P.nb);
-}
 
 template <typename ST>
 __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cstore, int cnb, int cnmax,
