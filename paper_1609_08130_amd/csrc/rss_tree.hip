@@ -250,42 +250,94 @@ __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cst
                                                       double coef) {
     __shared__ int mp[kMaxBox], mq[kMaxBox];
     __shared__ double xp[kMaxBox], yp[kMaxBox], xq[kMaxBox], yq[kMaxBox];
-    int P = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
-    int dx = o % 5 - 2, dy = o / 5 - 2;
-    int Px = P % pnb, Py = P / pnb;
-    int Qx = Px + dx, Qy = Py + dy;
+    __shared__ ST tile[64][65];
+    const int tid = threadIdx.x;
+    const int P = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
+    const int dx = o % 5 - 2, dy = o / 5 - 2;
+    // Parent offsets with |dx| = 2 or |dy| = 2: every child pair is at distance >= 3, so the
+    // whole block is kernel entries, and A(B_Q, B_P) is its transpose bit for bit; the
+    // workgroup of the upper offset writes both, the lower one has nothing to do.
+    const bool far_only = abs(dx) == 2 || abs(dy) == 2;
+    if (far_only && o < 12) return;
+    const int Px = P % pnb, Py = P / pnb;
+    const int Qx = Px + dx, Qy = Py + dy;
     if (Qx < 0 || Qy < 0 || Qx >= pnb || Qy >= pnb) return;
-    int Q = Qx + pnb * Qy;
-    int np = pcnt[P], nq = pcnt[Q];
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const int Q = Qx + pnb * Qy;
+    const int np = pcnt[P], nq = pcnt[Q];
+    for (int i = tid; i < np; i += blockDim.x) {
         mp[i] = pmap[(int64_t)P * pnmax + i];
         int g = pgidx[(int64_t)P * pnmax + i];
         xp[i] = pts[2 * (int64_t)g]; yp[i] = pts[2 * (int64_t)g + 1];
     }
-    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+    for (int i = tid; i < nq; i += blockDim.x) {
         mq[i] = pmap[(int64_t)Q * pnmax + i];
         int g = pgidx[(int64_t)Q * pnmax + i];
         xq[i] = pts[2 * (int64_t)g]; yq[i] = pts[2 * (int64_t)g + 1];
     }
     __syncthreads();
     ST* blk = pstore + ((int64_t)P * kNbr + o) * pnmax * pnmax;
-    int tot = np * nq;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        int i = e % np, j = e / np;
-        int sa = mp[i] >> 16, pa = mp[i] & 0xffff;
-        int sb = mq[j] >> 16, qb = mq[j] & 0xffff;
-        int ax = 2 * Px + (sa & 1), ay = 2 * Py + (sa >> 1);
-        int bx = 2 * Qx + (sb & 1), by = 2 * Qy + (sb >> 1);
-        int ddx = bx - ax, ddy = by - ay;
-        double v;
-        if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
-            int a = ax + cnb * ay;
-            const ST* cb = cstore + ((int64_t)a * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
-            v = cb[pa + (int64_t)qb * cnmax];
-        } else {
-            v = kernel_entry(xp[i], yp[i], xq[j], yq[j], coef);
+    if (far_only) {
+        ST* blk_t = pstore + ((int64_t)Q * kNbr + (24 - o)) * pnmax * pnmax;
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int i0 = 0; i0 < np; i0 += 64)
+            for (int j0 = 0; j0 < nq; j0 += 64) {
+                const int ti = min(64, np - i0), tj = min(64, nq - j0);
+                // rows i0 + lane, columns j0 + wv + 4 t; the tile goes out transposed
+                for (int jj = wv; jj < tj; jj += 4) {
+                    ST v = (ST)0;
+                    if (lane < ti) {
+                        v = (ST)kernel_entry(xp[i0 + lane], yp[i0 + lane], xq[j0 + jj], yq[j0 + jj], coef);
+                        blk[(i0 + lane) + (int64_t)(j0 + jj) * pnmax] = v;
+                    }
+                    tile[jj][lane] = v;
+                }
+                __syncthreads();
+                for (int ii = wv; ii < ti; ii += 4)
+                    if (lane < tj) blk_t[(j0 + lane) + (int64_t)(i0 + ii) * pnmax] = tile[lane][ii];
+                __syncthreads();
+            }
+        return;
+    }
+    // Adjacent parents: child pairs within distance 2 copy their entry of the child store,
+    // the others (distance 3) are kernel entries.  Element e = i + np j, taken U at a time
+    // per thread with every load issued before the first store; (i, j) advance by a fixed
+    // step instead of a division per element.
+    constexpr int U = 4;
+    const int tot = np * nq;
+    if (tot == 0) return;
+    const int di = 256 % np, dj = 256 / np;
+    int i = tid % np, j = tid / np;
+    for (int e0 = tid; e0 < tot; e0 += 256 * U) {
+        double v[U];
+        int iu[U], ju[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            iu[u] = i;
+            ju[u] = j;
+            i += di;
+            j += dj;
+            if (i >= np) { i -= np; ++j; }
         }
-        blk[i + (int64_t)j * pnmax] = (ST)v;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = 0.0;
+            if (e0 + 256 * u >= tot) continue;
+            const int ii = iu[u], jj = ju[u];
+            const int sa = mp[ii] >> 16, pa = mp[ii] & 0xffff;
+            const int sb = mq[jj] >> 16, qb = mq[jj] & 0xffff;
+            const int ax = 2 * Px + (sa & 1), ay = 2 * Py + (sa >> 1);
+            const int bx = 2 * Qx + (sb & 1), by = 2 * Qy + (sb >> 1);
+            const int ddx = bx - ax, ddy = by - ay;
+            if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
+                const ST* cb = cstore + ((int64_t)(ax + cnb * ay) * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
+                v[u] = (double)cb[pa + (int64_t)qb * cnmax];
+            } else {
+                v[u] = kernel_entry(xp[ii], yp[ii], xq[jj], yq[jj], coef);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + 256 * u < tot) blk[iu[u] + (int64_t)ju[u] * pnmax] = (ST)v[u];
     }
 }
 
