@@ -141,11 +141,15 @@ __global__ void __launch_bounds__(NTH) k_solve_bwd(SweepArgs a, const int* __res
     }
 }
 
-// y = F x: W_i then D on R_i (factor order)
-__global__ void __launch_bounds__(256) k_apply_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
+// y = F x: W_i then D on R_i (factor order).  z_S is updated before z_J is gathered (S is
+// the first part of J).  Dynamic LDS: zJ[ldJ].
+template <int NTH>
+__global__ void __launch_bounds__(NTH) k_apply_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
+    constexpr int NW = NTH / 64;
+    extern __shared__ double zJ[];
     __shared__ double zR[kMaxBox], w[kMaxBox];
-    __shared__ double part[4][kMaxBox];
+    __shared__ double part[NW][kMaxBox];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -158,45 +162,45 @@ __global__ void __launch_bounds__(256) k_apply_fwd(SweepArgs a, const int* __res
     const double* G = (const double*)a.G + (int64_t)c * nmax * ldJ;
     const double* X = a.XRR + c * bsz;
     const int* J = a.Jg + (int64_t)c * ldJ;
-    for (int i = tid; i < k; i += 256) sg[i] = a.Sg[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += 256) rg[i] = a.Rg[(int64_t)c * nmax + i];
+    for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     const int wv = tid >> 6, lane = tid & 63;
+    const int q4 = (nj + NW - 1) / NW;   // J entries per wave
     for (int h = 0; h < nrhs; ++h) {
         double* zc = z + (int64_t)h * ld;
-        for (int b = tid; b < r; b += 256) zR[b] = zc[rg[b]];
+        for (int b = tid; b < r; b += NTH) zR[b] = zc[rg[b]];
         __syncthreads();
-        for (int q = tid; q < k; q += 256) {           // z_S += T z_R
-            double s = 0.0;
-            for (int b = 0; b < r; ++b) s += T[q + (int64_t)b * nmax] * zR[b];
-            zc[sg[q]] += s;
+        for (int q = tid; q < k; q += NTH) zc[sg[q]] += dot_strided(T + q, nmax, zR, r);   // z_S += T z_R
+        __syncthreads();
+        for (int jj = tid; jj < nj; jj += NTH) zJ[jj] = zc[J[jj]];
+        __syncthreads();
+        // z_R += G z_J: wave wv takes a contiguous 1/NW of J, lanes take rows b
+        const int j0 = wv * q4, j1 = min(nj, j0 + q4);
+        for (int b0 = 0; b0 < r; b0 += 64) {
+            const int b = b0 + lane;
+            if (b < r) part[wv][b] = j1 > j0 ? dot_strided(G + b + (int64_t)j0 * nmax, nmax, zJ + j0, j1 - j0) : 0.0;
         }
         __syncthreads();
-        for (int b0 = 0; b0 < r; b0 += 64) {           // z_R += G z_J
-            int b = b0 + lane;
-            double s = 0.0;
-            if (b < r)
-                for (int jj = wv; jj < nj; jj += 4) s += G[b + (int64_t)jj * nmax] * zc[J[jj]];
-            if (b < r) part[wv][b] = s;
+        for (int b = tid; b < r; b += NTH) {
+            double sp = 0.0;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) sp += part[u][b];
+            zR[b] += sp;
         }
         __syncthreads();
-        for (int b = tid; b < r; b += 256) zR[b] += part[0][b] + part[1][b] + part[2][b] + part[3][b];
+        for (int b = tid; b < r; b += NTH) w[b] = dot_strided(X + b, nmax, zR, r);   // z_R <- X_RR z_R
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {           // z_R <- X_RR z_R
-            double s = 0.0;
-            for (int q = 0; q < r; ++q) s += X[b + (int64_t)q * nmax] * zR[q];
-            w[b] = s;
-        }
-        __syncthreads();
-        for (int b = tid; b < r; b += 256) zc[rg[b]] = w[b];
+        for (int b = tid; b < r; b += NTH) zc[rg[b]] = w[b];
         __syncthreads();
     }
 }
 
-// y = F x: V_i (reverse order)
-__global__ void __launch_bounds__(256) k_apply_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
+// y = F x: V_i (reverse order).  z_J is updated before z_S is read (S is part of J).
+template <int NTH>
+__global__ void __launch_bounds__(NTH) k_apply_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
-    __shared__ double zR[kMaxBox], w[kMaxBox];
+    __shared__ double zR[kMaxBox], w[kMaxBox], zS[kMaxBox];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -209,30 +213,20 @@ __global__ void __launch_bounds__(256) k_apply_bwd(SweepArgs a, const int* __res
     const double* Xi = (const double*)a.Xinv + c * bsz;
     const double* E = (const double*)a.XJR + (int64_t)c * ldJ * nmax;
     const int* J = a.Jg + (int64_t)c * ldJ;
-    for (int i = tid; i < k; i += 256) sg[i] = a.Sg[(int64_t)c * nmax + i];
-    for (int i = tid; i < r; i += 256) rg[i] = a.Rg[(int64_t)c * nmax + i];
+    for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
+    for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     for (int h = 0; h < nrhs; ++h) {
         double* zc = z + (int64_t)h * ld;
-        for (int b = tid; b < r; b += 256) zR[b] = zc[rg[b]];
+        for (int b = tid; b < r; b += NTH) zR[b] = zc[rg[b]];
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {           // w = X_RR^{-1} z_R
-            double s = 0.0;
-            for (int q = 0; q < r; ++q) s += Xi[b + (int64_t)q * nmax] * zR[q];
-            w[b] = s;
-        }
+        for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Xi + b, nmax, zR, r);   // w = X_RR^{-1} z_R
         __syncthreads();
-        for (int jj = tid; jj < nj; jj += 256) {       // z_J += X_JR w
-            double s = 0.0;
-            for (int b = 0; b < r; ++b) s += E[jj + (int64_t)b * ldJ] * w[b];
-            zc[J[jj]] += s;
-        }
+        for (int jj = tid; jj < nj; jj += NTH) zc[J[jj]] += dot_strided(E + jj, ldJ, w, r);   // z_J += X_JR w
         __syncthreads();
-        for (int b = tid; b < r; b += 256) {           // z_R += T^T z_S
-            double s = 0.0;
-            for (int q = 0; q < k; ++q) s += T[q + (int64_t)b * nmax] * zc[sg[q]];
-            zc[rg[b]] = zR[b] + s;
-        }
+        for (int q = tid; q < k; q += NTH) zS[q] = zc[sg[q]];
+        __syncthreads();
+        for (int b = tid; b < r; b += NTH) zc[rg[b]] = zR[b] + dot_strided(T + (int64_t)b * nmax, 1, zS, k);   // z_R += T^T z_S
         __syncthreads();
     }
 }
@@ -277,13 +271,16 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
 void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
                       hipStream_t s) {
     if (nboxes <= 0) return;
-    k_apply_fwd<<<dim3(nboxes), dim3(256), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    const size_t lds = sizeof(double) * (size_t)L.ldJ;
+    if (nboxes < 256) k_apply_fwd<1024><<<dim3(nboxes), dim3(1024), lds, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    else k_apply_fwd<256><<<dim3(nboxes), dim3(256), lds, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
 }
 
 void launch_apply_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
                       hipStream_t s) {
     if (nboxes <= 0) return;
-    k_apply_bwd<<<dim3(nboxes), dim3(256), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    if (nboxes < 256) k_apply_bwd<1024><<<dim3(nboxes), dim3(1024), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    else k_apply_bwd<256><<<dim3(nboxes), dim3(256), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
 }
 
 // ---- top block ------------------------------------------------------------------------
