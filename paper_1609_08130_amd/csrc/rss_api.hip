@@ -341,8 +341,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
 
     f->pts = dalloc<double>(f, (size_t)f->n * 2);
     HIPCHK(hipMemcpyAsync(f->pts, d_points, sizeof(double) * 2 * f->n, hipMemcpyDeviceToDevice, s));
-    f->flag = dalloc<int>(f, 4);
-    HIPCHK(hipMemsetAsync(f->flag, 0, sizeof(int) * 4, s));
+    f->flag = dalloc<int>(f, 16);   // [0]: error bits; [4 + c]: largest |J| of colour c in the level
+    HIPCHK(hipMemsetAsync(f->flag, 0, sizeof(int) * 16, s));
 
     // root box
     double lo_x = p.root_lo[0], lo_y = p.root_lo[1], side = p.root_side;
@@ -442,6 +442,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             work = dalloc<double>(f, need);
             work_n = need;
         }
+        HIPCHK(hipMemsetAsync(f->flag + 4, 0, sizeof(int) * 9, s));
         std::vector<hipEvent_t> ev;
         ev.push_back(evs.rec(s));
         for (int col = 0; col < 9; ++col) {
@@ -451,11 +452,11 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, s);
+            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, f->flag + 4 + col, s);
             if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
             check_launch();
             ev.push_back(evs.rec(s));
-            rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, s);
+            rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, f->flag + 4 + col, s);
             check_launch();
             ev.push_back(evs.rec(s));
             f->kernel_launches[PH_ID] += ni;

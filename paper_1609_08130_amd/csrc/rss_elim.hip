@@ -24,6 +24,7 @@ namespace rss {
 
 struct ElimArgs {
     const void* store;   // FP64 or FP32 entries (the kernels' ST)
+    int* colmax;         // largest |J| of the colour (atomic maximum)
     int nb, nmax, ldJ;
     const int* cnt;
     const int* gidx;
@@ -808,6 +809,7 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     if (tid == 0) {
         a.nJ[c] = nj;
         a.nact[c] = k;
+        atomicMax(a.colmax, nj);
     }
     for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
 }
@@ -869,9 +871,10 @@ static void set_lds(K kernel, size_t bytes) {
 
 template <typename ST>
 static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
-                         hipStream_t s) {
+                         int* colmax, hipStream_t s) {
     if (nboxes <= 0) return 0;
     ElimArgs a;
+    a.colmax = colmax;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;
     a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
@@ -935,9 +938,10 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     return 3;
 }
 
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, hipStream_t s) {
-    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, s)
-                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, s);
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, int* colmax,
+                hipStream_t s) {
+    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, colmax, s)
+                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, colmax, s);
 }
 
 }  // namespace rss

@@ -156,9 +156,10 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
                     const KernelParams& kp, double* work, hipStream_t s);
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
 // Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, int* colmax,
                  hipStream_t s);
-void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s);
+void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const int* colmax,
+                  hipStream_t s);
 
 // dense top block (rss_solve.hip)
 // piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)

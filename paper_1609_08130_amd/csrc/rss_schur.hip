@@ -32,7 +32,8 @@ struct SchurArgs {
 typedef double f64x4 __attribute__((ext_vector_type(4)));   // accumulator of one FP64 MFMA block
 
 template <typename TT, typename ST>
-__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd) {
+__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd,
+                                               const int* __restrict__ colmax) {
     constexpr int TM = 64, TK = 16;
     __shared__ TT As[TK][TM + 1];
     __shared__ TT Bs[TK][TM + 1];
@@ -50,9 +51,12 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     const int xcd = blockIdx.x & 7, sidx = blockIdx.x >> 3;
     const int bi = xcd + 8 * (sidx / ntile);
     if (bi >= nbox) return;
-    const int c = boxes[bi];
     const int tile = sidx % ntile;
     const int ti = tile % tpd, tj = tile / tpd;
+    // tiles beyond the widest |J| of the colour leave at once (one load of a shared value)
+    const int tmax = (*colmax + TM - 1) / TM;
+    if (ti >= tmax || tj >= tmax) return;
+    const int c = boxes[bi];
     const int nj = a.nJ[c];
     if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
     const int n = a.cnt[c], k = a.krank[c], r = n - k;
@@ -223,7 +227,8 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     }
 }
 
-void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, hipStream_t s) {
+void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const int* colmax,
+                  hipStream_t s) {
     if (nboxes <= 0) return;
     SchurArgs a;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
@@ -233,11 +238,11 @@ void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mi
     dim3 grid((unsigned)nwg), block(256);
     if (mixed) {
         a.XJR = L.XJR32; a.G = L.G32;
-        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
-        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
+        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
+        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
     } else {
         a.XJR = L.XJR; a.G = L.G;
-        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd);
+        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
     }
 }
 
