@@ -589,7 +589,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     rss::launch_top_assemble(L, tmap, f->top_idx, ntop, f->pts, f->kp, f->top_A, s);
     check_launch();
     HIPCHK(hipMemcpyAsync(LU, f->top_A, sizeof(double) * ntop * ntop, hipMemcpyDeviceToDevice, s));
-    rss::launch_lu_inverse(LU, f->top_inv, ntop, piv, nullptr, f->flag, dlog, dsign, s);
+    double* luw = dalloc<double>(f, (size_t)rss::lu_work_doubles(ntop));
+    rss::launch_lu_inverse(LU, f->top_inv, ntop, piv, luw, f->flag, dlog, dsign, s);
     check_launch();
     if (mixed && ntop > 0) {
         f->top_inv32 = dalloc<float>(f, (size_t)ntop * ntop);

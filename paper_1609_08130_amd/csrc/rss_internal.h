@@ -164,6 +164,8 @@ void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mi
 // dense top block (rss_solve.hip)
 // piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)
 int64_t lu_piv_ints(int64_t n);
+// work: lu_work_doubles(n) doubles (inverses of the diagonal blocks of L and U)
+int64_t lu_work_doubles(int64_t n);
 void launch_lu_inverse(double* A, double* Ainv, int64_t n, int* piv, double* work, int* flag,
                        double* logdet, int* sign, hipStream_t s);
 

@@ -560,11 +560,46 @@ __global__ void k_lu_perm(const int* __restrict__ ipiv, int n, int* __restrict__
 // Columns [c0, c0 + NC) of A^{-1} = U^{-1} L^{-1} P: X = P e_c in LDS, then blocked
 // forward and backward substitution (a kNB x kNB diagonal block in LDS, then one
 // rectangular update per block).
+// Inverses of the kNB x kNB diagonal blocks of the LU factors: block b < nblk of the unit
+// lower L, block nblk + b of U.  One thread per column of the block, by substitution.
+// Dinv[(which * nblk + b) * kNB * kNB + i + kNB c].
+__global__ void __launch_bounds__(kNB) k_tri_diag_inv(const double* __restrict__ LU, int n, int nblk,
+                                                       double* __restrict__ Dinv, const int* flag) {
+    __shared__ double D[kNB * kNB];
+    __shared__ double X[kNB * kNB];   // X[i * kNB + c]: row i of column c of the inverse
+    if (*flag & 8) return;
+    const int upper = blockIdx.x >= nblk;
+    const int b = blockIdx.x - (upper ? nblk : 0);
+    const int jb = b * kNB, bs = min(kNB, n - jb);
+    const int c = threadIdx.x;
+    for (int e = c; e < bs * bs; e += kNB) D[e] = LU[(jb + e % bs) + (int64_t)(jb + e / bs) * n];
+    __syncthreads();
+    double* out = Dinv + (int64_t)(upper * nblk + b) * kNB * kNB;
+    if (c >= bs) return;
+    if (!upper) {
+        for (int i = 0; i < bs; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int j = c; j < i; ++j) v -= D[i + bs * j] * X[j * kNB + c];
+            X[i * kNB + c] = v;
+        }
+    } else {
+        for (int i = bs - 1; i >= 0; --i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int j = i + 1; j <= c; ++j) v -= D[i + bs * j] * X[j * kNB + c];
+            X[i * kNB + c] = v / D[i + bs * i];
+        }
+    }
+    for (int i = 0; i < bs; ++i) out[i + kNB * c] = X[i * kNB + c];
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restrict__ LU, const int* __restrict__ perm,
-                                                         int n, double* __restrict__ Ainv, const int* flag) {
+                                                         int n, double* __restrict__ Ainv, const double* __restrict__ Dinv,
+                                                         const int* flag) {
     extern __shared__ double xs[];   // n x NC, xs[i * NC + c]
     __shared__ double D[kNB * kNB];
+    __shared__ double yt[kNB * NC];
+    const int nblk = (n + kNB - 1) / kNB;
     const int tid = threadIdx.x;
     if (*flag & 8) return;
     const int c0 = blockIdx.x * NC;
@@ -573,20 +608,25 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
         xs[e] = (perm[i] == c0 + c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int jb = 0; jb < n; jb += kNB) {            // L y = P e (unit lower)
-        const int bs = min(kNB, n - jb);
-        for (int e = tid; e < bs * bs; e += 256) {
-            int i = e % bs, j = e / bs;
-            D[e] = LU[(jb + i) + (int64_t)(jb + j) * n];
+    // x_blk <- (inverse of the diagonal block) x_blk, lower or upper triangular
+    auto diag_apply = [&](int jb, int bs, bool lower) {
+        for (int e = tid; e < bs * NC; e += 256) {
+            const int i = e / NC, c = e % NC;
+            double v = 0.0;
+            if (lower) for (int j = 0; j <= i; ++j) v += D[i + kNB * j] * xs[(jb + j) * NC + c];
+            else for (int j = i; j < bs; ++j) v += D[i + kNB * j] * xs[(jb + j) * NC + c];
+            yt[e] = v;
         }
         __syncthreads();
-        for (int j = 0; j < bs - 1; ++j) {
-            for (int e = tid; e < (bs - 1 - j) * NC; e += 256) {
-                int i = j + 1 + e / NC, c = e % NC;
-                xs[(jb + i) * NC + c] -= D[i + bs * j] * xs[(jb + j) * NC + c];
-            }
-            __syncthreads();
-        }
+        for (int e = tid; e < bs * NC; e += 256) xs[(jb + e / NC) * NC + e % NC] = yt[e];
+        __syncthreads();
+    };
+    for (int jb = 0; jb < n; jb += kNB) {            // L y = P e (unit lower)
+        const int bs = min(kNB, n - jb);
+        const double* Di = Dinv + (int64_t)(jb / kNB) * kNB * kNB;
+        for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
+        __syncthreads();
+        diag_apply(jb, bs, true);
         for (int e = tid; e < (n - jb - bs) * NC; e += 256) {
             int i = jb + bs + e / NC, c = e % NC;
             double v = 0.0;
@@ -595,23 +635,12 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
         }
         __syncthreads();
     }
-    const int nblk = (n + kNB - 1) / kNB;
     for (int b = nblk - 1; b >= 0; --b) {            // U x = y
         const int jb = b * kNB, bs = min(kNB, n - jb);
-        for (int e = tid; e < bs * bs; e += 256) {
-            int i = e % bs, j = e / bs;
-            D[e] = LU[(jb + i) + (int64_t)(jb + j) * n];
-        }
+        const double* Di = Dinv + (int64_t)(nblk + b) * kNB * kNB;
+        for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
         __syncthreads();
-        for (int j = bs - 1; j >= 0; --j) {
-            if (tid < NC) xs[(jb + j) * NC + tid] /= D[j + bs * j];
-            __syncthreads();
-            for (int e = tid; e < j * NC; e += 256) {
-                int i = e / NC, c = e % NC;
-                xs[(jb + i) * NC + c] -= D[i + bs * j] * xs[(jb + j) * NC + c];
-            }
-            __syncthreads();
-        }
+        diag_apply(jb, bs, false);
         for (int e = tid; e < jb * NC; e += 256) {
             int i = e / NC, c = e % NC;
             double v = 0.0;
@@ -627,10 +656,10 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
 }
 
 int64_t lu_piv_ints(int64_t n) { return 2 * n + 4 * kNB + 1; }
+int64_t lu_work_doubles(int64_t n) { return 2 * ((n + kNB - 1) / kNB) * kNB * kNB; }
 
 void launch_lu_inverse(double* A, double* Ainv, int64_t n64, int* piv, double* work, int* flag, double* logdet,
                        int* sign, hipStream_t s) {
-    (void)work;
     if (n64 <= 0) return;
     const int n = (int)n64;
     int* ipiv = piv;
@@ -654,14 +683,16 @@ void launch_lu_inverse(double* A, double* Ainv, int64_t n64, int* piv, double* w
     }
     const bool pl = (size_t)n * sizeof(int) + 1024 <= (size_t)lim;
     k_lu_perm<<<dim3(1), dim3(64), pl ? sizeof(int) * (size_t)n : 0, s>>>(ipiv, n, perm, flag, pl ? 1 : 0);
+    k_tri_diag_inv<<<dim3(2 * nblk), dim3(kNB), 0, s>>>(A, n, nblk, work, flag);
     constexpr int NC = 8;
     const size_t lds = sizeof(double) * (size_t)n * NC;
-    if ((long)lds + (long)sizeof(double) * kNB * kNB + 1024 > lim) {
+    if ((long)lds + (long)sizeof(double) * kNB * (kNB + NC) + 1024 > lim) {
         // n beyond what one LDS column block holds (about 2000 DOFs)
         hipLaunchKernelGGL(k_top_inverse_blk<1>, dim3((unsigned)n), dim3(256), sizeof(double) * (size_t)n, s, A, perm, n,
-                           Ainv, flag);
+                           Ainv, (const double*)work, flag);
     } else {
-        k_top_inverse_blk<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, perm, n, Ainv, flag);
+        k_top_inverse_blk<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, perm, n, Ainv,
+                                                                                          (const double*)work, flag);
     }
 }
 
