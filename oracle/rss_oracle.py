@@ -542,6 +542,41 @@ def logdet(F: Factor):
     return sign, total
 
 
+def _chol(X: np.ndarray) -> np.ndarray:
+    try:
+        return np.linalg.cholesky(X)
+    except np.linalg.LinAlgError:
+        raise OracleError("a diagonal block of D is not positive definite (no square root)")
+
+
+def sqrt_apply(F: Factor, x: np.ndarray, adjoint: bool = False) -> np.ndarray:
+    """Generalized square root of F for a positive definite matrix (Section 3.3).
+
+    F^{1/2} = (prod V_i) P_t D^{1/2}, where D^{1/2} is the lower Cholesky factor of every
+    diagonal block of D (X_RR of each record, A_top).  Since V_i = W_i^* when the matrix is
+    positive definite, F = F^{1/2} (F^{1/2})^* with
+    (F^{1/2})^* = D^{1/2 *} P_t^* (prod' W_i).  adjoint selects the second operator.
+    """
+    z = np.array(x, dtype=np.float64, copy=True)
+    if not adjoint:
+        for r in F.records:                       # D^{1/2} on every R block
+            z[r.R] = _chol(r.XRR) @ z[r.R]
+        if len(F.top):
+            z[F.top] = _chol(F.A_top) @ z[F.top]
+        for r in reversed(F.records):             # V_1 acts last
+            z[r.J] += r.E @ z[r.R]
+            z[r.R] += r.T.T @ z[r.S]
+    else:
+        for r in F.records:                       # W_1 acts first
+            z[r.S] += r.T @ z[r.R]
+            z[r.R] += r.G @ z[r.J]
+        for r in F.records:                       # D^{1/2 *}
+            z[r.R] = _chol(r.XRR).T @ z[r.R]
+        if len(F.top):
+            z[F.top] = _chol(F.A_top).T @ z[F.top]
+    return z
+
+
 # --------------------------------------------------------------------------
 # The exact operator and the outer iteration (Section 4: K applied by FFT; CG with F)
 # --------------------------------------------------------------------------

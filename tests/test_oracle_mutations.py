@@ -70,3 +70,31 @@ def test_mutation_is_caught(name):
     except Exception:
         agrees = False
     assert not agrees
+
+
+SQRT_MUTATIONS = {
+    "transposed_block_root": ("z[r.R] = _chol(r.XRR) @ z[r.R]", "z[r.R] = _chol(r.XRR).T @ z[r.R]"),
+    "transposed_top_root": ("z[F.top] = _chol(F.A_top) @ z[F.top]", "z[F.top] = _chol(F.A_top).T @ z[F.top]"),
+    "adjoint_without_root": ("z[r.R] = _chol(r.XRR).T @ z[r.R]", "z[r.R] = 1.0 * z[r.R]"),
+}
+
+
+def _sqrt_pins_hold(mod):
+    pts, p = W.grid_points(24), O.Params(**W.problem(24, 1e-3, leaf_size=16))
+    F = mod.factor(pts, mod.Params(**p.__dict__))
+    eye = np.eye(len(pts))
+    C = mod.sqrt_apply(F, eye)
+    Ca = mod.sqrt_apply(F, eye, adjoint=True)
+    Fd = mod.apply(F, eye)
+    return bool(np.allclose(Ca, C.T, rtol=0, atol=1e-12) and np.allclose(C @ C.T, Fd, rtol=0, atol=1e-12))
+
+
+def test_sqrt_pins_hold_unmutated():
+    assert _sqrt_pins_hold(O)
+
+
+@pytest.mark.parametrize("name", sorted(SQRT_MUTATIONS))
+def test_sqrt_pins_catch_planted_mistake(name):
+    old, new = SQRT_MUTATIONS[name]
+    assert not _sqrt_pins_hold(_mutant(old, new)), f"mutation {name} not caught"
+

@@ -257,6 +257,50 @@ def test_factor_accuracy_grid64(tol):
         np.testing.assert_allclose(r.E, r.G.T, rtol=0, atol=1e-13)
 
 
+# ---------------------------------------------------------------- generalized square root (Section 3.3)
+
+def test_sqrt_depth_one_is_the_cholesky_factor():
+    # no records: F^{1/2} = D^{1/2} = the factor C with C C^T = A, lower triangular with a
+    # positive diagonal (unique), and the adjoint is its transpose
+    pts = W.random_points(100, seed=4)
+    p = O.Params(weight=0.01, tol=1e-3, leaf_size=64)
+    F = O.factor(pts, p)
+    assert F.depth <= 1 and len(F.records) == 0
+    A = O.dense_matrix(pts, p)
+    C = O.sqrt_apply(F, np.eye(100))
+    Ca = O.sqrt_apply(F, np.eye(100), adjoint=True)
+    assert np.all(np.triu(C, 1) == 0.0) and np.all(np.diag(C) > 0.0)
+    np.testing.assert_allclose(C @ C.T, A, rtol=0, atol=1e-14 * np.abs(A).max())
+    np.testing.assert_array_equal(Ca, C.T)
+
+
+def test_sqrt_factorizes_F():
+    # F = F^{1/2} (F^{1/2})^* against the dense F from the pinned apply, the adjoint equals
+    # the transpose (V_i = W_i^*), and F^{1/2} (F^{1/2})^T approximates A to the tolerance
+    n, tol = 32, 1e-6
+    pts = W.grid_points(n)
+    p = _params(n, tol, leaf_size=16)
+    F = O.factor(pts, p)
+    assert F.depth >= 3 and len(F.records) > 0
+    N = n * n
+    C = O.sqrt_apply(F, np.eye(N))
+    Ca = O.sqrt_apply(F, np.eye(N), adjoint=True)
+    Fd = O.apply(F, np.eye(N))
+    np.testing.assert_allclose(Ca, C.T, rtol=0, atol=1e-13 * np.abs(C).max())
+    np.testing.assert_allclose(C @ C.T, Fd, rtol=0, atol=1e-13 * np.abs(Fd).max())
+    A = O.dense_matrix(pts, p)
+    assert np.linalg.norm(C @ C.T - A) <= 10 * tol * np.linalg.norm(A)
+
+
+def test_sqrt_needs_positive_definite_blocks():
+    # a negative definite matrix: D has no real square root
+    pts = W.grid_points(16)
+    p = O.Params(diag=-1.0, weight=1.0 / 256, tol=1e-6, leaf_size=16)
+    F = O.factor(pts, p)
+    with pytest.raises(O.OracleError):
+        O.sqrt_apply(F, np.ones(256))
+
+
 def test_rank_growth_is_mild():
     # Cor. 2 assumption: per-level skeleton sizes grow slowly with N
     ks = []
