@@ -11,7 +11,8 @@
  *     K(z) = -log|z| / (2 pi)                       (2D Laplace, Section 3.2).
  * rss_factor_create builds F ~ A (eq. rss, Algorithm 1) to tolerance tol;
  * rss_solve applies F^{-1} (Section 3.3, the F^{-1} product), rss_apply applies F,
- * rss_logdet returns log|det D| (Section 3.3), rss_matvec applies A exactly and
+ * rss_logdet returns log|det D| (Section 3.3), rss_sqrt_apply applies the generalized
+ * square root F^{1/2} or its adjoint (Section 3.3), rss_matvec applies A exactly and
  * rss_gmres solves A x = b by GMRES preconditioned with F^{-1} (Section 4 uses F
  * as a preconditioner for an outer Krylov iteration).
  *
@@ -112,6 +113,18 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
 
 /* sign * exp(logabs) = det D = det F (the V_i, W_i are unit triangular). */
 rss_status rss_logdet(rss_factor f, double* sign, double* logabs);
+
+/* Generalized square root of F for a positive definite matrix (Section 3.3):
+ *     C = F^{1/2} = (prod V_i) P_t D^{1/2},   F = C C^*,
+ * with D^{1/2} the lower Cholesky factor of each diagonal block of D (X_RR of every
+ * skeletonization step and the top block) and C^* = D^{1/2 *} P_t^* (prod' W_i), which
+ * uses V_i = W_i^* (a symmetric kernel).  adjoint == 0: y = C x; otherwise y = C^* x.
+ * d_x, d_y: device, N x nrhs, leading dimension ld, must not alias.  FP64 records.  The
+ * first call on a factor computes the Cholesky factors (one more N-sized set of blocks,
+ * kept until rss_factor_destroy) and synchronizes the stream; RSS_E_SINGULAR when a
+ * block is not positive definite (then no square root exists and nothing is written). */
+rss_status rss_sqrt_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld,
+                          int32_t adjoint, void* stream);
 
 /* Tree depth D (leaves at depth D; levels D..2 are skeletonized) and the number of
  * DOFs in the top block. */

@@ -791,7 +791,7 @@ rss_status rss_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs,
         check_launch();
         for (auto& L : f->levels)
             for (int col = 0; col < 9; ++col) {
-                rss::launch_apply_fwd(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), d_y, nrhs, ld, s);
+                rss::launch_apply_fwd(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), d_y, nrhs, ld, nullptr, s);
                 check_launch();
             }
         if ((size_t)f->ntop * nrhs > f->work_elems) fail(RSS_E_ARG, "nrhs too large for the top workspace");
@@ -799,9 +799,73 @@ rss_status rss_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs,
         check_launch();
         for (auto it = f->levels.rbegin(); it != f->levels.rend(); ++it)
             for (int col = 8; col >= 0; --col) {
-                rss::launch_apply_bwd(*it, it->d_rec_boxes[col], (int)it->rec_boxes[col].size(), d_y, nrhs, ld, s);
+                rss::launch_apply_bwd(*it, it->d_rec_boxes[col], (int)it->rec_boxes[col].size(), d_y, nrhs, ld, nullptr, s);
                 check_launch();
             }
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
+// Cholesky factors of the blocks of D, built once per factor on the first square-root
+// call (synchronizes).  Throws RSS_E_SINGULAR when a block is not positive definite.
+static void ensure_sqrt(rss_factor f, hipStream_t s) {
+    if (f->sqrt_ready) return;
+    int* fl = f->flag + 15;
+    HIPCHK(hipMemsetAsync(fl, 0, sizeof(int), s));
+    for (auto& L : f->levels) {
+        if (!L.Lc) L.Lc = dalloc<double>(f, (size_t)L.nbox * L.nmax * L.nmax, s);
+        for (int col = 0; col < 9; ++col) {
+            rss::launch_chol_records(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), fl, s);
+            check_launch();
+        }
+    }
+    if (f->ntop > 0) {
+        if (!f->top_L) f->top_L = dalloc<double>(f, (size_t)f->ntop * f->ntop, s);
+        if (!f->top_LT) f->top_LT = dalloc<double>(f, (size_t)f->ntop * f->ntop, s);
+        rss::launch_chol_top(f->top_A, f->ntop, f->top_L, f->top_LT, fl, s);
+        check_launch();
+    }
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, fl, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag & 16) fail(RSS_E_SINGULAR, "a diagonal block of D is not positive definite: no square root");
+    f->sqrt_ready = 1;
+}
+
+rss_status rss_sqrt_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld, int32_t adjoint,
+                          void* stream) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_x || !d_y || nrhs < 1 || ld < f->n || d_x == d_y) { g_err = "bad sqrt_apply arguments"; return RSS_E_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if ((size_t)f->ntop * nrhs > f->work_elems) fail(RSS_E_ARG, "nrhs too large for the top workspace");
+        ensure_sqrt(f, s);
+        rss::launch_copy_cols(d_x, ld, d_y, ld, f->n, nrhs, s);
+        check_launch();
+        if (!adjoint) {
+            // (prod V_i) P_t D^{1/2}: the top block first, then each record's L just before its V_i
+            rss::launch_top_apply(f->top_idx, f->ntop, f->top_L, nullptr, d_y, nrhs, ld, f->work, s);
+            check_launch();
+            for (auto it = f->levels.rbegin(); it != f->levels.rend(); ++it)
+                for (int col = 8; col >= 0; --col) {
+                    rss::launch_apply_bwd(*it, it->d_rec_boxes[col], (int)it->rec_boxes[col].size(), d_y, nrhs, ld,
+                                          it->Lc, s);
+                    check_launch();
+                }
+        } else {
+            // D^{1/2 *} P_t^* (prod' W_i): each W_i followed by its record's L^T, the top last
+            for (auto& L : f->levels)
+                for (int col = 0; col < 9; ++col) {
+                    rss::launch_apply_fwd(L, L.d_rec_boxes[col], (int)L.rec_boxes[col].size(), d_y, nrhs, ld, L.Lc,
+                                          s);
+                    check_launch();
+                }
+            rss::launch_top_apply(f->top_idx, f->ntop, f->top_LT, nullptr, d_y, nrhs, ld, f->work, s);
+            check_launch();
+        }
     } catch (const Fail& e) {
         return e.st;
     }

@@ -57,6 +57,7 @@ struct Level {
     double* G = nullptr;       // nbox * nmax * ldJ, |R| x |J| (ld nmax)
     double* XRR = nullptr;     // nbox * nmax * nmax
     double* Xinv = nullptr;    // nbox * nmax * nmax
+    double* Lc = nullptr;      // nbox * nmax * nmax: lower Cholesky factor of X_RR (built on first use)
     float* XJR32 = nullptr;    // mixed: FP32 copies
     float* G32 = nullptr;
     float* Xinv32 = nullptr;
@@ -112,6 +113,9 @@ struct rss_factor_s {
     double* top_A = nullptr;        // ntop x ntop
     double* top_inv = nullptr;      // explicit inverse
     float* top_inv32 = nullptr;
+    double* top_L = nullptr;        // lower Cholesky factor of top_A (built on first use) ...
+    double* top_LT = nullptr;       // ... and its transpose, both dense ntop x ntop
+    int sqrt_ready = 0;
     double top_logdet = 0;
     int top_sign = 1;
     // workspaces
@@ -174,10 +178,16 @@ void launch_solve_fwd(const Level& L, const int* boxes, int nboxes, double* z, i
                       int use32, hipStream_t s);
 void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
                       int use32, hipStream_t s);
+// Lroot == nullptr: F x.  Lroot == L.Lc: the generalized square root, with the block
+// Cholesky factors in place of X_RR (forward sweep: L^T after W_i; backward: L before V_i).
 void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
-                      hipStream_t s);
+                      const double* Lroot, hipStream_t s);
 void launch_apply_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
-                      hipStream_t s);
+                      const double* Lroot, hipStream_t s);
+// Cholesky factors: of X_RR for the listed records (into L.Lc), and of the dense top block
+// (L and its transpose LT).  A block that is not positive definite sets bit 16 of *flag.
+void launch_chol_records(const Level& L, const int* boxes, int nboxes, int* flag, hipStream_t s);
+void launch_chol_top(const double* A, int64_t n, double* Lt, double* LT, int* flag, hipStream_t s);
 void launch_top_apply(const int* top_idx, int64_t ntop, const double* M, const float* M32, double* z,
                       int nrhs, int64_t ld, double* tmp, hipStream_t s);
 void launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);

@@ -29,6 +29,7 @@ struct SweepArgs {
     const void* G;
     const void* Xinv;
     const double* XRR;
+    const double* Lc;   // Cholesky factors of X_RR (square-root sweeps) or nullptr
 };
 
 // sum_{t < cnt} M[t * stride] v[t] in eight partial sums, with sixteen loads of M in
@@ -189,7 +190,12 @@ __global__ void __launch_bounds__(NTH) k_apply_fwd(SweepArgs a, const int* __res
             zR[b] += sp;
         }
         __syncthreads();
-        for (int b = tid; b < r; b += NTH) w[b] = dot_strided(X + b, nmax, zR, r);   // z_R <- X_RR z_R
+        if (a.Lc) {   // z_R <- L^T z_R (L lower, column-major)
+            const double* Lb = a.Lc + c * bsz;
+            for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Lb + (int64_t)b * nmax + b, 1, zR + b, r - b);
+        } else {
+            for (int b = tid; b < r; b += NTH) w[b] = dot_strided(X + b, nmax, zR, r);   // z_R <- X_RR z_R
+        }
         __syncthreads();
         for (int b = tid; b < r; b += NTH) zc[rg[b]] = w[b];
         __syncthreads();
@@ -220,6 +226,13 @@ __global__ void __launch_bounds__(NTH) k_apply_bwd(SweepArgs a, const int* __res
         double* zc = z + (int64_t)h * ld;
         for (int b = tid; b < r; b += NTH) zR[b] = zc[rg[b]];
         __syncthreads();
+        if (a.Lc) {   // z_R <- L z_R first (the square root of this record's block of D)
+            const double* Lb = a.Lc + c * bsz;
+            for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Lb + b, nmax, zR, b + 1);
+            __syncthreads();
+            for (int b = tid; b < r; b += NTH) zR[b] = w[b];
+            __syncthreads();
+        }
         for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Xi + b, nmax, zR, r);   // w = X_RR^{-1} z_R
         __syncthreads();
         for (int jj = tid; jj < nj; jj += NTH) zc[J[jj]] += dot_strided(E + jj, ldJ, w, r);   // z_J += X_JR w
@@ -234,7 +247,7 @@ __global__ void __launch_bounds__(NTH) k_apply_bwd(SweepArgs a, const int* __res
 static SweepArgs sweep_args(const Level& L, int use32) {
     SweepArgs a;
     a.nmax = L.nmax; a.ldJ = L.ldJ; a.cnt = L.cnt; a.krank = L.krank; a.nJ = L.nJ;
-    a.Sg = L.Sg; a.Rg = L.Rg; a.Jg = L.Jg; a.XRR = L.XRR;
+    a.Sg = L.Sg; a.Rg = L.Rg; a.Jg = L.Jg; a.XRR = L.XRR; a.Lc = nullptr;
     if (use32) { a.T = L.T32; a.XJR = L.XJR32; a.G = L.G32; a.Xinv = L.Xinv32; }
     else { a.T = L.T; a.XJR = L.XJR; a.G = L.G; a.Xinv = L.Xinv; }
     return a;
@@ -269,18 +282,98 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
 }
 
 void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
-                      hipStream_t s) {
+                      const double* Lroot, hipStream_t s) {
     if (nboxes <= 0) return;
     const size_t lds = sizeof(double) * (size_t)L.ldJ;
-    if (nboxes < 256) k_apply_fwd<1024><<<dim3(nboxes), dim3(1024), lds, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
-    else k_apply_fwd<256><<<dim3(nboxes), dim3(256), lds, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    SweepArgs a = sweep_args(L, 0);
+    a.Lc = Lroot;
+    if (nboxes < 256) k_apply_fwd<1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
+    else k_apply_fwd<256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
 }
 
 void launch_apply_bwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
-                      hipStream_t s) {
+                      const double* Lroot, hipStream_t s) {
     if (nboxes <= 0) return;
-    if (nboxes < 256) k_apply_bwd<1024><<<dim3(nboxes), dim3(1024), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
-    else k_apply_bwd<256><<<dim3(nboxes), dim3(256), 0, s>>>(sweep_args(L, 0), boxes, z, nrhs, ld);
+    SweepArgs a = sweep_args(L, 0);
+    a.Lc = Lroot;
+    if (nboxes < 256) k_apply_bwd<1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
+    else k_apply_bwd<256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+}
+
+// ---- generalized square root (Section 3.3): Cholesky factors of the blocks of D --------
+
+// In-place lower Cholesky factor of the n x n block at L (column-major, leading dimension
+// ld; only the lower triangle is read), right-looking, one column per step.  Every thread
+// of the workgroup calls it; a pivot that is not positive (or NaN) sets bit 16 of *flag and
+// ends the factorization (the same decision on every thread).
+template <int NTH>
+__device__ void chol_inplace(double* L, int n, int64_t ld, int* flag) {
+    const int tid = threadIdx.x;
+    for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const double d = L[j + ld * j];
+        if (!(d > 0.0)) {
+            if (tid == 0) atomicOr(flag, 16);
+            return;
+        }
+        const double sd = sqrt(d), inv = 1.0 / sd;
+        for (int i = j + 1 + tid; i < n; i += NTH) L[i + ld * j] *= inv;
+        __syncthreads();
+        if (tid == 0) L[j + ld * j] = sd;
+        const int m = n - j - 1;
+        for (int e = tid; e < m * m; e += NTH) {
+            const int ii = e % m, ll = e / m;
+            if (ii >= ll) {
+                const int i = j + 1 + ii, l = j + 1 + ll;
+                L[i + ld * l] -= L[i + ld * j] * L[l + ld * j];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// One workgroup per record: L.Lc of the box <- lower Cholesky factor of X_RR (upper
+// triangle zero).
+__global__ void __launch_bounds__(256) k_chol_records(const int* __restrict__ boxes, const int* __restrict__ cnt,
+                                                      const int* __restrict__ krank, const int* __restrict__ nJ,
+                                                      const double* __restrict__ XRR, double* Lc, int nmax,
+                                                      int* flag) {
+    const int c = boxes[blockIdx.x];
+    if (nJ[c] == 0) return;
+    const int r = cnt[c] - krank[c];
+    const int64_t bsz = (int64_t)nmax * nmax;
+    const double* X = XRR + c * bsz;
+    double* L = Lc + c * bsz;
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+        const int i = e % r, j = e / r;
+        L[i + (int64_t)nmax * j] = i >= j ? X[i + (int64_t)nmax * j] : 0.0;
+    }
+    chol_inplace<256>(L, r, nmax, flag);
+}
+
+// One workgroup: Lt <- lower Cholesky factor of the dense top block A, LT <- its transpose.
+__global__ void __launch_bounds__(1024) k_chol_top(const double* __restrict__ A, int n, double* Lt, double* LT,
+                                                   int* flag) {
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 1024) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        Lt[e] = i >= j ? A[e] : 0.0;
+    }
+    chol_inplace<1024>(Lt, n, n, flag);
+    if (*flag & 16) return;
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 1024) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        LT[(int64_t)j + (int64_t)n * i] = Lt[e];
+    }
+}
+
+void launch_chol_records(const Level& L, const int* boxes, int nboxes, int* flag, hipStream_t s) {
+    if (nboxes <= 0) return;
+    k_chol_records<<<dim3(nboxes), dim3(256), 0, s>>>(boxes, L.cnt, L.krank, L.nJ, L.XRR, L.Lc, L.nmax, flag);
+}
+
+void launch_chol_top(const double* A, int64_t n, double* Lt, double* LT, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    k_chol_top<<<dim3(1), dim3(1024), 0, s>>>(A, (int)n, Lt, LT, flag);
 }
 
 // ---- top block ------------------------------------------------------------------------

@@ -27,7 +27,7 @@ STATUS = {0: "RSS_OK", 1: "RSS_E_ARG", 2: "RSS_E_NOMEM", 3: "RSS_E_DEVICE", 4: "
           5: "RSS_E_UNSUPPORTED", 6: "RSS_E_NOCONV"}
 
 # exported names declared in include/rss.h
-EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_matvec", "rss_gmres",
+EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_sqrt_apply", "rss_matvec", "rss_gmres",
            "rss_logdet", "rss_shape", "rss_box_sets", "rss_top_set", "rss_info", "rss_factor_destroy",
            "rss_last_error", "rss_trim"]
 
@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rss_factor_create.argtypes = [vp, i64, P(Params), vp, P(vp)]
     lib.rss_solve.argtypes = [vp, vp, vp, i32, i64, i32, vp]
     lib.rss_apply.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.rss_sqrt_apply.argtypes = [vp, vp, vp, i32, i64, i32, vp]
     lib.rss_matvec.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.rss_gmres.argtypes = [vp, vp, vp, dbl, i32, i32, i32, vp, P(i32), P(dbl)]
     lib.rss_logdet.argtypes = [vp, P(dbl), P(dbl)]
@@ -186,6 +187,14 @@ class Factor:
         if st != 6 or raise_on_noconv:
             _check(st)
         return x, it.value, rr.value
+
+    def sqrt_apply(self, x, adjoint: bool = False):
+        """y = F^{1/2} x, or (F^{1/2})^* x with adjoint (generalized square root, Section 3.3)."""
+        xx, single = self._vec(x)
+        y = self._torch.empty_like(xx).t().contiguous().t()
+        _check(lib().rss_sqrt_apply(self._h, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                    xx.shape[1], self.n, int(bool(adjoint)), _stream(self._torch)))
+        return y.reshape(-1) if single else y
 
     def logdet(self):
         s, l = ctypes.c_double(), ctypes.c_double()

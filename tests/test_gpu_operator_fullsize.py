@@ -91,4 +91,10 @@ def test_full_size_properties(rss, n, precision, tol):
     rel = res / np.linalg.norm(W.rhs(n * n, seed=0))
     say(f"[fullsize] n={n} gmres iters={it} relres(gpu)={rr:.2e} relres(oracle operator)={rel:.2e}")
     assert rr <= 1e-10 and rel <= 2e-10 and it <= 8
+    if precision == "fp64":
+        # generalized square root at full size: F^{1/2} (F^{1/2})^* b = F b
+        y2 = F.sqrt_apply(F.sqrt_apply(b, adjoint=True))
+        e2 = float(torch.linalg.norm(y2 - F.apply(b)) / torch.linalg.norm(F.apply(b)))
+        say(f"[fullsize] n={n} |C C^* b - F b|/|F b| = {e2:.2e}")
+        assert e2 <= 1e-12
     F.close()

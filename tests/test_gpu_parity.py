@@ -199,3 +199,62 @@ def test_argument_errors_on_device(rss):
     with pytest.raises(rss.RSSError) as ei:
         _gpu_factor(rss, pts, O.Params(**W.problem(16, 1e-6)))
     assert ei.value.name == "RSS_E_ARG"
+
+
+# ---- generalized square root F^{1/2} = (prod V_i) P_t D^{1/2} (Section 3.3) ---------------
+
+@pytest.mark.parametrize("n,tol,precision", [(64, 1e-6, "fp64"), (64, 1e-9, "mixed"), (100, 1e-6, "fp64")])
+def test_sqrt_apply_matches_oracle(rss, n, tol, precision):
+    pts = W.grid_points(n)
+    p = O.Params(**W.problem(n, tol))
+    say(f"[parity] case=sqrt grid{n} tol={tol} precision={precision}")
+    F = _gpu_factor(rss, pts, p, precision)
+    R = O.factor(pts, p)
+    b = W.rhs(n * n, seed=5, nrhs=2)
+    bt = torch.tensor(b, device="cuda")
+    # mixed: the FP32 Schur products perturb F by a few u32 (as for F^{-1} b above)
+    ftol = factor_tol(tol) if precision == "fp64" else 40 * float(np.finfo(np.float32).eps) / 2
+    for adj in (False, True):
+        y = F.sqrt_apply(bt, adjoint=adj).cpu().numpy()
+        yr = O.sqrt_apply(R, b, adjoint=adj)
+        e = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+        say(f"[parity] sqrt adjoint={adj} rel={e:.2e}")
+        assert e <= ftol
+    # F = F^{1/2} (F^{1/2})^* on the device itself.  FP64: to rounding.  Mixed: the FP32
+    # Schur products leave the stored blocks symmetric only to a few u32, so V_i^* = W_i
+    # (E^T = G) holds to that order (measured 6e-6, about 100 u32, at N = 4096 and tol 1e-9).
+    y2 = F.sqrt_apply(F.sqrt_apply(bt, adjoint=True)).cpu().numpy()
+    yf = F.apply(bt).cpu().numpy()
+    e2 = np.linalg.norm(y2 - yf) / np.linalg.norm(yf)
+    say(f"[parity] sqrt C C^* vs F rel={e2:.2e}")
+    assert e2 <= (1e-12 if precision == "fp64" else 400 * float(np.finfo(np.float32).eps) / 2)
+    F.close()
+
+
+def test_sqrt_apply_without_skeletonization_is_cholesky(rss):
+    # depth <= 1: F = A and F^{1/2} is the Cholesky factor of A
+    pts = W.random_points(200, seed=11)
+    p = O.Params(weight=1.0 / 200, tol=1e-6, leaf_size=256)
+    F = _gpu_factor(rss, pts, p)
+    assert F.shape()[0] <= 1
+    A = O.dense_matrix(pts, p)
+    Lc = np.linalg.cholesky(A)
+    b = W.rhs(200, seed=3)
+    bt = torch.tensor(b, device="cuda")
+    np.testing.assert_allclose(F.sqrt_apply(bt).cpu().numpy(), Lc @ b, rtol=0, atol=1e-13 * np.abs(Lc @ b).max())
+    np.testing.assert_allclose(F.sqrt_apply(bt, adjoint=True).cpu().numpy(), Lc.T @ b, rtol=0,
+                               atol=1e-13 * np.abs(Lc.T @ b).max())
+    F.close()
+
+
+def test_sqrt_apply_rejects_indefinite_blocks(rss):
+    pts = W.grid_points(16)
+    p = O.Params(diag=-1.0, weight=1.0 / 256, tol=1e-6, leaf_size=16)
+    F = _gpu_factor(rss, pts, p)
+    with pytest.raises(rss.RSSError) as ei:
+        F.sqrt_apply(torch.ones(256, dtype=torch.float64, device="cuda"))
+    assert ei.value.name == "RSS_E_SINGULAR"
+    # the factor itself stays usable
+    x = F.solve(torch.ones(256, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.all(np.isfinite(x))
+    F.close()
