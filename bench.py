@@ -234,7 +234,7 @@ def main():
         args.no_fp64 = True
         args.no_cpu_baseline = True
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 (multi-GPU sharding is a "
                                    "design note, not implemented)"}))
         sys.exit(2)
     mixed = run_gpu(args, "mixed")

@@ -48,7 +48,7 @@ typedef enum {
     RSS_E_NOMEM = 2,        /* device allocation failed */
     RSS_E_DEVICE = 3,       /* a HIP runtime call or kernel failed */
     RSS_E_SINGULAR = 4,     /* an exactly singular pivot block (X_RR or the top block) */
-    RSS_E_UNSUPPORTED = 5,  /* a size or mode this build does not handle (e.g. |B| > 256) */
+    RSS_E_UNSUPPORTED = 5,  /* a size or mode the library does not handle (e.g. |B| > 256) */
     RSS_E_NOCONV = 6        /* rss_gmres reached maxit before rtol */
 } rss_status;
 

@@ -20,8 +20,10 @@ its order and notation:
                               are the union of its children's skeletons
 * final factorization      -- Section 3.3, eq. (rss) and the F^{-1} formula after it
 * log-determinant          -- Section 3.3 (log|D| approximates log|K|)
+* generalized square root  -- Section 3.3, F^{1/2} = (prod V_i) P_t D^{1/2}, with the
+                              Cholesky factor of each block of D as D^{1/2}
 
-Readings of points the paper leaves open (all stated again in the design doc):
+Readings of points the paper leaves open:
 
 * O-ring / far split: O = boxes at Chebyshev distance exactly 2 (the boxes inside
   the proxy circle), P = distance >= 3, represented by the proxy points only.
@@ -36,6 +38,8 @@ Readings of points the paper leaves open (all stated again in the design doc):
 * Box order inside a level: 3^d colouring, colour-major, ascending box index.
 * DOF order inside every set: ascending global index.
 * Diagonal blocks X_RR and the top block are factored by LU with partial pivoting.
+* Square root: D^{1/2} = the lower Cholesky factor of each block; the adjoint uses
+  W_i for V_i^* (equal for a symmetric positive definite matrix).
 
 parity pinned by tests/test_oracle_*.py (dense operator products, LAPACK pivoted
 QR, brute-force factors at tiny N, closed-form counts).

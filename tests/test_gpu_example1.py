@@ -57,7 +57,7 @@ def test_first_kind_accuracy_against_paper(rss, n, tol, precision):
 
 def test_first_kind_tol1e9_exceeds_box_limit(rss):
     # At tol 1e-9 the first-kind system of N = 512^2 needs more than 256 active DOFs in a
-    # box of the upper levels, beyond this build's per-box limit: a clean error, no factor.
+    # box of the upper levels, beyond the library's per-box limit (256 DOFs): a clean error, no factor.
     n = 512
     say(f"[example1] N={n * n} tol=1e-9: expecting RSS_E_UNSUPPORTED")
     with pytest.raises(rss.RSSError) as ei:
