@@ -12,6 +12,8 @@
 //   F = (prod V_i) P_t D P_t^* (prod' W_i)
 //   W_i z : z_S += T z_R ; z_R += G z_J     (then D: z_R <- X_RR z_R)
 //   V_i z : z_J += E z_R ; z_R += T^T z_S
+#include <algorithm>
+
 #include "rss_internal.h"
 
 namespace rss {
@@ -56,10 +58,60 @@ __device__ inline double dot_strided(const TT* __restrict__ M, int64_t stride, c
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-template <typename TT, int NTH>
+// NR dot products sharing the loads of M: out[h] = sum_{t < cnt} M[t * stride] v[h * ldv + t].
+// Per h the partial sums, their order and the final combination are those of
+// dot_strided, so each result is bit for bit the single-vector one.
+template <typename TT, int NR>
+__device__ inline void dot_strided_m(const TT* __restrict__ M, int64_t stride, const double* v, int ldv, int cnt,
+                                     double (&out)[NR]) {
+    double s[NR][8];
+#pragma unroll
+    for (int h = 0; h < NR; ++h)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[h][u] = 0.0;
+    // loads in flight: sixteen, or eight for several FP64 vectors (registers); the
+    // sequence of terms each partial sum receives is the same either way
+    constexpr int UL = (sizeof(TT) == 8 && NR > 1) ? 8 : 16;
+    int t = 0;
+    for (; t + 16 <= cnt; t += 16) {
+#pragma unroll
+        for (int u0 = 0; u0 < 16; u0 += UL) {
+            TT m[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) m[u] = M[(int64_t)(t + u0 + u) * stride];
+#pragma unroll
+            for (int u = 0; u < UL; ++u)
+#pragma unroll
+                for (int h = 0; h < NR; ++h) s[h][(u0 + u) & 7] += (double)m[u] * v[h * ldv + t + u0 + u];
+        }
+    }
+    for (; t + 8 <= cnt; t += 8) {
+        TT m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m[u] = M[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int h = 0; h < NR; ++h) s[h][u] += (double)m[u] * v[h * ldv + t + u];
+    }
+    for (; t < cnt; ++t) {
+        const TT m = M[(int64_t)t * stride];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) s[h][0] += (double)m * v[h * ldv + t];
+    }
+#pragma unroll
+    for (int h = 0; h < NR; ++h)
+        out[h] = ((s[h][0] + s[h][1]) + (s[h][2] + s[h][3])) + ((s[h][4] + s[h][5]) + (s[h][6] + s[h][7]));
+}
+
+// NR = 1: the right-hand sides one after the other (nrhs of them).  NR > 1: nrhs <= NR
+// right-hand sides together, so every entry of the record is loaded once for all of
+// them.
+template <typename TT, int NTH, int NR>
 __global__ void __launch_bounds__(NTH) k_solve_fwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
-    __shared__ double zS[kMaxBox], zR[kMaxBox], w[kMaxBox];
+    constexpr int PL = kMaxBox;
+    __shared__ double zS[NR * PL], zR[NR * PL], w[NR * PL];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -75,32 +127,52 @@ __global__ void __launch_bounds__(NTH) k_solve_fwd(SweepArgs a, const int* __res
     for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
     for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
-    for (int h = 0; h < nrhs; ++h) {
-        double* zc = z + (int64_t)h * ld;
-        for (int i = tid; i < k; i += NTH) zS[i] = zc[sg[i]];
-        for (int i = tid; i < r; i += NTH) zR[i] = zc[rg[i]];
-        __syncthreads();
-        for (int b = tid; b < r; b += NTH) zR[b] -= dot_strided(T + (int64_t)b * nmax, 1, zS, k);   // z_R -= T^T z_S
-        __syncthreads();
-        for (int b = tid; b < r; b += NTH) w[b] = dot_strided(Xi + b, nmax, zR, r);   // X_RR^{-1} z_R
-        __syncthreads();
-        for (int jj = tid; jj < nj; jj += NTH) {                                        // z_J -= E w
-            const int g = J[jj];
-            const double sj = dot_strided(E + jj, ldJ, w, r);
-            zc[g] -= sj;
+    const int nh = NR == 1 ? 1 : nrhs;          // right-hand sides per pass
+    const int npass = NR == 1 ? nrhs : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+        double* z0 = z + (int64_t)pass * ld;
+        for (int h = 0; h < nh; ++h) {
+            const double* zc = z0 + (int64_t)h * ld;
+            for (int i = tid; i < k; i += NTH) zS[h * PL + i] = zc[sg[i]];
+            for (int i = tid; i < r; i += NTH) zR[h * PL + i] = zc[rg[i]];
         }
-        for (int b = tid; b < r; b += NTH) zc[rg[b]] = w[b];
+        __syncthreads();
+        for (int b = tid; b < r; b += NTH) {   // z_R -= T^T z_S
+            double o[NR];
+            dot_strided_m<TT, NR>(T + (int64_t)b * nmax, 1, zS, PL, k, o);
+#pragma unroll
+            for (int h = 0; h < NR; ++h) zR[h * PL + b] -= o[h];
+        }
+        __syncthreads();
+        for (int b = tid; b < r; b += NTH) {   // X_RR^{-1} z_R
+            double o[NR];
+            dot_strided_m<TT, NR>(Xi + b, nmax, zR, PL, r, o);
+#pragma unroll
+            for (int h = 0; h < NR; ++h) w[h * PL + b] = o[h];
+        }
+        __syncthreads();
+        for (int jj = tid; jj < nj; jj += NTH) {   // z_J -= E w
+            const int g = J[jj];
+            double o[NR];
+            dot_strided_m<TT, NR>(E + jj, ldJ, w, PL, r, o);
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+                if (h < nh) z0[(int64_t)h * ld + g] -= o[h];
+        }
+        for (int b = tid; b < r; b += NTH)
+            for (int h = 0; h < nh; ++h) z0[(int64_t)h * ld + rg[b]] = w[h * PL + b];
         __syncthreads();
     }
 }
 
-template <typename TT, int NTH>
+// Dynamic LDS: zJ[NR * ldJ], and for NR > 1 the wave partial sums part[NW][NR][nmax].
+template <typename TT, int NTH, int NR>
 __global__ void __launch_bounds__(NTH) k_solve_bwd(SweepArgs a, const int* __restrict__ boxes, double* z,
                                                    int nrhs, int64_t ld) {
     constexpr int NW = NTH / 64;
-    extern __shared__ double zJ[];   // ldJ
-    __shared__ double zR[kMaxBox];
-    __shared__ double part[NW][kMaxBox];
+    extern __shared__ double dyn[];
+    __shared__ double zR[NR * kMaxBox];
+    __shared__ double part_s[NR == 1 ? NW * kMaxBox : 1];
     __shared__ int sg[kMaxBox], rg[kMaxBox];
     const int tid = threadIdx.x;
     const int c = boxes[blockIdx.x];
@@ -112,32 +184,56 @@ __global__ void __launch_bounds__(NTH) k_solve_bwd(SweepArgs a, const int* __res
     const TT* T = (const TT*)a.T + c * bsz;
     const TT* G = (const TT*)a.G + (int64_t)c * nmax * ldJ;
     const int* J = a.Jg + (int64_t)c * ldJ;
+    double* zJ = dyn;
+    double* part = NR == 1 ? part_s : dyn + (int64_t)NR * ldJ;
+    const int PL = NR == 1 ? kMaxBox : nmax;   // part[(w * NR + h) * PL + b]
     for (int i = tid; i < k; i += NTH) sg[i] = a.Sg[(int64_t)c * nmax + i];
     for (int i = tid; i < r; i += NTH) rg[i] = a.Rg[(int64_t)c * nmax + i];
     __syncthreads();
     const int wv = tid >> 6, lane = tid & 63;
     const int q4 = (nj + NW - 1) / NW;   // J entries per wave
-    for (int h = 0; h < nrhs; ++h) {
-        double* zc = z + (int64_t)h * ld;
-        for (int jj = tid; jj < nj; jj += NTH) zJ[jj] = zc[J[jj]];
+    const int nh = NR == 1 ? 1 : nrhs;
+    const int npass = NR == 1 ? nrhs : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+        double* z0 = z + (int64_t)pass * ld;
+        for (int h = 0; h < nh; ++h)
+            for (int jj = tid; jj < nj; jj += NTH) zJ[h * ldJ + jj] = z0[(int64_t)h * ld + J[jj]];
         __syncthreads();
         // z_R -= G z_J : wave wv takes a contiguous 1/NW of J, lanes take rows b
         const int j0 = wv * q4, j1 = min(nj, j0 + q4);
         for (int b0 = 0; b0 < r; b0 += 64) {
             const int b = b0 + lane;
-            if (b < r) part[wv][b] = j1 > j0 ? dot_strided(G + b + (int64_t)j0 * nmax, nmax, zJ + j0, j1 - j0) : 0.0;
-        }
-        __syncthreads();
-        for (int b = tid; b < r; b += NTH) {
-            double sp = 0.0;
+            if (b < r) {
+                double o[NR];
+                if (j1 > j0) {
+                    dot_strided_m<TT, NR>(G + b + (int64_t)j0 * nmax, nmax, zJ + j0, ldJ, j1 - j0, o);
+                } else {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) sp += part[w][b];
-            double v = zc[rg[b]] - sp;
-            zR[b] = v;
-            zc[rg[b]] = v;
+                    for (int h = 0; h < NR; ++h) o[h] = 0.0;
+                }
+#pragma unroll
+                for (int h = 0; h < NR; ++h) part[(wv * NR + h) * PL + b] = o[h];
+            }
         }
         __syncthreads();
-        for (int q = tid; q < k; q += NTH) zc[sg[q]] -= dot_strided(T + q, nmax, zR, r);   // z_S -= T z_R
+        for (int b = tid; b < r; b += NTH)
+            for (int h = 0; h < nh; ++h) {
+                double sp = 0.0;
+#pragma unroll
+                for (int u = 0; u < NW; ++u) sp += part[(u * NR + h) * PL + b];
+                double* zc = z0 + (int64_t)h * ld;
+                const double v = zc[rg[b]] - sp;
+                zR[h * kMaxBox + b] = v;
+                zc[rg[b]] = v;
+            }
+        __syncthreads();
+        for (int q = tid; q < k; q += NTH) {   // z_S -= T z_R
+            double o[NR];
+            dot_strided_m<TT, NR>(T + q, nmax, zR, kMaxBox, r, o);
+#pragma unroll
+            for (int h = 0; h < NR; ++h)
+                if (h < nh) z0[(int64_t)h * ld + sg[q]] -= o[h];
+        }
         __syncthreads();
     }
 }
@@ -253,17 +349,64 @@ static SweepArgs sweep_args(const Level& L, int use32) {
     return a;
 }
 
+// Several right-hand sides go through the sweeps in groups of kSolveGroup, each group in
+// one launch per colour (the record is read once per group); one right-hand side, or a
+// box size whose group buffers do not fit in LDS, takes the one-at-a-time kernels.
+constexpr int kSolveGroup = 4;
+
+template <typename TT, int NTH, int NR>
+static void solve_fwd_k(const SweepArgs& a, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                        hipStream_t s) {
+    k_solve_fwd<TT, NTH, NR><<<dim3(nboxes), dim3(NTH), 0, s>>>(a, boxes, z, nrhs, ld);
+}
+
+template <typename TT, int NTH, int NR>
+static void solve_bwd_k(const SweepArgs& a, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                        size_t lds, hipStream_t s) {
+    if (lds > 65536)
+        hipFuncSetAttribute((const void*)k_solve_bwd<TT, NTH, NR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_solve_bwd<TT, NTH, NR><<<dim3(nboxes), dim3(NTH), lds, s>>>(a, boxes, z, nrhs, ld);
+}
+
+template <typename TT, int NTH>
+static void solve_fwd_t(const SweepArgs& a, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                        hipStream_t s) {
+    if (nrhs == 1) {
+        solve_fwd_k<TT, NTH, 1>(a, boxes, nboxes, z, 1, ld, s);
+        return;
+    }
+    for (int h0 = 0; h0 < nrhs; h0 += kSolveGroup)
+        solve_fwd_k<TT, NTH, kSolveGroup>(a, boxes, nboxes, z + (int64_t)h0 * ld, std::min(kSolveGroup, nrhs - h0),
+                                          ld, s);
+}
+
+template <typename TT, int NTH>
+static void solve_bwd_t(const SweepArgs& a, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
+                        hipStream_t s) {
+    constexpr int NW = NTH / 64;
+    const size_t lds1 = sizeof(double) * (size_t)a.ldJ;
+    const size_t ldsg = sizeof(double) * ((size_t)kSolveGroup * a.ldJ + (size_t)NW * kSolveGroup * a.nmax);
+    const size_t stat = sizeof(double) * kSolveGroup * kMaxBox + 2 * sizeof(int) * kMaxBox + 1024;
+    if (nrhs == 1 || ldsg + stat > (size_t)elim_lds_limit()) {
+        solve_bwd_k<TT, NTH, 1>(a, boxes, nboxes, z, nrhs, ld, lds1, s);
+        return;
+    }
+    for (int h0 = 0; h0 < nrhs; h0 += kSolveGroup)
+        solve_bwd_k<TT, NTH, kSolveGroup>(a, boxes, nboxes, z + (int64_t)h0 * ld, std::min(kSolveGroup, nrhs - h0),
+                                          ld, ldsg, s);
+}
+
 void launch_solve_fwd(const Level& L, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld, int use32,
                       hipStream_t s) {
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
     // few boxes: a large workgroup per box keeps more loads of the record in flight
     if (nboxes < 256) {
-        if (use32) k_solve_fwd<float, 1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
-        else k_solve_fwd<double, 1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
+        if (use32) solve_fwd_t<float, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
+        else solve_fwd_t<double, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
     } else {
-        if (use32) k_solve_fwd<float, 256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
-        else k_solve_fwd<double, 256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
+        if (use32) solve_fwd_t<float, 256>(a, boxes, nboxes, z, nrhs, ld, s);
+        else solve_fwd_t<double, 256>(a, boxes, nboxes, z, nrhs, ld, s);
     }
 }
 
@@ -271,13 +414,12 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
                       hipStream_t s) {
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
-    const size_t lds = sizeof(double) * (size_t)L.ldJ;
     if (nboxes < 256) {
-        if (use32) k_solve_bwd<float, 1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
-        else k_solve_bwd<double, 1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
+        if (use32) solve_bwd_t<float, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
+        else solve_bwd_t<double, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
     } else {
-        if (use32) k_solve_bwd<float, 256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
-        else k_solve_bwd<double, 256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
+        if (use32) solve_bwd_t<float, 256>(a, boxes, nboxes, z, nrhs, ld, s);
+        else solve_bwd_t<double, 256>(a, boxes, nboxes, z, nrhs, ld, s);
     }
 }
 
