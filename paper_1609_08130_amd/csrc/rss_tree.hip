@@ -17,6 +17,44 @@ __device__ inline double kernel_entry(double xi, double yi, double xj, double yj
     return coef * log(dx * dx + dy * dy);
 }
 
+// log x (x > 0) to ~1.3e-12 relative: x = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// log m = 2 atanh(t), t = (m - 1) / (m + 1), |t| <= 0.172, by the odd series of atanh up to
+// t^13 (the first omitted term is below 5e-13).  Used for entries stored in FP32, whose
+// rounding (3e-8 relative) it leaves unchanged in all but rare ties; about a third of the
+// cost of the full-precision FP64 logarithm, which bounds the store kernels.
+__device__ inline double log_for_f32(double x) {
+    int e;
+    double m = frexp(x, &e);   // m in [1/2, 1)
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double t = (m - 1.0) / (m + 1.0);
+    const double t2 = t * t;
+    double p = 1.0 / 13.0;
+    p = fma(p, t2, 1.0 / 11.0);
+    p = fma(p, t2, 1.0 / 9.0);
+    p = fma(p, t2, 1.0 / 7.0);
+    p = fma(p, t2, 1.0 / 5.0);
+    p = fma(p, t2, 1.0 / 3.0);
+    p = fma(p, t2, 1.0);
+    return fma((double)e, 0.69314718055994531, 2.0 * t * p);
+}
+
+// A store entry w K(x_i - x_j) in the store's type: FP64 entries take the full-precision
+// logarithm, FP32 entries the series above.
+template <typename ST>
+__device__ inline double store_entry(double xi, double yi, double xj, double yj, double coef) {
+    if constexpr (sizeof(ST) == 8) {
+        return kernel_entry(xi, yi, xj, yj, coef);
+    } else {
+#pragma clang fp contract(off)
+        const double dx = xi - xj;
+        const double dy = yi - yj;
+        return coef * log_for_f32(dx * dx + dy * dy);
+    }
+}
+
 __device__ inline void box_coord(double x, double y, double lo_x, double lo_y, double s, int nb,
                                  int& cx, int& cy) {
 #pragma clang fp contract(off)
@@ -161,7 +199,7 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
                     if (gi == gb[j]) {
                         v = (ST)diag;
                     } else {
-                        v = (ST)kernel_entry(xi, yi, xb[j], yb[j], coef);
+                        v = (ST)store_entry<ST>(xi, yi, xb[j], yb[j], coef);
                         dup |= (xi == xb[j] && yi == yb[j]);
                     }
                     blk_ab[i + (int64_t)j * nmax] = v;
@@ -286,7 +324,7 @@ __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cst
                 for (int jj = wv; jj < tj; jj += 4) {
                     ST v = (ST)0;
                     if (lane < ti) {
-                        v = (ST)kernel_entry(xp[i0 + lane], yp[i0 + lane], xq[j0 + jj], yq[j0 + jj], coef);
+                        v = (ST)store_entry<ST>(xp[i0 + lane], yp[i0 + lane], xq[j0 + jj], yq[j0 + jj], coef);
                         blk[(i0 + lane) + (int64_t)(j0 + jj) * pnmax] = v;
                     }
                     tile[jj][lane] = v;
@@ -332,7 +370,7 @@ __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cst
                 const ST* cb = cstore + ((int64_t)(ax + cnb * ay) * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
                 v[u] = (double)cb[pa + (int64_t)qb * cnmax];
             } else {
-                v[u] = kernel_entry(xp[ii], yp[ii], xq[jj], yq[jj], coef);
+                v[u] = store_entry<ST>(xp[ii], yp[ii], xq[jj], yq[jj], coef);
             }
         }
 #pragma unroll
