@@ -63,7 +63,7 @@ __device__ inline double dot_strided(const TT* __restrict__ M, int64_t stride, c
 // dot_strided, so each result is bit for bit the single-vector one.
 template <typename TT, int NR>
 __device__ inline void dot_strided_m(const TT* __restrict__ M, int64_t stride, const double* v, int ldv, int cnt,
-                                     double (&out)[NR]) {
+                                     double (&out)[NR], int vs = 1) {
     double s[NR][8];
 #pragma unroll
     for (int h = 0; h < NR; ++h)
@@ -82,7 +82,7 @@ __device__ inline void dot_strided_m(const TT* __restrict__ M, int64_t stride, c
 #pragma unroll
             for (int u = 0; u < UL; ++u)
 #pragma unroll
-                for (int h = 0; h < NR; ++h) s[h][(u0 + u) & 7] += (double)m[u] * v[h * ldv + t + u0 + u];
+                for (int h = 0; h < NR; ++h) s[h][(u0 + u) & 7] += (double)m[u] * v[h * ldv + (t + u0 + u) * vs];
         }
     }
     for (; t + 8 <= cnt; t += 8) {
@@ -92,16 +92,52 @@ __device__ inline void dot_strided_m(const TT* __restrict__ M, int64_t stride, c
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int h = 0; h < NR; ++h) s[h][u] += (double)m[u] * v[h * ldv + t + u];
+            for (int h = 0; h < NR; ++h) s[h][u] += (double)m[u] * v[h * ldv + (t + u) * vs];
     }
     for (; t < cnt; ++t) {
         const TT m = M[(int64_t)t * stride];
 #pragma unroll
-        for (int h = 0; h < NR; ++h) s[h][0] += (double)m * v[h * ldv + t];
+        for (int h = 0; h < NR; ++h) s[h][0] += (double)m * v[h * ldv + t * vs];
     }
 #pragma unroll
     for (int h = 0; h < NR; ++h)
         out[h] = ((s[h][0] + s[h][1]) + (s[h][2] + s[h][3])) + ((s[h][4] + s[h][5]) + (s[h][6] + s[h][7]));
+}
+
+// Lanes per output for `outs` outputs on NTH threads: the largest of 8, 4, 2, 1 that still
+// covers every output in one pass (1 when there are more outputs than threads).
+template <int NTH>
+__device__ inline int lanes_per_output(int outs) {
+    int g = 8;
+    while (g > 1 && outs * g > NTH) g >>= 1;
+    return g;
+}
+
+// Outputs o < outs of y_o = sum_t M_o[t * stride] v_t, each split over G adjacent lanes
+// (lane g of the group takes t = g, g + G, ...; the G parts are then added by a
+// butterfly), NR vectors at once.  mrow(o) is the first entry of output o's terms.
+// Called by every thread of the block (the butterfly needs whole groups).
+template <typename TT, int NTH, int NR, class MRow, class Out>
+__device__ inline void split_dots(int outs, int cnt, int64_t stride, const double* v, int ldv, MRow mrow, Out out) {
+    const int tid = threadIdx.x;
+    // FP32 records only: split FP64 rows measured slower (8-byte loads G rows apart)
+    const int G = sizeof(TT) == 4 ? lanes_per_output<NTH>(outs) : 1;
+    const int g = tid % G;
+    for (int o0 = 0; o0 < outs; o0 += NTH / G) {
+        const int o = o0 + tid / G;
+        double res[NR];
+        if (o < outs && g < cnt) {
+            dot_strided_m<TT, NR>(mrow(o) + (int64_t)g * stride, stride * G, v + g, ldv, (cnt - g + G - 1) / G, res,
+                                  G);
+        } else {
+#pragma unroll
+            for (int h = 0; h < NR; ++h) res[h] = 0.0;
+        }
+        for (int m = 1; m < G; m <<= 1)
+#pragma unroll
+            for (int h = 0; h < NR; ++h) res[h] += __shfl_xor(res[h], m, 64);
+        if (o < outs && g == 0) out(o, res);
+    }
 }
 
 // NR = 1: the right-hand sides one after the other (nrhs of them).  NR > 1: nrhs <= NR
@@ -137,19 +173,19 @@ __global__ void __launch_bounds__(NTH) k_solve_fwd(SweepArgs a, const int* __res
             for (int i = tid; i < r; i += NTH) zR[h * PL + i] = zc[rg[i]];
         }
         __syncthreads();
-        for (int b = tid; b < r; b += NTH) {   // z_R -= T^T z_S
-            double o[NR];
-            dot_strided_m<TT, NR>(T + (int64_t)b * nmax, 1, zS, PL, k, o);
+        split_dots<TT, NTH, NR>(   // z_R -= T^T z_S
+            r, k, 1, zS, PL, [&](int b) { return T + (int64_t)b * nmax; },
+            [&](int b, const double(&o)[NR]) {
 #pragma unroll
-            for (int h = 0; h < NR; ++h) zR[h * PL + b] -= o[h];
-        }
+                for (int h = 0; h < NR; ++h) zR[h * PL + b] -= o[h];
+            });
         __syncthreads();
-        for (int b = tid; b < r; b += NTH) {   // X_RR^{-1} z_R
-            double o[NR];
-            dot_strided_m<TT, NR>(Xi + b, nmax, zR, PL, r, o);
+        split_dots<TT, NTH, NR>(   // X_RR^{-1} z_R
+            r, r, nmax, zR, PL, [&](int b) { return Xi + b; },
+            [&](int b, const double(&o)[NR]) {
 #pragma unroll
-            for (int h = 0; h < NR; ++h) w[h * PL + b] = o[h];
-        }
+                for (int h = 0; h < NR; ++h) w[h * PL + b] = o[h];
+            });
         __syncthreads();
         for (int jj = tid; jj < nj; jj += NTH) {   // z_J -= E w
             const int g = J[jj];
@@ -227,13 +263,13 @@ __global__ void __launch_bounds__(NTH) k_solve_bwd(SweepArgs a, const int* __res
                 zc[rg[b]] = v;
             }
         __syncthreads();
-        for (int q = tid; q < k; q += NTH) {   // z_S -= T z_R
-            double o[NR];
-            dot_strided_m<TT, NR>(T + q, nmax, zR, kMaxBox, r, o);
+        split_dots<TT, NTH, NR>(   // z_S -= T z_R
+            k, r, nmax, zR, kMaxBox, [&](int q) { return T + q; },
+            [&](int q, const double(&o)[NR]) {
 #pragma unroll
-            for (int h = 0; h < NR; ++h)
-                if (h < nh) z0[(int64_t)h * ld + sg[q]] -= o[h];
-        }
+                for (int h = 0; h < NR; ++h)
+                    if (h < nh) z0[(int64_t)h * ld + sg[q]] -= o[h];
+            });
         __syncthreads();
     }
 }
