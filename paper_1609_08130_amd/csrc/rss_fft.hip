@@ -26,7 +26,11 @@ __global__ void __launch_bounds__(256) k_fft_lines(cplx* __restrict__ a, int L, 
                                                    const cplx* __restrict__ tw, int inverse) {
     extern __shared__ cplx sl[];
     const int tid = threadIdx.x;
-    cplx* line = a + (int64_t)blockIdx.x * rs;
+    // workgroups go to the 8 XCDs round-robin: give each XCD a run of adjacent lines, so
+    // that the lines sharing a cache line (strided passes) meet in one L2
+    const int nl = gridDim.x, b = blockIdx.x;
+    const int li = (nl % 8 == 0) ? (b & 7) * (nl >> 3) + (b >> 3) : b;
+    cplx* line = a + (int64_t)li * rs;
     for (int k = tid; k < L; k += 256) {
         unsigned r = __brev((unsigned)k) >> (32 - logL);
         sl[r] = line[(int64_t)k * es];
