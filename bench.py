@@ -112,6 +112,20 @@ def dominant_roofline(infos: list, mixed: bool) -> dict:
                 **common)
 
 
+def schur_level_roofline(l):
+    """Schur update of one level against its attainable roofline: achieved flop rate over
+    min(FP32 vector peak, arithmetic intensity x HBM peak), and over the FP32 peak alone
+    (mixed factors multiply in FP32 on the vector units)."""
+    ms = l["ms_schur"]
+    if ms <= 0 or l["bytes_schur"] <= 0:
+        return {}
+    tflops = l["flops_schur"] / (ms / 1e3) / 1e12
+    ai = l["flops_schur"] / l["bytes_schur"]
+    attain = min(FP32_PEAK_TFS, ai * HBM_PEAK_GBS / 1e3)
+    return {"schur_tflops": round(tflops, 3), "schur_ai": round(ai, 3),
+            "schur_frac_attainable": round(tflops / attain, 4), "schur_frac_peak": round(tflops / FP32_PEAK_TFS, 4)}
+
+
 def run_gpu(args, precision: str):
     import torch
 
@@ -263,9 +277,9 @@ def main():
         "phase_ms_mixed": mixed["info"]["phase_ms"],
         "phase_ms_fp64": None if fp64 is None else fp64["info"]["phase_ms"],
         "roofline": roof,
-        "levels": [{k: (round(l[k], 3) if isinstance(l[k], float) else l[k])
-                    for k in ("depth", "boxes", "nmax", "records", "sum_k", "max_k", "max_J", "ms_id", "ms_elim",
-                              "ms_schur")}
+        "levels": [dict({k: (round(l[k], 3) if isinstance(l[k], float) else l[k])
+                         for k in ("depth", "boxes", "nmax", "records", "sum_k", "max_k", "max_J", "ms_id", "ms_elim",
+                                   "ms_schur")}, **schur_level_roofline(l))
                    for l in mixed["info"]["levels"]],
         "n_top": mixed["info"]["n_top"],
         "bytes_device": mixed["info"]["bytes_device"],
