@@ -134,15 +134,19 @@ def test_unskeletonized_top_block_961(rss, diag, weight):
     F.close()
 
 
-def test_solve_nrhs_matches_single(rss):
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 4), ("fp64", 6), ("mixed", 7)])
+def test_solve_nrhs_matches_single(rss, precision, nrhs):
+    # right-hand sides go through the sweeps in groups of four (the last group partial):
+    # every column equals its single-vector solve bit for bit
     n = 64
     p = O.Params(**W.problem(n, 1e-6))
-    F = _gpu_factor(rss, W.grid_points(n), p)
-    B = torch.tensor(W.rhs(n * n, seed=5, nrhs=4), device="cuda")
-    X = F.solve(B)
-    for j in range(4):
-        xj = F.solve(B[:, j].contiguous())
-        assert torch.equal(X[:, j], xj)
+    F = _gpu_factor(rss, W.grid_points(n), p, precision)
+    B = torch.tensor(W.rhs(n * n, seed=5, nrhs=nrhs), device="cuda")
+    u32 = precision == "mixed"
+    X = F.solve(B, use_fp32=u32)
+    for j in range(nrhs):
+        xj = F.solve(B[:, j].contiguous(), use_fp32=u32)
+        assert torch.equal(X[:, j], xj), j
     # F^{-1} F = I
     Y = F.apply(B)
     Z = F.solve(Y)
