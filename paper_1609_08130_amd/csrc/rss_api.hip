@@ -427,6 +427,9 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     const bool mixed = p.precision == RSS_MIXED;
     double* work = nullptr;
     size_t work_n = 0;
+    int* tl_cnt = nullptr;
+    int* tl_tiles = nullptr;
+    size_t tl_n = 0;
 
     while (L.t >= 2) {
         const int nb = L.nb;
@@ -442,7 +445,16 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             work = dalloc<double>(f, need);
             work_n = need;
         }
-        HIPCHK(hipMemsetAsync(f->flag + 4, 0, sizeof(int) * 9, s));
+        // Schur tile lists: 8 counters per colour, zero at the level start; one entry buffer
+        // reused by the colours in turn
+        const int capx = rss::schur_tile_capx((int)maxc, L.ldJ);
+        if (!tl_cnt) tl_cnt = dalloc<int>(f, 9 * 8);
+        if ((size_t)capx * 8 > tl_n) {
+            if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
+            tl_n = (size_t)capx * 8;
+            tl_tiles = dalloc<int>(f, tl_n);
+        }
+        HIPCHK(hipMemsetAsync(tl_cnt, 0, sizeof(int) * 9 * 8, s));
         std::vector<hipEvent_t> ev;
         ev.push_back(evs.rec(s));
         for (int col = 0; col < 9; ++col) {
@@ -452,11 +464,16 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, f->flag + 4 + col, s);
+            rss::TileList tl;
+            tl.cnt = tl_cnt + 8 * col;
+            tl.tiles = tl_tiles;
+            tl.capx = capx;
+            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, tl, s);
             if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
             check_launch();
             ev.push_back(evs.rec(s));
-            rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, f->flag + 4 + col, s);
+            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, tl, s) < 0)
+                fail(RSS_E_DEVICE, "Schur tile list too small");
             check_launch();
             ev.push_back(evs.rec(s));
             f->kernel_launches[PH_ID] += ni;
@@ -560,6 +577,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         L = std::move(P);
     }
     if (work) dfree(f, work, work_n * sizeof(double));
+    if (tl_tiles) dfree(f, tl_tiles, tl_n * sizeof(int));
+    if (tl_cnt) dfree(f, tl_cnt, sizeof(int) * 9 * 8);
     if (first_sync) {
         // no skeletonized level (depth <= 1): the flag, the phase times and the active
         // counts of the leaves are read here

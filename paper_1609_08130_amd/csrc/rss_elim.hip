@@ -24,7 +24,9 @@ namespace rss {
 
 struct ElimArgs {
     const void* store;   // FP64 or FP32 entries (the kernels' ST)
-    int* colmax;         // largest |J| of the colour (atomic maximum)
+    int* tl_cnt;         // Schur tile lists of the colour (TileList)
+    int* tl_tiles;
+    int tl_capx;
     int nb, nmax, ldJ;
     const int* cnt;
     const int* gidx;
@@ -809,9 +811,17 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     if (tid == 0) {
         a.nJ[c] = nj;
         a.nact[c] = k;
-        atomicMax(a.colmax, nj);
     }
     for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
+    if (tid < 64) {
+        // the box's ceil(|J| / 64)^2 Schur tiles, appended to the list of its XCD by wave 0
+        const int nt1 = (nj + 63) >> 6, ntl = nt1 * nt1, x = blockIdx.x & 7;
+        int off = 0;
+        if (tid == 0) off = atomicAdd(a.tl_cnt + x, ntl);
+        off = __shfl(off, 0, 64);
+        int* lst = a.tl_tiles + (int64_t)x * a.tl_capx + off;
+        for (int t = tid; t < ntl; t += 64) lst[t] = ((int)blockIdx.x << 12) | ((t % nt1) << 6) | (t / nt1);
+    }
 }
 
 // grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[(nmax + 1) tw] | tX[(nmax + 1) tw]
@@ -871,10 +881,10 @@ static void set_lds(K kernel, size_t bytes) {
 
 template <typename ST>
 static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
-                         int* colmax, hipStream_t s) {
+                         const TileList& tl, hipStream_t s) {
     if (nboxes <= 0) return 0;
     ElimArgs a;
-    a.colmax = colmax;
+    a.tl_cnt = tl.cnt; a.tl_tiles = tl.tiles; a.tl_capx = tl.capx;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;
     a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
@@ -941,10 +951,10 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     return 3;
 }
 
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, int* colmax,
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, const TileList& tl,
                 hipStream_t s) {
-    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, colmax, s)
-                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, colmax, s);
+    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, tl, s)
+                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, tl, s);
 }
 
 }  // namespace rss

@@ -160,10 +160,22 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
                     const KernelParams& kp, double* work, hipStream_t s);
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
 // Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, int* colmax,
+// Active 64 x 64 tiles of the Schur updates of one colour, in 8 lists (one per XCD: the
+// boxes with position bi = x mod 8 in the colour's list go to list x).  An entry packs
+// (bi << 12) | (tile row << 6) | tile column; cnt[x] counts the entries of list x, which
+// start at tiles + x * capx.  Filled by launch_elim, read by launch_schur.
+struct TileList {
+    int* cnt = nullptr;     // 8 counters, zero before the colour's elimination
+    int* tiles = nullptr;   // 8 * capx entries
+    int capx = 0;           // ceil(boxes / 8) * ceil(ldJ / 64)^2
+};
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, const TileList& tl,
                  hipStream_t s);
-void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const int* colmax,
-                  hipStream_t s);
+// Entries per tile list for a colour of nboxes boxes with |J| <= maxJ.
+int schur_tile_capx(int nboxes, int maxJ);
+// Returns -1 when tl.capx is below schur_tile_capx(nboxes, maxJ) (nothing launched).
+int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const TileList& tl,
+                 hipStream_t s);
 
 // dense top block (rss_solve.hip)
 // piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)

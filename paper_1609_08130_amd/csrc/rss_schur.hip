@@ -32,8 +32,9 @@ struct SchurArgs {
 typedef double f64x4 __attribute__((ext_vector_type(4)));   // accumulator of one FP64 MFMA block
 
 template <typename TT, typename ST>
-__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes, int nbox, int tpd,
-                                               const int* __restrict__ colmax) {
+__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes,
+                                               const int* __restrict__ tl_cnt, const int* __restrict__ tl_tiles,
+                                               int tl_capx) {
     constexpr int TM = 64, TK = 16;
     __shared__ TT As[TK][TM + 1];
     __shared__ TT Bs[TK][TM + 1];
@@ -45,17 +46,14 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     __shared__ int64_t blkoff[81];   // [row slot * 9 + column slot]: first entry of that block
 
     const int tid = threadIdx.x;
-    // Workgroups are dealt to the 8 XCDs round-robin in launch order; id = x + 8 s puts all
-    // tiles of box x + 8 (s / tpd^2) on XCD x, so its X_JR and G stay in one L2.
-    const int ntile = tpd * tpd;
+    // Workgroups are dealt to the 8 XCDs round-robin in launch order: workgroup x + 8 s
+    // takes entry s of tile list x, which holds the active tiles of the boxes at positions
+    // bi = x mod 8 of the colour, so all tiles of a box run on one XCD and its X_JR and G
+    // stay in one L2.  Workgroups past the end of their list leave after one load.
     const int xcd = blockIdx.x & 7, sidx = blockIdx.x >> 3;
-    const int bi = xcd + 8 * (sidx / ntile);
-    if (bi >= nbox) return;
-    const int tile = sidx % ntile;
-    const int ti = tile % tpd, tj = tile / tpd;
-    // tiles beyond the widest |J| of the colour leave at once (one load of a shared value)
-    const int tmax = (*colmax + TM - 1) / TM;
-    if (ti >= tmax || tj >= tmax) return;
+    if (sidx >= tl_cnt[xcd]) return;
+    const int ent = tl_tiles[(int64_t)xcd * tl_capx + sidx];
+    const int bi = ent >> 12, ti = (ent >> 6) & 63, tj = ent & 63;
     const int c = boxes[bi];
     const int nj = a.nJ[c];
     if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
@@ -227,23 +225,30 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     }
 }
 
-void launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const int* colmax,
-                  hipStream_t s) {
-    if (nboxes <= 0) return;
+int schur_tile_capx(int nboxes, int maxJ) {
+    const int tpd = (maxJ + 63) / 64;
+    return tpd * tpd * ((nboxes + 7) / 8);
+}
+
+int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const TileList& tl,
+                 hipStream_t s) {
+    if (nboxes <= 0) return 0;
+    if (tl.capx < schur_tile_capx(nboxes, maxJ)) return -1;
     SchurArgs a;
     a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ; a.spos = L.spos;
     const int tpd = (maxJ + 63) / 64;
-    const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);
+    const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);   // 8 lists of at most capx entries
     dim3 grid((unsigned)nwg), block(256);
     if (mixed) {
         a.XJR = L.XJR32; a.G = L.G32;
-        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
-        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
+        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
     } else {
         a.XJR = L.XJR; a.G = L.G;
-        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, nboxes, tpd, colmax);
+        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
     }
+    return 0;
 }
 
 }  // namespace rss
