@@ -758,6 +758,17 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     const int k = a.krank[c];
     const int r = n - k;
     if (n == 0 || r == 0) return;
+    if (tile > 0) {
+        // |J| + |R| from the active counts of the adjacent boxes: workgroups whose rows all
+        // lie beyond it leave before the set-up
+        const int nb = a.nb, cx = c % nb, cy = c / nb;
+        int njr = k + r;
+        for (int t = 0; t < 9; ++t) {
+            const int ox = cx + t % 3 - 1, oy = cy + t / 3 - 1;
+            if (t != 4 && ox >= 0 && oy >= 0 && ox < nb && oy < nb) njr += a.nact[ox + nb * oy];
+        }
+        if (tile * tpw * tw >= njr) return;
+    }
     const int nmax = a.nmax, ldJ = a.ldJ;
     double* Ts = dyn;
     double* tA = dyn + tsz;
@@ -837,6 +848,9 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     const int k = a.krank[c];
     const int r = n - k;
     if (n == 0 || r == 0 || (*flag & 4)) return;
+    // |J| is known from the inverse kernel: workgroups whose tiles all lie beyond it leave
+    // before the set-up
+    if (tile * tpw * tw >= a.nJ[c]) return;
     const int nmax = a.nmax, ldJ = a.ldJ;
     const int64_t bsz = (int64_t)nmax * nmax;
     double* Ts = dyn;
