@@ -229,6 +229,20 @@ __device__ inline void gram_row(const double* row, const int (&tp)[TPT], const i
     }
 }
 
+// Rows of M of box c: active DOFs of the distance-2 boxes plus the proxies.
+__device__ inline int id_rows(const int* nact, int c, int nb, int n_proxy) {
+    const int cx = c % nb, cy = c / nb;
+    int mO = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            if (max(abs(dx), abs(dy)) != 2) continue;
+            int ox = cx + dx, oy = cy + dy;
+            if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
+            mO += nact[ox + nb * oy];
+        }
+    return mO + n_proxy;
+}
+
 // grid (slices x tile groups, boxes); thread owns TPT 2x2 tiles of the upper triangle of G.
 template <int NTH, int TPT, typename ST>
 __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int nb, int nmax,
@@ -253,6 +267,12 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     const int grp = blockIdx.x / nslice;
     const int n = cnt[c];
     if (n == 0) return;
+    // slices past the box's rows and tile groups past its triangle leave before the set-up
+    if (sl * slice_rows >= id_rows(nact, c, nb, kp.n_proxy)) return;
+    {
+        const int nt0 = (n + 1) >> 1;
+        if (grp * NTH * TPT >= nt0 * (nt0 + 1) / 2) return;
+    }
     build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax);
     {
 #pragma clang fp contract(off)
@@ -375,19 +395,6 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
 }
 
 // ---- 2. sum of the partial Gram matrices (few-box colours) ---------------------------------
-// Rows of M of box c: active DOFs of the distance-2 boxes plus the proxies.
-__device__ inline int id_rows(const int* nact, int c, int nb, int n_proxy) {
-    const int cx = c % nb, cy = c / nb;
-    int mO = 0;
-    for (int dy = -2; dy <= 2; ++dy)
-        for (int dx = -2; dx <= 2; ++dx) {
-            if (max(abs(dx), abs(dy)) != 2) continue;
-            int ox = cx + dx, oy = cy + dy;
-            if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
-            mO += nact[ox + nb * oy];
-        }
-    return mO + n_proxy;
-}
 
 // grid (nmax^2 / 256, boxes): slice 0 <- sum over the slices that hold rows, in slice order.
 __global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ cnt, const int* __restrict__ nact,
