@@ -81,13 +81,33 @@ void launch_validate_points(const double* pts, int64_t n, double lo_x, double lo
 }
 
 // counts[box] += 1 for every point; counts[nbox] = max count (atomicMax)
+// Runs of equal boxes among the lanes of a wave (consecutive points mostly share a box):
+// bit l of the result is set when lane l starts a run.  Lanes past the end carry box -1.
+__device__ inline unsigned long long run_heads(int b) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(b, 1, 64);
+    return __ballot(lane == 0 || prev != b);
+}
+
+// Length of the run that lane `lane` starts (heads: run_heads).
+__device__ inline int run_length(unsigned long long heads, int lane) {
+    const unsigned long long later = lane == 63 ? 0ull : heads >> (lane + 1);
+    return later ? __ffsll((long long)later) : 64 - lane;
+}
+
 __global__ void k_count_boxes(const double* __restrict__ pts, int64_t n, int nb, double lo_x, double lo_y,
                               double s, int* counts) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int cx, cy;
-    box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
-    atomicAdd(&counts[cx + nb * cy], 1);
+    // one atomic per run of equal boxes in a wave instead of one per point
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int b = -1;
+    if (i < n) {
+        int cx, cy;
+        box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
+        b = cx + nb * cy;
+    }
+    const unsigned long long heads = run_heads(b);
+    if (b >= 0 && ((heads >> lane) & 1ull)) atomicAdd(&counts[b], run_length(heads, lane));
 }
 
 __global__ void k_max_count(const int* __restrict__ counts, int64_t nbox, int* out) {
@@ -109,13 +129,23 @@ void launch_count_boxes(const double* pts, int64_t n, int t, double lo_x, double
 
 __global__ void k_leaf_scatter(const double* __restrict__ pts, int64_t n, int nb, double lo_x, double lo_y,
                                double s, int* fill, int* gidx, int nmax) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int cx, cy;
-    box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
-    int b = cx + nb * cy;
-    int p = atomicAdd(&fill[b], 1);
-    gidx[(int64_t)b * nmax + p] = (int)i;
+    // the head of each run of equal boxes reserves the run's slots with one atomic; the
+    // order inside a box is made ascending afterwards (k_leaf_sort)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int b = -1;
+    if (i < n) {
+        int cx, cy;
+        box_coord(pts[2 * i], pts[2 * i + 1], lo_x, lo_y, s, nb, cx, cy);
+        b = cx + nb * cy;
+    }
+    const unsigned long long heads = run_heads(b);
+    const bool head = (heads >> lane) & 1ull;
+    int base = 0;
+    if (b >= 0 && head) base = atomicAdd(&fill[b], run_length(heads, lane));
+    const int h = 63 - __clzll((long long)(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull))));
+    base = __shfl(base, h, 64);
+    if (b >= 0) gidx[(int64_t)b * nmax + base + (lane - h)] = (int)i;
 }
 
 // Sort each box's DOF list ascending (rank sort in LDS); fill[] holds the counts.
