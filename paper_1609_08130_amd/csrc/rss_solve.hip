@@ -892,18 +892,29 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
         for (int e = tid; e < bs * NC; e += 256) xs[(jb + e / NC) * NC + e % NC] = yt[e];
         __syncthreads();
     };
+    // rows i0 <= i < i1: x_i -= LU(i, jb .. jb + bs) x_blk for all NC columns; a thread takes
+    // a row, with the bs entries of LU loaded at once (one read of L2 per row and block)
+    auto offdiag = [&](int i0, int i1, int jb, int bs) {
+        for (int i = i0 + tid; i < i1; i += 256) {
+            double l[kNB];
+#pragma unroll
+            for (int j = 0; j < kNB; ++j) l[j] = j < bs ? LU[i + (int64_t)(jb + j) * n] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < kNB; ++j) v += l[j] * xs[min(jb + j, n - 1) * NC + c];
+                xs[i * NC + c] -= v;
+            }
+        }
+    };
     for (int jb = 0; jb < n; jb += kNB) {            // L y = P e (unit lower)
         const int bs = min(kNB, n - jb);
         const double* Di = Dinv + (int64_t)(jb / kNB) * kNB * kNB;
         for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
         __syncthreads();
         diag_apply(jb, bs, true);
-        for (int e = tid; e < (n - jb - bs) * NC; e += 256) {
-            int i = jb + bs + e / NC, c = e % NC;
-            double v = 0.0;
-            for (int j = 0; j < bs; ++j) v += LU[i + (int64_t)(jb + j) * n] * xs[(jb + j) * NC + c];
-            xs[i * NC + c] -= v;
-        }
+        offdiag(jb + bs, n, jb, bs);
         __syncthreads();
     }
     for (int b = nblk - 1; b >= 0; --b) {            // U x = y
@@ -912,12 +923,7 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
         for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
         __syncthreads();
         diag_apply(jb, bs, false);
-        for (int e = tid; e < jb * NC; e += 256) {
-            int i = e / NC, c = e % NC;
-            double v = 0.0;
-            for (int j = 0; j < bs; ++j) v += LU[i + (int64_t)(jb + j) * n] * xs[(jb + j) * NC + c];
-            xs[i * NC + c] -= v;
-        }
+        offdiag(0, jb, jb, bs);
         __syncthreads();
     }
     for (int e = tid; e < n * NC; e += 256) {
