@@ -251,6 +251,24 @@ def test_sqrt_apply_without_skeletonization_is_cholesky(rss):
     F.close()
 
 
+def test_sqrt_apply_argument_errors(rss):
+    import ctypes
+    pts = W.grid_points(16)
+    F = _gpu_factor(rss, pts, O.Params(**W.problem(16, 1e-6, leaf_size=16)))
+    x = torch.ones(256, dtype=torch.float64, device="cuda")
+    lib = rss.lib()
+    p = ctypes.c_void_p(x.data_ptr())
+    # aliasing input and output, nrhs < 1, ld < N: RSS_E_ARG, nothing written
+    assert lib.rss_sqrt_apply(F._h, p, p, 1, 256, 0, None) == 1
+    y = torch.zeros(256, dtype=torch.float64, device="cuda")
+    q = ctypes.c_void_p(y.data_ptr())
+    assert lib.rss_sqrt_apply(F._h, p, q, 0, 256, 0, None) == 1
+    assert lib.rss_sqrt_apply(F._h, p, q, 1, 255, 1, None) == 1
+    torch.cuda.synchronize()
+    assert float(y.abs().max()) == 0.0
+    F.close()
+
+
 def test_sqrt_apply_rejects_indefinite_blocks(rss):
     pts = W.grid_points(16)
     p = O.Params(diag=-1.0, weight=1.0 / 256, tol=1e-6, leaf_size=16)
