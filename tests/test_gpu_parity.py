@@ -86,6 +86,16 @@ def test_parity_jittered_grid_small_leaf(rss):
     _compare(rss, "jitter48_leaf16", pts, p)
 
 
+@pytest.mark.parametrize("root_side", [3.0, 0.0])
+def test_parity_translated_domain(rss, root_side):
+    # points in [2, 5] x [-1, 2]: an explicit root box, or (root_side 0) the bounding
+    # square of the points, so box geometry and proxy circles are not those of [0, 1]^2
+    rng = np.random.default_rng(21)
+    pts = np.column_stack([2.0 + 3.0 * rng.random(2500), -1.0 + 3.0 * rng.random(2500)])
+    p = O.Params(weight=9.0 / 2500, tol=1e-6, leaf_size=32, root_lo=(2.0, -1.0), root_side=root_side)
+    _compare(rss, f"translated_root{root_side}", pts, p)
+
+
 @pytest.mark.parametrize("npts,leaf", [(1, 64), (50, 64), (200, 64), (300, 40)])
 def test_small_and_degenerate_trees(rss, npts, leaf):
     pts = W.random_points(npts, seed=npts)
