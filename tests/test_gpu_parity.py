@@ -86,6 +86,15 @@ def test_parity_jittered_grid_small_leaf(rss):
     _compare(rss, "jitter48_leaf16", pts, p)
 
 
+@pytest.mark.parametrize("n_proxy,radius", [(64, 2.5), (32, 1.0)])
+def test_parity_proxy_surfaces(rss, n_proxy, radius):
+    # the paper's proxy circle (64 points at 2.5 box sides, Section 4) and a tight one
+    n = 64
+    d = W.problem(n, 1e-6)
+    d.update(n_proxy=n_proxy, proxy_radius=radius)
+    _compare(rss, f"grid64_proxy{n_proxy}_r{radius}", W.grid_points(n), O.Params(**d))
+
+
 @pytest.mark.parametrize("root_side", [3.0, 0.0])
 def test_parity_translated_domain(rss, root_side):
     # points in [2, 5] x [-1, 2]: an explicit root box, or (root_side 0) the bounding
