@@ -12,6 +12,13 @@
 //   F = (prod V_i) P_t D P_t^* (prod' W_i)
 //   W_i z : z_S += T z_R ; z_R += G z_J     (then D: z_R <- X_RR z_R)
 //   V_i z : z_J += E z_R ; z_R += T^T z_S
+//
+//   F^{1/2} = (prod V_i) P_t D^{1/2}, D^{1/2} = Cholesky factors L of the blocks of D;
+//   (F^{1/2})^* = D^{1/2 *} P_t^* (prod' W_i) (V_i = W_i^* for a symmetric matrix): the
+//   F sweeps with L (before V_i) or L^T (after W_i) in place of X_RR.
+//
+// Several right-hand sides of one solve go through in groups of four per launch, each
+// loaded entry of a record used for all of them.
 #include <algorithm>
 
 #include "rss_internal.h"
