@@ -87,9 +87,29 @@ __device__ inline dd dd_sqrt(dd a) {
     return {s, t};
 }
 
+// Largest value of the wave (fmax semantics), on every lane: DPP row shifts within rows
+// of 16 lanes, then the row broadcasts of lanes 15 and 31, read back from lane 63.  Lanes
+// without a source contribute +0.0 (the values reduced here are >= 0 or -1 for "none",
+// and a result of 0 and one of -1 lead to the same decision).
+template <int CTRL, int ROWS>
+__device__ inline double dpp_fmax_step(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, ROWS, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, ROWS, 0xf, true);
+    return fmax(v, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
+}
+
 __device__ inline double wave_max_d(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = dpp_fmax_step<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_fmax_step<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_fmax_step<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_fmax_step<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_fmax_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_fmax_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ inline int wave_min_i(int v) {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
