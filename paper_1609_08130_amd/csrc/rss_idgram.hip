@@ -452,22 +452,36 @@ __device__ inline dd gram_entry(const double2* G, int nsl, int nmax, int64_t sst
 
 // Sum of v over the SUB adjacent lanes of a column group, identical on all of them
 // (double-double addition is commutative bit for bit, so both orders agree).
-template <int SUB>
-__device__ inline dd group_sum_dd(dd v) {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int o = 1; o < SUB; o <<= 1) {
-        const dd w = {__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)};
-        v = dd_add(v, w);
+// The value of lane l ^ O (O = 1 or 2: a DPP quad permutation; otherwise an LDS-crossbar
+// shuffle), moved bit for bit.
+template <int O>
+__device__ inline double xor_lane(double v) {
+    if constexpr (O == 1 || O == 2) {
+        constexpr int ctrl = O == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] and [2,3,0,1]
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), ctrl, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), ctrl, 0xf, 0xf, false);
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    } else {
+        return __shfl_xor(v, O, 64);
     }
-    return v;
 }
 
-template <int SUB>
+template <int SUB, int O = 1>
+__device__ inline dd group_sum_dd(dd v) {
+#pragma clang fp contract(off)
+    if constexpr (O < SUB) {
+        const dd w = {xor_lane<O>(v.hi), xor_lane<O>(v.lo)};
+        return group_sum_dd<SUB, 2 * O>(dd_add(v, w));
+    } else {
+        return v;
+    }
+}
+
+template <int SUB, int O = 1>
 __device__ inline double group_sum(double v) {
-#pragma unroll
-    for (int o = 1; o < SUB; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    if constexpr (O < SUB) return group_sum<SUB, 2 * O>(v + xor_lane<O>(v));
+    else return v;
 }
 
 // One workgroup per box; the SUB adjacent threads 4 q .. 4 q + SUB - 1 own column q and
