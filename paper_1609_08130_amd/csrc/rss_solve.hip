@@ -111,6 +111,16 @@ __device__ inline void dot_strided_m(const TT* __restrict__ M, int64_t stride, c
         out[h] = ((s[h][0] + s[h][1]) + (s[h][2] + s[h][3])) + ((s[h][4] + s[h][5]) + (s[h][6] + s[h][7]));
 }
 
+// The value of another lane moved bit for bit by a DPP control that reaches every lane
+// (quad permutations, half-row mirror).
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Lanes per output for `outs` outputs on NTH threads: the largest of 8, 4, 2, 1 that still
 // covers every output in one pass (1 when there are more outputs than threads).
 template <int NTH>
@@ -140,9 +150,12 @@ __device__ inline void split_dots(int outs, int cnt, int64_t stride, const doubl
 #pragma unroll
             for (int h = 0; h < NR; ++h) res[h] = 0.0;
         }
-        for (int m = 1; m < G; m <<= 1)
 #pragma unroll
-            for (int h = 0; h < NR; ++h) res[h] += __shfl_xor(res[h], m, 64);
+        for (int h = 0; h < NR; ++h) {
+            if (G >= 2) res[h] += dpp_double<0xB1>(res[h]);    // lane ^ 1 (quad permutation)
+            if (G >= 4) res[h] += dpp_double<0x4E>(res[h]);    // lane ^ 2
+            if (G >= 8) res[h] += dpp_double<0x141>(res[h]);   // the other quad of 8 (half-row mirror)
+        }
         if (o < outs && g == 0) out(o, res);
     }
 }
