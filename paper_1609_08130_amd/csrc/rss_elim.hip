@@ -384,11 +384,7 @@ __device__ bool gj_inverse(double* Xs, int ldx, int r, int* colswap, double* sc,
                 double v = fabs(Xs[i + j * ldx]);
                 if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                double v2 = __shfl_xor(best, o, 64);
-                int i2 = __shfl_xor(bi, o, 64);
-                if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-            }
+            wave_argmax(best, bi);
             if (lane == 0) {
                 piv_idx = bi;
                 piv_val = (bi < r && best > 0.0) ? Xs[bi + j * ldx] : 0.0;
@@ -467,29 +463,6 @@ __device__ bool gj_inverse(double* Xs, int ldx, int r, int* colswap, double* sc,
 }
 
 // Value of v held by lane `ln` of the wave (ln wave-uniform).
-// Largest 64-bit key of the wave, on every lane: within each row of 16 lanes by DPP row
-// shifts (1, 2, 4, 8), then across rows by the row broadcasts of lanes 15 and 31, so that
-// lane 63 ends with the maximum; lanes without a source take 0 (the identity).
-template <int CTRL, int ROWS>
-__device__ inline unsigned long long dpp_max_step(unsigned long long k) {
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k & 0xffffffffull), CTRL, ROWS, 0xf, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), CTRL, ROWS, 0xf, true);
-    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-    return o > k ? o : k;
-}
-
-__device__ inline unsigned long long wave_max_u64(unsigned long long k) {
-    k = dpp_max_step<0x111, 0xf>(k);   // row_shr:1
-    k = dpp_max_step<0x112, 0xf>(k);   // row_shr:2
-    k = dpp_max_step<0x114, 0xf>(k);   // row_shr:4
-    k = dpp_max_step<0x118, 0xf>(k);   // row_shr:8
-    k = dpp_max_step<0x142, 0xa>(k);   // row_bcast:15 into rows 1 and 3
-    k = dpp_max_step<0x143, 0xc>(k);   // row_bcast:31 into rows 2 and 3
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k & 0xffffffffull), 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 __device__ inline double lane_read(double v, int ln) {
     const long long b = __double_as_longlong(v);
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffff), ln);

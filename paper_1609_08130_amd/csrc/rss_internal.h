@@ -137,6 +137,57 @@ struct rss_factor_s {
 
 namespace rss {
 
+// Largest 64-bit key of the wave, on every lane: within each row of 16 lanes by DPP row
+// shifts (1, 2, 4, 8), then across rows by the row broadcasts of lanes 15 and 31, so that
+// lane 63 ends with the maximum; lanes without a source take 0 (the identity).
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_max_step(unsigned long long k) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k & 0xffffffffull), CTRL, ROWS, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), CTRL, ROWS, 0xf, true);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    return o > k ? o : k;
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long k) {
+    k = dpp_max_step<0x111, 0xf>(k);   // row_shr:1
+    k = dpp_max_step<0x112, 0xf>(k);   // row_shr:2
+    k = dpp_max_step<0x114, 0xf>(k);   // row_shr:4
+    k = dpp_max_step<0x118, 0xf>(k);   // row_shr:8
+    k = dpp_max_step<0x142, 0xa>(k);   // row_bcast:15 into rows 1 and 3
+    k = dpp_max_step<0x143, 0xc>(k);   // row_bcast:31 into rows 2 and 3
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k & 0xffffffffull), 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Smallest unsigned value of the wave, on every lane (DPP as above; lanes without a
+// source keep the identity 0xffffffff).
+template <int CTRL, int ROWS>
+__device__ inline unsigned dpp_min_step(unsigned v) {
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)0xffffffffu, (int)v, CTRL, ROWS, 0xf, false);
+    return o < v ? o : v;
+}
+
+__device__ inline unsigned wave_min_u32(unsigned v) {
+    v = dpp_min_step<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_min_step<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_min_step<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_min_step<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_min_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_min_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Partial-pivoting choice over the wave: the largest best (each lane's largest |entry|,
+// >= 0, or -1 for none) and, among lanes that hold it, the lowest index bi; the result on
+// every lane.  Non-negative doubles order like their bit patterns.
+__device__ inline void wave_argmax(double& best, int& bi) {
+    const unsigned long long key = best >= 0.0 ? (unsigned long long)__double_as_longlong(best) + 1ull : 0ull;
+    const unsigned long long km = wave_max_u64(key);
+    bi = (int)wave_min_u32(key == km ? (unsigned)bi : 0xffffffffu);
+    best = km == 0 ? -1.0 : __longlong_as_double((long long)(km - 1ull));
+}
+
 // ---- launchers (each enqueues on `s`) -------------------------------------------------
 // tree / store (rss_tree.hip)
 void launch_validate_points(const double* pts, int64_t n, double lo_x, double lo_y, double side,

@@ -677,11 +677,7 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
                 double v = fabs(P[i + (int64_t)j * ld]);
                 if (v > best || (v == best && i < bi)) { best = v; bi = i; }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                double v2 = __shfl_xor(best, o, 64);
-                int i2 = __shfl_xor(bi, o, 64);
-                if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-            }
+            wave_argmax(best, bi);
             if (lane == 0) { piv_idx = bi; piv_val = best; }
         }
         __syncthreads();
