@@ -20,6 +20,21 @@
 
 namespace rss {
 int elim_lds_limit();
+
+static thread_local std::vector<std::string>* g_shape_log = nullptr;
+
+void set_shape_log(std::vector<std::string>* log) { g_shape_log = log; }
+
+void note_shape(const std::string& name) {
+    if (!g_shape_log) return;
+    if (std::find(g_shape_log->begin(), g_shape_log->end(), name) == g_shape_log->end()) g_shape_log->push_back(name);
+}
+
+// Sets the shape log of factor f for the lifetime of the guard.
+struct ShapeLogScope {
+    explicit ShapeLogScope(rss_factor f) { set_shape_log(&f->shapes); }
+    ~ShapeLogScope() { set_shape_log(nullptr); }
+};
 }
 
 namespace {
@@ -68,6 +83,10 @@ template <class T>
 T* dalloc(rss_factor f, size_t n, hipStream_t s) {
     (void)s;
     if (n == 0) n = 1;
+    if (f->params.arena_bytes && f->bytes_device + n * sizeof(T) > f->params.arena_bytes)
+        fail(RSS_E_ARENA, "the factorization needs more than arena_bytes = " + std::to_string(f->params.arena_bytes) +
+                              " bytes of device memory (" + std::to_string(f->bytes_device + n * sizeof(T)) +
+                              " requested)");
     const size_t want = round_block(n * sizeof(T));
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -506,6 +525,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             et_pend0 = et_pend1 = nullptr;
         }
         if (hv[0][0] & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
+        if (hv[0][0] & 64) rss::note_shape("elim_inv_gauss_jordan_lds");
         L.h_cnt = std::move(hv[1]);
         L.h_k = std::move(hv[2]);
         std::vector<int> hJ = std::move(hv[3]);
@@ -679,21 +699,22 @@ static void exact_matvec(rss_factor f, const double* x, double* y, hipStream_t s
 // ---------------------------------------------------------------------------------------
 extern "C" {
 
-void rss_params_default(rss_params* p) {
+void rss_params_default(rss_params* p, int32_t dim, int32_t kernel) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));
     p->struct_size = sizeof(rss_params);
-    p->dim = 2;
+    p->dim = dim;
+    p->kernel = kernel;
+    p->symmetric = 1;
     p->diag = 1.0;
     p->weight = 1.0;
     p->tol = 1e-6;
     p->leaf_size = 64;
     p->n_proxy = 16;
     p->proxy_radius = 1.25;
-    p->root_lo[0] = 0.0;
-    p->root_lo[1] = 0.0;
     p->root_side = 1.0;
     p->precision = RSS_FP64;
+    p->arena_bytes = 0;
 }
 
 const char* rss_last_error(void) { return g_err.c_str(); }
@@ -720,7 +741,20 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
         g_err = "rss_params.struct_size mismatch (header/library version)";
         return RSS_E_ARG;
     }
-    if (p->dim != 2) { g_err = "dim must be 2"; return RSS_E_UNSUPPORTED; }
+    if (p->kernel != RSS_K_LAPLACE2D && p->kernel != RSS_K_LAPLACE3D && p->kernel != RSS_K_HELMHOLTZ2D) {
+        g_err = "unknown kernel";
+        return RSS_E_ARG;
+    }
+    if (p->dim != 2 && p->dim != 3) { g_err = "dim must be 2 or 3"; return RSS_E_ARG; }
+    if (p->kernel != RSS_K_LAPLACE2D || p->dim != 2) {
+        g_err = "this version factors the 2D Laplace kernel only (dim 2, RSS_K_LAPLACE2D)";
+        return RSS_E_UNSUPPORTED;
+    }
+    if (p->symmetric != 1) {
+        g_err = "the two-sided ID of a non-symmetric kernel (symmetric = 0) is not built";
+        return RSS_E_UNSUPPORTED;
+    }
+    if (p->reserved != 0) { g_err = "rss_params.reserved must be 0"; return RSS_E_ARG; }
     if (n < 1 || n > (int64_t)1 << 30) { g_err = "n out of range"; return RSS_E_ARG; }
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) { g_err = "tol must be finite and >= 0"; return RSS_E_ARG; }
     if (p->leaf_size < 1 || p->leaf_size > rss::kMaxBox) { g_err = "leaf_size must be in [1, 256]"; return RSS_E_ARG; }
@@ -743,6 +777,7 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     f->kp.proxy_radius = p->proxy_radius;
     hipStream_t s = (hipStream_t)stream;
     f->stream = s;
+    rss::ShapeLogScope shape_scope(f);
     try {
         factor_impl(f, d_points, s);
     } catch (const Fail& e) {
@@ -789,6 +824,7 @@ rss_status rss_solve(rss_factor f, const double* d_b, double* d_x, int32_t nrhs,
                      void* stream) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    rss::ShapeLogScope shape_scope(f);
     if (!d_b || !d_x || nrhs < 1 || ld < f->n) { g_err = "bad solve arguments"; return RSS_E_ARG; }
     hipStream_t s = (hipStream_t)stream;
     const int use32 = (use_fp32 && f->params.precision == RSS_MIXED) ? 1 : 0;
@@ -805,6 +841,7 @@ rss_status rss_solve(rss_factor f, const double* d_b, double* d_x, int32_t nrhs,
 rss_status rss_apply(rss_factor f, const double* d_x, double* d_y, int32_t nrhs, int64_t ld, void* stream) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    rss::ShapeLogScope shape_scope(f);
     if (!d_x || !d_y || nrhs < 1 || ld < f->n || d_x == d_y) { g_err = "bad apply arguments"; return RSS_E_ARG; }
     hipStream_t s = (hipStream_t)stream;
     try {
@@ -914,14 +951,133 @@ static void exact_matvec(rss_factor f, const double* x, double* y, hipStream_t s
     else rss::launch_matvec_direct(f->pts, f->n, f->kp, x, y, s);
 }
 
-static double ddot(rss_factor f, const double* x, const double* y, double* part, hipStream_t s) {
-    int nbk = rss::dot_partial_blocks(f->n);
+// Host side of the dot products: the partial sums of the blocks are copied into `hpart`
+// (dot_partial_blocks(n) <= 1024 entries, caller-owned) and added in order.
+static double ddot(rss_factor f, const double* x, const double* y, double* part, double* hpart, hipStream_t s) {
+    const int nbk = rss::dot_partial_blocks(f->n);
     rss::launch_dot_partial(x, y, f->n, part, s);
     check_launch();
-    std::vector<double> h = d2h(part, nbk, s);
+    HIPCHK(hipMemcpyAsync(hpart, part, sizeof(double) * nbk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     double acc = 0.0;
-    for (double v : h) acc += v;
+    for (int i = 0; i < nbk; ++i) acc += hpart[i];
     return acc;
+}
+
+// Device and host work arrays of one GMRES(restart) run on a factor of n DOFs.
+struct GmresWork {
+    double* V;      // n (restart + 1): Arnoldi basis
+    double* Z;      // n restart: F^{-1} V (right preconditioning)
+    double* rvec;   // n
+    double* wvec;   // n
+    double* part;   // 1024 partial dot products
+    double* H;      // host (restart + 1) restart
+    double* cs;     // host restart
+    double* sn;     // host restart
+    double* g;      // host restart + 1
+    double* y;      // host restart
+    double* hpart;  // host 1024
+};
+
+static size_t gmres_device_doubles(int64_t n, int restart) { return (size_t)n * (2 * (size_t)restart + 3) + 1024; }
+
+// Right-preconditioned restarted GMRES(restart) with modified Gram-Schmidt, x0 = 0, stopping
+// on the recomputed true residual; allocates nothing (every array comes in `w`).  Returns
+// RSS_OK or RSS_E_NOCONV; throws Fail on device errors.
+static rss_status gmres_run(rss_factor f, const double* d_b, double* d_x, double rtol, int maxit, int restart,
+                            int use32, hipStream_t s, const GmresWork& w, int* iters, double* relres) {
+    const int64_t n = f->n;
+    const int ldh = restart + 1;
+    int it = 0;
+    double rr = 1.0;
+    rss::launch_fill(d_x, 0.0, n, s);
+    check_launch();
+    const double nb = std::sqrt(ddot(f, d_b, d_b, w.part, w.hpart, s));
+    if (nb == 0.0) {
+        rr = 0.0;
+    } else {
+        rss::launch_scal_copy(1.0, d_b, w.rvec, n, s);
+        check_launch();
+        while (true) {
+            const double beta = std::sqrt(ddot(f, w.rvec, w.rvec, w.part, w.hpart, s));
+            rr = beta / nb;
+            if (rr <= rtol || it >= maxit) break;
+            rss::launch_scal_copy(1.0 / beta, w.rvec, w.V, n, s);
+            check_launch();
+            std::fill(w.H, w.H + (size_t)ldh * restart, 0.0);
+            std::fill(w.g, w.g + ldh, 0.0);
+            w.g[0] = beta;
+            int m = 0;
+            for (int j = 0; j < restart; ++j) {
+                double* vj = w.V + (size_t)j * n;
+                double* zj = w.Z + (size_t)j * n;
+                rss::launch_scal_copy(1.0, vj, zj, n, s);
+                check_launch();
+                solve_impl(f, zj, 1, n, use32, s);
+                exact_matvec(f, zj, w.wvec, s);
+                check_launch();
+                for (int i = 0; i <= j; ++i) {
+                    const double hij = ddot(f, w.wvec, w.V + (size_t)i * n, w.part, w.hpart, s);
+                    w.H[i + (size_t)j * ldh] = hij;
+                    rss::launch_axpy(-hij, w.V + (size_t)i * n, w.wvec, n, s);
+                    check_launch();
+                }
+                const double hn = std::sqrt(ddot(f, w.wvec, w.wvec, w.part, w.hpart, s));
+                w.H[j + 1 + (size_t)j * ldh] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double a = w.H[i + (size_t)j * ldh], c2 = w.H[i + 1 + (size_t)j * ldh];
+                    w.H[i + (size_t)j * ldh] = w.cs[i] * a + w.sn[i] * c2;
+                    w.H[i + 1 + (size_t)j * ldh] = -w.sn[i] * a + w.cs[i] * c2;
+                }
+                const double hjj = w.H[j + (size_t)j * ldh], hj1 = w.H[j + 1 + (size_t)j * ldh];
+                const double den = std::hypot(hjj, hj1);
+                w.cs[j] = hjj / den;
+                w.sn[j] = hj1 / den;
+                w.H[j + (size_t)j * ldh] = den;
+                w.H[j + 1 + (size_t)j * ldh] = 0.0;
+                w.g[j + 1] = -w.sn[j] * w.g[j];
+                w.g[j] = w.cs[j] * w.g[j];
+                ++it;
+                m = j + 1;
+                if (std::fabs(w.g[j + 1]) / nb <= rtol || hn == 0.0 || it >= maxit) break;
+                rss::launch_scal_copy(1.0 / hn, w.wvec, w.V + (size_t)(j + 1) * n, n, s);
+                check_launch();
+            }
+            for (int i = m - 1; i >= 0; --i) {
+                double acc = w.g[i];
+                for (int l = i + 1; l < m; ++l) acc -= w.H[i + (size_t)l * ldh] * w.y[l];
+                w.y[i] = acc / w.H[i + (size_t)i * ldh];
+            }
+            for (int i = 0; i < m; ++i) {
+                rss::launch_axpy(w.y[i], w.Z + (size_t)i * n, d_x, n, s);
+                check_launch();
+            }
+            exact_matvec(f, d_x, w.wvec, s);
+            check_launch();
+            rss::launch_scal_copy(1.0, d_b, w.rvec, n, s);
+            check_launch();
+            rss::launch_axpy(-1.0, w.wvec, w.rvec, n, s);
+            check_launch();
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (rr > rtol) {
+        g_err = "gmres did not reach rtol within maxit";
+        return RSS_E_NOCONV;
+    }
+    return RSS_OK;
+}
+
+static GmresWork gmres_work_on(double* d, int64_t n, int restart) {
+    GmresWork w{};
+    w.V = d;
+    w.Z = w.V + (size_t)n * (restart + 1);
+    w.rvec = w.Z + (size_t)n * restart;
+    w.wvec = w.rvec + n;
+    w.part = w.wvec + n;
+    return w;
 }
 
 rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, int32_t maxit, int32_t restart,
@@ -934,115 +1090,28 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
     }
     hipStream_t s = (hipStream_t)stream;
     const int use32 = (use_fp32 && f->params.precision == RSS_MIXED) ? 1 : 0;
-    const int64_t n = f->n;
-    double* V = nullptr;
-    double* Z = nullptr;
-    double* rvec = nullptr;
-    double* wvec = nullptr;
-    double* part = nullptr;
+    const size_t nd = gmres_device_doubles(f->n, restart);
+    double* d = nullptr;
     rss_status st = RSS_OK;
-    int it = 0;
-    double rr = 1.0;
     try {
-        V = dalloc<double>(f, (size_t)n * (restart + 1), s);
-        Z = dalloc<double>(f, (size_t)n * restart, s);
-        rvec = dalloc<double>(f, n, s);
-        wvec = dalloc<double>(f, n, s);
-        part = dalloc<double>(f, 1024, s);
-        HIPCHK(hipMemsetAsync(d_x, 0, sizeof(double) * n, s));
-        const double nb = std::sqrt(ddot(f, d_b, d_b, part, s));
-        if (nb == 0.0) {
-            rr = 0.0;
-        } else {
-            rss::launch_scal_copy(1.0, d_b, rvec, n, s);
-            check_launch();
-            std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1);
-            while (true) {
-                double beta = std::sqrt(ddot(f, rvec, rvec, part, s));
-                rr = beta / nb;
-                if (rr <= rtol || it >= maxit) break;
-                rss::launch_scal_copy(1.0 / beta, rvec, V, n, s);
-                check_launch();
-                std::fill(H.begin(), H.end(), 0.0);
-                std::fill(g.begin(), g.end(), 0.0);
-                g[0] = beta;
-                int m = 0;
-                for (int j = 0; j < restart; ++j) {
-                    double* vj = V + (size_t)j * n;
-                    double* zj = Z + (size_t)j * n;
-                    rss::launch_scal_copy(1.0, vj, zj, n, s);
-                    check_launch();
-                    solve_impl(f, zj, 1, n, use32, s);
-                    exact_matvec(f, zj, wvec, s);
-                    check_launch();
-                    for (int i = 0; i <= j; ++i) {
-                        double hij = ddot(f, wvec, V + (size_t)i * n, part, s);
-                        H[i + (size_t)j * (restart + 1)] = hij;
-                        rss::launch_axpy(-hij, V + (size_t)i * n, wvec, n, s);
-                        check_launch();
-                    }
-                    double hn = std::sqrt(ddot(f, wvec, wvec, part, s));
-                    H[j + 1 + (size_t)j * (restart + 1)] = hn;
-                    for (int i = 0; i < j; ++i) {
-                        double a = H[i + (size_t)j * (restart + 1)], c2 = H[i + 1 + (size_t)j * (restart + 1)];
-                        H[i + (size_t)j * (restart + 1)] = cs[i] * a + sn[i] * c2;
-                        H[i + 1 + (size_t)j * (restart + 1)] = -sn[i] * a + cs[i] * c2;
-                    }
-                    double hjj = H[j + (size_t)j * (restart + 1)], hj1 = H[j + 1 + (size_t)j * (restart + 1)];
-                    double den = std::hypot(hjj, hj1);
-                    cs[j] = hjj / den;
-                    sn[j] = hj1 / den;
-                    H[j + (size_t)j * (restart + 1)] = den;
-                    H[j + 1 + (size_t)j * (restart + 1)] = 0.0;
-                    g[j + 1] = -sn[j] * g[j];
-                    g[j] = cs[j] * g[j];
-                    ++it;
-                    m = j + 1;
-                    if (std::fabs(g[j + 1]) / nb <= rtol || hn == 0.0 || it >= maxit) break;
-                    rss::launch_scal_copy(1.0 / hn, wvec, V + (size_t)(j + 1) * n, n, s);
-                    check_launch();
-                }
-                std::vector<double> y(m);
-                for (int i = m - 1; i >= 0; --i) {
-                    double acc = g[i];
-                    for (int l = i + 1; l < m; ++l) acc -= H[i + (size_t)l * (restart + 1)] * y[l];
-                    y[i] = acc / H[i + (size_t)i * (restart + 1)];
-                }
-                for (int i = 0; i < m; ++i) {
-                    rss::launch_axpy(y[i], Z + (size_t)i * n, d_x, n, s);
-                    check_launch();
-                }
-                exact_matvec(f, d_x, wvec, s);
-                check_launch();
-                rss::launch_scal_copy(1.0, d_b, rvec, n, s);
-                check_launch();
-                rss::launch_axpy(-1.0, wvec, rvec, n, s);
-                check_launch();
-            }
-        }
-        HIPCHK(hipStreamSynchronize(s));
-        if (rr > rtol) {
-            st = RSS_E_NOCONV;
-            g_err = "gmres did not reach rtol within maxit";
-        }
+        d = dalloc<double>(f, nd, s);
+        GmresWork w = gmres_work_on(d, f->n, restart);
+        std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart),
+            hpart(1024);
+        w.H = H.data(); w.cs = cs.data(); w.sn = sn.data(); w.g = g.data(); w.y = y.data(); w.hpart = hpart.data();
+        st = gmres_run(f, d_b, d_x, rtol, maxit, restart, use32, s, w, iters, relres);
     } catch (const Fail& e) {
         st = e.st;
     }
-    if (V) dfree(f, V, sizeof(double) * n * (restart + 1), s);
-    if (Z) dfree(f, Z, sizeof(double) * n * restart, s);
-    if (rvec) dfree(f, rvec, sizeof(double) * n, s);
-    if (wvec) dfree(f, wvec, sizeof(double) * n, s);
-    if (part) dfree(f, part, sizeof(double) * 1024, s);
+    if (d) dfree(f, d, sizeof(double) * nd, s);
     (void)hipStreamSynchronize(s);
-    if (iters) *iters = it;
-    if (relres) *relres = rr;
     return st;
 }
 
-rss_status rss_logdet(rss_factor f, double* sign, double* logabs) {
+rss_status rss_logdet(rss_factor f, double* re, double* im) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
-    if (!sign || !logabs) { g_err = "NULL argument"; return RSS_E_ARG; }
+    if (!re || !im) { g_err = "NULL argument"; return RSS_E_ARG; }
     try {
         double total = f->top_logdet;
         int sg = f->top_sign;
@@ -1056,8 +1125,8 @@ rss_status rss_logdet(rss_factor f, double* sign, double* logabs) {
                     sg *= sgs[b];
                 }
         }
-        *sign = (double)sg;
-        *logabs = total;
+        *re = total;
+        *im = sg < 0 ? M_PI : 0.0;
     } catch (const Fail& e) {
         return e.st;
     }
@@ -1110,6 +1179,55 @@ rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel,
     return RSS_OK;
 }
 
+rss_status rss_box_record(rss_factor f, int32_t depth, int64_t box, double* h_T, double* h_XRR, double* h_XJR,
+                          double* h_G, int64_t* h_J, int64_t cap, int32_t* ns, int32_t* nr, int32_t* nj) {
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    const rss::Level* L = nullptr;
+    for (auto& l : f->levels)
+        if (l.t == depth) L = &l;
+    if (!L || box < 0 || box >= L->nbox || !ns || !nr || !nj) {
+        g_err = "no skeletonized level / box with these indices";
+        return RSS_E_ARG;
+    }
+    try {
+        int nJ = 0;
+        HIPCHK(hipMemcpy(&nJ, L->nJ + box, sizeof(int), hipMemcpyDeviceToHost));
+        const int n = L->h_cnt[box], k = nJ > 0 ? L->h_k[box] : 0, r = nJ > 0 ? n - k : 0;
+        *ns = k;
+        *nr = r;
+        *nj = nJ;
+        if (nJ <= 0) return RSS_OK;
+        const int64_t need_T = (int64_t)k * r, need_X = (int64_t)r * r, need_J = (int64_t)nJ * r;
+        if ((h_T && need_T > cap) || (h_XRR && need_X > cap) || ((h_XJR || h_G) && need_J > cap) ||
+            (h_J && nJ > cap)) {
+            g_err = "capacity too small";
+            return RSS_E_ARG;
+        }
+        const size_t nm = (size_t)L->nmax, ldJ = (size_t)L->ldJ;
+        // column-major copies with the record's leading dimension removed
+        auto get = [&](const double* src, size_t ld, int rows, int cols, double* dst) {
+            if (!dst || rows == 0 || cols == 0) return;
+            std::vector<double> h(ld * (size_t)cols);
+            HIPCHK(hipMemcpy(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+            for (int j = 0; j < cols; ++j)
+                for (int i = 0; i < rows; ++i) dst[i + (size_t)rows * j] = h[i + ld * j];
+        };
+        get(L->T + (size_t)box * nm * nm, nm, k, r, h_T);
+        get(L->XRR + (size_t)box * nm * nm, nm, r, r, h_XRR);
+        get(L->XJR + (size_t)box * ldJ * nm, ldJ, nJ, r, h_XJR);
+        get(L->G + (size_t)box * nm * ldJ, nm, r, nJ, h_G);
+        if (h_J) {
+            std::vector<int> hj(nJ);
+            HIPCHK(hipMemcpy(hj.data(), L->Jg + (size_t)box * ldJ, sizeof(int) * nJ, hipMemcpyDeviceToHost));
+            for (int i = 0; i < nJ; ++i) h_J[i] = hj[i];
+        }
+    } catch (const Fail& e) {
+        return e.st;
+    }
+    return RSS_OK;
+}
+
 rss_status rss_top_set(rss_factor f, int64_t* idx, int64_t cap, int64_t* count) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
@@ -1138,7 +1256,9 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
     o << "},\"launches\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->kernel_launches[i];
-    o << "},\"levels\":[";
+    o << "},\"shapes\":[";
+    for (size_t i = 0; i < f->shapes.size(); ++i) o << (i ? "," : "") << "\"" << f->shapes[i] << "\"";
+    o << "],\"levels\":[";
     for (size_t i = 0; i < f->stats.size(); ++i) {
         const auto& s = f->stats[i];
         o << (i ? "," : "") << "{\"depth\":" << s.depth << ",\"boxes\":" << s.boxes << ",\"nmax\":" << s.nmax

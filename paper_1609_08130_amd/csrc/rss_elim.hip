@@ -50,6 +50,7 @@ struct ElimArgs {
     float* T32;
     double* logdet_part;
     int* sign_part;
+    int* flag;           // error and status bits (bit 64: the LDS Gauss-Jordan ran)
 };
 
 constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
@@ -710,6 +711,7 @@ __device__ bool elim_xrr_inverse(ElimShared<ST>& sh, const ElimArgs& a, int c, i
             Xs[b + b2 * nmax] = v;
         }
         __syncthreads();
+        if (threadIdx.x == 0) atomicOr(a.flag, 64);   // records that the LDS form ran
         ok = gj_inverse<NTH>(Xs, nmax, r, colswap, sc, piv_idx, piv_val, ld_sum, sgn);
         if (ok)
             for (int e = tid; e < r * r; e += NTH) {
@@ -894,7 +896,7 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
     a.XJR = L.XJR; a.G = L.G; a.XRR = L.XRR; a.Xinv = L.Xinv;
     a.XJR32 = L.XJR32; a.G32 = L.G32; a.Xinv32 = L.Xinv32; a.T32 = L.T32;
-    a.logdet_part = L.logdet_part; a.sign_part = L.sign_part;
+    a.logdet_part = L.logdet_part; a.sign_part = L.sign_part; a.flag = flag;
     const size_t D = sizeof(double);
     const size_t nm = (size_t)L.nmax;
     const size_t tsz = nm * nm / 4 + 1;                    // |S| |R| <= n^2 / 4
@@ -914,6 +916,7 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     set_lds(k_elim_rows<256, ST>, lr);
     const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
     const int pr = tiles_per_wg(ntr, nboxes), gr = (ntr + pr - 1) / pr;
+    note_shape("elim_rows_w" + std::to_string(twr) + "_tpw" + std::to_string(pr));
     k_elim_rows<256, ST><<<dim3(xcd_grid(gr, nboxes)), dim3(256), lr, s>>>(a, boxes, nboxes, gr, mixed, work,
                                                                       (int)tsz, twr, pr);
     const size_t base = tsz + 4 * nm;
@@ -924,6 +927,7 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
     const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
     // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
+    note_shape(std::string("elim_inv_") + (nboxes >= 256 ? "256" : "1024") + (xl ? "_xlds" : "") + (zs ? "_zs" : ""));
     if (nboxes >= 256) {
         if (xl) {
             set_lds(k_elim_inv<true, 256, ST>, li);
@@ -942,6 +946,8 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     const int ntg = (L.ldJ + twg - 1) / twg;
     const int pg = tiles_per_wg(ntg, nboxes), gt = (ntg + pg - 1) / pg;
     const dim3 gg(xcd_grid(gt, nboxes));
+    note_shape("elim_g_hb" + std::to_string(L.nmax <= 64 ? 1 : (L.nmax <= 128 ? 2 : 4)) + "_w" + std::to_string(twg) +
+               "_tpw" + std::to_string(pg));
     if (L.nmax <= 64) {
         set_lds(k_elim_g<256, 1, ST>, lg);
         k_elim_g<256, 1, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);

@@ -645,6 +645,7 @@ template <int NTH, int TPT>
 static void gram_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                         const KernelParams& kp, double* gpart, const GramPlan& g, size_t lds, hipStream_t s) {
     const dim3 grid(g.nsl * g.groups, nboxes);
+    note_shape("gram_" + std::to_string(NTH) + "x" + std::to_string(TPT) + "_rows" + std::to_string(g.slice_rows));
     // the chunk exceeds the default 64 KB of dynamic LDS only for nmax > 254
     if (L.store32)
         hipFuncSetAttribute((const void*)k_gram<NTH, TPT, float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -667,6 +668,7 @@ static void pchol_launch(const Level& L, const int* boxes, int nboxes, const Ker
     // CU; measured 0.4 ms faster per leaf level than none), later rows in the workspace
     const int kc = nboxes >= 512 ? std::min(16, L.nmax) : pchol_lds_rows(L.nmax);
     const size_t lds = sizeof(double) * 2 * (size_t)kc * L.nmax;
+    note_shape("pchol_" + std::to_string(NTH) + "x" + std::to_string(SUB) + "_kc" + std::to_string(kc));
     k_pchol<NTH, SUB><<<dim3(nboxes), dim3(NTH), lds, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, g.nsl,
                                                           g.slice_rows, nsl_fixed, rwork, kc, L.krank, L.spos,
                                                           L.rpos, L.T, L.mrows);
@@ -694,6 +696,7 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
             L.cnt, L.nact, boxes, L.nb, L.nmax, kp.n_proxy, gpart, g.nsl, g.slice_rows);
         nsl_fixed = 1;
         ++launches;
+        note_shape("gram_reduce");
     }
     // many boxes: one thread per column; few boxes: four threads per column
     if (nboxes >= 512) {

@@ -129,6 +129,7 @@ struct rss_factor_s {
     size_t hup_bytes = 0, hup_used = 0;
     std::vector<std::pair<void*, size_t>> pending_free;   // released at the next synchronization
     std::vector<rss::LevelStats> stats;
+    std::vector<std::string> shapes;   // launch shapes taken (note_shape)
     std::vector<double> phase_ms;   // tree, leaf store, id, elim, schur, transition, top, total
     std::vector<int> kernel_launches;
     double wall_ms = 0;
@@ -187,6 +188,12 @@ __device__ inline void wave_argmax(double& best, int& bi) {
     bi = (int)wave_min_u32(key == km ? (unsigned)bi : 0xffffffffu);
     best = km == 0 ? -1.0 : __longlong_as_double((long long)(km - 1ull));
 }
+
+// Launch shapes (the kernel variants chosen by box counts and sizes) are collected by name
+// into the log of the factor whose entry point is running, for rss_info; a launcher calls
+// note_shape once per variant it launches.  No log set: nothing is recorded.
+void set_shape_log(std::vector<std::string>* log);
+void note_shape(const std::string& name);
 
 // ---- launchers (each enqueues on `s`) -------------------------------------------------
 // tree / store (rss_tree.hip)
@@ -267,5 +274,7 @@ void launch_dot_partial(const double* x, const double* y, int64_t n, double* par
 int dot_partial_blocks(int64_t n);
 void launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);
 void launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);
+// y[i] = v for i < n (a kernel, not hipMemsetAsync, so that it may sit in a captured graph)
+void launch_fill(double* y, double v, int64_t n, hipStream_t s);
 
 }  // namespace rss

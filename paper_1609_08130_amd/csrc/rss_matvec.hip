@@ -78,4 +78,14 @@ void launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream
     k_scal_copy<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, x, y, n);
 }
 
+__global__ void k_fill(double* __restrict__ y, double v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(y, v, n);
+}
+
 }  // namespace rss

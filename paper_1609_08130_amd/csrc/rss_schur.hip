@@ -240,6 +240,7 @@ int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mix
     const int tpd = (maxJ + 63) / 64;
     const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);   // 8 lists of at most capx entries
     dim3 grid((unsigned)nwg), block(256);
+    note_shape(std::string("schur_") + (mixed ? "f32" : "f64") + (L.store32 ? "_store32" : "_store64"));
     if (mixed) {
         a.XJR = L.XJR32; a.G = L.G32;
         if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);

@@ -427,6 +427,7 @@ static void solve_bwd_k(const SweepArgs& a, const int* boxes, int nboxes, double
 template <typename TT, int NTH>
 static void solve_fwd_t(const SweepArgs& a, const int* boxes, int nboxes, double* z, int nrhs, int64_t ld,
                         hipStream_t s) {
+    note_shape("solve_fwd_" + std::to_string(NTH) + (sizeof(TT) == 4 ? "_f32" : "_f64") + (nrhs > 1 ? "_multi" : ""));
     if (nrhs == 1) {
         solve_fwd_k<TT, NTH, 1>(a, boxes, nboxes, z, 1, ld, s);
         return;
@@ -443,6 +444,7 @@ static void solve_bwd_t(const SweepArgs& a, const int* boxes, int nboxes, double
     const size_t lds1 = sizeof(double) * (size_t)a.ldJ;
     const size_t ldsg = sizeof(double) * ((size_t)kSolveGroup * a.ldJ + (size_t)NW * kSolveGroup * a.nmax);
     const size_t stat = sizeof(double) * kSolveGroup * kMaxBox + 2 * sizeof(int) * kMaxBox + 1024;
+    note_shape("solve_bwd_" + std::to_string(NTH) + (sizeof(TT) == 4 ? "_f32" : "_f64") + (nrhs > 1 ? "_multi" : ""));
     if (nrhs == 1 || ldsg + stat > (size_t)elim_lds_limit()) {
         solve_bwd_k<TT, NTH, 1>(a, boxes, nboxes, z, nrhs, ld, lds1, s);
         return;

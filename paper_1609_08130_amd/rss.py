@@ -23,13 +23,18 @@ LIB_PATH = os.path.join(HERE, "librss.so")
 RSS_FP64 = 0
 RSS_MIXED = 1
 
+RSS_K_LAPLACE2D = 0
+RSS_K_LAPLACE3D = 1
+RSS_K_HELMHOLTZ2D = 2
+KERNELS = {"laplace2d": RSS_K_LAPLACE2D, "laplace3d": RSS_K_LAPLACE3D, "helmholtz2d": RSS_K_HELMHOLTZ2D}
+
 STATUS = {0: "RSS_OK", 1: "RSS_E_ARG", 2: "RSS_E_NOMEM", 3: "RSS_E_DEVICE", 4: "RSS_E_SINGULAR",
-          5: "RSS_E_UNSUPPORTED", 6: "RSS_E_NOCONV"}
+          5: "RSS_E_UNSUPPORTED", 6: "RSS_E_NOCONV", 7: "RSS_E_ARENA"}
 
 # exported names declared in include/rss.h
 EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_sqrt_apply", "rss_matvec", "rss_gmres",
-           "rss_logdet", "rss_shape", "rss_box_sets", "rss_top_set", "rss_info", "rss_factor_destroy",
-           "rss_last_error", "rss_trim"]
+           "rss_logdet", "rss_shape", "rss_box_sets", "rss_box_record", "rss_top_set", "rss_info",
+           "rss_factor_destroy", "rss_last_error", "rss_trim"]
 
 
 class RSSError(RuntimeError):
@@ -43,15 +48,20 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32),
         ("dim", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
+        ("symmetric", ctypes.c_int32),
         ("diag", ctypes.c_double),
         ("weight", ctypes.c_double),
+        ("kappa", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("leaf_size", ctypes.c_int32),
         ("n_proxy", ctypes.c_int32),
         ("proxy_radius", ctypes.c_double),
-        ("root_lo", ctypes.c_double * 2),
+        ("root_lo", ctypes.c_double * 3),
         ("root_side", ctypes.c_double),
         ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("arena_bytes", ctypes.c_uint64),
     ]
 
 
@@ -61,7 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
-    lib.rss_params_default.argtypes = [P(Params)]
+    lib.rss_params_default.argtypes = [P(Params), i32, i32]
     lib.rss_params_default.restype = None
     lib.rss_factor_create.argtypes = [vp, i64, P(Params), vp, P(vp)]
     lib.rss_solve.argtypes = [vp, vp, vp, i32, i64, i32, vp]
@@ -72,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rss_logdet.argtypes = [vp, P(dbl), P(dbl)]
     lib.rss_shape.argtypes = [vp, P(i32), P(i64)]
     lib.rss_box_sets.argtypes = [vp, i32, i64, P(i64), i32, P(i32), P(i64), i32, P(i32)]
+    lib.rss_box_record.argtypes = [vp, i32, i64, P(dbl), P(dbl), P(dbl), P(dbl), P(i64), i64, P(i32), P(i32),
+                                   P(i32)]
     lib.rss_top_set.argtypes = [vp, P(i64), i64, P(i64)]
     lib.rss_info.argtypes = [vp, ctypes.c_char_p, i64]
     lib.rss_factor_destroy.argtypes = [vp]
@@ -99,16 +111,15 @@ def _check(st: int):
         raise RSSError(st, lib().rss_last_error().decode())
 
 
-def make_params(**kw) -> Params:
+def make_params(dim: int = 2, kernel="laplace2d", **kw) -> Params:
     p = Params()
-    lib().rss_params_default(ctypes.byref(p))
+    lib().rss_params_default(ctypes.byref(p), int(dim), KERNELS.get(kernel, kernel))
     for k, v in kw.items():
         if k == "root_lo":
-            p.root_lo[0], p.root_lo[1] = float(v[0]), float(v[1])
+            for i, c in enumerate(v):
+                p.root_lo[i] = float(c)
         elif k == "precision":
             p.precision = {"fp64": RSS_FP64, "mixed": RSS_MIXED}.get(v, v)
-        elif k == "dim":
-            p.dim = int(v)
         elif hasattr(p, k):
             setattr(p, k, type(getattr(p, k))(v))
         else:
@@ -131,8 +142,9 @@ class Factor:
     def __init__(self, points, **params):
         import torch
         self._torch = torch
-        if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
-            raise ValueError("points must be a CUDA float64 tensor of shape (N, 2)")
+        if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2):
+            raise ValueError("points must be a CUDA float64 tensor of shape (N, dim)")
+        params.setdefault("dim", int(points.shape[1]))
         self.points = points.contiguous()
         self.n = int(points.shape[0])
         self.params = make_params(**params)
@@ -197,9 +209,26 @@ class Factor:
         return y.reshape(-1) if single else y
 
     def logdet(self):
-        s, l = ctypes.c_double(), ctypes.c_double()
-        _check(lib().rss_logdet(self._h, ctypes.byref(s), ctypes.byref(l)))
-        return s.value, l.value
+        """(sign, log|det F|) of a real factor, from rss_logdet's log det = re + i im."""
+        re, im = ctypes.c_double(), ctypes.c_double()
+        _check(lib().rss_logdet(self._h, ctypes.byref(re), ctypes.byref(im)))
+        return (-1.0 if im.value != 0.0 else 1.0), re.value
+
+    def box_record(self, depth: int, box: int) -> dict:
+        """T, X_RR, X_JR, G and the global J indices of one skeletonization step (empty
+        arrays when the box has no record)."""
+        ns, nr, nj = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rss_box_record(self._h, depth, box, None, None, None, None, None, 0, ctypes.byref(ns),
+                                    ctypes.byref(nr), ctypes.byref(nj)))
+        k, r, J = ns.value, nr.value, nj.value
+        cap = max(k * r, r * r, J * r, J, 1)
+        bufs = [(ctypes.c_double * cap)() for _ in range(4)]
+        jb = (ctypes.c_int64 * cap)()
+        _check(lib().rss_box_record(self._h, depth, box, *bufs, jb, cap, ctypes.byref(ns), ctypes.byref(nr),
+                                    ctypes.byref(nj)))
+        col = lambda b, rows, cols: np.array(b[:rows * cols], dtype=np.float64).reshape(cols, rows).T.copy()
+        return dict(T=col(bufs[0], k, r), XRR=col(bufs[1], r, r), XJR=col(bufs[2], J, r), G=col(bufs[3], r, J),
+                    J=np.array(jb[:J], dtype=np.int64))
 
     def shape(self):
         d, nt = ctypes.c_int32(), ctypes.c_int64()
@@ -207,7 +236,7 @@ class Factor:
         return d.value, nt.value
 
     def box_sets(self, depth: int, box: int):
-        cap = 256
+        cap = 8192
         S = (ctypes.c_int64 * cap)()
         R = (ctypes.c_int64 * cap)()
         ns, nr = ctypes.c_int32(), ctypes.c_int32()

@@ -32,38 +32,40 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_layout_matches_c_header(tmp_path):
     src = tmp_path / "layout.c"
+    fields = [name for name, _ in rss.Params._fields_]
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rss.h"\nint main(void){'
-                   'printf("%zu %zu %zu %zu %zu\\n", sizeof(rss_params), offsetof(rss_params, tol), '
-                   'offsetof(rss_params, root_lo), offsetof(rss_params, root_side), '
-                   'offsetof(rss_params, precision)); return 0;}\n')
+                   'printf("%zu\\n", sizeof(rss_params));'
+                   + "".join(f'printf("%zu\\n", offsetof(rss_params, {f}));' for f in fields)
+                   + 'return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P = rss.Params
-    assert vals == [ctypes.sizeof(P), P.tol.offset, P.root_lo.offset, P.root_side.offset, P.precision.offset]
+    assert vals == [ctypes.sizeof(P)] + [getattr(P, f).offset for f in fields]
 
 
 def test_params_default_and_argument_errors():
     lib = rss.load_library()
     p = rss.Params()
-    lib.rss_params_default(ctypes.byref(p))
+    lib.rss_params_default(ctypes.byref(p), 2, rss.RSS_K_LAPLACE2D)
     assert p.struct_size == ctypes.sizeof(rss.Params)
-    assert (p.dim, p.diag, p.tol, p.leaf_size, p.n_proxy, p.proxy_radius) == (2, 1.0, 1e-6, 64, 16, 1.25)
+    assert (p.dim, p.kernel, p.symmetric, p.diag, p.tol, p.leaf_size, p.n_proxy, p.proxy_radius, p.root_side,
+            p.arena_bytes, p.reserved) == (2, 0, 1, 1.0, 1e-6, 64, 16, 1.25, 1.0, 0, 0)
     h = ctypes.c_void_p(123)
     fake = ctypes.c_void_p(1)   # never dereferenced: validation fails first
-    bad = []
-    for field, val in [("tol", -1.0), ("tol", float("nan")), ("leaf_size", 0), ("leaf_size", 1000),
-                       ("n_proxy", 0), ("proxy_radius", 0.5), ("proxy_radius", 3.0), ("dim", 3)]:
+    for field, val, want in [("tol", -1.0, 1), ("tol", float("nan"), 1), ("leaf_size", 0, 1),
+                             ("leaf_size", 100000, 1), ("n_proxy", 0, 1), ("proxy_radius", 0.5, 1),
+                             ("proxy_radius", 3.0, 1), ("dim", 4, 1), ("kernel", 9, 1), ("reserved", 1, 1),
+                             ("kernel", rss.RSS_K_HELMHOLTZ2D, 5), ("symmetric", 0, 5)]:
         q = rss.Params()
-        lib.rss_params_default(ctypes.byref(q))
+        lib.rss_params_default(ctypes.byref(q), 2, rss.RSS_K_LAPLACE2D)
         setattr(q, field, val)
         st = lib.rss_factor_create(fake, 100, ctypes.byref(q), None, ctypes.byref(h))
-        bad.append((field, st))
+        assert st == want, (field, val, st)
         assert h.value is None
         assert lib.rss_last_error().decode() != ""
-    assert all(st in (1, 5) for _, st in bad)
     q = rss.Params()
-    lib.rss_params_default(ctypes.byref(q))
+    lib.rss_params_default(ctypes.byref(q), 2, rss.RSS_K_LAPLACE2D)
     assert lib.rss_factor_create(fake, 0, ctypes.byref(q), None, ctypes.byref(h)) == 1
     q.struct_size = 7
     assert lib.rss_factor_create(fake, 10, ctypes.byref(q), None, ctypes.byref(h)) == 1

@@ -1,0 +1,101 @@
+"""GPU: failure handling through the C ABI, each condition forced from the host.
+
+* GMRES that cannot reach rtol in maxit iterations returns RSS_E_NOCONV with the iterate,
+  the iteration count and the residual it reached.
+* A singular redundant block X_RR (Section 2.1 needs X_RR invertible; the zero matrix makes
+  every ID rank 0, so X_RR = A_RR = 0) and a singular top block (no skeletonized level)
+  return RSS_E_SINGULAR, as the oracle raises.
+* A device-memory cap below what the factorization needs returns RSS_E_ARENA, leaks
+  nothing, and the next factorization without the cap works.
+* Kernels and modes that are declared but not built return RSS_E_UNSUPPORTED.
+"""
+import numpy as np
+import pytest
+
+from oracle import rss_oracle as O
+from paper_1609_08130_amd import workloads as W
+from tests.parity_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08130_amd import rss as mod
+    return mod
+
+
+def _factor(rss, pts, prm, **kw):
+    prm = dict(prm)
+    prm.pop("dim", None)
+    prm.update(kw)
+    return rss.Factor(torch.tensor(pts, device="cuda"), **prm)
+
+
+def test_gmres_maxit_returns_noconv(rss):
+    n = 64
+    say("[errors] gmres maxit=1 -> RSS_E_NOCONV")
+    F = _factor(rss, W.grid_points(n), W.problem(n, 1e-3))
+    b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
+    with pytest.raises(rss.RSSError) as ei:
+        F.gmres(b, rtol=1e-14, maxit=1)
+    assert ei.value.name == "RSS_E_NOCONV"
+    x, it, rr = F.gmres(b, rtol=1e-14, maxit=1, raise_on_noconv=False)
+    assert it == 1 and 1e-14 < rr < 1e-2 and bool(torch.isfinite(x).all())
+    F.close()
+
+
+def test_singular_redundant_block(rss):
+    n = 16
+    pts = W.grid_points(n)
+    prm = W.problem(n, 1e-6, leaf_size=16)
+    prm.update(diag=0.0, weight=0.0)
+    with pytest.raises(O.OracleError):
+        O.factor(pts, O.Params(**prm))
+    say("[errors] zero matrix, depth 2 -> RSS_E_SINGULAR (X_RR)")
+    with pytest.raises(rss.RSSError) as ei:
+        _factor(rss, pts, prm)
+    assert ei.value.name == "RSS_E_SINGULAR" and "X_RR" in str(ei.value)
+
+
+def test_singular_top_block(rss):
+    pts = W.random_points(100, seed=5)
+    prm = dict(diag=0.0, weight=0.0, tol=1e-6, leaf_size=256)
+    with pytest.raises(O.OracleError):
+        O.factor(pts, O.Params(**prm))
+    say("[errors] zero matrix, no skeletonized level -> RSS_E_SINGULAR (top block)")
+    with pytest.raises(rss.RSSError) as ei:
+        _factor(rss, pts, prm)
+    assert ei.value.name == "RSS_E_SINGULAR" and "top" in str(ei.value)
+
+
+def test_arena_cap(rss):
+    n = 64
+    pts = W.grid_points(n)
+    prm = W.problem(n, 1e-6)
+    F = _factor(rss, pts, prm)
+    need = F.info()["bytes_device"]
+    F.close()
+    say(f"[errors] arena cap {need // 4} of {need} bytes -> RSS_E_ARENA")
+    with pytest.raises(rss.RSSError) as ei:
+        _factor(rss, pts, prm, arena_bytes=need // 4)
+    assert ei.value.name == "RSS_E_ARENA"
+    # the failed factorization released everything: a capped one with enough room and an
+    # uncapped one both work and agree bit for bit
+    b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
+    G = _factor(rss, pts, prm, arena_bytes=4 * need)
+    H = _factor(rss, pts, prm)
+    assert torch.equal(G.solve(b), H.solve(b))
+    G.close()
+    H.close()
+
+
+def test_unsupported_kernels_and_modes(rss):
+    pts = W.grid_points(16)
+    for kw in (dict(kernel="helmholtz2d", kappa=25.0), dict(symmetric=0)):
+        with pytest.raises(rss.RSSError) as ei:
+            _factor(rss, pts, W.problem(16, 1e-6), **kw)
+        assert ei.value.name == "RSS_E_UNSUPPORTED", kw

@@ -337,3 +337,15 @@ def test_gmres_preconditioned_converges():
     x2, it2, rr2 = O.gmres(lambda v: A @ v, lambda v: v, b, rtol=1e-12, restart=40, maxit=400)
     assert rr2 <= 1e-12
     np.testing.assert_allclose(x2, x, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_unpreconditioned_gmres_needs_more_iterations(n):
+    """The GPU tests bound the iterations of GMRES preconditioned by F^{-1} at 2 (FP64) and 3
+    (mixed) for rtol 1e-10 and 1e-12; without the factor GMRES needs more on the same
+    systems, so those bounds fail unless the preconditioner works."""
+    p = _params(n, 1e-6)
+    b = W.rhs(n * n, seed=0)
+    for rtol in (1e-10, 1e-12):
+        _, it, rr = O.gmres(lambda v: O.matvec_grid_fft(n, p, v), lambda v: v, b, rtol=rtol, maxit=100)
+        assert rr <= rtol and it >= 5, (n, rtol, it)
