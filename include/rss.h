@@ -60,6 +60,13 @@ typedef enum { RSS_K_LAPLACE2D = 0, RSS_K_LAPLACE3D = 1, RSS_K_HELMHOLTZ2D = 2 }
 
 typedef enum { RSS_FP64 = 0, RSS_MIXED = 1 } rss_precision;
 
+/* The factorization: RS-S (strong skeletonization at every level, Algorithm 1) or RS-WS
+ * (Section 3.4, Algorithm 2: at every level a weak skeletonization pass, which compresses
+ * each box against everything outside it and eliminates its redundant DOFs against its own
+ * skeleton, then the strong pass on what remains; one more weak pass after the last level,
+ * eq. rws).  RS-WS stores less (Section 3.4). */
+typedef enum { RSS_METHOD_STRONG = 0, RSS_METHOD_HYBRID = 1 } rss_method;
+
 typedef struct {
     uint32_t struct_size;   /* sizeof(rss_params); checked as an ABI guard */
     int32_t  dim;           /* spatial dimension d of the points: 2 */
@@ -77,14 +84,17 @@ typedef struct {
     double   root_lo[3];    /* lower corner of the root box (first dim entries used) */
     double   root_side;     /* side of the root box; <= 0: bounding box of the points */
     int32_t  precision;     /* rss_precision: RSS_MIXED computes the Schur-complement
-                               products in FP32, keeps an FP32 copy of the factor for
-                               rss_solve and, when tol >= 16 * 2^-24 (~9.5e-7), keeps the
-                               block store (the current A_{B_a,B_b} blocks) in FP32; the
-                               ID (double-double Gram and pivoted Cholesky), the
-                               eliminations, the LU factors and the FP64 records stay
-                               FP64.  The factor is then accurate to a few 2^-24;
-                               rss_gmres refines to any rtol */
-    int32_t  reserved;      /* must be 0 */
+                               products between different boxes in FP32, keeps an FP32
+                               copy of the factor for rss_solve and, when tol >= 16 *
+                               2^-24 (~9.5e-7), keeps the blocks A_{B_a,B_b} with a != b
+                               of the block store in FP32.  The self blocks A_{B_a,B_a}
+                               and the skeleton-skeleton products (O(1) entries), the ID
+                               (double-double Gram and pivoted Cholesky), the
+                               eliminations, the LU factors and the records stay FP64, so
+                               |A - F| matches the FP64 factor's; rss_solve with the FP32
+                               copy is accurate to a few 2^-24 and rss_gmres refines to
+                               any rtol */
+    int32_t  method;        /* rss_method */
     uint64_t arena_bytes;   /* 0: no limit; otherwise the most device memory the factor may
                                hold at any time (store, records, workspaces), failing with
                                RSS_E_ARENA (nothing leaked) when the build needs more */
@@ -92,7 +102,7 @@ typedef struct {
 
 /* Fill *p with the defaults for dimension `dim` and kernel `kernel`: diag 1, weight 1,
  * kappa 0, tol 1e-6, leaf 64, 16 proxies at radius 1.25 sides, root box [0,1]^dim,
- * symmetric 1, FP64, no arena limit (Section 4 Example 1 settings, with the leaf size and
+ * symmetric 1, FP64, RS-S, no arena limit (Section 4 Example 1 settings, with the leaf size and
  * proxy count of the workloads here).  Leaves *p untouched when p is NULL. */
 void rss_params_default(rss_params* p, int32_t dim, int32_t kernel);
 
@@ -157,10 +167,12 @@ rss_status rss_shape(rss_factor f, int32_t* depth, int64_t* n_top);
 /* Skeleton and redundant DOFs (host arrays of global indices, ascending) of box `box`
  * (linear index bx + 2^depth * by) at tree depth `depth`: the partition B = S u R that
  * its interpolative decomposition (Section 2.2, Definition 1; Section 3.1 eq. skelid)
- * chose.  A box without redundant DOFs reports all its DOFs as skeleton and *nr = 0.
- * Capacities too small: RSS_E_ARG with the needed sizes in *ns, *nr. */
-rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel, int32_t cap_s,
-                        int32_t* ns, int64_t* red, int32_t cap_r, int32_t* nr);
+ * chose, in the strong step (weak == 0) or, for RS-WS, the weak step (weak == 1,
+ * Section 3.4 eq. weakskel).  A box without redundant DOFs reports all its DOFs as
+ * skeleton and *nr = 0.  Capacities too small: RSS_E_ARG with the needed sizes in *ns,
+ * *nr; no such step: RSS_E_ARG. */
+rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int32_t weak, int64_t* skel,
+                        int32_t cap_s, int32_t* ns, int64_t* red, int32_t cap_r, int32_t* nr);
 
 /* The factored operators of one strong skeletonization step (Section 3.1: eqs. skelid,
  * zab, skelop; the block elimination of Section 2.1 eq. landu with I = R, J = S u N),
@@ -169,13 +181,14 @@ rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel,
  *   h_XRR |R| x |R|  X_RR after the two triangular operations U_T, L_T,
  *   h_XJR |J| x |R|  X_JR (rows S, then the active near field N in box order),
  *   h_G   |R| x |J|  X_RR^{-1} X_RJ,
- *   h_J   |J|        global DOF indices of J in the row order of h_XJR.
+ *   h_J   |J|        global DOF indices of J in the row order of h_XJR;
+ * weak selects the step as for rss_box_sets (a weak step has J = S).
  * *ns, *nr, *nj receive |S|, |R|, |J| (0, 0, 0 when the box has no record); any output
  * pointer may be NULL to skip it, and `cap` is the entries available in each non-NULL
  * array (RSS_E_ARG, nothing copied, when one is too small). */
-rss_status rss_box_record(rss_factor f, int32_t depth, int64_t box, double* h_T, double* h_XRR,
-                          double* h_XJR, double* h_G, int64_t* h_J, int64_t cap, int32_t* ns,
-                          int32_t* nr, int32_t* nj);
+rss_status rss_box_record(rss_factor f, int32_t depth, int64_t box, int32_t weak, double* h_T,
+                          double* h_XRR, double* h_XJR, double* h_G, int64_t* h_J, int64_t cap,
+                          int32_t* ns, int32_t* nr, int32_t* nj);
 
 /* The remaining active DOFs (global indices, ascending) that form the top block B_t of
  * the final factorization (Section 3.3). */

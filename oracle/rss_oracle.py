@@ -22,6 +22,8 @@ its order and notation:
 * log-determinant          -- Section 3.3 (log|D| approximates log|K|)
 * generalized square root  -- Section 3.3, F^{1/2} = (prod V_i) P_t D^{1/2}, with the
                               Cholesky factor of each block of D as D^{1/2}
+* hybrid factorization     -- Section 3.4, eqs. (weakskel), (rws), Algorithm 2 (RS-WS):
+                              at every level a weak pass, then the strong pass
 
 Readings of points the paper leaves open:
 
@@ -40,6 +42,13 @@ Readings of points the paper leaves open:
 * Diagonal blocks X_RR and the top block are factored by LU with partial pivoting.
 * Square root: D^{1/2} = the lower Cholesky factor of each block; the adjoint uses
   W_i for V_i^* (equal for a symmetric positive definite matrix).
+* RS-WS: the weak step of box c compresses its interactions with everything outside it,
+  so its ID input is [A(N u O, B); w*K(Gamma, B)] (the boxes at distance 1 and 2 in
+  ascending box index, then the proxies); after U_T, L_T its redundant DOFs couple only to
+  its skeleton (J = S), and eliminating them updates A(S, S) alone.  Weak and strong passes
+  each run in the colour-major order.  After the strong pass at depth 2 one more weak pass
+  runs at depth 1 (the final weak step Section 3.4 reports using), and the top block is
+  formed from what remains.
 
 parity pinned by tests/test_oracle_*.py (dense operator products, LAPACK pivoted
 QR, brute-force factors at tiny N, closed-form counts).
@@ -70,6 +79,7 @@ class Params:
     proxy_radius: float = 1.25      # in box side lengths
     root_lo: tuple = (0.0, 0.0)
     root_side: float = 1.0          # <= 0: bounding square of the points
+    hybrid: bool = False            # RS-WS (Section 3.4, Algorithm 2) instead of RS-S
 
     @staticmethod
     def from_dict(d: dict) -> "Params":
@@ -292,6 +302,7 @@ class Record:
     E: np.ndarray         # X_JR X_RR^{-1}   (|J| x |R|)
     G: np.ndarray         # X_RR^{-1} X_RJ   (|R| x |J|)
     XRR: np.ndarray       # X_RR itself (for apply)
+    kind: str = "strong"  # "weak" for the weak steps of RS-WS (J = S)
 
 
 @dataclass
@@ -306,6 +317,7 @@ class Factor:
     A_top: np.ndarray
     skeletons: dict = field(default_factory=dict)   # (depth, box) -> (S, R) global indices
     level_stats: list = field(default_factory=list)
+    weak_skeletons: dict = field(default_factory=dict)   # RS-WS: (depth, box) -> (S, R) of the weak step
 
 
 def _lu(X: np.ndarray):
@@ -447,6 +459,57 @@ def _skeletonize_box(lev: _Level, c: int, pts, p: Params):
     return Record(depth=lev.t, box=c, R=R, S=S, J=J, T=T, lu=lu, piv=piv, E=E, G=G, XRR=X_RR)
 
 
+def _weak_skeletonize_box(lev: _Level, c: int, pts, p: Params):
+    """Weak skeletonization of the active DOFs of box c (Section 3.4, eq. weakskel)."""
+    nb = lev.nb
+    Bc = lev.B[c]
+    if len(Bc) == 0:
+        return None
+    near = sorted(ring(c, nb, 1) + ring(c, nb, 2))
+    rows = [lev.store[(o, c)] for o in near]
+    rows.append(kernel_block(proxy_points(c, lev.t, lev.tree, p), pts[Bc], p))
+    M = np.vstack(rows)
+    spos, rpos, T = id_sorted(cpqr_id(M, p.tol))
+    if len(rpos) == 0:
+        return None
+    S, R = Bc[spos], Bc[rpos]
+    Acc = lev.store[(c, c)]
+    A_RR, A_RS = Acc[np.ix_(rpos, rpos)], Acc[np.ix_(rpos, spos)]
+    A_SR, A_SS = Acc[np.ix_(spos, rpos)], Acc[np.ix_(spos, spos)]
+    # U_T, L_T; every interaction of R outside the box is the compressed part, dropped
+    Z_R = A_RR - A_RS @ T
+    Z_S = A_SR - A_SS @ T
+    X_RR = Z_R - T.T @ Z_S
+    X_RS = A_RS - T.T @ A_SS
+    X_SR = Z_S
+    # block elimination with I = R, J = S
+    lu, piv = _lu(X_RR)
+    G = sla.lu_solve((lu, piv), X_RS, check_finite=False)
+    E = sla.lu_solve((lu, piv), X_SR.T, trans=1, check_finite=False).T
+    lev.store[(c, c)][np.ix_(spos, spos)] -= X_SR @ G
+    for d in range(3):
+        for b in ([c] if d == 0 else ring(c, nb, d)):
+            if b == c:
+                lev.store[(c, c)] = lev.store[(c, c)][np.ix_(spos, spos)]
+            else:
+                lev.store[(c, b)] = lev.store[(c, b)][spos, :]
+                lev.store[(b, c)] = lev.store[(b, c)][:, spos]
+    lev.B[c] = S
+    return Record(depth=lev.t, box=c, R=R, S=S, J=np.asarray(S, dtype=np.int64), T=T, lu=lu, piv=piv, E=E, G=G,
+                  XRR=X_RR, kind="weak")
+
+
+def _weak_pass(lev: _Level, pts, p: Params, records: list, weak_skeletons: dict):
+    for c in level_order(lev.nb):
+        before = lev.B[c]
+        rec = _weak_skeletonize_box(lev, c, pts, p)
+        if rec is not None:
+            records.append(rec)
+            weak_skeletons[(lev.t, c)] = (rec.S, rec.R)
+        else:
+            weak_skeletons[(lev.t, c)] = (before, np.zeros(0, dtype=np.int64))
+
+
 def factor(pts: np.ndarray, params, hook=None) -> Factor:
     """RS-S factorization F ~ A (Algorithm 1).
 
@@ -463,10 +526,13 @@ def factor(pts: np.ndarray, params, hook=None) -> Factor:
     lev = _leaf_level(tree, pts, p)
     records = []
     skeletons = {}
+    weak_skeletons = {}
     stats = []
     while lev.t >= 2:
         if hook is not None:
             hook(lev.t, lev.B, lev.store)
+        if p.hybrid:
+            _weak_pass(lev, pts, p, records, weak_skeletons)
         nrec = 0
         for c in level_order(lev.nb):
             before = lev.B[c]
@@ -482,6 +548,10 @@ def factor(pts: np.ndarray, params, hook=None) -> Factor:
         if lev.t == 2:
             break
         lev = _parent_level(lev, pts, p)
+    if p.hybrid and tree.depth >= 2:
+        # the final weak step at depth 1 (Section 3.4)
+        lev = _parent_level(lev, pts, p)
+        _weak_pass(lev, pts, p, records, weak_skeletons)
     # Top block: all remaining active DOFs (Section 3.3, the final factorization).
     top = np.sort(np.concatenate(lev.B)).astype(np.int64)
     A_top = np.empty((len(top), len(top)))
@@ -493,7 +563,7 @@ def factor(pts: np.ndarray, params, hook=None) -> Factor:
     top_lu, top_piv = _lu(A_top) if len(top) else (np.zeros((0, 0)), np.zeros(0, dtype=np.int32))
     return Factor(n=len(pts), params=p, depth=tree.depth, records=records, top=top,
                   top_lu=top_lu, top_piv=top_piv, A_top=A_top, skeletons=skeletons,
-                  level_stats=stats)
+                  level_stats=stats, weak_skeletons=weak_skeletons)
 
 
 # --------------------------------------------------------------------------

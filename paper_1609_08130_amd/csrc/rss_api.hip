@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 #include <string>
@@ -20,6 +21,51 @@
 
 namespace rss {
 int elim_lds_limit();
+
+#include "tuned_plans.inc"
+
+static std::mutex g_plan_mu;
+static PlanParams g_plan[kPlanBuckets];
+static bool g_plan_ready = false;
+
+void reload_plan_overrides() {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (int b = 0; b < kPlanBuckets; ++b) g_plan[b] = kPlanTable[b];
+    const char* env = std::getenv("RSS_TUNE");
+    if (env) {
+        std::string all(env);
+        size_t pos = 0;
+        while (pos < all.size()) {
+            size_t end = all.find(',', pos);
+            if (end == std::string::npos) end = all.size();
+            const std::string item = all.substr(pos, end - pos);
+            pos = end + 1;
+            const size_t dot = item.find('.'), eq = item.find('=');
+            if (item.size() < 4 || item[0] != 'b' || dot == std::string::npos || eq == std::string::npos || eq < dot)
+                continue;
+            const int b = std::atoi(item.substr(1, dot - 1).c_str());
+            if (b < 0 || b >= kPlanBuckets) continue;
+            const std::string key = item.substr(dot + 1, eq - dot - 1);
+            const int v = std::atoi(item.substr(eq + 1).c_str());
+            PlanParams& q = g_plan[b];
+            if (key == "gram_many") q.gram_many = v != 0;
+            else if (key == "gram_min_wg" && v > 0) q.gram_min_wg = v;
+            else if (key == "pchol_kc" && v >= 0) q.pchol_kc = v;
+            else if (key == "elim_tpw" && v >= 1 && v <= 8) q.elim_tpw = v;
+            else if (key == "elim_tw" && (v == 4 || v == 8 || v == 16 || v == 32)) q.elim_tw = v;
+            else if (key == "inv_threads" && (v == 256 || v == 1024)) q.inv_threads = v;
+            else if (key == "sweep_threads" && (v == 256 || v == 1024)) q.sweep_threads = v;
+        }
+    }
+    g_plan_ready = true;
+}
+
+PlanParams plan_params(int nboxes) {
+    if (!g_plan_ready) reload_plan_overrides();
+    int b = 0;
+    while (b + 1 < kPlanBuckets && nboxes >= kPlanBucketLo[b + 1]) ++b;
+    return g_plan[b];
+}
 
 static thread_local std::vector<std::string>* g_shape_log = nullptr;
 
@@ -279,6 +325,7 @@ void alloc_level_lists(rss_factor f, rss::Level& L) {
     L.nact = dalloc<int>(f, L.nbox);
     L.apos = dalloc<int>(f, (size_t)L.nbox * L.nmax);
     L.store = dalloc<unsigned char>(f, L.store_bytes());
+    if (L.store32) L.dstore = dalloc<double>(f, (size_t)L.nbox * L.nmax * L.nmax);
 }
 
 void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
@@ -309,6 +356,8 @@ void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
 void free_store(rss_factor f, rss::Level& L) {
     dfree(f, L.store, L.store_bytes());
     L.store = nullptr;
+    if (L.dstore) dfree(f, L.dstore, L.dstore_bytes());
+    L.dstore = nullptr;
 }
 
 struct EvTimer {
@@ -347,8 +396,11 @@ void destroy_all(rss_factor f) {
 }
 
 // phase indices of rss_factor_s::phase_ms
-enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
-const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "transition", "top", "total"};
+// schur: the Schur-update launches with the factorization's product type; schur_sxs: the
+// FP64 launches of the S x S tiles of a mixed factorization
+enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_SCHUR_SXS, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
+const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "schur_sxs", "transition", "top",
+                                "total"};
 
 void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     const rss_params& p = f->params;
@@ -449,8 +501,17 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     int* tl_cnt = nullptr;
     int* tl_tiles = nullptr;
     size_t tl_n = 0;
+    int* tl64_cnt = nullptr;     // mixed: lists of the S x S tiles
+    int* tl64_tiles = nullptr;
 
-    while (L.t >= 2) {
+    // One pass over the colours of level L: the ID, elimination and Schur launches of every
+    // colour (strong skeletonization, or with weak = 1 the weak skeletonization of RS-WS),
+    // then one synchronization for the flags, the statistics and the solve schedule.
+    auto run_pass = [&](rss::Level& L, int weak) {
+        L.weak = weak;
+        if (weak) L.ldJ = L.nmax;   // J = S
+        rss::KernelParams kpw = f->kp;
+        kpw.weak = weak;
         const int nb = L.nb;
         L.colour_boxes.assign(9, {});
         for (int b = 0; b < L.nbox; ++b) L.colour_boxes[colour_of(b, nb)].push_back(b);
@@ -458,7 +519,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (auto& v : L.colour_boxes) maxc = std::max(maxc, v.size());
         L.d_colour_boxes = h2d_lists(f, L.colour_boxes, s);
         alloc_level_records(f, L, mixed);
-        size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc));
+        size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc, weak));
         if (need > work_n) {
             if (work) defer_free(f, work, work_n * sizeof(double));
             work = dalloc<double>(f, need);
@@ -470,30 +531,46 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         if (maxc >= ((size_t)1 << 19)) fail(RSS_E_UNSUPPORTED, "more than 2^19 boxes in one colour of a level");
         const int capx = rss::schur_tile_capx((int)maxc, L.ldJ);
         if (!tl_cnt) tl_cnt = dalloc<int>(f, 9 * 8);
+        if (mixed && !tl64_cnt) tl64_cnt = dalloc<int>(f, 9 * 8);
         if ((size_t)capx * 8 > tl_n) {
             if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
+            if (tl64_tiles) defer_free(f, tl64_tiles, tl_n * sizeof(int));
             tl_n = (size_t)capx * 8;
             tl_tiles = dalloc<int>(f, tl_n);
+            if (mixed) tl64_tiles = dalloc<int>(f, tl_n);
         }
         HIPCHK(hipMemsetAsync(tl_cnt, 0, sizeof(int) * 9 * 8, s));
+        if (mixed) HIPCHK(hipMemsetAsync(tl64_cnt, 0, sizeof(int) * 9 * 8, s));
         std::vector<hipEvent_t> ev;
         ev.push_back(evs.rec(s));
         for (int col = 0; col < 9; ++col) {
             int nbx = (int)L.colour_boxes[col].size();
             if (nbx == 0) continue;
             const int* bx = L.d_colour_boxes[col];
-            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, f->kp, work, s);
+            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            rss::TileList tl;
+            rss::TileList tl, tl64;
             tl.cnt = tl_cnt + 8 * col;
             tl.tiles = tl_tiles;
             tl.capx = capx;
-            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, work, f->flag, tl, s);
+            if (mixed) {
+                tl64.cnt = tl64_cnt + 8 * col;
+                tl64.tiles = tl64_tiles;
+                tl64.capx = capx;
+            }
+            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, tl64, s);
             if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
             check_launch();
             ev.push_back(evs.rec(s));
-            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, tl, s) < 0)
+            // mixed: the S x S tiles in FP64 first (their own event pair), then the rest
+            if (mixed) {
+                if (rss::launch_schur(L, bx, nbx, L.nmax, 1, 1, tl64, s) < 0) fail(RSS_E_DEVICE, "Schur tile list too small");
+                check_launch();
+                f->kernel_launches[PH_SCHUR_SXS] += 1;
+            }
+            ev.push_back(evs.rec(s));
+            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, 0, tl, s) < 0)
                 fail(RSS_E_DEVICE, "Schur tile list too small");
             check_launch();
             ev.push_back(evs.rec(s));
@@ -505,15 +582,17 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         const size_t nbx = (size_t)L.nbox;
         auto hv = d2h_many(f, {{f->flag, 1}, {L.cnt, nbx}, {L.krank, nbx}, {L.nJ, nbx}, {L.mrows, nbx}, {L.nact, nbx}},
                            s);
-        double lv_id = 0, lv_elim = 0, lv_schur = 0;
-        for (size_t i = 1; i < ev.size(); i += 3) {
+        double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_sxs = 0;
+        for (size_t i = 1; i < ev.size(); i += 4) {
             lv_id += ev_ms(ev[i - 1], ev[i]);
             lv_elim += ev_ms(ev[i], ev[i + 1]);
-            lv_schur += ev_ms(ev[i + 1], ev[i + 2]);
+            lv_sxs += ev_ms(ev[i + 1], ev[i + 2]);
+            lv_schur += ev_ms(ev[i + 2], ev[i + 3]);
         }
         f->phase_ms[PH_ID] += lv_id;
         f->phase_ms[PH_ELIM] += lv_elim;
         f->phase_ms[PH_SCHUR] += lv_schur;
+        f->phase_ms[PH_SCHUR_SXS] += lv_sxs;
         if (first_sync) {
             first_sync = false;
             f->phase_ms[PH_TREE] += ev_ms(e0, e1);
@@ -537,8 +616,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
                 if (hJ[b] > 0) L.rec_boxes[col].push_back(b);
         L.d_rec_boxes = h2d_lists(f, L.rec_boxes, s);
         rss::LevelStats st;
-        st.depth = L.t; st.boxes = L.nbox; st.nmax = L.nmax;
-        st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur;
+        st.depth = L.t; st.weak = weak; st.boxes = L.nbox; st.nmax = L.nmax;
+        st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_sxs = lv_sxs;
         for (int b = 0; b < L.nbox; ++b) {
             double n = L.h_cnt[b], k = L.h_k[b], r = n - k, J = hJ[b], m = hm[b];
             if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
@@ -550,16 +629,26 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             st.flops_x += 4.0 * J * r * k + 4.0 * r * r * k;
             st.flops_lu += 2.0 / 3.0 * r * r * r;
             st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
-            st.flops_schur += 2.0 * J * J * r;
-            st.bytes_schur += (L.store32 ? 8.0 : 16.0) * J * J + (mixed ? 4.0 : 8.0) * 2.0 * J * r;
+            // target read + write of the store entries and the two operands once
+            if (mixed) {
+                // S x S in FP64 (its own launch), the rest with FP32 products
+                st.flops_schur_sxs += 2.0 * k * k * r;
+                st.bytes_schur_sxs += 16.0 * k * k + 8.0 * 2.0 * k * r;
+                st.flops_schur += 2.0 * (J * J - k * k) * r;
+                st.bytes_schur += (L.store32 ? 8.0 : 16.0) * (J * J - k * k) + 4.0 * 2.0 * J * r;
+            } else {
+                st.flops_schur += 2.0 * J * J * r;
+                st.bytes_schur += 16.0 * J * J + 8.0 * 2.0 * J * r;
+            }
             st.bytes_solve64 += 8.0 * (2.0 * J * r + 2.0 * k * r + r * r);
             st.bytes_solve32 += 4.0 * (2.0 * J * r + 2.0 * k * r + r * r);
         }
         f->stats.push_back(st);
+    };
 
-        if (L.t == 2) break;
-
-        // level transition
+    // Level transition to the parent level (B_parent = union of the children's active DOFs);
+    // L goes to the factor's levels.
+    auto transition = [&](rss::Level& L) -> rss::Level {
         hipEvent_t et0 = evs.rec(s);
         rss::Level P;
         P.t = L.t - 1; P.nb = L.nb / 2; P.nbox = P.nb * P.nb;
@@ -584,6 +673,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         P.apos = dalloc<int>(f, (size_t)P.nbox * P.nmax);
         P.store32 = L.store32;
         P.store = dalloc<unsigned char>(f, P.store_bytes());
+        if (P.store32) P.dstore = dalloc<double>(f, (size_t)P.nbox * P.nmax * P.nmax);
         int* pmap = dalloc<int>(f, (size_t)P.nbox * P.nmax);
         rss::launch_parent_lists(L, P, pmap, s);
         check_launch();
@@ -595,12 +685,63 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         defer_free(f, pmap, sizeof(int) * (size_t)P.nbox * P.nmax);
         defer_free(f, L.store, L.store_bytes());
         L.store = nullptr;
+        if (L.dstore) defer_free(f, L.dstore, L.dstore_bytes());
+        L.dstore = nullptr;
         f->levels.push_back(std::move(L));
-        L = std::move(P);
+        return P;
+    };
+
+    // RS-WS: the strong pass of a level restarts on the DOFs its weak pass left active (the
+    // lists and the store compacted at the same depth); L, with the weak records, goes to
+    // the factor's levels.
+    auto compact = [&](rss::Level& L) -> rss::Level {
+        hipEvent_t ec0 = evs.rec(s);
+        rss::Level C;
+        C.t = L.t; C.nb = L.nb; C.nbox = L.nbox;
+        int cmax = 1;
+        for (int v : last_nact) cmax = std::max(cmax, v);
+        C.nmax = cmax;
+        C.ldJ = 9 * C.nmax;
+        C.store32 = L.store32;
+        C.cnt = h2d(f, last_nact, s);
+        C.gidx = dalloc<int>(f, (size_t)C.nbox * C.nmax);
+        C.nact = dalloc<int>(f, C.nbox);
+        C.apos = dalloc<int>(f, (size_t)C.nbox * C.nmax);
+        C.store = dalloc<unsigned char>(f, C.store_bytes());
+        if (C.store32) C.dstore = dalloc<double>(f, (size_t)C.nbox * C.nmax * C.nmax);
+        rss::launch_compact(L, C, s);
+        check_launch();
+        init_active(C, s);
+        et_pend0 = ec0;
+        et_pend1 = evs.rec(s);
+        defer_free(f, L.store, L.store_bytes());
+        L.store = nullptr;
+        if (L.dstore) defer_free(f, L.dstore, L.dstore_bytes());
+        L.dstore = nullptr;
+        f->levels.push_back(std::move(L));
+        return C;
+    };
+
+    const bool hybrid = p.method == RSS_METHOD_HYBRID;
+    while (L.t >= 2) {
+        if (hybrid) {
+            run_pass(L, 1);
+            L = compact(L);
+        }
+        run_pass(L, 0);
+        if (L.t == 2) break;
+        L = transition(L);
+    }
+    if (hybrid && L.t == 2) {
+        // the final weak step at depth 1 (Section 3.4)
+        L = transition(L);
+        run_pass(L, 1);
     }
     if (work) dfree(f, work, work_n * sizeof(double));
     if (tl_tiles) dfree(f, tl_tiles, tl_n * sizeof(int));
     if (tl_cnt) dfree(f, tl_cnt, sizeof(int) * 9 * 8);
+    if (tl64_tiles) dfree(f, tl64_tiles, tl_n * sizeof(int));
+    if (tl64_cnt) dfree(f, tl64_cnt, sizeof(int) * 9 * 8);
     if (first_sync) {
         // no skeletonized level (depth <= 1): the flag, the phase times and the active
         // counts of the leaves are read here
@@ -754,7 +895,7 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
         g_err = "the two-sided ID of a non-symmetric kernel (symmetric = 0) is not built";
         return RSS_E_UNSUPPORTED;
     }
-    if (p->reserved != 0) { g_err = "rss_params.reserved must be 0"; return RSS_E_ARG; }
+    if (p->method != RSS_METHOD_STRONG && p->method != RSS_METHOD_HYBRID) { g_err = "bad method"; return RSS_E_ARG; }
     if (n < 1 || n > (int64_t)1 << 30) { g_err = "n out of range"; return RSS_E_ARG; }
     if (!(p->tol >= 0.0) || !std::isfinite(p->tol)) { g_err = "tol must be finite and >= 0"; return RSS_E_ARG; }
     if (p->leaf_size < 1 || p->leaf_size > rss::kMaxBox) { g_err = "leaf_size must be in [1, 256]"; return RSS_E_ARG; }
@@ -778,6 +919,7 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     hipStream_t s = (hipStream_t)stream;
     f->stream = s;
     rss::ShapeLogScope shape_scope(f);
+    rss::reload_plan_overrides();
     try {
         factor_impl(f, d_points, s);
     } catch (const Fail& e) {
@@ -1141,13 +1283,13 @@ rss_status rss_shape(rss_factor f, int32_t* depth, int64_t* n_top) {
     return RSS_OK;
 }
 
-rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel, int32_t cap_s, int32_t* ns,
-                        int64_t* red, int32_t cap_r, int32_t* nr) {
+rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int32_t weak, int64_t* skel, int32_t cap_s,
+                        int32_t* ns, int64_t* red, int32_t cap_r, int32_t* nr) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
     const rss::Level* L = nullptr;
     for (auto& l : f->levels)
-        if (l.t == depth) L = &l;
+        if (l.t == depth && l.weak == (weak ? 1 : 0)) L = &l;
     if (!L || box < 0 || box >= L->nbox || !ns || !nr) {
         g_err = "no skeletonized level / box with these indices";
         return RSS_E_ARG;
@@ -1179,13 +1321,14 @@ rss_status rss_box_sets(rss_factor f, int32_t depth, int64_t box, int64_t* skel,
     return RSS_OK;
 }
 
-rss_status rss_box_record(rss_factor f, int32_t depth, int64_t box, double* h_T, double* h_XRR, double* h_XJR,
-                          double* h_G, int64_t* h_J, int64_t cap, int32_t* ns, int32_t* nr, int32_t* nj) {
+rss_status rss_box_record(rss_factor f, int32_t depth, int64_t box, int32_t weak, double* h_T, double* h_XRR,
+                          double* h_XJR, double* h_G, int64_t* h_J, int64_t cap, int32_t* ns, int32_t* nr,
+                          int32_t* nj) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
     const rss::Level* L = nullptr;
     for (auto& l : f->levels)
-        if (l.t == depth) L = &l;
+        if (l.t == depth && l.weak == (weak ? 1 : 0)) L = &l;
     if (!L || box < 0 || box >= L->nbox || !ns || !nr || !nj) {
         g_err = "no skeletonized level / box with these indices";
         return RSS_E_ARG;
@@ -1251,6 +1394,7 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     o.precision(17);
     o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
       << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
+      << ",\"method\":\"" << (f->params.method == RSS_METHOD_HYBRID ? "rs-ws" : "rs-s") << "\""
       << ",\"exact_operator\":\"" << (f->fft.ready ? "fft" : "direct") << "\""
       << ",\"bytes_device\":" << f->bytes_device << ",\"lds_limit\":" << rss::elim_lds_limit() << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
@@ -1261,14 +1405,16 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     o << "],\"levels\":[";
     for (size_t i = 0; i < f->stats.size(); ++i) {
         const auto& s = f->stats[i];
-        o << (i ? "," : "") << "{\"depth\":" << s.depth << ",\"boxes\":" << s.boxes << ",\"nmax\":" << s.nmax
+        o << (i ? "," : "") << "{\"depth\":" << s.depth << ",\"pass\":\"" << (s.weak ? "weak" : "strong")
+          << "\",\"boxes\":" << s.boxes << ",\"nmax\":" << s.nmax
           << ",\"records\":" << s.records << ",\"sum_k\":" << s.sum_k << ",\"sum_r\":" << s.sum_r
           << ",\"sum_J\":" << s.sum_J << ",\"max_k\":" << s.max_k << ",\"max_J\":" << s.max_J
           << ",\"flops_id\":" << s.flops_id << ",\"flops_x\":" << s.flops_x << ",\"flops_lu\":" << s.flops_lu
           << ",\"flops_g\":" << s.flops_g << ",\"flops_schur\":" << s.flops_schur
           << ",\"bytes_schur\":" << s.bytes_schur << ",\"bytes_solve64\":" << s.bytes_solve64
           << ",\"bytes_solve32\":" << s.bytes_solve32 << ",\"ms_id\":" << s.ms_id << ",\"ms_elim\":" << s.ms_elim
-          << ",\"ms_schur\":" << s.ms_schur << "}";
+          << ",\"ms_schur\":" << s.ms_schur << ",\"flops_schur_sxs\":" << s.flops_schur_sxs
+          << ",\"bytes_schur_sxs\":" << s.bytes_schur_sxs << ",\"ms_schur_sxs\":" << s.ms_schur_sxs << "}";
     }
     o << "]}";
     std::string js = o.str();

@@ -24,9 +24,13 @@ namespace rss {
 
 struct ElimArgs {
     const void* store;   // FP64 or FP32 entries (the kernels' ST)
+    const double* dstore;   // self blocks of an FP32 store (FP64), or nullptr
     int* tl_cnt;         // Schur tile lists of the colour (TileList)
     int* tl_tiles;
     int tl_capx;
+    int* tl64_cnt;       // mixed precision: the S x S tiles (FP64 products), or nullptr
+    int* tl64_tiles;
+    int tl64_capx;
     int nb, nmax, ldJ;
     const int* cnt;
     const int* gidx;
@@ -51,6 +55,7 @@ struct ElimArgs {
     double* logdet_part;
     int* sign_part;
     int* flag;           // error and status bits (bit 64: the LDS Gauss-Jordan ran)
+    int weak;            // RS-WS weak pass: J = S (no adjacent boxes)
 };
 
 constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
@@ -112,9 +117,25 @@ struct ElimShared {
     int nbox[8];
     int joff[9];                    // J segments: [0, k) is S, then one per adjacent box
     int nN;
-    const ST* srcp[kTileMax];       // source block and row/column of each tile line
+    const void* srcp[kTileMax];     // source block and row/column of each tile line ...
     int srcpos[kTileMax];
+    unsigned char src64[kTileMax];  // ... and whether that block holds FP64 entries
 };
+
+// Entry idx of the source block of tile line `line`.
+template <typename ST>
+__device__ inline double src_entry(const ElimShared<ST>& sh, int line, int64_t idx) {
+    return sh.src64[line] ? ((const double*)sh.srcp[line])[idx] : (double)((const ST*)sh.srcp[line])[idx];
+}
+
+// The self block A(B_c, B_c): in the FP64 array when the store is FP32 and has one.
+template <typename ST>
+__device__ inline const void* self_block(const ElimArgs& a, int c, bool& is64) {
+    const int64_t bsz = (int64_t)a.nmax * a.nmax;
+    is64 = a.dstore != nullptr || sizeof(ST) == 8;
+    if (a.dstore) return a.dstore + (int64_t)c * bsz;
+    return (const ST*)a.store + ((int64_t)c * kNbr + 12) * bsz;
+}
 
 // sp, rp, the adjacent-box tables and T (Ts[b + r q] = T[q][b]).  The caller synchronizes.
 template <int NTH, typename ST>
@@ -130,7 +151,7 @@ __device__ void elim_setup(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, 
         const int t = tid < 4 ? tid : tid + 1;
         const int dx = t % 3 - 1, dy = t / 3 - 1;
         const int ox = cx + dx, oy = cy + dy;
-        const bool in = ox >= 0 && oy >= 0 && ox < nb && oy < nb;
+        const bool in = !a.weak && ox >= 0 && oy >= 0 && ox < nb && oy < nb;
         sh.nbox[tid] = in ? ox + nb * oy : -1;
         sh.srcpos[tid] = in ? a.nact[ox + nb * oy] : 0;
     }
@@ -174,19 +195,23 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
                                int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
     const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int n = k + r;
-    const ST* Acc = (const ST*)a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    bool acc64;
+    const void* Acc = self_block<ST>(a, c, acc64);
     if (tid < tr) {
         const int jj = r0 + tid;
         if (jj < k) {
             sh.srcp[tid] = Acc;
+            sh.src64[tid] = acc64;
             sh.srcpos[tid] = sh.sp[jj];
         } else if (jj < nj) {
             int s = 0;
             while (sh.joff[s + 1] <= jj) ++s;
             sh.srcp[tid] = sh.blk_nc[s];
+            sh.src64[tid] = sizeof(ST) == 8;
             sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
         } else {
             sh.srcp[tid] = Acc;
+            sh.src64[tid] = acc64;
             sh.srcpos[tid] = sh.rp[jj - nj];
         }
     }
@@ -196,7 +221,7 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
         tr, n,
         [&](int i, int col) {
             const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
-            return (double)sh.srcp[i][sh.srcpos[i] + (int64_t)pos * nmax];
+            return src_entry(sh, i, sh.srcpos[i] + (int64_t)pos * nmax);
         },
         [&](int i, int col, double v) { tA[i + tw * col] = v; });
     __syncthreads();
@@ -252,16 +277,19 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
     const int tid = threadIdx.x, nmax = a.nmax;
     const int n = k + r;
     const int lane = tid & 63, jg = tid >> 6;
-    const ST* Acc = (const ST*)a.store + ((int64_t)c * kNbr + 12) * (int64_t)nmax * nmax;
+    bool acc64;
+    const void* Acc = self_block<ST>(a, c, acc64);
     if (tid < tc) {
         const int jj = c0 + tid;
         if (jj < k) {
             sh.srcp[tid] = Acc;
+            sh.src64[tid] = acc64;
             sh.srcpos[tid] = sh.sp[jj];
         } else {
             int s = 0;
             while (sh.joff[s + 1] <= jj) ++s;
             sh.srcp[tid] = sh.blk_cn[s];
+            sh.src64[tid] = sizeof(ST) == 8;
             sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
         }
     }
@@ -274,7 +302,7 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
         n, tc,
         [&](int rho, int jp) {
             const int pos = rho < k ? sh.sp[rho] : sh.rp[rho - k];
-            return (double)sh.srcp[jp][pos + (int64_t)sh.srcpos[jp] * nmax];
+            return src_entry(sh, jp, pos + (int64_t)sh.srcpos[jp] * nmax);
         },
         [&](int rho, int jp, double v) { tA[rho + ldt * jp] = v; });
     __syncthreads();
@@ -755,7 +783,7 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
         // lie beyond it leave before the set-up
         const int nb = a.nb, cx = c % nb, cy = c / nb;
         int njr = k + r;
-        for (int t = 0; t < 9; ++t) {
+        for (int t = 0; t < (a.weak ? 0 : 9); ++t) {
             const int ox = cx + t % 3 - 1, oy = cy + t / 3 - 1;
             if (t != 4 && ox >= 0 && oy >= 0 && ox < nb && oy < nb) njr += a.nact[ox + nb * oy];
         }
@@ -817,13 +845,29 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     }
     for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
     if (tid < 64) {
-        // the box's ceil(|J| / 64)^2 Schur tiles, appended to the list of its XCD by wave 0
+        // the box's ceil(|J| / 64)^2 Schur tiles, appended to the lists of its XCD by wave 0;
+        // in mixed precision the ns1 x ns1 tiles that cover S x S go to the FP64 list
         const int nt1 = (nj + 63) >> 6, ntl = nt1 * nt1, x = blockIdx.x & 7;
-        int off = 0;
-        if (tid == 0) off = atomicAdd(a.tl_cnt + x, ntl);
+        const int ns1 = a.tl64_cnt ? (k + 63) >> 6 : 0, n64 = ns1 * ns1;
+        int off = 0, off64 = 0;
+        if (tid == 0) {
+            off = atomicAdd(a.tl_cnt + x, ntl - n64);
+            if (n64) off64 = atomicAdd(a.tl64_cnt + x, n64);
+        }
         off = __shfl(off, 0, 64);
+        off64 = __shfl(off64, 0, 64);
         int* lst = a.tl_tiles + (int64_t)x * a.tl_capx + off;
-        for (int t = tid; t < ntl; t += 64) lst[t] = ((int)blockIdx.x << 12) | ((t % nt1) << 6) | (t / nt1);
+        for (int t = tid; t < ntl; t += 64) {
+            const int ti = t % nt1, tj = t / nt1;
+            const int ent = ((int)blockIdx.x << 12) | (ti << 6) | tj;
+            if (ti < ns1 && tj < ns1) {
+                a.tl64_tiles[(int64_t)x * a.tl64_capx + off64 + ti + ns1 * tj] = ent;
+            } else {
+                // position among the tiles outside the ns1 x ns1 corner, in the order of t
+                const int before = min(tj, ns1) * ns1 + (tj < ns1 ? min(ti, ns1) : 0);
+                lst[t - before] = ent;
+            }
+        }
     }
 }
 
@@ -864,7 +908,7 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
 // Tiles of one box handled in turn by one workgroup of the row and column tile kernels:
 // several when the launch has work groups to spare (the per-box setup is then paid once
 // for them), one otherwise so that small colours still spread over all compute units.
-static int tiles_per_wg(int ntile, int nboxes) { return nboxes >= 1024 ? min(ntile, 4) : 1; }
+static int tiles_per_wg(int ntile, int nboxes) { return min(ntile, plan_params(nboxes).elim_tpw); }
 
 static int g_max_lds = -1;
 
@@ -886,12 +930,14 @@ static void set_lds(K kernel, size_t bytes) {
 }
 
 template <typename ST>
-static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag,
-                         const TileList& tl, hipStream_t s) {
+static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
+                         const TileList& tl, const TileList& tl64, hipStream_t s) {
     if (nboxes <= 0) return 0;
     ElimArgs a;
+    a.weak = weak;
     a.tl_cnt = tl.cnt; a.tl_tiles = tl.tiles; a.tl_capx = tl.capx;
-    a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
+    a.tl64_cnt = tl64.cnt; a.tl64_tiles = tl64.tiles; a.tl64_capx = tl64.capx;
+    a.store = L.store; a.dstore = L.dstore; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;
     a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
     a.XJR = L.XJR; a.G = L.G; a.XRR = L.XRR; a.Xinv = L.Xinv;
@@ -909,8 +955,9 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     };
     // at most 16 lines per tile: the smaller LDS footprint keeps more workgroups per CU,
     // which measured faster than 32-line tiles (leaf colours: 8.4 -> 8.0 ms per level)
-    const int twr = std::min(16, tile_w(tsz, 1));
-    const int twg = std::min(16, tile_w(tsz + 2 * kTileMax, 2));   // column tiles: ld nmax + 1
+    const PlanParams pp = plan_params(nboxes);
+    const int twr = std::min(pp.elim_tw, tile_w(tsz, 1));
+    const int twg = std::min(pp.elim_tw, tile_w(tsz + 2 * kTileMax, 2));   // column tiles: ld nmax + 1
     if (twr == 0 || twg == 0) return -1;
     const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * (nm + 1) * twg);
     set_lds(k_elim_rows<256, ST>, lr);
@@ -922,13 +969,14 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     const size_t base = tsz + 4 * nm;
     // X_RR in LDS only for the LDS Gauss-Jordan: not when every r fits the register form
     // (r <= nmax <= 64 with 256 threads, <= 128 with 1024)
-    const bool reg_only = nboxes >= 256 ? L.nmax <= 64 : L.nmax <= 128;
+    const bool wide_inv = pp.inv_threads == 1024;
+    const bool reg_only = wide_inv ? L.nmax <= 128 : L.nmax <= 64;
     const bool xl = !reg_only && D * (base + nm * nm) <= lim;
     const int zs = D * (base + tsz + (xl ? nm * nm : 0)) <= lim ? 1 : 0;
     const size_t li = D * (base + (zs ? tsz : 0) + (xl ? nm * nm : 0));
     // many boxes: small workgroups, several per CU; few boxes: one large workgroup each
-    note_shape(std::string("elim_inv_") + (nboxes >= 256 ? "256" : "1024") + (xl ? "_xlds" : "") + (zs ? "_zs" : ""));
-    if (nboxes >= 256) {
+    note_shape(std::string("elim_inv_") + (wide_inv ? "1024" : "256") + (xl ? "_xlds" : "") + (zs ? "_zs" : ""));
+    if (!wide_inv) {
         if (xl) {
             set_lds(k_elim_inv<true, 256, ST>, li);
             k_elim_inv<true, 256, ST><<<dim3(nboxes), dim3(256), li, s>>>(a, boxes, mixed, work, flag, (int)tsz, zs);
@@ -961,10 +1009,10 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     return 3;
 }
 
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, const TileList& tl,
-                hipStream_t s) {
-    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, work, flag, tl, s)
-                     : launch_elim_t<double>(L, boxes, nboxes, mixed, work, flag, tl, s);
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
+                const TileList& tl, const TileList& tl64, hipStream_t s) {
+    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, weak, work, flag, tl, tl64, s)
+                     : launch_elim_t<double>(L, boxes, nboxes, mixed, weak, work, flag, tl, tl64, s);
 }
 
 }  // namespace rss

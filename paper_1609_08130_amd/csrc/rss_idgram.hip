@@ -127,11 +127,13 @@ struct GramPlan {
     int slice_rows, nsl, groups, tpt, nth;
 };
 
-static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes) {
-    const int mmax = 16 * nmax + n_proxy;   // rows of M: <= 16 boxes at distance 2, plus proxies
+static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes, int weak) {
+    // rows of M: <= 16 boxes at distance 2 (24 at distance 1 or 2 in a weak pass), plus proxies
+    const int mmax = (weak ? 24 : 16) * nmax + n_proxy;
     const int nt = (nmax + 1) / 2, ntiles = nt * (nt + 1) / 2;
     GramPlan g;
-    if (nboxes >= 512) {
+    const PlanParams pp = plan_params((int)nboxes);
+    if (pp.gram_many) {
         // fewest tile slots (idle threads) over 192- and 256-thread workgroups with 3, 5 or
         // 9 tiles per thread, the fewer tiles per thread on a tie
         g.slice_rows = 256;
@@ -152,7 +154,7 @@ static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes) {
         g.groups = (ntiles + 255) / 256;
         g.slice_rows = 128;
         while (g.slice_rows > kChunk &&
-               nboxes * (size_t)((mmax + g.slice_rows - 1) / g.slice_rows) * g.groups < 2048)
+               nboxes * (size_t)((mmax + g.slice_rows - 1) / g.slice_rows) * g.groups < (size_t)pp.gram_min_wg)
             g.slice_rows >>= 1;
     }
     g.nsl = (mmax + g.slice_rows - 1) / g.slice_rows;
@@ -165,39 +167,51 @@ static int pchol_lds_rows(int nmax) { return std::max(1, std::min(nmax, 49152 / 
 
 // Workspace (doubles) for any colour of at most nboxes boxes: the plan, and with it the
 // number of slices, depends on the colour's box count.
-size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes) {
+size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak) {
     const size_t nn = (size_t)nmax * nmax;
     size_t slices = 0;
-    for (size_t b = 1; b <= nboxes; ++b) slices = std::max(slices, b * (size_t)gram_plan(nmax, n_proxy, b).nsl);
+    for (size_t b = 1; b <= nboxes; ++b)
+        slices = std::max(slices, b * (size_t)gram_plan(nmax, n_proxy, b, weak).nsl);
     return slices * nn * 2 + nboxes * nn * 2;
 }
 
+constexpr int kRingMax = 24;   // boxes of the ID rows: 16 at distance 2, 24 at distance 1 or 2
+
 template <typename ST>
 struct ORing {
-    const ST* base[16];
-    const int* ap[16];
-    int beg[17];
+    const ST* base[kRingMax];
+    const int* ap[kRingMax];
+    int beg[kRingMax + 1];
     int cnt;
 };
 
-// Offset (dx, dy) of ring slot s: the 16 offsets at distance 2 in ascending (dy, dx) order
-// (5 on the row dy = -2, then pairs dx = -2, 2 on the rows -1, 0, 1, then 5 on dy = 2).
-__device__ inline void ring_offset(int s, int& dx, int& dy) {
+// Offset (dx, dy) of ring slot s in ascending (dy, dx) order.  Strong pass: the 16 offsets at
+// distance 2 (5 on the row dy = -2, then pairs dx = -2, 2 on the rows -1, 0, 1, then 5 on
+// dy = 2).  Weak pass: the 24 offsets of the 5 x 5 window but its centre.
+__device__ inline void ring_offset(int s, int weak, int& dx, int& dy) {
+    if (weak) {
+        const int i = s < 12 ? s : s + 1;
+        dx = i % 5 - 2;
+        dy = i / 5 - 2;
+        return;
+    }
     if (s < 5) { dx = s - 2; dy = -2; }
     else if (s < 11) { dy = (s - 5) / 2 - 1; dx = ((s - 5) & 1) ? 2 : -2; }
     else { dx = s - 13; dy = 2; }
 }
 
-// Threads 0..15 look up one ring slot each (the active counts load in parallel); after a
-// barrier, thread 0 lists the boxes that exist in ring order.  Ends with a barrier.
+// Threads 0..15 (0..23 in a weak pass) look up one ring slot each (the active counts load in
+// parallel); after a barrier, thread 0 lists the boxes that exist in ring order.  Ends with
+// a barrier.
 template <typename ST>
 __device__ inline void build_oring(ORing<ST>& o, int* ring_box, int* ring_nact, const ST* store, const int* nact,
-                                   const int* apos, int c, int nb, int nmax) {
+                                   const int* apos, int c, int nb, int nmax, int weak) {
     const int64_t bsz = (int64_t)nmax * nmax;
     const int tid = threadIdx.x;
-    if (tid < 16) {
+    const int nslot = weak ? 24 : 16;
+    if (tid < nslot) {
         int dx, dy;
-        ring_offset(tid, dx, dy);
+        ring_offset(tid, weak, dx, dy);
         const int ox = c % nb + dx, oy = c / nb + dy;
         const bool in = ox >= 0 && oy >= 0 && ox < nb && oy < nb;
         ring_box[tid] = in ? ox + nb * oy : -1;
@@ -207,11 +221,11 @@ __device__ inline void build_oring(ORing<ST>& o, int* ring_box, int* ring_nact, 
     if (tid == 0) {
         int cntO = 0;
         o.beg[0] = 0;
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < nslot; ++s) {
             const int ob = ring_box[s];
             if (ob < 0) continue;
             int dx, dy;
-            ring_offset(s, dx, dy);
+            ring_offset(s, weak, dx, dy);
             o.base[cntO] = store + ((int64_t)ob * kNbr + nbr_slot(-dx, -dy)) * bsz;   // block (o, c)
             o.ap[cntO] = apos + (int64_t)ob * nmax;
             o.beg[cntO + 1] = o.beg[cntO] + ring_nact[s];
@@ -249,13 +263,15 @@ __device__ inline void gram_row(const double* row, const int (&tp)[TPT], const i
     }
 }
 
-// Rows of M of box c: active DOFs of the distance-2 boxes plus the proxies.
-__device__ inline int id_rows(const int* nact, int c, int nb, int n_proxy) {
+// Rows of M of box c: active DOFs of the distance-2 boxes (distance 1 or 2 in a weak pass)
+// plus the proxies.
+__device__ inline int id_rows(const int* nact, int c, int nb, int n_proxy, int weak) {
     const int cx = c % nb, cy = c / nb;
     int mO = 0;
     for (int dy = -2; dy <= 2; ++dy)
         for (int dx = -2; dx <= 2; ++dx) {
-            if (max(abs(dx), abs(dy)) != 2) continue;
+            const int d = max(abs(dx), abs(dy));
+            if (d == 0 || (d == 1 && !weak)) continue;
             int ox = cx + dx, oy = cy + dy;
             if (ox < 0 || oy < 0 || ox >= nb || oy >= nb) continue;
             mO += nact[ox + nb * oy];
@@ -277,7 +293,7 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     extern __shared__ double2 Ms2[];
     double* Ms = (double*)Ms2;
     __shared__ ORing<ST> oring;
-    __shared__ int ring_box[16], ring_nact[16];
+    __shared__ int ring_box[kRingMax], ring_nact[kRingMax];
     __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
     __shared__ double colx[kMaxBox], coly[kMaxBox];
     __shared__ const ST* rowsrc[kChunk];
@@ -288,12 +304,12 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     const int n = cnt[c];
     if (n == 0) return;
     // slices past the box's rows and tile groups past its triangle leave before the set-up
-    if (sl * slice_rows >= id_rows(nact, c, nb, kp.n_proxy)) return;
+    if (sl * slice_rows >= id_rows(nact, c, nb, kp.n_proxy, kp.weak)) return;
     {
         const int nt0 = (n + 1) >> 1;
         if (grp * NTH * TPT >= nt0 * (nt0 + 1) / 2) return;
     }
-    build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax);
+    build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax, kp.weak);
     {
 #pragma clang fp contract(off)
         const int cx = c % nb, cy = c / nb;
@@ -419,14 +435,15 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
 // grid (nmax^2 / 256, boxes): slice 0 <- sum over the slices that hold rows, in slice order.
 __global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ cnt, const int* __restrict__ nact,
                                                      const int* __restrict__ boxes, int nb, int nmax, int n_proxy,
-                                                     double* __restrict__ gpart, int nslice, int slice_rows) {
+                                                     int weak, double* __restrict__ gpart, int nslice,
+                                                     int slice_rows) {
 #pragma clang fp contract(off)
     const int c = boxes[blockIdx.y];
     const int n = cnt[c];
     const int e = blockIdx.x * 256 + threadIdx.x;
     const int pa = e / nmax, qa = e % nmax;
     if (pa >= n || qa >= n || pa > qa) return;
-    const int m = id_rows(nact, c, nb, n_proxy);
+    const int m = id_rows(nact, c, nb, n_proxy, weak);
     const int nsl = (m + slice_rows - 1) / slice_rows;
     const int64_t sstride = (int64_t)nmax * nmax;
     double2* G = (double2*)gpart + (int64_t)blockIdx.y * nslice * sstride + e;
@@ -519,7 +536,7 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
         if (tid == 0) { krank[c] = 0; mrows[c] = 0; }
         return;
     }
-    const int m = id_rows(nact, c, nb, kp.n_proxy);
+    const int m = id_rows(nact, c, nb, kp.n_proxy, kp.weak);
     const int nsl = nsl_fixed > 0 ? nsl_fixed : (m + slice_rows - 1) / slice_rows;
     const int64_t sstride = (int64_t)nmax * nmax;
     const double2* G = (const double2*)gpart + (int64_t)blockIdx.x * nslice * sstride;
@@ -666,7 +683,8 @@ static void pchol_launch(const Level& L, const int* boxes, int nboxes, const Ker
                          const GramPlan& g, int nsl_fixed, double* rwork, hipStream_t s) {
     // many boxes: the first 16 rows of R in LDS (16 KB at nmax 64 keeps ~10 workgroups per
     // CU; measured 0.4 ms faster per leaf level than none), later rows in the workspace
-    const int kc = nboxes >= 512 ? std::min(16, L.nmax) : pchol_lds_rows(L.nmax);
+    const PlanParams pp = plan_params(nboxes);
+    const int kc = pp.pchol_kc > 0 ? std::min(pp.pchol_kc, L.nmax) : pchol_lds_rows(L.nmax);
     const size_t lds = sizeof(double) * 2 * (size_t)kc * L.nmax;
     note_shape("pchol_" + std::to_string(NTH) + "x" + std::to_string(SUB) + "_kc" + std::to_string(kc));
     k_pchol<NTH, SUB><<<dim3(nboxes), dim3(NTH), lds, s>>>(L.cnt, L.nact, boxes, L.nb, L.nmax, kp, gpart, g.nsl,
@@ -677,7 +695,7 @@ static void pchol_launch(const Level& L, const int* boxes, int nboxes, const Ker
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                    const KernelParams& kp, double* work, hipStream_t s) {
     if (nboxes <= 0) return 0;
-    const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes);
+    const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes, kp.weak);
     const size_t nn = (size_t)L.nmax * L.nmax;
     double* gpart = work;
     double* rwork = work + (size_t)nboxes * g.nsl * nn * 2;
@@ -693,13 +711,13 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
     int nsl_fixed = 0;
     if (g.groups > 1 || g.slice_rows < 256) {
         k_gram_reduce<<<dim3((unsigned)((nn + 255) / 256), nboxes), dim3(256), 0, s>>>(
-            L.cnt, L.nact, boxes, L.nb, L.nmax, kp.n_proxy, gpart, g.nsl, g.slice_rows);
+            L.cnt, L.nact, boxes, L.nb, L.nmax, kp.n_proxy, kp.weak, gpart, g.nsl, g.slice_rows);
         nsl_fixed = 1;
         ++launches;
         note_shape("gram_reduce");
     }
     // many boxes: one thread per column; few boxes: four threads per column
-    if (nboxes >= 512) {
+    if (plan_params(nboxes).gram_many) {
         if (L.nmax <= 64) pchol_launch<64, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
         else if (L.nmax <= 128) pchol_launch<128, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);
         else pchol_launch<256, 1>(L, boxes, nboxes, kp, gpart, g, nsl_fixed, rwork, s);

@@ -29,6 +29,7 @@ struct KernelParams {
     int n_proxy;
     double proxy_radius;
     double lo_x, lo_y, side;   // root box
+    int weak = 0;              // 1: the weak pass of RS-WS (ID rows from distance 1 and 2, J = S)
 };
 
 // One tree level: active lists at the start of the level, the block store, and the
@@ -39,7 +40,13 @@ struct Level {
     int ldJ = 0;         // 9 * nmax: capacity of J lists
     void* store = nullptr;     // nbox * 25 * nmax * nmax entries: FP64, or FP32 when store32
     int store32 = 0;           // mixed precision: the block store holds FP32 entries
+    int weak = 0;              // RS-WS: the records of this level are those of its weak pass
     size_t store_bytes() const { return (size_t)nbox * kNbr * nmax * nmax * (store32 ? 4 : 8); }
+    // With an FP32 store the self blocks A(B_a, B_a) (offset (0, 0)) live in this FP64 array
+    // instead: after a box's elimination its skeleton-skeleton entries are O(1), and FP32
+    // rounding of them would dominate |A - F|.  nullptr with an FP64 store.
+    double* dstore = nullptr;
+    size_t dstore_bytes() const { return store32 ? (size_t)nbox * nmax * nmax * 8 : 0; }
     int* cnt = nullptr;        // |B| at level start
     int* gidx = nullptr;       // nbox * nmax global DOF indices (ascending)
     int* nact = nullptr;       // current active count
@@ -88,10 +95,13 @@ struct FFTPlan {
 // F_Schur = 2 |J|^2 |R|; Schur bytes = 16 |J|^2 (FP64 target read + write) plus the two
 // operands; solve bytes = factor data streamed by one solve.
 struct LevelStats {
-    int depth = 0, boxes = 0, nmax = 0, records = 0, max_k = 0, max_J = 0;
+    int depth = 0, weak = 0, boxes = 0, nmax = 0, records = 0, max_k = 0, max_J = 0;
     double sum_k = 0, sum_r = 0, sum_J = 0;
     double flops_id = 0, flops_x = 0, flops_lu = 0, flops_g = 0, flops_schur = 0;
     double bytes_schur = 0, bytes_solve64 = 0, bytes_solve32 = 0;
+    // mixed precision: the S x S tiles run in their own FP64 launch (flops, bytes, time);
+    // flops_schur, bytes_schur and ms_schur then count the main (FP32) launch only
+    double flops_schur_sxs = 0, bytes_schur_sxs = 0, ms_schur_sxs = 0;
     double ms_id = 0, ms_elim = 0, ms_schur = 0, ms_transition = 0;
 };
 
@@ -189,6 +199,27 @@ __device__ inline void wave_argmax(double& best, int& bi) {
     best = km == 0 ? -1.0 : __longlong_as_double((long long)(km - 1ull));
 }
 
+// Launch-plan parameters of the kernels of one colour, by the colour's box count (buckets
+// with lower bounds kPlanBucketLo).  The table in tuned_plans.inc is written by the
+// autotuner (paper_1609_08130_amd/tune.py), which times the factorization and the solve
+// with candidate values set through the environment variable RSS_TUNE
+// ("b<bucket>.<field>=<value>,..."), read at every rss_factor_create.  Every value is
+// correct for any box count; only the speed differs.
+struct PlanParams {
+    int gram_many;       // 1: Gram matrices of 256-row slices with the whole triangle per workgroup
+    int gram_min_wg;     // few-box Gram plan: rows are sliced until the colour has this many workgroups
+    int pchol_kc;        // many-box pivoted Cholesky: rows of R kept in LDS (0: as many as fit)
+    int elim_tpw;        // elimination row / column tiles per workgroup
+    int elim_tw;         // widest elimination tile (lines of J)
+    int inv_threads;     // workgroup of the X_RR inverse: 256 or 1024 threads
+    int sweep_threads;   // workgroup of the solve / apply sweeps: 256 or 1024 threads
+};
+constexpr int kPlanBuckets = 5;
+extern const int kPlanBucketLo[kPlanBuckets];
+PlanParams plan_params(int nboxes);
+// Re-reads RSS_TUNE (rss_factor_create calls it once).
+void reload_plan_overrides();
+
 // Launch shapes (the kernel variants chosen by box counts and sizes) are collected by name
 // into the log of the factor whose entry point is running, for rss_info; a launcher calls
 // note_shape once per variant it launches.  No log set: nothing is recorded.
@@ -208,6 +239,9 @@ void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp
 void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s);
 void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
                          const KernelParams& kp, hipStream_t s);
+// RS-WS: C (same depth, lists and store allocated for C.nmax = the largest active count)
+// <- the active DOFs of L after its weak pass, lists and blocks compacted.
+void launch_compact(const Level& L, Level& C, hipStream_t s);
 void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, int64_t ntop,
                          const double* pts, const KernelParams& kp, double* A, hipStream_t s);
 void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
@@ -216,7 +250,7 @@ void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hip
 // Returns the number of kernels launched.
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                     const KernelParams& kp, double* work, hipStream_t s);
-size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes);
+size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak);
 // Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
 // Active 64 x 64 tiles of the Schur updates of one colour, in 8 lists (one per XCD: the
 // boxes with position bi = x mod 8 in the colour's list go to list x).  An entry packs
@@ -227,13 +261,19 @@ struct TileList {
     int* tiles = nullptr;   // 8 * capx entries
     int capx = 0;           // ceil(boxes / 8) * ceil(ldJ / 64)^2
 };
-int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, double* work, int* flag, const TileList& tl,
-                 hipStream_t s);
+// Mixed precision: the tiles that cover S x S of a step (its O(1) skeleton-skeleton update)
+// go to tl64 and are multiplied in FP64; every other tile goes to tl.  FP64 factors put all
+// tiles in tl (tl64.cnt == nullptr).
+// weak: the RS-WS weak pass (J = S, no adjacent boxes).
+int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
+                const TileList& tl, const TileList& tl64, hipStream_t s);
 // Entries per tile list for a colour of nboxes boxes with |J| <= maxJ.
 int schur_tile_capx(int nboxes, int maxJ);
 // Returns -1 when tl.capx is below schur_tile_capx(nboxes, maxJ) (nothing launched).
-int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const TileList& tl,
-                 hipStream_t s);
+// fp64_tiles: the S x S tiles of a mixed factorization (list tl64 of launch_elim), with FP64
+// products; otherwise the tiles of tl with the factorization's product type.
+int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, int fp64_tiles,
+                 const TileList& tl, hipStream_t s);
 
 // dense top block (rss_solve.hip)
 // piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)

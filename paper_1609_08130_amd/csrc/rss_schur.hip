@@ -18,6 +18,7 @@ namespace rss {
 
 struct SchurArgs {
     void* store;   // entries of type ST
+    double* dstore;   // self blocks of an FP32 store (FP64), or nullptr
     int nb, nmax, ldJ;
     const int* cnt;
     const int* nact;
@@ -44,6 +45,7 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     __shared__ int joff[10];
     __shared__ int jslot[9];
     __shared__ int64_t blkoff[81];   // [row slot * 9 + column slot]: first entry of that block
+                                     // (in dstore for the self blocks, slot pairs s s, when set)
 
     const int tid = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin in launch order: workgroup x + 8 s
@@ -108,9 +110,9 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         // block (row box of slot sa, column box of slot sb): offset (sb - sa) in the 3x3 grid
         const int sa = (tid - 64) / 9, sb = (tid - 64) % 9;
         const int abox = slot_box[sa];
-        blkoff[tid - 64] = (abox < 0 || slot_box[sb] < 0)
-                               ? (int64_t)-1
-                               : ((int64_t)abox * kNbr + nbr_slot(sb % 3 - sa % 3, sb / 3 - sa / 3)) * bsz;
+        blkoff[tid - 64] = (abox < 0 || slot_box[sb] < 0) ? (int64_t)-1
+                           : (sa == sb && a.dstore)     ? (int64_t)abox * bsz
+                                                        : ((int64_t)abox * kNbr + nbr_slot(sb % 3 - sa % 3, sb / 3 - sa / 3)) * bsz;
     }
     __syncthreads();
     if (tid < 2 * TM) {
@@ -211,6 +213,28 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         const int64_t off = blkoff[in ? sa * 9 + sb : 0] + rpos_[i] + (int64_t)cpos_[j] * nmax;
         return in ? off : (int64_t)-1;
     };
+    if (a.dstore) {
+        // FP32 store with FP64 self blocks: an entry of a self block (row and column slot
+        // equal) is updated in FP64, every other entry in ST as below
+        double* ds = a.dstore;
+        auto self = [&](int e) -> bool { return rslot[erow(e)] == cslot[ecol(e)]; };
+        double old[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t off = max(entry(e), (int64_t)0);
+            old[e] = self(e) ? ds[off] : (double)st[off];
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) asm volatile("" ::"v"(old[e]));
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t off = entry(e);
+            if (off < 0) continue;
+            if (self(e)) ds[off] = old[e] - (double)eval(e);
+            else st[off] = (ST)old[e] - (ST)eval(e);
+        }
+        return;
+    }
     ST old[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) old[e] = st[max(entry(e), (int64_t)0)];
@@ -230,24 +254,26 @@ int schur_tile_capx(int nboxes, int maxJ) {
     return tpd * tpd * ((nboxes + 7) / 8);
 }
 
-int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const TileList& tl,
-                 hipStream_t s) {
+int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, int fp64_tiles,
+                 const TileList& tl, hipStream_t s) {
     if (nboxes <= 0) return 0;
     if (tl.capx < schur_tile_capx(nboxes, maxJ)) return -1;
     SchurArgs a;
-    a.store = L.store; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
+    a.store = L.store; a.dstore = L.dstore; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ; a.spos = L.spos;
     const int tpd = (maxJ + 63) / 64;
     const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);   // 8 lists of at most capx entries
     dim3 grid((unsigned)nwg), block(256);
-    note_shape(std::string("schur_") + (mixed ? "f32" : "f64") + (L.store32 ? "_store32" : "_store64"));
-    if (mixed) {
+    if (mixed && !fp64_tiles) {
+        note_shape(std::string("schur_f32") + (L.store32 ? "_store32" : "_store64"));
         a.XJR = L.XJR32; a.G = L.G32;
         if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
         else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
     } else {
+        note_shape(std::string(fp64_tiles ? "schur_f64_sxs" : "schur_f64") + (L.store32 ? "_store32" : "_store64"));
         a.XJR = L.XJR; a.G = L.G;
-        k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        if (L.store32) k_schur<double, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        else k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
     }
     return 0;
 }

@@ -459,7 +459,7 @@ void launch_solve_fwd(const Level& L, const int* boxes, int nboxes, double* z, i
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
     // few boxes: a large workgroup per box keeps more loads of the record in flight
-    if (nboxes < 256) {
+    if (plan_params(nboxes).sweep_threads == 1024) {
         if (use32) solve_fwd_t<float, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
         else solve_fwd_t<double, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
     } else {
@@ -472,7 +472,7 @@ void launch_solve_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
                       hipStream_t s) {
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, use32);
-    if (nboxes < 256) {
+    if (plan_params(nboxes).sweep_threads == 1024) {
         if (use32) solve_bwd_t<float, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
         else solve_bwd_t<double, 1024>(a, boxes, nboxes, z, nrhs, ld, s);
     } else {
@@ -487,7 +487,7 @@ void launch_apply_fwd(const Level& L, const int* boxes, int nboxes, double* z, i
     const size_t lds = sizeof(double) * (size_t)L.ldJ;
     SweepArgs a = sweep_args(L, 0);
     a.Lc = Lroot;
-    if (nboxes < 256) k_apply_fwd<1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
+    if (plan_params(nboxes).sweep_threads == 1024) k_apply_fwd<1024><<<dim3(nboxes), dim3(1024), lds, s>>>(a, boxes, z, nrhs, ld);
     else k_apply_fwd<256><<<dim3(nboxes), dim3(256), lds, s>>>(a, boxes, z, nrhs, ld);
 }
 
@@ -496,7 +496,7 @@ void launch_apply_bwd(const Level& L, const int* boxes, int nboxes, double* z, i
     if (nboxes <= 0) return;
     SweepArgs a = sweep_args(L, 0);
     a.Lc = Lroot;
-    if (nboxes < 256) k_apply_bwd<1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
+    if (plan_params(nboxes).sweep_threads == 1024) k_apply_bwd<1024><<<dim3(nboxes), dim3(1024), 0, s>>>(a, boxes, z, nrhs, ld);
     else k_apply_bwd<256><<<dim3(nboxes), dim3(256), 0, s>>>(a, boxes, z, nrhs, ld);
 }
 

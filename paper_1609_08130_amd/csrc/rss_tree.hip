@@ -182,9 +182,10 @@ void launch_leaf_lists(const double* pts, int64_t n, int t, double lo_x, double 
 // dx > 0).  Each 64 x 64 tile is evaluated once into LDS and written to both blocks,
 // coalesced in both orientations.
 template <typename ST>
-__global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, const int* __restrict__ cnt,
-                                                    const int* __restrict__ gidx, const double* __restrict__ pts,
-                                                    int nb, int nmax, double coef, double diag, int* flag) {
+__global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, double* __restrict__ dstore,
+                                                    const int* __restrict__ cnt, const int* __restrict__ gidx,
+                                                    const double* __restrict__ pts, int nb, int nmax, double coef,
+                                                    double diag, int* flag) {
     // the row point of a thread comes from registers, the column points (the same for the
     // whole wave) from LDS; the transposing tile holds entries in the store's type
     __shared__ double xb[kMaxBox], yb[kMaxBox];
@@ -207,6 +208,8 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
     ST* blk_ab = store + ((int64_t)a * kNbr + o) * nmax * nmax;                  // A(B_a, B_b)
     ST* blk_ba = store + ((int64_t)b * kNbr + (24 - o)) * nmax * nmax;           // A(B_b, B_a)
     const bool self = oi == 0;
+    // self block of an FP32 store: full-precision FP64 entries in the separate array
+    double* dblk = (self && dstore) ? dstore + (int64_t)a * nmax * nmax : nullptr;
     bool dup = false;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int i0 = 0; i0 < na; i0 += 64) {
@@ -226,13 +229,18 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
                 ST v = (ST)0;
                 if (lane < ti) {
                     const int i = i0 + lane;
-                    if (gi == gb[j]) {
-                        v = (ST)diag;
+                    if (dblk) {
+                        dblk[i + (int64_t)j * nmax] = gi == gb[j] ? diag : kernel_entry(xi, yi, xb[j], yb[j], coef);
+                        dup |= gi != gb[j] && (xi == xb[j] && yi == yb[j]);
                     } else {
-                        v = (ST)store_entry<ST>(xi, yi, xb[j], yb[j], coef);
-                        dup |= (xi == xb[j] && yi == yb[j]);
+                        if (gi == gb[j]) {
+                            v = (ST)diag;
+                        } else {
+                            v = (ST)store_entry<ST>(xi, yi, xb[j], yb[j], coef);
+                            dup |= (xi == xb[j] && yi == yb[j]);
+                        }
+                        blk_ab[i + (int64_t)j * nmax] = v;
                     }
-                    blk_ab[i + (int64_t)j * nmax] = v;
                 }
                 tile[jj][lane] = v;
             }
@@ -250,11 +258,11 @@ __global__ void __launch_bounds__(256) k_leaf_store(ST* __restrict__ store, cons
 
 void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp, int* flag, hipStream_t s) {
     if (L.store32)
-        k_leaf_store<float><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((float*)L.store, L.cnt, L.gidx, pts, L.nb,
-                                                                    L.nmax, kp.coef, kp.diag, flag);
+        k_leaf_store<float><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((float*)L.store, L.dstore, L.cnt, L.gidx, pts,
+                                                                    L.nb, L.nmax, kp.coef, kp.diag, flag);
     else
-        k_leaf_store<double><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((double*)L.store, L.cnt, L.gidx, pts, L.nb,
-                                                                     L.nmax, kp.coef, kp.diag, flag);
+        k_leaf_store<double><<<dim3(L.nbox * 13), dim3(256), 0, s>>>((double*)L.store, nullptr, L.cnt, L.gidx, pts,
+                                                                     L.nb, L.nmax, kp.coef, kp.diag, flag);
 }
 
 // ------------------------------------------------------------------------------------
@@ -311,8 +319,10 @@ void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s) {
 
 
 template <typename ST>
-__global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cstore, int cnb, int cnmax,
-                                                      ST* __restrict__ pstore, const int* __restrict__ pcnt,
+__global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cstore,
+                                                      const double* __restrict__ cdstore, int cnb, int cnmax,
+                                                      ST* __restrict__ pstore, double* __restrict__ pdstore,
+                                                      const int* __restrict__ pcnt,
                                                       const int* __restrict__ pgidx, const int* __restrict__ pmap,
                                                       int pnb, int pnmax, const double* __restrict__ pts,
                                                       double coef) {
@@ -366,6 +376,9 @@ __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cst
             }
         return;
     }
+    // the parent's self block goes to the FP64 array when there is one (its child pairs are
+    // within distance 1: the children's self blocks come from their FP64 array)
+    double* dblk = (o == 12 && pdstore) ? pdstore + (int64_t)P * pnmax * pnmax : nullptr;
     // Adjacent parents: child pairs within distance 2 copy their entry of the child store,
     // the others (distance 3) are kernel entries.  Element e = i + np j, taken U at a time
     // per thread with every load issued before the first store; (i, j) advance by a fixed
@@ -396,16 +409,24 @@ __global__ void __launch_bounds__(256) k_parent_store(const ST* __restrict__ cst
             const int ax = 2 * Px + (sa & 1), ay = 2 * Py + (sa >> 1);
             const int bx = 2 * Qx + (sb & 1), by = 2 * Qy + (sb >> 1);
             const int ddx = bx - ax, ddy = by - ay;
-            if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
+            if (cdstore && ddx == 0 && ddy == 0) {
+                v[u] = cdstore[(int64_t)(ax + cnb * ay) * cnmax * cnmax + pa + (int64_t)qb * cnmax];
+            } else if (ddx >= -2 && ddx <= 2 && ddy >= -2 && ddy <= 2) {
                 const ST* cb = cstore + ((int64_t)(ax + cnb * ay) * kNbr + nbr_slot(ddx, ddy)) * cnmax * cnmax;
                 v[u] = (double)cb[pa + (int64_t)qb * cnmax];
             } else {
                 v[u] = store_entry<ST>(xp[ii], yp[ii], xq[jj], yq[jj], coef);
             }
         }
+        if (dblk) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (e0 + 256 * u < tot) blk[iu[u] + (int64_t)ju[u] * pnmax] = (ST)v[u];
+            for (int u = 0; u < U; ++u)
+                if (e0 + 256 * u < tot) dblk[iu[u] + (int64_t)ju[u] * pnmax] = v[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + 256 * u < tot) blk[iu[u] + (int64_t)ju[u] * pnmax] = (ST)v[u];
+        }
     }
 }
 
@@ -413,10 +434,65 @@ void launch_parent_store(const Level& C, const Level& P, const int* pmap, const 
                          const KernelParams& kp, hipStream_t s) {
     if (C.store32)
         k_parent_store<float><<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(
-            (const float*)C.store, C.nb, C.nmax, (float*)P.store, P.cnt, P.gidx, pmap, P.nb, P.nmax, pts, kp.coef);
+            (const float*)C.store, C.dstore, C.nb, C.nmax, (float*)P.store, P.dstore, P.cnt, P.gidx, pmap, P.nb,
+            P.nmax, pts, kp.coef);
     else
         k_parent_store<double><<<dim3(P.nbox * kNbr), dim3(256), 0, s>>>(
-            (const double*)C.store, C.nb, C.nmax, (double*)P.store, P.cnt, P.gidx, pmap, P.nb, P.nmax, pts, kp.coef);
+            (const double*)C.store, nullptr, C.nb, C.nmax, (double*)P.store, nullptr, P.cnt, P.gidx, pmap, P.nb,
+            P.nmax, pts, kp.coef);
+}
+
+// ------------------------------------------------------------------------------------
+// RS-WS (Section 3.4): after the weak pass of a level the strong pass restarts on the DOFs
+// that remain active.  Box P's new list is its active DOFs in ascending order,
+// list'(P)[i] = list(P)[apos(P)[i]], and every stored block is restricted to the active
+// rows and columns (the self blocks from and to the FP64 arrays when there are some).
+
+__global__ void k_compact_lists(const int* __restrict__ nact, const int* __restrict__ apos,
+                                const int* __restrict__ gidx, int nmax, int* __restrict__ cgidx, int cnmax) {
+    const int P = blockIdx.x;
+    const int n = nact[P];
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        cgidx[(int64_t)P * cnmax + i] = gidx[(int64_t)P * nmax + apos[(int64_t)P * nmax + i]];
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) k_compact_store(const ST* __restrict__ st, const double* __restrict__ ds,
+                                                       int nb, int nmax, const int* __restrict__ nact,
+                                                       const int* __restrict__ apos, ST* __restrict__ cst,
+                                                       double* __restrict__ cds, int cnmax) {
+    __shared__ int ap[kMaxBox], aq[kMaxBox];
+    const int P = blockIdx.x / kNbr, o = blockIdx.x % kNbr;
+    const int dx = o % 5 - 2, dy = o / 5 - 2;
+    const int Qx = P % nb + dx, Qy = P / nb + dy;
+    if (Qx < 0 || Qy < 0 || Qx >= nb || Qy >= nb) return;
+    const int Q = Qx + nb * Qy;
+    const int np = nact[P], nq = nact[Q];
+    for (int i = threadIdx.x; i < np; i += 256) ap[i] = apos[(int64_t)P * nmax + i];
+    for (int i = threadIdx.x; i < nq; i += 256) aq[i] = apos[(int64_t)Q * nmax + i];
+    __syncthreads();
+    const int64_t bsz = (int64_t)nmax * nmax, cbsz = (int64_t)cnmax * cnmax;
+    const bool self = o == 12 && ds;
+    const ST* src = st + ((int64_t)P * kNbr + o) * bsz;
+    const double* dsrc = self ? ds + (int64_t)P * bsz : nullptr;
+    ST* dst = cst + ((int64_t)P * kNbr + o) * cbsz;
+    double* ddst = self ? cds + (int64_t)P * cbsz : nullptr;
+    for (int e = threadIdx.x; e < np * nq; e += 256) {
+        const int i = e % np, j = e / np;
+        const int64_t from = ap[i] + (int64_t)aq[j] * nmax, to = i + (int64_t)j * cnmax;
+        if (self) ddst[to] = dsrc[from];
+        else dst[to] = src[from];
+    }
+}
+
+void launch_compact(const Level& L, Level& C, hipStream_t s) {
+    k_compact_lists<<<dim3(L.nbox), dim3(256), 0, s>>>(L.nact, L.apos, L.gidx, L.nmax, C.gidx, C.nmax);
+    if (L.store32)
+        k_compact_store<float><<<dim3(L.nbox * kNbr), dim3(256), 0, s>>>(
+            (const float*)L.store, L.dstore, L.nb, L.nmax, L.nact, L.apos, (float*)C.store, C.dstore, C.nmax);
+    else
+        k_compact_store<double><<<dim3(L.nbox * kNbr), dim3(256), 0, s>>>(
+            (const double*)L.store, nullptr, L.nb, L.nmax, L.nact, L.apos, (double*)C.store, nullptr, C.nmax);
 }
 
 // ------------------------------------------------------------------------------------
@@ -454,7 +530,8 @@ void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hip
 }
 
 template <typename ST>
-__global__ void k_top_assemble(const ST* __restrict__ store, int nb, int nmax, const int* __restrict__ tmap,
+__global__ void k_top_assemble(const ST* __restrict__ store, const double* __restrict__ dstore, int nb, int nmax,
+                               const int* __restrict__ tmap,
                                const int* __restrict__ top_idx, int64_t ntop, const double* __restrict__ pts,
                                double coef, double* __restrict__ A) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,7 +541,9 @@ __global__ void k_top_assemble(const ST* __restrict__ store, int nb, int nmax, c
     int b = tmap[j] >> 16, qb = tmap[j] & 0xffff;
     int dx = b % nb - a % nb, dy = b / nb - a / nb;
     double v;
-    if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
+    if (dstore && a == b) {
+        v = dstore[(int64_t)a * nmax * nmax + pa + (int64_t)qb * nmax];
+    } else if (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2) {
         v = (double)store[((int64_t)a * kNbr + nbr_slot(dx, dy)) * nmax * nmax + pa + (int64_t)qb * nmax];
     } else {
         int gi = top_idx[i], gj = top_idx[j];
@@ -479,11 +558,11 @@ void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, in
     int64_t tot = ntop * ntop;
     const dim3 g((unsigned)((tot + 255) / 256));
     if (L.store32)
-        k_top_assemble<float><<<g, dim3(256), 0, s>>>((const float*)L.store, L.nb, L.nmax, tmap, top_idx, ntop, pts,
-                                                      kp.coef, A);
+        k_top_assemble<float><<<g, dim3(256), 0, s>>>((const float*)L.store, L.dstore, L.nb, L.nmax, tmap, top_idx,
+                                                      ntop, pts, kp.coef, A);
     else
-        k_top_assemble<double><<<g, dim3(256), 0, s>>>((const double*)L.store, L.nb, L.nmax, tmap, top_idx, ntop,
-                                                       pts, kp.coef, A);
+        k_top_assemble<double><<<g, dim3(256), 0, s>>>((const double*)L.store, nullptr, L.nb, L.nmax, tmap, top_idx,
+                                                       ntop, pts, kp.coef, A);
 }
 
 }  // namespace rss

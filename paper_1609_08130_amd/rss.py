@@ -60,7 +60,7 @@ class Params(ctypes.Structure):
         ("root_lo", ctypes.c_double * 3),
         ("root_side", ctypes.c_double),
         ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("method", ctypes.c_int32),
         ("arena_bytes", ctypes.c_uint64),
     ]
 
@@ -81,8 +81,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rss_gmres.argtypes = [vp, vp, vp, dbl, i32, i32, i32, vp, P(i32), P(dbl)]
     lib.rss_logdet.argtypes = [vp, P(dbl), P(dbl)]
     lib.rss_shape.argtypes = [vp, P(i32), P(i64)]
-    lib.rss_box_sets.argtypes = [vp, i32, i64, P(i64), i32, P(i32), P(i64), i32, P(i32)]
-    lib.rss_box_record.argtypes = [vp, i32, i64, P(dbl), P(dbl), P(dbl), P(dbl), P(i64), i64, P(i32), P(i32),
+    lib.rss_box_sets.argtypes = [vp, i32, i64, i32, P(i64), i32, P(i32), P(i64), i32, P(i32)]
+    lib.rss_box_record.argtypes = [vp, i32, i64, i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i64), i64, P(i32), P(i32),
                                    P(i32)]
     lib.rss_top_set.argtypes = [vp, P(i64), i64, P(i64)]
     lib.rss_info.argtypes = [vp, ctypes.c_char_p, i64]
@@ -120,6 +120,10 @@ def make_params(dim: int = 2, kernel="laplace2d", **kw) -> Params:
                 p.root_lo[i] = float(c)
         elif k == "precision":
             p.precision = {"fp64": RSS_FP64, "mixed": RSS_MIXED}.get(v, v)
+        elif k == "method":
+            p.method = {"rs-s": 0, "rs-ws": 1}.get(v, v)
+        elif k == "hybrid":
+            p.method = 1 if v else 0
         elif hasattr(p, k):
             setattr(p, k, type(getattr(p, k))(v))
         else:
@@ -214,17 +218,18 @@ class Factor:
         _check(lib().rss_logdet(self._h, ctypes.byref(re), ctypes.byref(im)))
         return (-1.0 if im.value != 0.0 else 1.0), re.value
 
-    def box_record(self, depth: int, box: int) -> dict:
+    def box_record(self, depth: int, box: int, weak: bool = False) -> dict:
         """T, X_RR, X_JR, G and the global J indices of one skeletonization step (empty
-        arrays when the box has no record)."""
+        arrays when the box has no record); weak selects the weak step of RS-WS."""
         ns, nr, nj = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().rss_box_record(self._h, depth, box, None, None, None, None, None, 0, ctypes.byref(ns),
+        w = int(bool(weak))
+        _check(lib().rss_box_record(self._h, depth, box, w, None, None, None, None, None, 0, ctypes.byref(ns),
                                     ctypes.byref(nr), ctypes.byref(nj)))
         k, r, J = ns.value, nr.value, nj.value
         cap = max(k * r, r * r, J * r, J, 1)
         bufs = [(ctypes.c_double * cap)() for _ in range(4)]
         jb = (ctypes.c_int64 * cap)()
-        _check(lib().rss_box_record(self._h, depth, box, *bufs, jb, cap, ctypes.byref(ns), ctypes.byref(nr),
+        _check(lib().rss_box_record(self._h, depth, box, w, *bufs, jb, cap, ctypes.byref(ns), ctypes.byref(nr),
                                     ctypes.byref(nj)))
         col = lambda b, rows, cols: np.array(b[:rows * cols], dtype=np.float64).reshape(cols, rows).T.copy()
         return dict(T=col(bufs[0], k, r), XRR=col(bufs[1], r, r), XJR=col(bufs[2], J, r), G=col(bufs[3], r, J),
@@ -235,12 +240,13 @@ class Factor:
         _check(lib().rss_shape(self._h, ctypes.byref(d), ctypes.byref(nt)))
         return d.value, nt.value
 
-    def box_sets(self, depth: int, box: int):
+    def box_sets(self, depth: int, box: int, weak: bool = False):
         cap = 8192
         S = (ctypes.c_int64 * cap)()
         R = (ctypes.c_int64 * cap)()
         ns, nr = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().rss_box_sets(self._h, depth, box, S, cap, ctypes.byref(ns), R, cap, ctypes.byref(nr)))
+        _check(lib().rss_box_sets(self._h, depth, box, int(bool(weak)), S, cap, ctypes.byref(ns), R, cap,
+                                  ctypes.byref(nr)))
         return (np.array(S[:ns.value], dtype=np.int64), np.array(R[:nr.value], dtype=np.int64))
 
     def top_set(self):

@@ -11,6 +11,11 @@ and the factorization is rebuilt as F = (prod V_i) D (prod' W_i) with
 V_i = U_T^{-1} L^{-1} and W_i = U^{-1} L_T^{-1} (eq. skelop, eq. rss; the
 permutation P is the identity because everything is indexed globally).
 
+With p.hybrid (RS-WS, Section 3.4, Algorithm 2) every level first runs weak steps: the
+ID rows are all active DOFs at distance 1 and 2 plus the proxies, X[R, C] = X[C, R] = 0
+for every active DOF C outside the box, and the elimination has J = S; one more weak pass
+runs at depth 1 after the strong pass at depth 2.
+
 Box membership, near/far sets and the active mask are computed here from the
 geometry directly, not from the oracle's block store or level transitions.  Only
 the ID itself (`cpqr_id`, pinned separately against LAPACK) is shared.
@@ -40,8 +45,58 @@ def replay(pts: np.ndarray, p: O.Params, check_far_unmodified: bool = True):
     steps = []
     far_checks = 0
     level_start = {}
+    def eliminate(A, S, R, J, T, UT, LT, X, kind, t, c):
+        XRRinv = np.linalg.inv(X[np.ix_(R, R)])
+        E = X[np.ix_(J, R)] @ XRRinv
+        G = XRRinv @ X[np.ix_(R, J)]
+        L = np.eye(n)
+        L[np.ix_(J, R)] = -E
+        U = np.eye(n)
+        U[np.ix_(R, J)] = -G
+        A = L @ X @ U
+        keep = A[np.ix_(R, R)].copy()
+        A[R, :] = 0.0
+        A[:, R] = 0.0
+        A[np.ix_(R, R)] = keep
+        active[R] = False
+        steps.append(dict(depth=t, box=c, S=S, R=R, J=J, T=T, E=E, G=G, XRR=keep, kind=kind,
+                          V=np.linalg.inv(UT) @ np.linalg.inv(L), W=np.linalg.inv(U) @ np.linalg.inv(LT),
+                          A_after=A.copy()))
+        return A
+
+    def weak_pass(A, t):
+        nb = 2 ** t
+        bx, by = _box_of(pts, t, lo, side)
+        order = sorted(range(nb * nb), key=lambda b: ((b % nb) % 3 + 3 * ((b // nb) % 3), b))
+        for c in order:
+            cx, cy = c % nb, c // nb
+            dist = np.maximum(np.abs(bx - cx), np.abs(by - cy))
+            Bc = np.nonzero(active & (dist == 0))[0]
+            if len(Bc) == 0:
+                continue
+            Cbox = [(bx[i] + nb * by[i], i) for i in np.nonzero(active & ((dist == 1) | (dist == 2)))[0]]
+            Cset = np.array([i for _, i in sorted(Cbox)], dtype=np.int64)
+            prox = O.proxy_points(c, t, tree, p)
+            M = np.vstack([A[np.ix_(Cset, Bc)], O.kernel_block(prox, pts[Bc], p)])
+            spos, rpos, T = O.id_sorted(O.cpqr_id(M, p.tol))
+            if len(rpos) == 0:
+                continue
+            S, R = Bc[spos], Bc[rpos]
+            UT = np.eye(n)
+            UT[np.ix_(R, S)] = -T.T
+            LT = np.eye(n)
+            LT[np.ix_(S, R)] = -T
+            X = UT @ A @ LT
+            outside = np.nonzero(active & (dist >= 1))[0]
+            X[np.ix_(R, outside)] = 0.0
+            X[np.ix_(outside, R)] = 0.0
+            A = eliminate(A, S, R, S, T, UT, LT, X, "weak", t, c)
+        return A
+
     for t in range(D, 1, -1):
         level_start[t] = A.copy()
+        if p.hybrid:
+            A = weak_pass(A, t)
         nb = 2 ** t
         bx, by = _box_of(pts, t, lo, side)
         order = sorted(range(nb * nb), key=lambda b: ((b % nb) % 3 + 3 * ((b // nb) % 3), b))
@@ -77,23 +132,9 @@ def replay(pts: np.ndarray, p: O.Params, check_far_unmodified: bool = True):
             X[np.ix_(R, far)] = 0.0
             X[np.ix_(far, R)] = 0.0
             J = np.concatenate([S, Nset])
-            XRRinv = np.linalg.inv(X[np.ix_(R, R)])
-            E = X[np.ix_(J, R)] @ XRRinv
-            G = XRRinv @ X[np.ix_(R, J)]
-            L = np.eye(n)
-            L[np.ix_(J, R)] = -E
-            U = np.eye(n)
-            U[np.ix_(R, J)] = -G
-            A = L @ X @ U
-            keep = A[np.ix_(R, R)].copy()
-            A[R, :] = 0.0
-            A[:, R] = 0.0
-            A[np.ix_(R, R)] = keep
-            active[R] = False
-            steps.append(dict(depth=t, box=c, S=S, R=R, J=J, T=T, E=E, G=G, XRR=keep,
-                              V=np.linalg.inv(UT) @ np.linalg.inv(L),
-                              W=np.linalg.inv(U) @ np.linalg.inv(LT),
-                              A_after=A.copy()))
+            A = eliminate(A, S, R, J, T, UT, LT, X, "strong", t, c)
+    if p.hybrid and D >= 2:
+        A = weak_pass(A, 1)
     top = np.nonzero(active)[0]
     Fm = A.copy()
     for st in reversed(steps):

@@ -31,9 +31,11 @@ def vec_bound(tol: float) -> float:
 def record_bound(tol: float) -> float:
     """Element-wise bound on record blocks (T, X_RR, X_JR, G) relative to the block's
     largest entry: u cond(R11), and greedy pivoted QR keeps cond(R11) within a modest
-    factor of |R_00| / |R_kk| <= 1 / tol (measured up to 13 u / tol over the parity cases,
-    at tol 1e-3 to 1e-9 and on the first-kind system), so 100 u / tol, never below 1e-12."""
-    return max(1e-12, 100.0 * EPS / tol)
+    factor of |R_00| / |R_kk| <= 1 / tol: measured up to 13 u / tol over the strong steps
+    of the parity cases (tol 1e-3 to 1e-9) and 130 u / tol for a weak step of RS-WS at
+    tol 1e-9 (larger ranks, so R11 closer to its worst case), so 1000 u / tol, never below
+    1e-12."""
+    return max(1e-12, 1000.0 * EPS / tol)
 
 
 def say(*a):
@@ -63,10 +65,10 @@ def compare_skeletons(F, skeletons: dict):
     return len(skeletons)
 
 
-def compare_record(F, depth: int, box: int, ref: dict, tol: float):
+def compare_record(F, depth: int, box: int, ref: dict, tol: float, weak: bool = False):
     """T, X_RR, X_JR (= E X_RR of the oracle) and G element-wise, J exactly; the rows of J
     are matched by global index.  Returns the largest relative difference."""
-    g = F.box_record(depth, box)
+    g = F.box_record(depth, box, weak=weak)
     assert np.array_equal(g["J"], ref["J"]), (depth, box, "J list")
     worst = 0.0
     for key in ("T", "XRR", "XJR", "G"):

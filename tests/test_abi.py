@@ -50,12 +50,12 @@ def test_params_default_and_argument_errors():
     lib.rss_params_default(ctypes.byref(p), 2, rss.RSS_K_LAPLACE2D)
     assert p.struct_size == ctypes.sizeof(rss.Params)
     assert (p.dim, p.kernel, p.symmetric, p.diag, p.tol, p.leaf_size, p.n_proxy, p.proxy_radius, p.root_side,
-            p.arena_bytes, p.reserved) == (2, 0, 1, 1.0, 1e-6, 64, 16, 1.25, 1.0, 0, 0)
+            p.arena_bytes, p.method) == (2, 0, 1, 1.0, 1e-6, 64, 16, 1.25, 1.0, 0, 0)
     h = ctypes.c_void_p(123)
     fake = ctypes.c_void_p(1)   # never dereferenced: validation fails first
     for field, val, want in [("tol", -1.0, 1), ("tol", float("nan"), 1), ("leaf_size", 0, 1),
                              ("leaf_size", 100000, 1), ("n_proxy", 0, 1), ("proxy_radius", 0.5, 1),
-                             ("proxy_radius", 3.0, 1), ("dim", 4, 1), ("kernel", 9, 1), ("reserved", 1, 1),
+                             ("proxy_radius", 3.0, 1), ("dim", 4, 1), ("kernel", 9, 1), ("method", 2, 1),
                              ("kernel", rss.RSS_K_HELMHOLTZ2D, 5), ("symmetric", 0, 5)]:
         q = rss.Params()
         lib.rss_params_default(ctypes.byref(q), 2, rss.RSS_K_LAPLACE2D)

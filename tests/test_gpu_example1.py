@@ -28,9 +28,12 @@ def test_parity_first_kind_grid64(rss, tol):
     n = 64
     # cond(A) = 7.7e3 for this first-kind matrix (second kind: 1.13), which multiplies the
     # rounding differences of F^{-1} b: 1e-14 cond(A) ~ 1e-10 (measured 4e-12 in norm at
-    # tol 1e-9, 2e-14 at 1e-6)
+    # tol 1e-9, 2e-14 at 1e-6).  The records are not compared element by element here: the
+    # upper levels' ID inputs carry rounding amplified by cond(A), which T = R11^{-1} R12
+    # amplifies again by up to 1 / tol (1e-3 relative at tol 1e-9); they are compared on
+    # the second-kind cases, and the skeleton sets, F^{-1} b, F b and log|det| here.
     _compare(rss, f"first_kind_grid64_tol{tol}", W.grid_points(n), O.Params(**W.problem_first_kind(n, tol)),
-             bound=1e-10)
+             bound=1e-10, records=False)
 
 
 @pytest.mark.parametrize("n,tol,precision", [(512, 1e-6, "fp64"), (512, 1e-6, "mixed"), (1024, 1e-6, "mixed")])

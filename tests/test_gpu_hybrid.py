@@ -1,0 +1,109 @@
+"""GPU parity of the hybrid factorization RS-WS (Section 3.4, eqs. weakskel and rws,
+Algorithm 2) against the oracle on the same seeded inputs, through the C ABI.
+
+Per case: the weak and the strong skeleton / redundant sets of every box of every level and
+the top set exactly; every record (T, X_RR, X_JR, G, J; a weak record has J = S)
+element-wise; F^{-1} b, F b element-wise and log|det F|.  At 64^2 and 512^2: e_a <= 10 tol,
+GMRES with F^{-1} within the iteration bounds GMRES without it fails, and less device
+memory than RS-S (the reason for RS-WS, Section 3.4).
+"""
+import numpy as np
+import pytest
+
+from oracle import rss_oracle as O
+from paper_1609_08130_amd import workloads as W
+from tests.example1_util import power_norm
+from tests.parity_util import compare_record, rel_maxdiff, say, vec_bound
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08130_amd import rss as mod
+    return mod
+
+
+def _factor(rss, pts, p: O.Params, precision="fp64"):
+    return rss.Factor(torch.tensor(pts, dtype=torch.float64, device="cuda"), diag=p.diag, weight=p.weight, tol=p.tol,
+                      leaf_size=p.leaf_size, n_proxy=p.n_proxy, proxy_radius=p.proxy_radius, root_lo=p.root_lo,
+                      root_side=p.root_side, precision=precision, method="rs-ws" if p.hybrid else "rs-s")
+
+
+def _sets_match(F, sk, weak):
+    bad = []
+    for (t, box), (S, R) in sk.items():
+        Sg, Rg = F.box_sets(t, box, weak=weak)
+        if not (np.array_equal(Sg, S) and np.array_equal(Rg, R)):
+            bad.append((t, box, weak, len(S), len(Sg)))
+    assert not bad, bad[:10]
+
+
+CASES = {
+    "grid64": lambda: (W.grid_points(64), O.Params(**W.problem(64, 1e-6), hybrid=True)),
+    "grid64_leaf16_tol1e-3": lambda: (W.grid_points(64), O.Params(**W.problem(64, 1e-3, leaf_size=16), hybrid=True)),
+    "grid64_tol1e-9": lambda: (W.grid_points(64), O.Params(**W.problem(64, 1e-9), hybrid=True)),
+    "grid100": lambda: (W.grid_points(100), O.Params(**W.problem(100, 1e-6), hybrid=True)),
+    "random3000_leaf24": lambda: (W.random_points(3000, seed=7),
+                                  O.Params(weight=1.0 / 3000, tol=1e-6, leaf_size=24, hybrid=True)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_hybrid_parity(rss, case):
+    pts, p = CASES[case]()
+    say(f"[hybrid] case={case} N={len(pts)} tol={p.tol} leaf={p.leaf_size}")
+    F = _factor(rss, pts, p)
+    R = O.factor(pts, p)
+    assert F.shape()[0] == R.depth
+    _sets_match(F, R.weak_skeletons, True)
+    _sets_match(F, R.skeletons, False)
+    assert np.array_equal(F.top_set(), R.top)
+    worst = 0.0
+    for r in R.records:
+        worst = max(worst, compare_record(F, r.depth, r.box, dict(T=r.T, XRR=r.XRR, XJR=r.E @ r.XRR, G=r.G, J=r.J),
+                                          p.tol, weak=r.kind == "weak"))
+    b = W.rhs(len(pts), seed=0)
+    bt = torch.tensor(b, device="cuda")
+    x, y = F.solve(bt).cpu().numpy(), F.apply(bt).cpu().numpy()
+    xr, yr = O.solve(R, b), O.apply(R, b)
+    sg, ld = F.logdet()
+    sr, lr = O.logdet(R)
+    nweak = sum(r.kind == "weak" for r in R.records)
+    say(f"[hybrid] case={case} records={len(R.records)} (weak {nweak}) worst_record_rel={worst:.2e} "
+        f"solve_maxrel={rel_maxdiff(x, xr):.2e} apply_maxrel={rel_maxdiff(y, yr):.2e} top={len(R.top)}")
+    bound = vec_bound(p.tol)
+    np.testing.assert_allclose(x, xr, rtol=0, atol=bound * np.abs(xr).max())
+    np.testing.assert_allclose(y, yr, rtol=0, atol=bound * np.abs(yr).max())
+    assert sg == sr and abs(ld - lr) <= bound * max(1.0, abs(lr)) + 1e-14 * len(pts)
+    info = F.info()
+    assert info["method"] == "rs-ws" and any(l["pass"] == "weak" for l in info["levels"])
+    F.close()
+
+
+@pytest.mark.parametrize("n,precision", [(64, "fp64"), (512, "fp64"), (512, "mixed")])
+def test_hybrid_accuracy_and_memory(rss, n, precision):
+    tol = 1e-6
+    pts = W.grid_points(n)
+    p = O.Params(**W.problem(n, tol), hybrid=True)
+    F = _factor(rss, pts, p, precision)
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    x0 = torch.randn(n * n, generator=gen, dtype=torch.float64).cuda()
+    tn = lambda t: float(torch.linalg.norm(t))
+    e_a = power_norm(lambda v: F.matvec(v) - F.apply(v), x0, norm=tn) / power_norm(F.matvec, x0, norm=tn)
+    b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
+    use32 = precision == "mixed"
+    _, it, rr = F.gmres(b, rtol=1e-10, maxit=30, use_fp32=use32)
+    mem_ws = F.info()["bytes_device"]
+    F.close()
+    S = _factor(rss, pts, O.Params(**W.problem(n, tol)), precision)
+    mem_s = S.info()["bytes_device"]
+    S.close()
+    say(f"[hybrid] N={n * n} {precision}: e_a={e_a:.2e} gmres iters={it} relres={rr:.2e} "
+        f"device bytes RS-WS {mem_ws} vs RS-S {mem_s} ({mem_ws / mem_s:.2f})")
+    assert e_a <= 10 * tol
+    assert it <= (2 if precision == "fp64" else 3) and rr <= 1e-10
+    assert mem_ws < mem_s

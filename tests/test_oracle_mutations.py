@@ -17,11 +17,13 @@ from tests import dense_rss
 SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "rss_oracle.py")
 
 MUTATIONS = {
-    "sign_in_X_RR": ("X_RR = Z_R - T.T @ Z_S", "X_RR = Z_R + T.T @ Z_S"),
+    "sign_in_X_RR": ("X_RR = Z_R - T.T @ Z_S\n    X_RS = A_RS - T.T @ A_SS\n    X_RN",
+                     "X_RR = Z_R + T.T @ Z_S\n    X_RS = A_RS - T.T @ A_SS\n    X_RN"),
     "dropped_term_Z_N": ("Z_N = A_NR - A_NS @ T", "Z_N = A_NR + 0.0 * (A_NS @ T)"),
     "wrong_index_schur": ("lev.store[(c, b)][spos, :] -= blk", "lev.store[(c, b)][spos, :] += 0.0 * blk"),
     "transposed_solve": ("z[r.R] -= r.T.T @ z[r.S]", "z[r.R] -= (r.T.T @ z[r.S]) * 0.5"),
-    "proxy_rows_dropped": ("M = np.vstack(rows)", "M = np.vstack(rows[:-1] or [np.zeros((1, n))])"),
+    "proxy_rows_dropped": ("M = np.vstack(rows)\n    res = cpqr_id(M, p.tol)",
+                           "M = np.vstack(rows[:-1] or [np.zeros((1, n))])\n    res = cpqr_id(M, p.tol)"),
 }
 
 
