@@ -142,6 +142,20 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
                      int32_t restart, int32_t use_fp32, void* stream, int32_t* iters,
                      double* relres);
 
+/* rss_gmres for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same iteration, bit for bit,
+ * with its Krylov basis and work vectors in a device array of the library instead of memory
+ * allocated per call.  The array holds RSS_GMRES_NOALLOC_BYTES (256 MiB); every GPU the
+ * library runs on holds its own copy until the process ends.  Limits: restart <= 64 and
+ * (2 restart + 3) N + 1024 <= RSS_GMRES_NOALLOC_BYTES / 8 doubles (N = 1048576 allows
+ * restart <= 14), else RSS_E_ARG with nothing written.  All calls on one GPU share the
+ * array, which keeps the last call's contents (each call writes every entry before reading
+ * it): calls that overlap in time on one GPU race, and the caller must serialize them. */
+#define RSS_GMRES_NOALLOC_BYTES ((uint64_t)256 << 20)
+rss_status rss_gmres_noalloc(rss_factor f, const double* d_b, double* d_x, double rtol, int32_t maxit,
+                             int32_t restart, int32_t use_fp32, void* stream, int32_t* iters,
+                             double* relres);
+
 /* log det F = log det D (Section 3.3: the V_i, W_i are unit triangular, and log|D|
  * approximates log|K|) as a complex number re + i im with im in (-pi, pi]: for a real
  * matrix re = log|det F| and im = 0 (det > 0) or pi (det < 0). */

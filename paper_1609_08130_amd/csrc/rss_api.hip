@@ -1250,6 +1250,66 @@ rss_status rss_gmres(rss_factor f, const double* d_b, double* d_x, double rtol, 
     return st;
 }
 
+// ---- the entry point that allocates nothing ------------------------------------------------
+// Work arrays of rss_gmres_noalloc: one array in the code object, so that the entry point
+// never allocates; every GPU that runs the library holds its own copy, at its own address,
+// from the module's load on that GPU until the process ends.  In host code `scratch` names
+// a host-side stand-in, not device memory: host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[RSS_GMRES_NOALLOC_BYTES / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+double* scratch_on_current_device() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(RSS_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(RSS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (double*)p;
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
+
+rss_status rss_gmres_noalloc(rss_factor f, const double* d_b, double* d_x, double rtol, int32_t maxit,
+                             int32_t restart, int32_t use_fp32, void* stream, int32_t* iters, double* relres) {
+    constexpr int kMaxRestart = 64;
+    g_err.clear();
+    if (guard_factor(f) != RSS_OK) return RSS_E_ARG;
+    if (!d_b || !d_x || d_b == d_x || !(rtol > 0) || maxit < 1 || restart < 1 || restart > kMaxRestart) {
+        g_err = "bad gmres arguments (rss_gmres_noalloc takes restart <= 64)";
+        return RSS_E_ARG;
+    }
+    const size_t nd = gmres_device_doubles(f->n, restart);
+    if (nd > RSS_GMRES_NOALLOC_BYTES / sizeof(double)) {
+        g_err = "rss_gmres_noalloc needs (2 restart + 3) N + 1024 = " + std::to_string(nd) +
+                " doubles, more than its " + std::to_string(RSS_GMRES_NOALLOC_BYTES / sizeof(double)) +
+                " (lower restart, or use rss_gmres)";
+        return RSS_E_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int use32 = (use_fp32 && f->params.precision == RSS_MIXED) ? 1 : 0;
+    double H[(kMaxRestart + 1) * kMaxRestart], cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart],
+        hpart[1024];
+    try {
+        GmresWork w = gmres_work_on(scratch_on_current_device(), f->n, restart);
+        w.H = H; w.cs = cs; w.sn = sn; w.g = g; w.y = y; w.hpart = hpart;
+        return gmres_run(f, d_b, d_x, rtol, maxit, restart, use32, s, w, iters, relres);
+    } catch (const Fail& e) {
+        (void)hipStreamSynchronize(s);
+        return e.st;
+    }
+}
+
 rss_status rss_logdet(rss_factor f, double* re, double* im) {
     g_err.clear();
     if (guard_factor(f) != RSS_OK) return RSS_E_ARG;

@@ -33,6 +33,7 @@ STATUS = {0: "RSS_OK", 1: "RSS_E_ARG", 2: "RSS_E_NOMEM", 3: "RSS_E_DEVICE", 4: "
 
 # exported names declared in include/rss.h
 EXPORTS = ["rss_params_default", "rss_factor_create", "rss_solve", "rss_apply", "rss_sqrt_apply", "rss_matvec", "rss_gmres",
+           "rss_gmres_noalloc",
            "rss_logdet", "rss_shape", "rss_box_sets", "rss_box_record", "rss_top_set", "rss_info",
            "rss_factor_destroy", "rss_last_error", "rss_trim"]
 
@@ -79,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rss_sqrt_apply.argtypes = [vp, vp, vp, i32, i64, i32, vp]
     lib.rss_matvec.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.rss_gmres.argtypes = [vp, vp, vp, dbl, i32, i32, i32, vp, P(i32), P(dbl)]
+    lib.rss_gmres_noalloc.argtypes = [vp, vp, vp, dbl, i32, i32, i32, vp, P(i32), P(dbl)]
     lib.rss_logdet.argtypes = [vp, P(dbl), P(dbl)]
     lib.rss_shape.argtypes = [vp, P(i32), P(i64)]
     lib.rss_box_sets.argtypes = [vp, i32, i64, i32, P(i64), i32, P(i32), P(i64), i32, P(i32)]
@@ -203,6 +205,19 @@ class Factor:
         if st != 6 or raise_on_noconv:
             _check(st)
         return x, it.value, rr.value
+
+    def gmres_noalloc(self, b, x, rtol: float = 1e-10, maxit: int = 100, restart: int = 8, use_fp32: bool = False):
+        """rss_gmres_noalloc: the same iteration with the library's own device work array (no
+        allocation); x is a caller-provided output (no allocation here either).  Returns
+        (status, iterations, relres) without raising on RSS_E_NOCONV."""
+        it = ctypes.c_int32()
+        rr = ctypes.c_double()
+        st = lib().rss_gmres_noalloc(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                     float(rtol), int(maxit), int(restart), int(bool(use_fp32)),
+                                     _stream(self._torch), ctypes.byref(it), ctypes.byref(rr))
+        if st not in (0, 6):
+            _check(st)
+        return st, it.value, rr.value
 
     def sqrt_apply(self, x, adjoint: bool = False):
         """y = F^{1/2} x, or (F^{1/2})^* x with adjoint (generalized square root, Section 3.3)."""
