@@ -55,6 +55,7 @@ void reload_plan_overrides() {
             else if (key == "elim_tw" && (v == 4 || v == 8 || v == 16 || v == 32)) q.elim_tw = v;
             else if (key == "inv_threads" && (v == 256 || v == 1024)) q.inv_threads = v;
             else if (key == "sweep_threads" && (v == 256 || v == 1024)) q.sweep_threads = v;
+            else if (key == "gram_i8") q.gram_i8 = v != 0;
         }
     }
     g_plan_ready = true;
@@ -488,12 +489,11 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         tmpl[2 * i + 1] = std::sin(th);
     }
     double* ptmpl = h2d(f, tmpl, s);
-    // The tree and leaf-store times and the duplicate-point flag (bit 2) are read at the
-    // first synchronization, after the first level; the level transitions likewise report
-    // their time at the synchronization after them.
-    bool first_sync = true;
-    hipEvent_t et_pend0 = nullptr, et_pend1 = nullptr;
-    std::vector<int> last_nact;   // active DOFs per box after the last skeletonized level
+    // The level boundaries synchronize once each, for the one number the host needs to size
+    // the next level (its largest box) and the error flags; the per-level statistics, the
+    // solve schedule and the phase times are read once, after the top block.
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> trans_ev;   // transitions and compactions
+    bool checked_points = false;
 
     const bool mixed = p.precision == RSS_MIXED;
     double* work = nullptr;
@@ -504,9 +504,29 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     int* tl64_cnt = nullptr;     // mixed: lists of the S x S tiles
     int* tl64_tiles = nullptr;
 
+    // Error bits of the device flag: 1 points outside the root box, 2 duplicate points,
+    // 4 singular X_RR.
+    auto check_flag = [&](int fl) {
+        if (!checked_points) {
+            checked_points = true;
+            if (fl & 2) fail(RSS_E_ARG, "duplicate points");
+        }
+        if (fl & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
+    };
+
+    // Largest and total active counts of the next level (see launch_level_sizes): the
+    // boundary's one synchronization.
+    auto level_sizes = [&](const rss::Level& L, int group, int* pc) -> std::pair<int, int64_t> {
+        HIPCHK(hipMemsetAsync(f->flag + 8, 0, sizeof(int) * 2, s));
+        rss::launch_level_sizes(L.nact, L.nb, group, pc, f->flag + 8, s);
+        check_launch();
+        auto hv = d2h_many(f, {{f->flag, 1}, {f->flag + 8, 2}}, s);
+        check_flag(hv[0][0]);
+        return {hv[1][0], (int64_t)hv[1][1]};
+    };
+
     // One pass over the colours of level L: the ID, elimination and Schur launches of every
-    // colour (strong skeletonization, or with weak = 1 the weak skeletonization of RS-WS),
-    // then one synchronization for the flags, the statistics and the solve schedule.
+    // colour (strong skeletonization, or with weak = 1 the weak skeletonization of RS-WS).
     auto run_pass = [&](rss::Level& L, int weak) {
         L.weak = weak;
         if (weak) L.ldJ = L.nmax;   // J = S
@@ -519,7 +539,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (auto& v : L.colour_boxes) maxc = std::max(maxc, v.size());
         L.d_colour_boxes = h2d_lists(f, L.colour_boxes, s);
         alloc_level_records(f, L, mixed);
-        size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc, weak));
+        size_t need = std::max(maxc * (size_t)L.nmax * L.nmax, rss::id_work_doubles(L.nmax, p.n_proxy, maxc, weak, L.store32));
         if (need > work_n) {
             if (work) defer_free(f, work, work_n * sizeof(double));
             work = dalloc<double>(f, need);
@@ -541,7 +561,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         HIPCHK(hipMemsetAsync(tl_cnt, 0, sizeof(int) * 9 * 8, s));
         if (mixed) HIPCHK(hipMemsetAsync(tl64_cnt, 0, sizeof(int) * 9 * 8, s));
-        std::vector<hipEvent_t> ev;
+        std::vector<hipEvent_t>& ev = L.pass_ev;
+        ev.clear();
         ev.push_back(evs.rec(s));
         for (int col = 0; col < 9; ++col) {
             int nbx = (int)L.colour_boxes[col].size();
@@ -578,72 +599,6 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             f->kernel_launches[PH_ELIM] += ne;
             f->kernel_launches[PH_SCHUR] += 1;
         }
-        // flag, statistics and solve schedule: one synchronization
-        const size_t nbx = (size_t)L.nbox;
-        auto hv = d2h_many(f, {{f->flag, 1}, {L.cnt, nbx}, {L.krank, nbx}, {L.nJ, nbx}, {L.mrows, nbx}, {L.nact, nbx}},
-                           s);
-        double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_sxs = 0;
-        for (size_t i = 1; i < ev.size(); i += 4) {
-            lv_id += ev_ms(ev[i - 1], ev[i]);
-            lv_elim += ev_ms(ev[i], ev[i + 1]);
-            lv_sxs += ev_ms(ev[i + 1], ev[i + 2]);
-            lv_schur += ev_ms(ev[i + 2], ev[i + 3]);
-        }
-        f->phase_ms[PH_ID] += lv_id;
-        f->phase_ms[PH_ELIM] += lv_elim;
-        f->phase_ms[PH_SCHUR] += lv_schur;
-        f->phase_ms[PH_SCHUR_SXS] += lv_sxs;
-        if (first_sync) {
-            first_sync = false;
-            f->phase_ms[PH_TREE] += ev_ms(e0, e1);
-            f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
-            if (hv[0][0] & 2) fail(RSS_E_ARG, "duplicate points");
-        }
-        if (et_pend0) {
-            f->phase_ms[PH_TRANS] += ev_ms(et_pend0, et_pend1);
-            et_pend0 = et_pend1 = nullptr;
-        }
-        if (hv[0][0] & 4) fail(RSS_E_SINGULAR, "singular redundant block X_RR");
-        if (hv[0][0] & 64) rss::note_shape("elim_inv_gauss_jordan_lds");
-        L.h_cnt = std::move(hv[1]);
-        L.h_k = std::move(hv[2]);
-        std::vector<int> hJ = std::move(hv[3]);
-        std::vector<int> hm = std::move(hv[4]);
-        last_nact = std::move(hv[5]);   // active DOFs per box after this level
-        L.rec_boxes.assign(9, {});
-        for (int col = 0; col < 9; ++col)
-            for (int b : L.colour_boxes[col])
-                if (hJ[b] > 0) L.rec_boxes[col].push_back(b);
-        L.d_rec_boxes = h2d_lists(f, L.rec_boxes, s);
-        rss::LevelStats st;
-        st.depth = L.t; st.weak = weak; st.boxes = L.nbox; st.nmax = L.nmax;
-        st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_sxs = lv_sxs;
-        for (int b = 0; b < L.nbox; ++b) {
-            double n = L.h_cnt[b], k = L.h_k[b], r = n - k, J = hJ[b], m = hm[b];
-            if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
-            if (J <= 0) continue;
-            st.records += 1;
-            st.sum_k += k; st.sum_r += r; st.sum_J += J;
-            st.max_k = std::max(st.max_k, (int)k);
-            st.max_J = std::max(st.max_J, (int)J);
-            st.flops_x += 4.0 * J * r * k + 4.0 * r * r * k;
-            st.flops_lu += 2.0 / 3.0 * r * r * r;
-            st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
-            // target read + write of the store entries and the two operands once
-            if (mixed) {
-                // S x S in FP64 (its own launch), the rest with FP32 products
-                st.flops_schur_sxs += 2.0 * k * k * r;
-                st.bytes_schur_sxs += 16.0 * k * k + 8.0 * 2.0 * k * r;
-                st.flops_schur += 2.0 * (J * J - k * k) * r;
-                st.bytes_schur += (L.store32 ? 8.0 : 16.0) * (J * J - k * k) + 4.0 * 2.0 * J * r;
-            } else {
-                st.flops_schur += 2.0 * J * J * r;
-                st.bytes_schur += 16.0 * J * J + 8.0 * 2.0 * J * r;
-            }
-            st.bytes_solve64 += 8.0 * (2.0 * J * r + 2.0 * k * r + r * r);
-            st.bytes_solve32 += 4.0 * (2.0 * J * r + 2.0 * k * r + r * r);
-        }
-        f->stats.push_back(st);
     };
 
     // Level transition to the parent level (B_parent = union of the children's active DOFs);
@@ -652,18 +607,8 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         hipEvent_t et0 = evs.rec(s);
         rss::Level P;
         P.t = L.t - 1; P.nb = L.nb / 2; P.nbox = P.nb * P.nb;
-        // parent counts from the children's active counts, on the host (no synchronization)
-        std::vector<int> pc(P.nbox);
-        for (int py = 0; py < P.nb; ++py)
-            for (int px = 0; px < P.nb; ++px) {
-                int sum = 0;
-                for (int iy = 0; iy < 2; ++iy)
-                    for (int ix = 0; ix < 2; ++ix) sum += last_nact[(2 * px + ix) + L.nb * (2 * py + iy)];
-                pc[px + P.nb * py] = sum;
-            }
-        P.cnt = h2d(f, pc, s);
-        int pmax = 1;
-        for (int v : pc) pmax = std::max(pmax, v);
+        P.cnt = dalloc<int>(f, P.nbox);
+        const int pmax = std::max(1, level_sizes(L, 2, P.cnt).first);
         if (pmax > rss::kMaxBox) fail(RSS_E_UNSUPPORTED, "a box holds " + std::to_string(pmax) +
                                                              " active DOFs (limit 256); lower the tolerance demand");
         P.nmax = pmax;
@@ -680,8 +625,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         rss::launch_parent_store(L, P, pmap, f->pts, f->kp, s);
         check_launch();
         init_active(P, s);
-        et_pend0 = et0;
-        et_pend1 = evs.rec(s);
+        trans_ev.push_back({et0, evs.rec(s)});
         defer_free(f, pmap, sizeof(int) * (size_t)P.nbox * P.nmax);
         defer_free(f, L.store, L.store_bytes());
         L.store = nullptr;
@@ -698,12 +642,10 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         hipEvent_t ec0 = evs.rec(s);
         rss::Level C;
         C.t = L.t; C.nb = L.nb; C.nbox = L.nbox;
-        int cmax = 1;
-        for (int v : last_nact) cmax = std::max(cmax, v);
-        C.nmax = cmax;
+        C.cnt = dalloc<int>(f, C.nbox);
+        C.nmax = std::max(1, level_sizes(L, 1, C.cnt).first);
         C.ldJ = 9 * C.nmax;
         C.store32 = L.store32;
-        C.cnt = h2d(f, last_nact, s);
         C.gidx = dalloc<int>(f, (size_t)C.nbox * C.nmax);
         C.nact = dalloc<int>(f, C.nbox);
         C.apos = dalloc<int>(f, (size_t)C.nbox * C.nmax);
@@ -712,8 +654,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         rss::launch_compact(L, C, s);
         check_launch();
         init_active(C, s);
-        et_pend0 = ec0;
-        et_pend1 = evs.rec(s);
+        trans_ev.push_back({ec0, evs.rec(s)});
         defer_free(f, L.store, L.store_bytes());
         L.store = nullptr;
         if (L.dstore) defer_free(f, L.dstore, L.dstore_bytes());
@@ -737,26 +678,15 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         L = transition(L);
         run_pass(L, 1);
     }
-    if (work) dfree(f, work, work_n * sizeof(double));
-    if (tl_tiles) dfree(f, tl_tiles, tl_n * sizeof(int));
-    if (tl_cnt) dfree(f, tl_cnt, sizeof(int) * 9 * 8);
-    if (tl64_tiles) dfree(f, tl64_tiles, tl_n * sizeof(int));
-    if (tl64_cnt) dfree(f, tl64_cnt, sizeof(int) * 9 * 8);
-    if (first_sync) {
-        // no skeletonized level (depth <= 1): the flag, the phase times and the active
-        // counts of the leaves are read here
-        auto hv = d2h_many(f, {{f->flag, 1}, {L.nact, (size_t)L.nbox}}, s);
-        first_sync = false;
-        f->phase_ms[PH_TREE] += ev_ms(e0, e1);
-        f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
-        if (hv[0][0] & 2) fail(RSS_E_ARG, "duplicate points");
-        last_nact = std::move(hv[1]);
-    }
+    if (work) defer_free(f, work, work_n * sizeof(double));
+    if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
+    if (tl_cnt) defer_free(f, tl_cnt, sizeof(int) * 9 * 8);
+    if (tl64_tiles) defer_free(f, tl64_tiles, tl_n * sizeof(int));
+    if (tl64_cnt) defer_free(f, tl64_cnt, sizeof(int) * 9 * 8);
 
     // top block
     hipEvent_t eT0 = evs.rec(s);
-    int64_t ntop = 0;
-    for (int v : last_nact) ntop += v;
+    const int64_t ntop = level_sizes(L, 1, nullptr).second;
     f->ntop = ntop;
     f->top_idx = dalloc<int>(f, ntop);
     int* tmap = dalloc<int>(f, ntop);
@@ -807,6 +737,76 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         dfree(f, L.gidx, sizeof(int) * (size_t)L.nbox * L.nmax);
         dfree(f, L.nact, sizeof(int) * L.nbox);
         dfree(f, L.apos, sizeof(int) * (size_t)L.nbox * L.nmax);
+    }
+    // Per-level statistics, the solve schedule (boxes with a record, per colour) and the phase
+    // times: one read of every level's counts.
+    {
+        std::vector<std::pair<const int*, size_t>> src = {{f->flag, 1}};
+        for (auto& Lv : f->levels) {
+            const size_t nbx = (size_t)Lv.nbox;
+            src.push_back({Lv.cnt, nbx});
+            src.push_back({Lv.krank, nbx});
+            src.push_back({Lv.nJ, nbx});
+            src.push_back({Lv.mrows, nbx});
+        }
+        auto hv = d2h_many(f, src, s);
+        if (hv[0][0] & 64) rss::note_shape("elim_inv_gauss_jordan_lds");
+        f->phase_ms[PH_TREE] += ev_ms(e0, e1);
+        f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
+        for (auto& te : trans_ev) f->phase_ms[PH_TRANS] += ev_ms(te.first, te.second);
+        for (size_t li = 0; li < f->levels.size(); ++li) {
+            rss::Level& Lv = f->levels[li];
+            const std::vector<hipEvent_t>& ev = Lv.pass_ev;
+            double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_sxs = 0;
+            for (size_t i = 1; i + 2 < ev.size(); i += 4) {
+                lv_id += ev_ms(ev[i - 1], ev[i]);
+                lv_elim += ev_ms(ev[i], ev[i + 1]);
+                lv_sxs += ev_ms(ev[i + 1], ev[i + 2]);
+                lv_schur += ev_ms(ev[i + 2], ev[i + 3]);
+            }
+            f->phase_ms[PH_ID] += lv_id;
+            f->phase_ms[PH_ELIM] += lv_elim;
+            f->phase_ms[PH_SCHUR] += lv_schur;
+            f->phase_ms[PH_SCHUR_SXS] += lv_sxs;
+            Lv.h_cnt = std::move(hv[1 + 4 * li]);
+            Lv.h_k = std::move(hv[2 + 4 * li]);
+            const std::vector<int>& hJ = hv[3 + 4 * li];
+            const std::vector<int>& hm = hv[4 + 4 * li];
+            Lv.rec_boxes.assign(9, {});
+            for (int col = 0; col < 9; ++col)
+                for (int b : Lv.colour_boxes[col])
+                    if (hJ[b] > 0) Lv.rec_boxes[col].push_back(b);
+            Lv.d_rec_boxes = h2d_lists(f, Lv.rec_boxes, s);
+            rss::LevelStats st;
+            st.depth = Lv.t; st.weak = Lv.weak; st.boxes = Lv.nbox; st.nmax = Lv.nmax;
+            st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_sxs = lv_sxs;
+            for (int b = 0; b < Lv.nbox; ++b) {
+                double n = Lv.h_cnt[b], k = Lv.h_k[b], r = n - k, J = hJ[b], m = hm[b];
+                if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
+                if (J <= 0) continue;
+                st.records += 1;
+                st.sum_k += k; st.sum_r += r; st.sum_J += J;
+                st.max_k = std::max(st.max_k, (int)k);
+                st.max_J = std::max(st.max_J, (int)J);
+                st.flops_x += 4.0 * J * r * k + 4.0 * r * r * k;
+                st.flops_lu += 2.0 / 3.0 * r * r * r;
+                st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
+                // target read + write of the store entries and the two operands once
+                if (mixed) {
+                    // S x S in FP64 (its own launch), the rest with FP32 products
+                    st.flops_schur_sxs += 2.0 * k * k * r;
+                    st.bytes_schur_sxs += 16.0 * k * k + 8.0 * 2.0 * k * r;
+                    st.flops_schur += 2.0 * (J * J - k * k) * r;
+                    st.bytes_schur += (Lv.store32 ? 8.0 : 16.0) * (J * J - k * k) + 4.0 * 2.0 * J * r;
+                } else {
+                    st.flops_schur += 2.0 * J * J * r;
+                    st.bytes_schur += 16.0 * J * J + 8.0 * 2.0 * J * r;
+                }
+                st.bytes_solve64 += 8.0 * (2.0 * J * r + 2.0 * k * r + r * r);
+                st.bytes_solve32 += 4.0 * (2.0 * J * r + 2.0 * k * r + r * r);
+            }
+            f->stats.push_back(st);
+        }
     }
     f->work_elems = (size_t)f->n * 4 + (size_t)ntop * 8 + 4096;
     f->work = dalloc<double>(f, f->work_elems);

@@ -123,17 +123,38 @@ constexpr int kChunk = 32;        // rows staged in LDS at a time
 // the rows are cut into shorter slices and the triangle into groups of 256 2x2 tiles, so
 // that the colour still spreads over the whole chip.  The partial Gram matrices of the
 // slices are then summed by k_gram_reduce.
+// With an FP32 store and plan field gram_i8, k_gram_i8 (exact sums on the int8 matrix
+// cores, below) takes 256-row slices instead.
 struct GramPlan {
-    int slice_rows, nsl, groups, tpt, nth;
+    int slice_rows, nsl, groups, tpt, nth, i8;
 };
 
-static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes, int weak) {
+constexpr int kI8Rows = 256;   // rows of M per slice of the int8 Gram kernel
+constexpr int kI8Pitch = 80;   // LDS bytes per column of a 64-row digit chunk (+16: no bank conflicts)
+constexpr int kI8MaxN = 128;   // largest box of the int8 path
+constexpr int kI8L = 5;        // base-128 digits per entry
+constexpr int kI8Tpw = 3;      // 16 x 16 tiles of G per wave
+
+// waves of k_gram_i8 for boxes of at most nmax DOFs: 4, 8 or 12 (kI8Tpw tiles each)
+static int gram_i8_waves(int nmax) {
+    const int np16 = (nmax + 15) / 16, ntile = np16 * (np16 + 1) / 2;
+    return ntile <= 4 * kI8Tpw ? 4 : ntile <= 8 * kI8Tpw ? 8 : 12;
+}
+
+static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes, int weak, bool store32) {
     // rows of M: <= 16 boxes at distance 2 (24 at distance 1 or 2 in a weak pass), plus proxies
     const int mmax = (weak ? 24 : 16) * nmax + n_proxy;
     const int nt = (nmax + 1) / 2, ntiles = nt * (nt + 1) / 2;
     GramPlan g;
+    g.i8 = 0;
     const PlanParams pp = plan_params((int)nboxes);
-    if (pp.gram_many) {
+    if (store32 && pp.gram_i8 && nmax <= kI8MaxN) {
+        g.i8 = 1;
+        g.slice_rows = kI8Rows;
+        g.groups = 1;
+        g.tpt = 1;
+        g.nth = 64 * gram_i8_waves(nmax);
+    } else if (pp.gram_many) {
         // fewest tile slots (idle threads) over 192- and 256-thread workgroups with 3, 5 or
         // 9 tiles per thread, the fewer tiles per thread on a tie
         g.slice_rows = 256;
@@ -167,11 +188,11 @@ static int pchol_lds_rows(int nmax) { return std::max(1, std::min(nmax, 49152 / 
 
 // Workspace (doubles) for any colour of at most nboxes boxes: the plan, and with it the
 // number of slices, depends on the colour's box count.
-size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak) {
+size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak, bool store32) {
     const size_t nn = (size_t)nmax * nmax;
     size_t slices = 0;
     for (size_t b = 1; b <= nboxes; ++b)
-        slices = std::max(slices, b * (size_t)gram_plan(nmax, n_proxy, b, weak).nsl);
+        slices = std::max(slices, b * (size_t)gram_plan(nmax, n_proxy, b, weak, store32).nsl);
     return slices * nn * 2 + nboxes * nn * 2;
 }
 
@@ -430,6 +451,277 @@ __global__ void __launch_bounds__(NTH) k_gram(const ST* __restrict__ store, int 
     }
 }
 
+// ---- 1b. exact Gram sums of FP32 rows on the int8 matrix cores ---------------------------
+// In a slice of M, the rows copied from an FP32 store are fixed-point numbers column by
+// column: with E_q the largest binary exponent of column q over the slice (x = f 2^E,
+// f in [1/2, 1)) and U_q = E_q - 7 L + 1, every entry is an integer X = x 2^-U_q with
+// |X| < 2^(7 L - 1), exactly so when the column's exponents span at most 7 L - 25 (the last
+// mantissa bit of its smallest entry is then >= 2^U_q).  With L = 5 (spreads up to 10),
+// X splits into digits d_0 .. d_3 in [-64, 64] and a last one with |d| <= 64, and
+//     sum_k X_kp X_kq = sum_s 128^s S_s,   S_s = sum_{u+v=s} sum_k d_u(k,p) d_v(k,q),
+// every S_s an exact int32 sum (|S_s| <= 5 * 256 * 64^2 < 2^23) formed by
+// v_mfma_i32_16x16x64_i8, one 64-row chunk (one K step) at a time.  The 2L - 1 sums give the
+// slice's entry exactly as two int64 words (S_0..S_4 and S_5..S_8, each below 2^53 in
+// magnitude), hence as a double-double by one TwoSum, scaled by 2^(U_p + U_q).  The slice's
+// proxy rows (FP64 kernel values) add their products with TwoProd.  A slice with a wider
+// exponent spread sums on the vector units in double-double instead.  Output: k_gram's slice layout (upper triangle, hi and lo), for k_pchol.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Row and column of the 16 x 16 int32 result of v_mfma_i32_16x16x64_i8 held in element v of
+// lane l.
+__device__ inline void i8_out(int l, int v, int& i, int& j) {
+    i = 4 * (l >> 4) + v;
+    j = l & 15;
+}
+
+// The wave's tiles (P, Q) of one 64-row chunk: kI8L digit operands of each side, kI8L^2
+// products into the 2 kI8L - 1 sums of each tile.
+__device__ inline void i8_chunk_mma(const signed char* dig, int limb, const int (&tP)[kI8Tpw],
+                                    const int (&tQ)[kI8Tpw], i32x4 (&acc)[kI8Tpw][2 * kI8L - 1]) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, koff = 16 * (lane >> 4);
+#pragma unroll
+    for (int t = 0; t < kI8Tpw; ++t) {
+        if (tP[t] < 0) continue;   // the same on the whole wave
+        i32x4 a[kI8L], b[kI8L];
+#pragma unroll
+        for (int u = 0; u < kI8L; ++u) {
+            a[u] = *(const i32x4*)(dig + u * limb + (16 * tP[t] + r) * kI8Pitch + koff);
+            b[u] = *(const i32x4*)(dig + u * limb + (16 * tQ[t] + r) * kI8Pitch + koff);
+        }
+#pragma unroll
+        for (int u = 0; u < kI8L; ++u)
+#pragma unroll
+            for (int v = 0; v < kI8L; ++v)
+                acc[t][u + v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u], b[v], acc[t][u + v], 0, 0, 0);
+    }
+}
+
+// Digits of rows [c0, c0 + 64) of the slice (rows at or past nro are zero), four rows of one
+// column per item, packed four to a 32-bit LDS word: dig[u][q][row].
+template <int NTH>
+__device__ inline void i8_digits(signed char* dig, int limb, int npad_box, int c0, int nro,
+                                 const float* const* rsrc, int nmax, const int* ucol) {
+    for (int it = threadIdx.x; it < 16 * npad_box; it += NTH) {
+        const int i4 = it & 15, q = it >> 4;
+        int w[kI8L];
+#pragma unroll
+        for (int u = 0; u < kI8L; ++u) w[u] = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = c0 + 4 * i4 + e;
+            // x 2^-U_q is an integer below 2^34 in magnitude: exact in FP32, and so is every
+            // step below (rint of an exact quotient by 128; the remainder is an integer <= 64)
+            float y = 0.0f;
+            if (i < nro && q < npad_box) {
+                const float* src = rsrc[i];
+                y = src ? ldexpf(src[(int64_t)q * nmax], -ucol[q]) : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kI8L; ++u) {
+                float d = y;
+                if (u < kI8L - 1) {
+                    const float r = rintf(y * 0.0078125f);
+                    d = fmaf(r, -128.0f, y);
+                    y = r;
+                }
+                w[u] |= ((int)d & 255) << (8 * e);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kI8L; ++u) *(int*)(dig + u * limb + q * kI8Pitch + 4 * i4) = w[u];
+    }
+}
+
+// grid (slices, boxes), 64 NW threads; wave w owns tiles w, w + NW, w + 2 NW of the upper
+// triangle of 16 x 16 tiles of G.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_gram_i8(const float* __restrict__ store, int nb, int nmax,
+                                                     const int* __restrict__ cnt, const int* __restrict__ gidx,
+                                                     const int* __restrict__ nact, const int* __restrict__ apos,
+                                                     const int* __restrict__ boxes, const double* __restrict__ pts,
+                                                     const double* __restrict__ ptmpl, KernelParams kp, int t,
+                                                     double* __restrict__ gpart, int nslice) {
+#pragma clang fp contract(off)
+    constexpr int NTH = 64 * NW;
+    // one chunk's digits [L][npad][kI8Pitch]; after the products, the proxy rows [k][npad]
+    extern __shared__ double2 i8_lds[];
+    signed char* dig = (signed char*)i8_lds;
+    double* prox = (double*)i8_lds;
+    __shared__ ORing<float> oring;
+    __shared__ int ring_box[kRingMax], ring_nact[kRingMax];
+    __shared__ double pxs[kMaxProxy], pys[kMaxProxy];
+    __shared__ double colx[kI8MaxN], coly[kI8MaxN];
+    __shared__ int emax[kI8MaxN], emin[kI8MaxN], ucol[kI8MaxN];
+    __shared__ const float* rsrc[kI8Rows];
+    __shared__ int wide_s;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int c = boxes[blockIdx.y];
+    const int sl = blockIdx.x;
+    const int n = cnt[c];
+    if (n == 0) return;
+    if (sl * kI8Rows >= id_rows(nact, c, nb, kp.n_proxy, kp.weak)) return;
+    build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax, kp.weak);
+    {
+        const int cx = c % nb, cy = c / nb;
+        const double side_t = kp.side / (double)(1 << t);
+        const double ccx = kp.lo_x + ((double)cx + 0.5) * side_t;
+        const double ccy = kp.lo_y + ((double)cy + 0.5) * side_t;
+        const double rr = kp.proxy_radius * side_t;
+        for (int p = tid; p < kp.n_proxy; p += NTH) {
+            pxs[p] = ccx + rr * ptmpl[2 * p];
+            pys[p] = ccy + rr * ptmpl[2 * p + 1];
+        }
+    }
+    for (int q = tid; q < n; q += NTH) {
+        const int g = gidx[(int64_t)c * nmax + q];
+        colx[q] = pts[2 * (int64_t)g];
+        coly[q] = pts[2 * (int64_t)g + 1];
+    }
+    const int mO = oring.beg[oring.cnt];
+    const int m = mO + kp.n_proxy;
+    const int r0 = sl * kI8Rows, r1 = min(m, r0 + kI8Rows);
+    const int nro = max(min(r1, mO) - r0, 0);   // O-ring rows of the slice: [r0, r0 + nro)
+    const int p0 = max(r0, mO), npr = max(r1 - p0, 0);   // its proxy rows: [p0, p0 + npr)
+    for (int i = tid; i < kI8Rows; i += NTH) {
+        const float* src = nullptr;
+        if (i < nro) {
+            const int row = r0 + i;
+            int o = 0;
+            while (oring.beg[o + 1] <= row) ++o;
+            src = oring.base[o] + oring.ap[o][row - oring.beg[o]];
+        }
+        rsrc[i] = src;
+    }
+    __syncthreads();
+    // exponent range of every column over the slice's O-ring rows (zeros aside): one wave
+    // per column, one row per lane
+    for (int q = wv; q < n; q += NW) {
+        int hi = -100000, lo = 100000;
+        for (int i = lane; i < nro; i += 64) {
+            const float x = rsrc[i][(int64_t)q * nmax];
+            if (x != 0.0f) {
+                int ex;
+                (void)frexpf(x, &ex);
+                hi = max(hi, ex);
+                lo = min(lo, ex);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            hi = max(hi, __shfl_xor(hi, o, 64));
+            lo = min(lo, __shfl_xor(lo, o, 64));
+        }
+        if (lane == 0) {
+            emax[q] = hi;
+            emin[q] = lo;
+        }
+    }
+    if (tid == 0) wide_s = 0;
+    __syncthreads();
+    for (int q = tid; q < n; q += NTH)
+        if (emax[q] > -100000 && emax[q] - emin[q] > 7 * kI8L - 25) wide_s = 1;
+    __syncthreads();
+    double2* G = (double2*)gpart + ((int64_t)blockIdx.y * nslice + sl) * nmax * nmax;
+    if (wide_s) {
+        // exponent spread too wide for the digits: compensated sums on the vector units
+        for (int e = tid; e < n * n; e += NTH) {
+            const int p = e / n, q = e % n;
+            if (p > q) continue;
+            double sh = 0.0, se = 0.0;
+            for (int i = 0; i < nro; ++i) {
+                const double a = (double)rsrc[i][(int64_t)p * nmax], b = (double)rsrc[i][(int64_t)q * nmax];
+                double sn, te;
+                two_sum(sh, a * b, sn, te);   // FP32 products are exact in FP64
+                sh = sn;
+                se += te;
+            }
+            for (int k = 0; k < npr; ++k) {
+                const int pp = p0 - mO + k;
+                const double dxp = pxs[pp] - colx[p], dyp = pys[pp] - coly[p];
+                const double dxq = pxs[pp] - colx[q], dyq = pys[pp] - coly[q];
+                const double a = kp.coef * log(dxp * dxp + dyp * dyp), b = kp.coef * log(dxq * dxq + dyq * dyq);
+                const double pr = a * b;
+                double sn, te;
+                two_sum(sh, pr, sn, te);
+                sh = sn;
+                se += te + fma(a, b, -pr);
+            }
+            double hi, lo;
+            fast_two_sum(sh, se, hi, lo);
+            G[(int64_t)p * nmax + q] = make_double2(hi, lo);
+        }
+        return;
+    }
+    const int npad_box = (n + 15) & ~15, np16 = npad_box >> 4;
+    const int limb = ((nmax + 15) & ~15) * kI8Pitch;
+    for (int q = tid; q < npad_box; q += NTH) ucol[q] = q < n && emax[q] > -100000 ? emax[q] - 7 * kI8L + 1 : 0;
+    int tP[kI8Tpw], tQ[kI8Tpw];
+    {
+        const int ntile = np16 * (np16 + 1) / 2;
+#pragma unroll
+        for (int u = 0; u < kI8Tpw; ++u) {
+            const int tt = wv + NW * u;
+            tP[u] = -1;
+            tQ[u] = -1;
+            if (tt < ntile) {
+                int P = 0, rem = tt;
+                while (rem >= np16 - P) { rem -= np16 - P; ++P; }
+                tP[u] = P;
+                tQ[u] = P + rem;
+            }
+        }
+    }
+    i32x4 acc[kI8Tpw][2 * kI8L - 1];
+#pragma unroll
+    for (int u = 0; u < kI8Tpw; ++u)
+#pragma unroll
+        for (int s2 = 0; s2 < 2 * kI8L - 1; ++s2) acc[u][s2] = i32x4{0, 0, 0, 0};
+    for (int c0 = 0; c0 < nro; c0 += 64) {
+        __syncthreads();   // ucol written; the previous chunk's operands read
+        i8_digits<NTH>(dig, limb, npad_box, c0, nro, rsrc, nmax, ucol);
+        __syncthreads();
+        i8_chunk_mma(dig, limb, tP, tQ, acc);
+    }
+    __syncthreads();
+    // the slice's proxy rows, FP64, over the digits
+    for (int e = tid; e < npr * n; e += NTH) {
+        const int k = e / n, q = e % n;
+        const int pp = p0 - mO + k;
+        const double dx = pxs[pp] - colx[q], dy = pys[pp] - coly[q];
+        prox[k * npad_box + q] = kp.coef * log(dx * dx + dy * dy);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kI8Tpw; ++u) {
+        if (tP[u] < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int i, j;
+            i8_out(lane, v, i, j);
+            const int p = 16 * tP[u] + i, q = 16 * tQ[u] + j;
+            if (q >= n || p > q) continue;
+            // sum_s 128^s S_s = w1 2^35 + w0, both words exact in FP64
+            long long w0 = 0, w1 = 0;
+#pragma unroll
+            for (int s2 = 2 * kI8L - 2; s2 >= 0; --s2) {
+                if (s2 >= 5) w1 = w1 * 128 + acc[u][s2][v];
+                else w0 = w0 * 128 + acc[u][s2][v];
+            }
+            dd a;
+            two_sum(ldexp((double)w1, 35), (double)w0, a.hi, a.lo);
+            a.hi = ldexp(a.hi, ucol[p] + ucol[q]);
+            a.lo = ldexp(a.lo, ucol[p] + ucol[q]);
+            for (int k = 0; k < npr; ++k) {
+                const double x = prox[k * npad_box + p], y = prox[k * npad_box + q];
+                const double pr = x * y;
+                a = dd_add(a, {pr, fma(x, y, -pr)});
+            }
+            G[(int64_t)p * nmax + q] = make_double2(a.hi, a.lo);
+        }
+    }
+}
+
 // ---- 2. sum of the partial Gram matrices (few-box colours) ---------------------------------
 
 // grid (nmax^2 / 256, boxes): slice 0 <- sum over the slices that hold rows, in slice order.
@@ -678,6 +970,17 @@ static void gram_launch(const Level& L, const int* boxes, int nboxes, const doub
                                                                g.nsl, g.slice_rows);
 }
 
+template <int NW>
+static void gram_i8_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
+                           const KernelParams& kp, double* gpart, const GramPlan& g, hipStream_t s) {
+    const int npad = (L.nmax + 15) & ~15;
+    const size_t lds = std::max((size_t)kI8L * npad * kI8Pitch, sizeof(double) * kMaxProxy * npad);
+    note_shape("gram_i8_w" + std::to_string(NW));
+    k_gram_i8<NW><<<dim3(g.nsl, nboxes), dim3(64 * NW), lds, s>>>((const float*)L.store, L.nb, L.nmax, L.cnt, L.gidx,
+                                                                   L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart,
+                                                                   g.nsl);
+}
+
 template <int NTH, int SUB>
 static void pchol_launch(const Level& L, const int* boxes, int nboxes, const KernelParams& kp, double* gpart,
                          const GramPlan& g, int nsl_fixed, double* rwork, hipStream_t s) {
@@ -695,13 +998,17 @@ static void pchol_launch(const Level& L, const int* boxes, int nboxes, const Ker
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                    const KernelParams& kp, double* work, hipStream_t s) {
     if (nboxes <= 0) return 0;
-    const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes, kp.weak);
+    const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes, kp.weak, L.store32);
     const size_t nn = (size_t)L.nmax * L.nmax;
     double* gpart = work;
     double* rwork = work + (size_t)nboxes * g.nsl * nn * 2;
     const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 2);
     int launches = 2;
-    if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
+    if (g.i8) {
+        if (g.nth == 256) gram_i8_launch<4>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
+        else if (g.nth == 512) gram_i8_launch<8>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
+        else gram_i8_launch<12>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
+    } else if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3 && g.nth == 192) gram_launch<192, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3) gram_launch<256, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 5 && g.nth == 192) gram_launch<192, 5>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);

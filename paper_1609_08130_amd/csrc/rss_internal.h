@@ -78,6 +78,7 @@ struct Level {
     std::vector<int*> d_colour_boxes;
     std::vector<std::vector<int>> rec_boxes;      // boxes with a record, per colour
     std::vector<int*> d_rec_boxes;
+    std::vector<hipEvent_t> pass_ev;              // timing events of the pass (read at the end)
 };
 
 // FFT plan of the exact operator on a uniform n x n grid (L x L circulant embedding).
@@ -213,6 +214,7 @@ struct PlanParams {
     int elim_tw;         // widest elimination tile (lines of J)
     int inv_threads;     // workgroup of the X_RR inverse: 256 or 1024 threads
     int sweep_threads;   // workgroup of the solve / apply sweeps: 256 or 1024 threads
+    int gram_i8;         // 1: with an FP32 store, exact Gram sums on the int8 matrix cores
 };
 constexpr int kPlanBuckets = 5;
 extern const int kPlanBucketLo[kPlanBuckets];
@@ -239,6 +241,10 @@ void launch_leaf_store(const Level& L, const double* pts, const KernelParams& kp
 void launch_parent_lists(const Level& C, Level& P, int* pmap, hipStream_t s);
 void launch_parent_store(const Level& C, const Level& P, const int* pmap, const double* pts,
                          const KernelParams& kp, hipStream_t s);
+// Sizes of the next level from the active counts after a pass, on the device: with group 2
+// (level transition) pc[P] = sum of the active counts of P's 2 x 2 children, with group 1
+// pc = nact (pc may be nullptr); out[0] = max pc, out[1] = sum pc (zeroed by the caller).
+void launch_level_sizes(const int* nact, int nb, int group, int* pc, int* out, hipStream_t s);
 // RS-WS: C (same depth, lists and store allocated for C.nmax = the largest active count)
 // <- the active DOFs of L after its weak pass, lists and blocks compacted.
 void launch_compact(const Level& L, Level& C, hipStream_t s);
@@ -250,7 +256,7 @@ void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hip
 // Returns the number of kernels launched.
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
                     const KernelParams& kp, double* work, hipStream_t s);
-size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak);
+size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak, bool store32);
 // Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
 // Active 64 x 64 tiles of the Schur updates of one colour, in 8 lists (one per XCD: the
 // boxes with position bi = x mod 8 in the colour's list go to list x).  An entry packs

@@ -442,6 +442,33 @@ void launch_parent_store(const Level& C, const Level& P, const int* pmap, const 
             P.nmax, pts, kp.coef);
 }
 
+__global__ void k_level_sizes(const int* __restrict__ nact, int nb, int group, int* __restrict__ pc,
+                              int* __restrict__ out) {
+    const int pnb = nb / group;
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = 0;
+    if (P < pnb * pnb) {
+        const int px = P % pnb, py = P / pnb;
+        for (int iy = 0; iy < group; ++iy)
+            for (int ix = 0; ix < group; ++ix) v += nact[(group * px + ix) + nb * (group * py + iy)];
+        if (pc) pc[P] = v;
+    }
+    int mx = v, sm = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(out, mx);
+        atomicAdd(out + 1, sm);
+    }
+}
+
+void launch_level_sizes(const int* nact, int nb, int group, int* pc, int* out, hipStream_t s) {
+    const int pn = (nb / group) * (nb / group);
+    k_level_sizes<<<dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, s>>>(nact, nb, group, pc, out);
+}
+
 // ------------------------------------------------------------------------------------
 // RS-WS (Section 3.4): after the weak pass of a level the strong pass restarts on the DOFs
 // that remain active.  Box P's new list is its active DOFs in ascending order,

@@ -26,13 +26,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 BUCKET_LO = [1, 64, 256, 512, 1024]
-FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads"]
+FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads", "gram_i8"]
+# the order in which the fields are tuned (the Gram kernel first: it decides the slicing)
+ORDER = ["gram_i8", "gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads"]
 DEFAULTS = [
-    [0, 2048, 0, 1, 16, 1024, 1024],
-    [0, 2048, 0, 1, 16, 1024, 1024],
-    [0, 2048, 0, 1, 16, 256, 256],
-    [1, 2048, 16, 1, 16, 256, 256],
-    [1, 2048, 16, 4, 16, 256, 256],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0],
+    [0, 2048, 0, 1, 16, 256, 256, 0],
+    [1, 2048, 16, 1, 16, 256, 256, 0],
+    [1, 2048, 16, 4, 16, 256, 256, 0],
 ]
 # candidate values and the phase each field is judged by
 CANDIDATES = {
@@ -43,6 +45,7 @@ CANDIDATES = {
     "elim_tw": ([8, 16, 32], "elim"),
     "inv_threads": ([256, 1024], "elim"),
     "sweep_threads": ([256, 1024], "solve"),
+    "gram_i8": ([0, 1], "id"),
 }
 
 
@@ -120,7 +123,8 @@ def main():
     log = {"n": args.n, "tol": args.tol, "reps": args.reps, "buckets_used": used, "baseline_solve_ms": base_solve,
            "baseline": {f"{d}/{p}": v for (d, p), v in base.items()}, "steps": []}
     print(f"[tune] baseline solve {base_solve:.3f} ms; levels {sorted(base)}", flush=True)
-    for fi, field in enumerate(FIELDS):
+    for field in ORDER:
+        fi = FIELDS.index(field)
         cands, phase = CANDIDATES[field]
         if phase == "solve":
             for b in used:

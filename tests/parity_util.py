@@ -10,6 +10,8 @@ At tol >= 1e-6 that is <= 2.2e-10 in the worst case, but the measured agreement 
 every other record block and of F^{-1} b, F b is far tighter (see the per-case prints);
 the bounds below sit above the measured values by the margins stated with them.
 """
+import contextlib
+import os
 import sys
 
 import numpy as np
@@ -78,3 +80,20 @@ def compare_record(F, depth: int, box: int, ref: dict, tol: float, weak: bool = 
         worst = max(worst, e)
         assert e <= record_bound(tol), (depth, box, key, e)
     return worst
+
+
+@contextlib.contextmanager
+def plan_override(spec: str):
+    """Launch-plan values for the factorizations created inside the block (the library reads
+    RSS_TUNE at every rss_factor_create), so a test can run a kernel variant that the tuned
+    table does not pick for its box counts."""
+    old = os.environ.get("RSS_TUNE")
+    if spec:
+        os.environ["RSS_TUNE"] = spec
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("RSS_TUNE", None)
+        else:
+            os.environ["RSS_TUNE"] = old

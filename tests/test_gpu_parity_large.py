@@ -16,7 +16,7 @@ import pytest
 
 from paper_1609_08130_amd import workloads as W
 from tests.golden.make_oracle_fixtures import CASES, load
-from tests.parity_util import compare_record, compare_skeletons, rel_maxdiff, say, vec_bound
+from tests.parity_util import compare_record, compare_skeletons, plan_override, rel_maxdiff, say, vec_bound
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -35,11 +35,21 @@ def rss():
     # Cholesky with 16 LDS rows, 256-thread inverse) and the few-box shapes of the upper levels
     ("grid512_leaf16_tol1e-6", ["elim_rows_w16_tpw4", "elim_inv_256", "elim_inv_1024", "pchol_64x1_kc16",
                                 "solve_fwd_256_f64", "solve_fwd_1024_f64", "gram_reduce"]),
-    # leaf 64: 455 boxes per colour at the leaves (256-thread inverse and sweeps, one tile per
-    # elimination workgroup)
-    ("grid512_leaf64_tol1e-6", ["elim_rows_w16_tpw1", "elim_inv_256", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
+    # leaf 64: 455 boxes per colour at the leaves (the tuned plans of 256..511 boxes: two
+    # tiles per elimination workgroup, 1024-thread inverse, 256-thread sweeps)
+    ("grid512_leaf64_tol1e-6", ["elim_rows_w16_tpw2", "elim_inv_1024", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
+    # the same with the former plans of those colours forced (256-thread inverse, one tile per
+    # workgroup), so both variants stay checked
+    ("grid512_leaf64_tol1e-6@b2.inv_threads=256,b2.elim_tpw=1",
+     ["elim_rows_w16_tpw1", "elim_inv_256", "solve_fwd_256_f64"]),
 ])
 def test_parity_512_grid_against_stored_oracle(rss, name, shapes):
+    name, _, spec = name.partition("@")
+    with plan_override(spec):
+        _run_case(rss, name, shapes)
+
+
+def _run_case(rss, name, shapes):
     c = CASES[name]
     n = c["n"]
     ref = load(name)
