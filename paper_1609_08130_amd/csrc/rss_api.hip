@@ -505,7 +505,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     int* tl64_tiles = nullptr;
 
     // Error bits of the device flag: 1 points outside the root box, 2 duplicate points,
-    // 4 singular X_RR.
+    // 4 singular X_RR.  Bits 64 and 128 only record kernel forms that ran (rss_info shapes).
     auto check_flag = [&](int fl) {
         if (!checked_points) {
             checked_points = true;
@@ -568,7 +568,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             int nbx = (int)L.colour_boxes[col].size();
             if (nbx == 0) continue;
             const int* bx = L.d_colour_boxes[col];
-            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, s);
+            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, f->flag, s);
             check_launch();
             ev.push_back(evs.rec(s));
             rss::TileList tl, tl64;
@@ -751,6 +751,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         auto hv = d2h_many(f, src, s);
         if (hv[0][0] & 64) rss::note_shape("elim_inv_gauss_jordan_lds");
+        if (hv[0][0] & 128) rss::note_shape("gram_i8_wide");
         f->phase_ms[PH_TREE] += ev_ms(e0, e1);
         f->phase_ms[PH_KGEN] += ev_ms(e1, e2);
         for (auto& te : trans_ev) f->phase_ms[PH_TRANS] += ev_ms(te.first, te.second);

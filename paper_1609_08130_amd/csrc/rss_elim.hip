@@ -59,6 +59,7 @@ struct ElimArgs {
 };
 
 constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
+constexpr int kElimGLds = 98304;   // LDS bytes of k_elim_g with X_RR^{-1} held for all its tiles
 
 // Workgroups are dealt to the 8 XCDs round-robin in launch order.  With a grid of
 // 8 * ntile * ceil(nbox / 8) workgroups, id = x + 8 s takes box x + 8 (s / ntile) and
@@ -266,98 +267,46 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
     __syncthreads();
 }
 
-// Columns [c0, c0 + tc) of J: X_RJ = A_RJ - T^T A_SJ (tX, ld nmax + 1), then
-// G = X_RR^{-1} X_RJ.  tA, tX: (nmax + 1) x tw.  X_RR^{-1} (ld nmax) is read from Xi when
-// it is in LDS (xi_lds); otherwise it is staged through tA, tw columns at a time.  r <= 64 HB.
-template <int NTH, int HB, typename ST>
-__device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int c0, int tc, int tw,
-                            const double* Ts, double* tA, double* tX, const double* Xi, bool xi_lds, double* G,
-                            float* G32) {
+// Columns [c0, c0 + tc) of G = X_RR^{-1} X_RJ.  The kernel is real symmetric and so is
+// every stored update, so X_RJ = A_RJ - T^T A_SJ is the transpose of X_JR = A_JR - A_JS T
+// (the record k_elim_rows wrote): the tile is X_JR's rows c0 .. c0 + tc - 1, read into
+// tX[b + ldt col] (ldt = nmax + 1, odd: 16 lanes reading one row of 16 columns hit 16
+// banks).  X_RR^{-1} (ld ldw) is read from W when the workgroup holds it in LDS
+// (xi_lds); otherwise it is staged through Wst, tw columns at a time.  r <= 64 HB.
+template <int NTH, int HB>
+__device__ void elim_g_tile(const ElimArgs& a, int c, int r, int c0, int tc, int tw, double* tX, double* Wst,
+                            const double* Xi, const double* W, bool xi_lds, double* G, float* G32) {
     constexpr int NW = NTH / 64;
-    const int tid = threadIdx.x, nmax = a.nmax;
-    const int n = k + r;
+    const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int lane = tid & 63, jg = tid >> 6;
-    bool acc64;
-    const void* Acc = self_block<ST>(a, c, acc64);
-    if (tid < tc) {
-        const int jj = c0 + tid;
-        if (jj < k) {
-            sh.srcp[tid] = Acc;
-            sh.src64[tid] = acc64;
-            sh.srcpos[tid] = sh.sp[jj];
-        } else {
-            int s = 0;
-            while (sh.joff[s + 1] <= jj) ++s;
-            sh.srcp[tid] = sh.blk_cn[s];
-            sh.src64[tid] = sizeof(ST) == 8;
-            sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
-        }
-    }
-    __syncthreads();
-    // tA[rho + ldt jp] = A(B_c position of rho, J column c0 + jp), rows in the order S, R
-    // (rho < k: sp[rho]; else rp[rho - k]); ldt = nmax + 1 is odd, so that 16 lanes reading
-    // one row of 16 columns hit 16 different banks
     const int ldt = nmax + 1;
+    const double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     stage2d<NTH>(
-        n, tc,
-        [&](int rho, int jp) {
-            const int pos = rho < k ? sh.sp[rho] : sh.rp[rho - k];
-            return src_entry(sh, jp, pos + (int64_t)sh.srcpos[jp] * nmax);
-        },
-        [&](int rho, int jp, double v) { tA[rho + ldt * jp] = v; });
+        tc, r, [&](int col, int b) { return XJR[(c0 + col) + (int64_t)b * ldJ]; },
+        [&](int col, int b, double v) { tX[b + ldt * col] = v; });
     __syncthreads();
-    // Both products run transposed on the FP64 matrix cores (tc x r results, so that the 16
-    // lanes of a result row hold 16 consecutive rows of G): 16 x 16 blocks dealt to the
-    // waves, one v_mfma_f64_16x16x4 per 4 values of the inner index.  Operand layout of the
-    // instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-    // D[l / 16 + 4 v][l % 16] for v < 4.
+    // G^T = X_RJ^T X_RR^{-T} on the FP64 matrix cores (tc x r results, so that the 16 lanes
+    // of a result row hold 16 consecutive rows of G): 16 x 16 blocks dealt to the waves,
+    // one v_mfma_f64_16x16x4 per 4 values of the inner index; lane l supplies
+    // A[l % 16][l / 16] = tX[q + ldt col] and B[l / 16][l % 16] = X_RR^{-1}[b][q] and
+    // receives D[l / 16 + 4 v][l % 16] for v < 4.
     constexpr int MB = 2 * HB;   // blocks per wave: r <= 64 HB, tc <= 32, 4 waves
     static_assert(NW == 4 && kTileMax <= 32, "block count per wave assumes 4 waves and <= 32 columns");
     const int ncb = (tc + 15) / 16, nblk = ncb * ((r + 15) / 16);
     const int l16 = lane & 15, l4 = lane >> 4;
-    // X_RJ^T = A_RJ^T - A_SJ^T T: A[col][q] = tA[q + ldt col], B[q][b] = -Ts[b + r q], D
-    // starts at A_RJ^T; the result goes to tX[b + ldt col]
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int blk = jg + NW * m;
-        if (blk >= nblk) break;
-        const int cb = (blk % ncb) * 16, b = (blk / ncb) * 16 + l16;
-        f64x4 x;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = cb + l4 + 4 * v;
-            x[v] = (b < r && col < tc) ? tA[k + b + ldt * col] : 0.0;
-        }
-        const int acol = cb + l16;
-        for (int q0 = 0; q0 < k; q0 += 4) {
-            const int q = q0 + l4;
-            const double av = (acol < tc && q < k) ? tA[q + ldt * acol] : 0.0;
-            const double bv = (q < k && b < r) ? -Ts[b + r * q] : 0.0;
-            x = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = cb + l4 + 4 * v;
-            if (b < r && col < tc) tX[b + ldt * col] = x[v];
-        }
-    }
-    __syncthreads();
-    // G^T = X_RJ^T X_RR^{-T}: A[col][q] = tX[q + ldt col], B[q][b] = X_RR^{-1}[b][q]
     f64x4 acc[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) acc[m] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int qc = xi_lds ? r : tw;
     for (int q0 = 0; q0 < r; q0 += qc) {
         const int qn = min(qc, r - q0);
-        const double* W = Xi + (int64_t)q0 * nmax;
-        int ldw = nmax;
+        const double* Wq = W + (int64_t)q0 * ldt;
         if (!xi_lds) {
             stage2d<NTH>(
-                r, qn, [&](int b, int q) { return W[b + (int64_t)q * nmax]; },
-                [&](int b, int q, double v) { tA[b + ldt * q] = v; });
+                r, qn, [&](int b, int q) { return Xi[b + (int64_t)(q0 + q) * nmax]; },
+                [&](int b, int q, double v) { Wst[b + ldt * q] = v; });
             __syncthreads();
-            W = tA;
-            ldw = ldt;
+            Wq = Wst;
         }
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
@@ -367,7 +316,7 @@ __device__ void elim_g_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k,
             for (int qq = 0; qq < qn; qq += 4) {
                 const int kk = qq + l4;
                 const double av = (acol < tc && kk < qn) ? tX[(q0 + kk) + ldt * acol] : 0.0;
-                const double bv = (kk < qn && b < r) ? W[b + ldw * kk] : 0.0;
+                const double bv = (kk < qn && b < r) ? Wq[b + ldt * kk] : 0.0;
                 acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[m], 0, 0, 0);
             }
         }
@@ -871,12 +820,13 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     }
 }
 
-// grid (column tiles of J, boxes).  Dynamic LDS: Ts[tsz] | tA[(nmax + 1) tw] | tX[(nmax + 1) tw]
-template <int NTH, int HB, typename ST>
+// grid (column tiles of J, boxes).  Dynamic LDS: tX[(nmax + 1) tw] | W: X_RR^{-1}
+// [(nmax + 1) nmax] when xi_lds (loaded once for the workgroup's tiles), else a staging
+// buffer [(nmax + 1) tw].
+template <int NTH, int HB>
 __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restrict__ boxes, int nbox, int ntile,
-                                                int mixed, int* flag, int tsz, int tw, int tpw) {
+                                                int mixed, int* flag, int tw, int tpw, int xi_lds) {
     extern __shared__ double dyn[];
-    __shared__ ElimShared<ST> sh;
     int bi, tile;
     if (!xcd_tile(ntile, nbox, bi, tile)) return;
     const int c = boxes[bi];
@@ -886,22 +836,22 @@ __global__ void __launch_bounds__(NTH) k_elim_g(ElimArgs a, const int* __restric
     if (n == 0 || r == 0 || (*flag & 4)) return;
     // |J| is known from the inverse kernel: workgroups whose tiles all lie beyond it leave
     // before the set-up
-    if (tile * tpw * tw >= a.nJ[c]) return;
-    const int nmax = a.nmax, ldJ = a.ldJ;
-    const int64_t bsz = (int64_t)nmax * nmax;
-    double* Ts = dyn;
-    double* tA = dyn + tsz;
-    double* tX = tA + (int64_t)(nmax + 1) * tw;
-    elim_setup<NTH, ST>(sh, a, c, k, r, Ts);
-    __syncthreads();
-    const int nj = sh.joff[sh.nN];
+    const int nj = a.nJ[c];
+    if (tile * tpw * tw >= nj) return;
+    const int nmax = a.nmax, ldJ = a.ldJ, ldt = nmax + 1;
+    double* tX = dyn;
+    double* W = dyn + (int64_t)ldt * tw;
+    const double* Xi = a.Xinv + (int64_t)c * nmax * nmax;
+    if (xi_lds)
+        stage2d<NTH>(
+            r, r, [&](int b, int q) { return Xi[b + (int64_t)q * nmax]; },
+            [&](int b, int q, double v) { W[b + ldt * q] = v; });
     double* G = a.G + (int64_t)c * nmax * ldJ;
     float* G32 = mixed ? a.G32 + (int64_t)c * nmax * ldJ : nullptr;
-    for (int t = tile * tpw; t < (tile + 1) * tpw; ++t) {   // tpw consecutive tiles share the setup
+    for (int t = tile * tpw; t < (tile + 1) * tpw; ++t) {   // tpw consecutive tiles share the set-up
         const int c0 = t * tw;
         if (c0 >= nj) break;
-        elim_g_tile<NTH, HB, ST>(sh, a, c, k, r, c0, min(tw, nj - c0), tw, Ts, tA, tX, a.Xinv + (int64_t)c * bsz,
-                                 false, G, G32);
+        elim_g_tile<NTH, HB>(a, c, r, c0, min(tw, nj - c0), tw, tX, W, Xi, W, xi_lds != 0, G, G32);
     }
 }
 
@@ -957,9 +907,9 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     // which measured faster than 32-line tiles (leaf colours: 8.4 -> 8.0 ms per level)
     const PlanParams pp = plan_params(nboxes);
     const int twr = std::min(pp.elim_tw, tile_w(tsz, 1));
-    const int twg = std::min(pp.elim_tw, tile_w(tsz + 2 * kTileMax, 2));   // column tiles: ld nmax + 1
+    const int twg = std::min(pp.elim_tw, tile_w(2 * kTileMax, 2));   // column tiles: ld nmax + 1
     if (twr == 0 || twg == 0) return -1;
-    const size_t lr = D * (tsz + nm * twr), lg = D * (tsz + 2 * (nm + 1) * twg);
+    const size_t lr = D * (tsz + nm * twr);
     set_lds(k_elim_rows<256, ST>, lr);
     const int ntr = (L.ldJ + L.nmax + twr - 1) / twr;
     const int pr = tiles_per_wg(ntr, nboxes), gr = (ntr + pr - 1) / pr;
@@ -994,17 +944,20 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     const int ntg = (L.ldJ + twg - 1) / twg;
     const int pg = tiles_per_wg(ntg, nboxes), gt = (ntg + pg - 1) / pg;
     const dim3 gg(xcd_grid(gt, nboxes));
+    // X_RR^{-1} held in LDS for all tiles of the workgroup when it fits beside the tile
+    const int xi = D * (nm + 1) * (twg + nm) <= (size_t)kElimGLds ? 1 : 0;
+    const size_t lg = D * (nm + 1) * (twg + (xi ? nm : (size_t)twg));
     note_shape("elim_g_hb" + std::to_string(L.nmax <= 64 ? 1 : (L.nmax <= 128 ? 2 : 4)) + "_w" + std::to_string(twg) +
-               "_tpw" + std::to_string(pg));
+               "_tpw" + std::to_string(pg) + (xi ? "_xi" : ""));
     if (L.nmax <= 64) {
-        set_lds(k_elim_g<256, 1, ST>, lg);
-        k_elim_g<256, 1, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
+        set_lds(k_elim_g<256, 1>, lg);
+        k_elim_g<256, 1><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, twg, pg, xi);
     } else if (L.nmax <= 128) {
-        set_lds(k_elim_g<256, 2, ST>, lg);
-        k_elim_g<256, 2, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
+        set_lds(k_elim_g<256, 2>, lg);
+        k_elim_g<256, 2><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, twg, pg, xi);
     } else {
-        set_lds(k_elim_g<256, 4, ST>, lg);
-        k_elim_g<256, 4, ST><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, (int)tsz, twg, pg);
+        set_lds(k_elim_g<256, 4>, lg);
+        k_elim_g<256, 4><<<gg, dim3(256), lg, s>>>(a, boxes, nboxes, gt, mixed, flag, twg, pg, xi);
     }
     return 3;
 }

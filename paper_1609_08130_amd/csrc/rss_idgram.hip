@@ -129,16 +129,17 @@ struct GramPlan {
     int slice_rows, nsl, groups, tpt, nth, i8;
 };
 
-constexpr int kI8Rows = 256;   // rows of M per slice of the int8 Gram kernel
+constexpr int kI8Rows = 256;   // most rows of M per slice of the int8 Gram kernel
 constexpr int kI8Pitch = 80;   // LDS bytes per column of a 64-row digit chunk (+16: no bank conflicts)
-constexpr int kI8MaxN = 128;   // largest box of the int8 path
+constexpr int kI8MaxN = 96;    // largest box of the int8 path
 constexpr int kI8L = 5;        // base-128 digits per entry
 constexpr int kI8Tpw = 3;      // 16 x 16 tiles of G per wave
+constexpr int kI8It = 4;       // columns per thread in a 64-row chunk (16 npad <= 4 * 64 NW)
 
-// waves of k_gram_i8 for boxes of at most nmax DOFs: 4, 8 or 12 (kI8Tpw tiles each)
+// waves of k_gram_i8 for boxes of at most nmax <= kI8MaxN DOFs: 4 or 8 (kI8Tpw tiles each)
 static int gram_i8_waves(int nmax) {
     const int np16 = (nmax + 15) / 16, ntile = np16 * (np16 + 1) / 2;
-    return ntile <= 4 * kI8Tpw ? 4 : ntile <= 8 * kI8Tpw ? 8 : 12;
+    return ntile <= 4 * kI8Tpw ? 4 : 8;
 }
 
 static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes, int weak, bool store32) {
@@ -149,11 +150,16 @@ static GramPlan gram_plan(int nmax, int n_proxy, size_t nboxes, int weak, bool s
     g.i8 = 0;
     const PlanParams pp = plan_params((int)nboxes);
     if (store32 && pp.gram_i8 && nmax <= kI8MaxN) {
+        // 256-row slices; few-box colours halve them (down to one 64-row chunk) until the
+        // colour has gram_min_wg workgroups
         g.i8 = 1;
         g.slice_rows = kI8Rows;
         g.groups = 1;
         g.tpt = 1;
         g.nth = 64 * gram_i8_waves(nmax);
+        if (!pp.gram_many)
+            while (g.slice_rows > 64 && nboxes * (size_t)((mmax + g.slice_rows - 1) / g.slice_rows) < (size_t)pp.gram_min_wg)
+                g.slice_rows >>= 1;
     } else if (pp.gram_many) {
         // fewest tile slots (idle threads) over 192- and 256-thread workgroups with 3, 5 or
         // 9 tiles per thread, the fewer tiles per thread on a tie
@@ -497,26 +503,27 @@ __device__ inline void i8_chunk_mma(const signed char* dig, int limb, const int 
     }
 }
 
-// Digits of rows [c0, c0 + 64) of the slice (rows at or past nro are zero), four rows of one
-// column per item, packed four to a 32-bit LDS word: dig[u][q][row].
+// One thread's share of a 64-row chunk: for each of its kI8It columns q = (tid >> 4) +
+// (NTH / 16) j, the rows i4 + 16 e (i4 = tid & 15, e < 4) of the chunk, already loaded
+// (zero past the slice's O-ring rows or past column n).  Their digits go to LDS packed four
+// to a 32-bit word, dig[u][q][4 i4 + e]: the rows of a chunk sit in LDS in the order
+// (i4, e), the same for every column, so the products over a chunk are unchanged.
 template <int NTH>
-__device__ inline void i8_digits(signed char* dig, int limb, int npad_box, int c0, int nro,
-                                 const float* const* rsrc, int nmax, const int* ucol) {
-    for (int it = threadIdx.x; it < 16 * npad_box; it += NTH) {
-        const int i4 = it & 15, q = it >> 4;
+__device__ inline void i8_digits(signed char* dig, int limb, int npad_box, const float (&x)[kI8It][4],
+                                 const int* ucol) {
+    const int i4 = threadIdx.x & 15, qb = threadIdx.x >> 4;
+#pragma unroll
+    for (int j = 0; j < kI8It; ++j) {
+        const int q = qb + (NTH / 16) * j;
+        if (q >= npad_box) break;
         int w[kI8L];
 #pragma unroll
         for (int u = 0; u < kI8L; ++u) w[u] = 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int i = c0 + 4 * i4 + e;
             // x 2^-U_q is an integer below 2^34 in magnitude: exact in FP32, and so is every
             // step below (rint of an exact quotient by 128; the remainder is an integer <= 64)
-            float y = 0.0f;
-            if (i < nro && q < npad_box) {
-                const float* src = rsrc[i];
-                y = src ? ldexpf(src[(int64_t)q * nmax], -ucol[q]) : 0.0f;
-            }
+            float y = ldexpf(x[j][e], -ucol[q]);
 #pragma unroll
             for (int u = 0; u < kI8L; ++u) {
                 float d = y;
@@ -533,15 +540,18 @@ __device__ inline void i8_digits(signed char* dig, int limb, int npad_box, int c
     }
 }
 
-// grid (slices, boxes), 64 NW threads; wave w owns tiles w, w + NW, w + 2 NW of the upper
-// triangle of 16 x 16 tiles of G.
+// grid (slices of slice_rows <= kI8Rows rows, boxes), 64 NW threads; wave w owns tiles
+// w, w + NW, w + 2 NW of the upper triangle of 16 x 16 tiles of G.  Every thread holds its
+// share of the slice (kI8Rows / 64 chunks x kI8It columns x 4 rows) in registers from one
+// batch of loads, used by the exponent pass and then by the digits of each chunk.
 template <int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_gram_i8(const float* __restrict__ store, int nb, int nmax,
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) k_gram_i8(const float* __restrict__ store, int nb, int nmax,
                                                      const int* __restrict__ cnt, const int* __restrict__ gidx,
                                                      const int* __restrict__ nact, const int* __restrict__ apos,
                                                      const int* __restrict__ boxes, const double* __restrict__ pts,
                                                      const double* __restrict__ ptmpl, KernelParams kp, int t,
-                                                     double* __restrict__ gpart, int nslice) {
+                                                     double* __restrict__ gpart, int nslice, int slice_rows,
+                                                     int* __restrict__ flag) {
 #pragma clang fp contract(off)
     constexpr int NTH = 64 * NW;
     // one chunk's digits [L][npad][kI8Pitch]; after the products, the proxy rows [k][npad]
@@ -560,7 +570,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     const int sl = blockIdx.x;
     const int n = cnt[c];
     if (n == 0) return;
-    if (sl * kI8Rows >= id_rows(nact, c, nb, kp.n_proxy, kp.weak)) return;
+    if (sl * slice_rows >= id_rows(nact, c, nb, kp.n_proxy, kp.weak)) return;
     build_oring(oring, ring_box, ring_nact, store, nact, apos, c, nb, nmax, kp.weak);
     {
         const int cx = c % nb, cy = c / nb;
@@ -580,7 +590,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     }
     const int mO = oring.beg[oring.cnt];
     const int m = mO + kp.n_proxy;
-    const int r0 = sl * kI8Rows, r1 = min(m, r0 + kI8Rows);
+    const int r0 = sl * slice_rows, r1 = min(m, r0 + slice_rows);
     const int nro = max(min(r1, mO) - r0, 0);   // O-ring rows of the slice: [r0, r0 + nro)
     const int p0 = max(r0, mO), npr = max(r1 - p0, 0);   // its proxy rows: [p0, p0 + npr)
     for (int i = tid; i < kI8Rows; i += NTH) {
@@ -594,25 +604,42 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
         rsrc[i] = src;
     }
     __syncthreads();
-    // exponent range of every column over the slice's O-ring rows (zeros aside): one wave
-    // per column, one row per lane
-    for (int q = wv; q < n; q += NW) {
-        int hi = -100000, lo = 100000;
-        for (int i = lane; i < nro; i += 64) {
-            const float x = rsrc[i][(int64_t)q * nmax];
-            if (x != 0.0f) {
-                int ex;
-                (void)frexpf(x, &ex);
-                hi = max(hi, ex);
-                lo = min(lo, ex);
-            }
-        }
+    // The slice's O-ring values, all loads issued at once: chunk ch, column j of the thread,
+    // rows 64 ch + i4 + 16 e (16 lanes read 16 consecutive rows of one column).
+    const int i4 = tid & 15, qb = tid >> 4;
+    constexpr int NCH = kI8Rows / 64;
+    float xv[NCH][kI8It][4];
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int j = 0; j < kI8It; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 64 * ch + i4 + 16 * e, q = qb + (NTH / 16) * j;
+                xv[ch][j][e] = (row < nro && q < n) ? rsrc[row][(int64_t)q * nmax] : 0.0f;
+            }
+    // exponent range of each column (zeros aside): the 16 lanes of a column reduce by
+    // quarter-wave shuffles
+#pragma unroll
+    for (int j = 0; j < kI8It; ++j) {
+        int hi = -100000, lo = 100000;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (xv[ch][j][e] != 0.0f) {
+                    int ex;
+                    (void)frexpf(xv[ch][j][e], &ex);
+                    hi = max(hi, ex);
+                    lo = min(lo, ex);
+                }
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
             hi = max(hi, __shfl_xor(hi, o, 64));
             lo = min(lo, __shfl_xor(lo, o, 64));
         }
-        if (lane == 0) {
+        const int q = qb + (NTH / 16) * j;
+        if (i4 == 0 && q < n) {
             emax[q] = hi;
             emin[q] = lo;
         }
@@ -625,6 +652,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     double2* G = (double2*)gpart + ((int64_t)blockIdx.y * nslice + sl) * nmax * nmax;
     if (wide_s) {
         // exponent spread too wide for the digits: compensated sums on the vector units
+        if (tid == 0) atomicOr(flag, 128);   // records that this form ran
         for (int e = tid; e < n * n; e += NTH) {
             const int p = e / n, q = e % n;
             if (p > q) continue;
@@ -677,9 +705,11 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     for (int u = 0; u < kI8Tpw; ++u)
 #pragma unroll
         for (int s2 = 0; s2 < 2 * kI8L - 1; ++s2) acc[u][s2] = i32x4{0, 0, 0, 0};
-    for (int c0 = 0; c0 < nro; c0 += 64) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (64 * ch >= nro) break;
         __syncthreads();   // ucol written; the previous chunk's operands read
-        i8_digits<NTH>(dig, limb, npad_box, c0, nro, rsrc, nmax, ucol);
+        i8_digits<NTH>(dig, limb, npad_box, xv[ch], ucol);
         __syncthreads();
         i8_chunk_mma(dig, limb, tP, tQ, acc);
     }
@@ -972,13 +1002,13 @@ static void gram_launch(const Level& L, const int* boxes, int nboxes, const doub
 
 template <int NW>
 static void gram_i8_launch(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
-                           const KernelParams& kp, double* gpart, const GramPlan& g, hipStream_t s) {
+                           const KernelParams& kp, double* gpart, const GramPlan& g, int* flag, hipStream_t s) {
     const int npad = (L.nmax + 15) & ~15;
     const size_t lds = std::max((size_t)kI8L * npad * kI8Pitch, sizeof(double) * kMaxProxy * npad);
-    note_shape("gram_i8_w" + std::to_string(NW));
+    note_shape("gram_i8_w" + std::to_string(NW) + "_rows" + std::to_string(g.slice_rows));
     k_gram_i8<NW><<<dim3(g.nsl, nboxes), dim3(64 * NW), lds, s>>>((const float*)L.store, L.nb, L.nmax, L.cnt, L.gidx,
                                                                    L.nact, L.apos, boxes, pts, ptmpl, kp, L.t, gpart,
-                                                                   g.nsl);
+                                                                   g.nsl, g.slice_rows, flag);
 }
 
 template <int NTH, int SUB>
@@ -996,7 +1026,7 @@ static void pchol_launch(const Level& L, const int* boxes, int nboxes, const Ker
 }
 
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
-                   const KernelParams& kp, double* work, hipStream_t s) {
+                   const KernelParams& kp, double* work, int* flag, hipStream_t s) {
     if (nboxes <= 0) return 0;
     const GramPlan g = gram_plan(L.nmax, kp.n_proxy, nboxes, kp.weak, L.store32);
     const size_t nn = (size_t)L.nmax * L.nmax;
@@ -1005,9 +1035,8 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
     const size_t lds = sizeof(double) * (size_t)kChunk * (L.nmax + 2);
     int launches = 2;
     if (g.i8) {
-        if (g.nth == 256) gram_i8_launch<4>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
-        else if (g.nth == 512) gram_i8_launch<8>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
-        else gram_i8_launch<12>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, s);
+        if (g.nth == 256) gram_i8_launch<4>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, flag, s);
+        else gram_i8_launch<8>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, flag, s);
     } else if (g.tpt == 1) gram_launch<256, 1>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3 && g.nth == 192) gram_launch<192, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else if (g.tpt == 3) gram_launch<256, 3>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
@@ -1016,7 +1045,9 @@ int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* p
     else if (g.nth == 192) gram_launch<192, 9>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     else gram_launch<256, 9>(L, boxes, nboxes, pts, ptmpl, kp, gpart, g, lds, s);
     int nsl_fixed = 0;
-    if (g.groups > 1 || g.slice_rows < 256) {
+    // few-box colours sum the slices once before the pivoted Cholesky (its steps are the
+    // critical path; the many-box form sums each entry as it reads it)
+    if (g.groups > 1 || g.slice_rows < 256 || (g.i8 && !plan_params(nboxes).gram_many)) {
         k_gram_reduce<<<dim3((unsigned)((nn + 255) / 256), nboxes), dim3(256), 0, s>>>(
             L.cnt, L.nact, boxes, L.nb, L.nmax, kp.n_proxy, kp.weak, gpart, g.nsl, g.slice_rows);
         nsl_fixed = 1;

@@ -253,9 +253,10 @@ void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, in
 void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
 
 // skeletonization (rss_idgram.hip, rss_elim.hip, rss_schur.hip)
-// Returns the number of kernels launched.
+// Returns the number of kernels launched.  flag: the factor's device flag word; bit 128
+// records that the int8 Gram kernel summed a slice in double-double (wide exponent spread).
 int launch_id_gram(const Level& L, const int* boxes, int nboxes, const double* pts, const double* ptmpl,
-                    const KernelParams& kp, double* work, hipStream_t s);
+                   const KernelParams& kp, double* work, int* flag, hipStream_t s);
 size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak, bool store32);
 // Returns the number of kernels launched, or -1 when the box size leaves no LDS tile.
 // Active 64 x 64 tiles of the Schur updates of one colour, in 8 lists (one per XCD: the
