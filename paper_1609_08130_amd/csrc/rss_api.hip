@@ -56,6 +56,7 @@ void reload_plan_overrides() {
             else if (key == "inv_threads" && (v == 256 || v == 1024)) q.inv_threads = v;
             else if (key == "sweep_threads" && (v == 256 || v == 1024)) q.sweep_threads = v;
             else if (key == "gram_i8") q.gram_i8 = v != 0;
+            else if (key == "schur_atomic") q.schur_atomic = v != 0;
         }
     }
     g_plan_ready = true;

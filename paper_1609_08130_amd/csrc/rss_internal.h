@@ -215,6 +215,7 @@ struct PlanParams {
     int inv_threads;     // workgroup of the X_RR inverse: 256 or 1024 threads
     int sweep_threads;   // workgroup of the solve / apply sweeps: 256 or 1024 threads
     int gram_i8;         // 1: with an FP32 store, exact Gram sums on the int8 matrix cores
+    int schur_atomic;    // 1: Schur entries updated by no-return atomic adds (same rounding)
 };
 constexpr int kPlanBuckets = 5;
 extern const int kPlanBucketLo[kPlanBuckets];

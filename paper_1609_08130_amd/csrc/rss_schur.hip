@@ -32,7 +32,7 @@ struct SchurArgs {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));   // accumulator of one FP64 MFMA block
 
-template <typename TT, typename ST>
+template <typename TT, typename ST, bool ATOM>
 __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes,
                                                const int* __restrict__ tl_cnt, const int* __restrict__ tl_tiles,
                                                int tl_capx) {
@@ -213,6 +213,19 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
         const int64_t off = blkoff[in ? sa * 9 + sb : 0] + rpos_[i] + (int64_t)cpos_[j] * nmax;
         return in ? off : (int64_t)-1;
     };
+    if constexpr (ATOM) {
+        // Every entry has one writer per launch (the neighbourhoods of one colour are
+        // disjoint), so a no-return atomic add of -(X_JR G)_e rounds once, exactly as the
+        // load-subtract-store below, and the workgroup waits for no load.
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t off = entry(e);
+            if (off < 0) continue;
+            if (a.dstore && rslot[erow(e)] == cslot[ecol(e)]) unsafeAtomicAdd(a.dstore + off, -(double)eval(e));
+            else unsafeAtomicAdd(st + off, -(ST)eval(e));
+        }
+        return;
+    }
     if (a.dstore) {
         // FP32 store with FP64 self blocks: an entry of a self block (row and column slot
         // equal) is updated in FP64, every other entry in ST as below
@@ -264,16 +277,28 @@ int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mix
     const int tpd = (maxJ + 63) / 64;
     const int64_t nwg = 8 * (int64_t)tpd * tpd * ((nboxes + 7) / 8);   // 8 lists of at most capx entries
     dim3 grid((unsigned)nwg), block(256);
+    const bool atom = plan_params(nboxes).schur_atomic != 0;
+    const std::string form = atom ? "_atomic" : "";
     if (mixed && !fp64_tiles) {
-        note_shape(std::string("schur_f32") + (L.store32 ? "_store32" : "_store64"));
+        note_shape(std::string("schur_f32") + (L.store32 ? "_store32" : "_store64") + form);
         a.XJR = L.XJR32; a.G = L.G32;
-        if (L.store32) k_schur<float, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-        else k_schur<float, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        if (L.store32) {
+            if (atom) k_schur<float, float, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            else k_schur<float, float, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        } else {
+            if (atom) k_schur<float, double, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            else k_schur<float, double, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        }
     } else {
-        note_shape(std::string(fp64_tiles ? "schur_f64_sxs" : "schur_f64") + (L.store32 ? "_store32" : "_store64"));
+        note_shape(std::string(fp64_tiles ? "schur_f64_sxs" : "schur_f64") + (L.store32 ? "_store32" : "_store64") + form);
         a.XJR = L.XJR; a.G = L.G;
-        if (L.store32) k_schur<double, float><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-        else k_schur<double, double><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        if (L.store32) {
+            if (atom) k_schur<double, float, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            else k_schur<double, float, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        } else {
+            if (atom) k_schur<double, double, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            else k_schur<double, double, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+        }
     }
     return 0;
 }

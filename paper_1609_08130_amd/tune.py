@@ -4,7 +4,7 @@ The kernels of one colour choose their launch plan from a table indexed by the c
 count (buckets with lower bounds 1, 64, 256, 512, 1024 boxes).  This script measures the
 candidates on the GPU: for one field at a time it factors the 2D Laplace grid workload with
 every candidate value (set through RSS_TUNE for all buckets at once), reads the per-level
-phase times the library reports (rss_info: ID and elimination time per level; the solve's
+phase times the library reports (rss_info: ID, elimination and Schur time per level; the solve's
 time for the sweep widths, one bucket at a time), assigns each level to the bucket of its
 largest colour, and keeps per bucket the fastest value; fields are tuned in order, each
 with the best values found so far.  It then writes the table and a JSON summary.
@@ -26,15 +26,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 BUCKET_LO = [1, 64, 256, 512, 1024]
-FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads", "gram_i8"]
+FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads", "gram_i8", "schur_atomic"]
 # the order in which the fields are tuned (the Gram kernel first: it decides the slicing)
-ORDER = ["gram_i8", "gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads"]
+ORDER = ["gram_i8", "gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads",
+         "schur_atomic"]
 DEFAULTS = [
-    [0, 2048, 0, 1, 16, 1024, 1024, 0],
-    [0, 2048, 0, 1, 16, 1024, 1024, 0],
-    [0, 2048, 0, 1, 16, 256, 256, 0],
-    [1, 2048, 16, 1, 16, 256, 256, 0],
-    [1, 2048, 16, 4, 16, 256, 256, 0],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0],
+    [0, 2048, 0, 1, 16, 256, 256, 0, 0],
+    [1, 2048, 16, 1, 16, 256, 256, 0, 0],
+    [1, 2048, 16, 4, 16, 256, 256, 0, 0],
 ]
 # candidate values and the phase each field is judged by
 CANDIDATES = {
@@ -46,6 +47,7 @@ CANDIDATES = {
     "inv_threads": ([256, 1024], "elim"),
     "sweep_threads": ([256, 1024], "solve"),
     "gram_i8": ([0, 1], "id"),
+    "schur_atomic": ([0, 1], "schur"),
 }
 
 
@@ -66,7 +68,7 @@ def env_of(table):
 
 
 def measure(rss, torch, W, n, tol, table, reps, solves=0):
-    """Median per-level ID and elimination times (ms) by (depth, pass) and the median solve time."""
+    """Median per-level ID, elimination and Schur times (ms) by (depth, pass) and the median solve time."""
     os.environ["RSS_TUNE"] = env_of(table)
     prm = W.problem(n, tol)
     prm.pop("dim")
@@ -78,7 +80,7 @@ def measure(rss, torch, W, n, tol, table, reps, solves=0):
         info = F.info()
         for lv in info["levels"]:
             key = (lv["depth"], lv.get("pass", "strong"))
-            per.setdefault(key, []).append((lv["ms_id"], lv["ms_elim"]))
+            per.setdefault(key, []).append((lv["ms_id"], lv["ms_elim"], lv["ms_schur"]))
         if solves:
             b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
             F.solve(b, use_fp32=True)
@@ -89,7 +91,7 @@ def measure(rss, torch, W, n, tol, table, reps, solves=0):
             torch.cuda.synchronize()
             solve_ms = (time.perf_counter() - t0) * 1e3 / solves
         F.close()
-    med = {k: (statistics.median(v[0] for v in vals), statistics.median(v[1] for v in vals)) for k, vals in per.items()}
+    med = {k: tuple(statistics.median(v[i] for v in vals) for i in range(3)) for k, vals in per.items()}
     return med, solve_ms
 
 
@@ -145,7 +147,7 @@ def main():
             for b in range(len(trial)):
                 trial[b][fi] = v
             med, _ = measure(rss, torch, W, args.n, args.tol, trial, args.reps)
-            idx = 0 if phase == "id" else 1
+            idx = {"id": 0, "elim": 1, "schur": 2}[phase]
             per_bucket = {}
             for (d, p), t in med.items():
                 per_bucket.setdefault(level_bucket(d), 0.0)
@@ -163,8 +165,9 @@ def main():
     log["final"] = {f"{d}/{p}": v for (d, p), v in final.items()}
     sid = lambda m: sum(v[0] for v in m.values())
     sel = lambda m: sum(v[1] for v in m.values())
+    ssc = lambda m: sum(v[2] for v in m.values())
     print(f"[tune] ID {sid(base):.3f} -> {sid(final):.3f} ms, elimination {sel(base):.3f} -> {sel(final):.3f} ms, "
-          f"solve {base_solve:.3f} -> {final_solve:.3f} ms", flush=True)
+          f"Schur {ssc(base):.3f} -> {ssc(final):.3f} ms, solve {base_solve:.3f} -> {final_solve:.3f} ms", flush=True)
     write_table(args.out, table, f"{args.n}x{args.n} grid, tol {args.tol:g}, mixed precision, median of "
                 f"{args.reps} factorizations per candidate")
     if args.summary:

@@ -11,6 +11,8 @@ and the top set exactly (Section 3.1 eq. skelid, Algorithm 1), F^{-1} b and F b 
 and log|det F| (Section 3.3), and the full records of one interior box of the last colour
 per level (T, X_RR, X_JR, G, J; Section 3.1 eqs. zab, skelop).
 """
+import fnmatch
+
 import numpy as np
 import pytest
 
@@ -33,15 +35,15 @@ def rss():
 @pytest.mark.parametrize("name,shapes", [
     # leaf 16: >= 1024 boxes per colour (4 tiles per elimination workgroup, 64-thread pivoted
     # Cholesky with 16 LDS rows, 256-thread inverse) and the few-box shapes of the upper levels
-    ("grid512_leaf16_tol1e-6", ["elim_rows_w16_tpw4", "elim_inv_256", "elim_inv_1024", "pchol_64x1_kc16",
+    ("grid512_leaf16_tol1e-6", ["elim_rows_w*_tpw4", "elim_inv_256*", "elim_inv_1024*", "pchol_64x1_kc16",
                                 "solve_fwd_256_f64", "solve_fwd_1024_f64", "gram_reduce"]),
     # leaf 64: 455 boxes per colour at the leaves (the tuned plans of 256..511 boxes: two
     # tiles per elimination workgroup, 1024-thread inverse, 256-thread sweeps)
-    ("grid512_leaf64_tol1e-6", ["elim_rows_w16_tpw2", "elim_inv_1024", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
+    ("grid512_leaf64_tol1e-6", ["elim_rows_w*_tpw2", "elim_inv_1024*", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
     # the same with the former plans of those colours forced (256-thread inverse, one tile per
-    # workgroup), so both variants stay checked
-    ("grid512_leaf64_tol1e-6@b2.inv_threads=256,b2.elim_tpw=1",
-     ["elim_rows_w16_tpw1", "elim_inv_256", "solve_fwd_256_f64"]),
+    # workgroup, 16-line tiles), so both variants stay checked
+    ("grid512_leaf64_tol1e-6@b2.inv_threads=256,b2.elim_tpw=1,b2.elim_tw=16",
+     ["elim_rows_w16_tpw1", "elim_inv_256*", "solve_fwd_256_f64"]),
 ])
 def test_parity_512_grid_against_stored_oracle(rss, name, shapes):
     name, _, spec = name.partition("@")
@@ -78,6 +80,7 @@ def _run_case(rss, name, shapes):
     np.testing.assert_allclose(x, ref["x"], rtol=0, atol=bound * np.abs(ref["x"]).max())
     np.testing.assert_allclose(y, ref["y"], rtol=0, atol=bound * np.abs(ref["y"]).max())
     assert sg == ref["logdet"][0] and abs(ld - ref["logdet"][1]) <= bound * max(1.0, abs(ref["logdet"][1])) + 1e-14 * n * n
-    missing = [s for s in shapes if not any(t.startswith(s) for t in info["shapes"])]
+    # glob patterns (a pattern without "*" matches as a prefix)
+    missing = [s for s in shapes if not any(fnmatch.fnmatch(t, s if "*" in s else s + "*") for t in info["shapes"])]
     assert not missing, (missing, info["shapes"])
     F.close()
