@@ -57,6 +57,7 @@ void reload_plan_overrides() {
             else if (key == "sweep_threads" && (v == 256 || v == 1024)) q.sweep_threads = v;
             else if (key == "gram_i8") q.gram_i8 = v != 0;
             else if (key == "schur_atomic") q.schur_atomic = v != 0;
+            else if (key == "schur_form" && v >= 0 && v <= 1) q.schur_form = v;
         }
     }
     g_plan_ready = true;
@@ -339,6 +340,8 @@ void alloc_level_records(rss_factor f, rss::Level& L, bool mixed) {
     L.Sg = dalloc<int>(f, nbox * nm);
     L.Rg = dalloc<int>(f, nbox * nm);
     L.Jg = dalloc<int>(f, nbox * ldJ);
+    L.jmap = dalloc<int>(f, nbox * ldJ);
+    L.jseg = dalloc<int>(f, nbox * 9);
     L.T = dalloc<double>(f, nbox * nm * nm);
     L.XJR = dalloc<double>(f, nbox * ldJ * nm);
     L.G = dalloc<double>(f, nbox * nm * ldJ);
@@ -398,10 +401,10 @@ void destroy_all(rss_factor f) {
 }
 
 // phase indices of rss_factor_s::phase_ms
-// schur: the Schur-update launches with the factorization's product type; schur_sxs: the
-// FP64 launches of the S x S tiles of a mixed factorization
-enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_SCHUR_SXS, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
-const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "schur_sxs", "transition", "top",
+// schur: the Schur-update tile launches with the factorization's product type; schur_self:
+// the launches of the self blocks a mixed factorization keeps in FP64
+enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_SCHUR_SELF, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
+const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "schur_self", "transition", "top",
                                 "total"};
 
 void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
@@ -502,8 +505,6 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     int* tl_cnt = nullptr;
     int* tl_tiles = nullptr;
     size_t tl_n = 0;
-    int* tl64_cnt = nullptr;     // mixed: lists of the S x S tiles
-    int* tl64_tiles = nullptr;
 
     // Error bits of the device flag: 1 points outside the root box, 2 duplicate points,
     // 4 singular X_RR.  Bits 64 and 128 only record kernel forms that ran (rss_info shapes).
@@ -552,16 +553,12 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         if (maxc >= ((size_t)1 << 19)) fail(RSS_E_UNSUPPORTED, "more than 2^19 boxes in one colour of a level");
         const int capx = rss::schur_tile_capx((int)maxc, L.ldJ);
         if (!tl_cnt) tl_cnt = dalloc<int>(f, 9 * 8);
-        if (mixed && !tl64_cnt) tl64_cnt = dalloc<int>(f, 9 * 8);
         if ((size_t)capx * 8 > tl_n) {
             if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
-            if (tl64_tiles) defer_free(f, tl64_tiles, tl_n * sizeof(int));
             tl_n = (size_t)capx * 8;
             tl_tiles = dalloc<int>(f, tl_n);
-            if (mixed) tl64_tiles = dalloc<int>(f, tl_n);
         }
         HIPCHK(hipMemsetAsync(tl_cnt, 0, sizeof(int) * 9 * 8, s));
-        if (mixed) HIPCHK(hipMemsetAsync(tl64_cnt, 0, sizeof(int) * 9 * 8, s));
         std::vector<hipEvent_t>& ev = L.pass_ev;
         ev.clear();
         ev.push_back(evs.rec(s));
@@ -572,27 +569,21 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, f->flag, s);
             check_launch();
             ev.push_back(evs.rec(s));
-            rss::TileList tl, tl64;
+            rss::TileList tl;
             tl.cnt = tl_cnt + 8 * col;
             tl.tiles = tl_tiles;
             tl.capx = capx;
-            if (mixed) {
-                tl64.cnt = tl64_cnt + 8 * col;
-                tl64.tiles = tl64_tiles;
-                tl64.capx = capx;
-            }
-            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, tl64, s);
+            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, s);
             if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
             check_launch();
             ev.push_back(evs.rec(s));
-            // mixed: the S x S tiles in FP64 first (their own event pair), then the rest
+            // mixed: the self blocks kept in FP64 first (their own event pair), then the tiles
             if (mixed) {
-                if (rss::launch_schur(L, bx, nbx, L.nmax, 1, 1, tl64, s) < 0) fail(RSS_E_DEVICE, "Schur tile list too small");
+                f->kernel_launches[PH_SCHUR_SELF] += rss::launch_schur_self(L, bx, nbx, s);
                 check_launch();
-                f->kernel_launches[PH_SCHUR_SXS] += 1;
             }
             ev.push_back(evs.rec(s));
-            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, 0, tl, s) < 0)
+            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, tl, s) < 0)
                 fail(RSS_E_DEVICE, "Schur tile list too small");
             check_launch();
             ev.push_back(evs.rec(s));
@@ -682,8 +673,6 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     if (work) defer_free(f, work, work_n * sizeof(double));
     if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
     if (tl_cnt) defer_free(f, tl_cnt, sizeof(int) * 9 * 8);
-    if (tl64_tiles) defer_free(f, tl64_tiles, tl_n * sizeof(int));
-    if (tl64_cnt) defer_free(f, tl64_cnt, sizeof(int) * 9 * 8);
 
     // top block
     hipEvent_t eT0 = evs.rec(s);
@@ -749,6 +738,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             src.push_back({Lv.krank, nbx});
             src.push_back({Lv.nJ, nbx});
             src.push_back({Lv.mrows, nbx});
+            src.push_back({Lv.jseg, mixed ? nbx * 9 : (size_t)0});
         }
         auto hv = d2h_many(f, src, s);
         if (hv[0][0] & 64) rss::note_shape("elim_inv_gauss_jordan_lds");
@@ -759,21 +749,22 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (size_t li = 0; li < f->levels.size(); ++li) {
             rss::Level& Lv = f->levels[li];
             const std::vector<hipEvent_t>& ev = Lv.pass_ev;
-            double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_sxs = 0;
+            double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_self = 0;
             for (size_t i = 1; i + 2 < ev.size(); i += 4) {
                 lv_id += ev_ms(ev[i - 1], ev[i]);
                 lv_elim += ev_ms(ev[i], ev[i + 1]);
-                lv_sxs += ev_ms(ev[i + 1], ev[i + 2]);
+                lv_self += ev_ms(ev[i + 1], ev[i + 2]);
                 lv_schur += ev_ms(ev[i + 2], ev[i + 3]);
             }
             f->phase_ms[PH_ID] += lv_id;
             f->phase_ms[PH_ELIM] += lv_elim;
             f->phase_ms[PH_SCHUR] += lv_schur;
-            f->phase_ms[PH_SCHUR_SXS] += lv_sxs;
-            Lv.h_cnt = std::move(hv[1 + 4 * li]);
-            Lv.h_k = std::move(hv[2 + 4 * li]);
-            const std::vector<int>& hJ = hv[3 + 4 * li];
-            const std::vector<int>& hm = hv[4 + 4 * li];
+            f->phase_ms[PH_SCHUR_SELF] += lv_self;
+            Lv.h_cnt = std::move(hv[1 + 5 * li]);
+            Lv.h_k = std::move(hv[2 + 5 * li]);
+            const std::vector<int>& hJ = hv[3 + 5 * li];
+            const std::vector<int>& hm = hv[4 + 5 * li];
+            const std::vector<int>& hseg = hv[5 + 5 * li];
             Lv.rec_boxes.assign(9, {});
             for (int col = 0; col < 9; ++col)
                 for (int b : Lv.colour_boxes[col])
@@ -781,7 +772,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             Lv.d_rec_boxes = h2d_lists(f, Lv.rec_boxes, s);
             rss::LevelStats st;
             st.depth = Lv.t; st.weak = Lv.weak; st.boxes = Lv.nbox; st.nmax = Lv.nmax;
-            st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_sxs = lv_sxs;
+            st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_self = lv_self;
             for (int b = 0; b < Lv.nbox; ++b) {
                 double n = Lv.h_cnt[b], k = Lv.h_k[b], r = n - k, J = hJ[b], m = hm[b];
                 if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
@@ -795,11 +786,19 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
                 st.flops_g += 2.0 * r * r * J + 4.0 / 3.0 * r * r * r;
                 // target read + write of the store entries and the two operands once
                 if (mixed) {
-                    // S x S in FP64 (its own launch), the rest with FP32 products
-                    st.flops_schur_sxs += 2.0 * k * k * r;
-                    st.bytes_schur_sxs += 16.0 * k * k + 8.0 * 2.0 * k * r;
+                    // S x S with FP64 products (k_schur_self), the rest with FP32 products: into
+                    // the store, and with an FP32 store the adjacent boxes' self blocks into
+                    // their FP64 entries
+                    double adj = 0;
+                    if (Lv.store32)
+                        for (int sl = 0; sl < 9; ++sl) {
+                            const double len = hseg[(size_t)b * 9 + sl] & 0xffff;
+                            if (sl != 4) adj += len * len;
+                        }
+                    st.flops_schur_self += 2.0 * k * k * r;
+                    st.bytes_schur_self += 16.0 * k * k + 8.0 * 2.0 * k * r;
                     st.flops_schur += 2.0 * (J * J - k * k) * r;
-                    st.bytes_schur += (Lv.store32 ? 8.0 : 16.0) * (J * J - k * k) + 4.0 * 2.0 * J * r;
+                    st.bytes_schur += (Lv.store32 ? 8.0 : 16.0) * (J * J - k * k - adj) + 16.0 * adj + 4.0 * 2.0 * J * r;
                 } else {
                     st.flops_schur += 2.0 * J * J * r;
                     st.bytes_schur += 16.0 * J * J + 8.0 * 2.0 * J * r;
@@ -1475,8 +1474,8 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
           << ",\"flops_g\":" << s.flops_g << ",\"flops_schur\":" << s.flops_schur
           << ",\"bytes_schur\":" << s.bytes_schur << ",\"bytes_solve64\":" << s.bytes_solve64
           << ",\"bytes_solve32\":" << s.bytes_solve32 << ",\"ms_id\":" << s.ms_id << ",\"ms_elim\":" << s.ms_elim
-          << ",\"ms_schur\":" << s.ms_schur << ",\"flops_schur_sxs\":" << s.flops_schur_sxs
-          << ",\"bytes_schur_sxs\":" << s.bytes_schur_sxs << ",\"ms_schur_sxs\":" << s.ms_schur_sxs << "}";
+          << ",\"ms_schur\":" << s.ms_schur << ",\"flops_schur_self\":" << s.flops_schur_self
+          << ",\"bytes_schur_self\":" << s.bytes_schur_self << ",\"ms_schur_self\":" << s.ms_schur_self << "}";
     }
     o << "]}";
     std::string js = o.str();

@@ -28,9 +28,6 @@ struct ElimArgs {
     int* tl_cnt;         // Schur tile lists of the colour (TileList)
     int* tl_tiles;
     int tl_capx;
-    int* tl64_cnt;       // mixed precision: the S x S tiles (FP64 products), or nullptr
-    int* tl64_tiles;
-    int tl64_capx;
     int nb, nmax, ldJ;
     const int* cnt;
     const int* gidx;
@@ -41,6 +38,8 @@ struct ElimArgs {
     const int* spos;
     const int* rpos;
     int* Jg;
+    int* jmap;           // J row -> (3x3 slot << 16) | position in its box, for the Schur kernel
+    int* jseg;           // per 3x3 slot: (first J row << 16) | rows, for the self-block update
     int* Sg;
     int* Rg;
     const double* T;
@@ -186,6 +185,18 @@ __device__ inline int j_global(const ElimShared<ST>& sh, const ElimArgs& a, int 
     int i = 0;
     while (sh.joff[i + 1] <= jj) ++i;
     return a.gidx[(int64_t)sh.nbox[i] * a.nmax + sh.nap[i][jj - sh.joff[i]]];
+}
+
+// Store position of J entry jj: (slot << 16) | position in its box, slot = (dy + 1) 3 +
+// (dx + 1) of the box in the 3x3 neighbourhood of c (4: c itself, whose J rows are S).
+template <typename ST>
+__device__ inline int j_map(const ElimShared<ST>& sh, const ElimArgs& a, int c, int jj, int k) {
+    if (jj < k) return (4 << 16) | sh.sp[jj];
+    int i = 0;
+    while (sh.joff[i + 1] <= jj) ++i;
+    const int o = sh.nbox[i], nb = a.nb;
+    const int slot = (o / nb - c / nb + 1) * 3 + (o % nb - c % nb + 1);
+    return (slot << 16) | sh.nap[i][jj - sh.joff[i]];
 }
 
 // Rows [r0, r0 + tr) of E = [J; R] against the columns R: rows of J give X_JR (and its
@@ -751,7 +762,10 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
         const int r0 = t * tw;
         if (r0 >= nj + r) break;
         const int tr = min(tw, nj + r - r0);
-        for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+        for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) {
+            a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+            a.jmap[(int64_t)c * ldJ + jj] = j_map(sh, a, c, jj, k);
+        }
         elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
     }
 }
@@ -794,29 +808,26 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
     }
     for (int i = tid; i < k; i += NTH) a.apos[(int64_t)c * nmax + i] = sh.sp[i];
     if (tid < 64) {
-        // the box's ceil(|J| / 64)^2 Schur tiles, appended to the lists of its XCD by wave 0;
-        // in mixed precision the ns1 x ns1 tiles that cover S x S go to the FP64 list
+        // the box's ceil(|J| / 64)^2 Schur tiles, appended to the list of its XCD by wave 0
         const int nt1 = (nj + 63) >> 6, ntl = nt1 * nt1, x = blockIdx.x & 7;
-        const int ns1 = a.tl64_cnt ? (k + 63) >> 6 : 0, n64 = ns1 * ns1;
-        int off = 0, off64 = 0;
-        if (tid == 0) {
-            off = atomicAdd(a.tl_cnt + x, ntl - n64);
-            if (n64) off64 = atomicAdd(a.tl64_cnt + x, n64);
-        }
+        int off = 0;
+        if (tid == 0) off = atomicAdd(a.tl_cnt + x, ntl);
         off = __shfl(off, 0, 64);
-        off64 = __shfl(off64, 0, 64);
         int* lst = a.tl_tiles + (int64_t)x * a.tl_capx + off;
-        for (int t = tid; t < ntl; t += 64) {
-            const int ti = t % nt1, tj = t / nt1;
-            const int ent = ((int)blockIdx.x << 12) | (ti << 6) | tj;
-            if (ti < ns1 && tj < ns1) {
-                a.tl64_tiles[(int64_t)x * a.tl64_capx + off64 + ti + ns1 * tj] = ent;
-            } else {
-                // position among the tiles outside the ns1 x ns1 corner, in the order of t
-                const int before = min(tj, ns1) * ns1 + (tj < ns1 ? min(ti, ns1) : 0);
-                lst[t - before] = ent;
-            }
+        for (int t = tid; t < ntl; t += 64) lst[t] = ((int)blockIdx.x << 12) | ((t % nt1) << 6) | (t / nt1);
+    } else if (tid < 64 + 9) {
+        // J rows of the box at 3x3 slot s = (dy + 1) 3 + (dx + 1) (slot 4: S of c)
+        const int sl = tid - 64;
+        int v = 0;
+        if (sl == 4) {
+            v = k;
+        } else {
+            const int ox = c % a.nb + sl % 3 - 1, oy = c / a.nb + sl / 3 - 1;
+            for (int i = 0; i < sh.nN; ++i)
+                if (sh.nbox[i] == ox + a.nb * oy) v = (sh.joff[i] << 16) | (sh.joff[i + 1] - sh.joff[i]);
+            if ((v & 0xffff) == 0) v = 0;
         }
+        a.jseg[(int64_t)c * 9 + sl] = v;
     }
 }
 
@@ -881,15 +892,15 @@ static void set_lds(K kernel, size_t bytes) {
 
 template <typename ST>
 static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
-                         const TileList& tl, const TileList& tl64, hipStream_t s) {
+                         const TileList& tl, hipStream_t s) {
     if (nboxes <= 0) return 0;
     ElimArgs a;
     a.weak = weak;
     a.tl_cnt = tl.cnt; a.tl_tiles = tl.tiles; a.tl_capx = tl.capx;
-    a.tl64_cnt = tl64.cnt; a.tl64_tiles = tl64.tiles; a.tl64_capx = tl64.capx;
+    a.jseg = L.jseg;
     a.store = L.store; a.dstore = L.dstore; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;
-    a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
+    a.spos = L.spos; a.rpos = L.rpos; a.Jg = L.Jg; a.jmap = L.jmap; a.Sg = L.Sg; a.Rg = L.Rg; a.T = L.T;
     a.XJR = L.XJR; a.G = L.G; a.XRR = L.XRR; a.Xinv = L.Xinv;
     a.XJR32 = L.XJR32; a.G32 = L.G32; a.Xinv32 = L.Xinv32; a.T32 = L.T32;
     a.logdet_part = L.logdet_part; a.sign_part = L.sign_part; a.flag = flag;
@@ -963,9 +974,9 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
 }
 
 int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
-                const TileList& tl, const TileList& tl64, hipStream_t s) {
-    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, weak, work, flag, tl, tl64, s)
-                     : launch_elim_t<double>(L, boxes, nboxes, mixed, weak, work, flag, tl, tl64, s);
+                const TileList& tl, hipStream_t s) {
+    return L.store32 ? launch_elim_t<float>(L, boxes, nboxes, mixed, weak, work, flag, tl, s)
+                     : launch_elim_t<double>(L, boxes, nboxes, mixed, weak, work, flag, tl, s);
 }
 
 }  // namespace rss

@@ -57,6 +57,9 @@ struct Level {
     int* spos = nullptr;       // nbox * nmax
     int* rpos = nullptr;       // nbox * nmax
     int* Jg = nullptr;         // nbox * ldJ global indices of J = S then active near field
+    int* jmap = nullptr;       // nbox * ldJ: J row -> (3x3 neighbourhood slot << 16) | position in its box
+    int* jseg = nullptr;       // nbox * 9: J rows of the box at each 3x3 slot, (first << 16) | count
+                               // (0: no such box or no active DOFs); slot 4 is S
     int* Sg = nullptr;         // nbox * nmax
     int* Rg = nullptr;         // nbox * nmax
     double* T = nullptr;       // nbox * nmax * nmax, |S| x |R| col-major (ld nmax)
@@ -102,7 +105,7 @@ struct LevelStats {
     double bytes_schur = 0, bytes_solve64 = 0, bytes_solve32 = 0;
     // mixed precision: the S x S tiles run in their own FP64 launch (flops, bytes, time);
     // flops_schur, bytes_schur and ms_schur then count the main (FP32) launch only
-    double flops_schur_sxs = 0, bytes_schur_sxs = 0, ms_schur_sxs = 0;
+    double flops_schur_self = 0, bytes_schur_self = 0, ms_schur_self = 0;
     double ms_id = 0, ms_elim = 0, ms_schur = 0, ms_transition = 0;
 };
 
@@ -216,6 +219,7 @@ struct PlanParams {
     int sweep_threads;   // workgroup of the solve / apply sweeps: 256 or 1024 threads
     int gram_i8;         // 1: with an FP32 store, exact Gram sums on the int8 matrix cores
     int schur_atomic;    // 1: Schur entries updated by no-return atomic adds (same rounding)
+    int schur_form;      // FP32 Schur products: 0 vector FMAs, 1 matrix cores
 };
 constexpr int kPlanBuckets = 5;
 extern const int kPlanBucketLo[kPlanBuckets];
@@ -269,19 +273,19 @@ struct TileList {
     int* tiles = nullptr;   // 8 * capx entries
     int capx = 0;           // ceil(boxes / 8) * ceil(ldJ / 64)^2
 };
-// Mixed precision: the tiles that cover S x S of a step (its O(1) skeleton-skeleton update)
-// go to tl64 and are multiplied in FP64; every other tile goes to tl.  FP64 factors put all
-// tiles in tl (tl64.cnt == nullptr).
+// Every active tile goes to tl; the J segment of each 3x3 slot goes to L.jseg.
 // weak: the RS-WS weak pass (J = S, no adjacent boxes).
 int launch_elim(const Level& L, const int* boxes, int nboxes, int mixed, int weak, double* work, int* flag,
-                const TileList& tl, const TileList& tl64, hipStream_t s);
+                const TileList& tl, hipStream_t s);
 // Entries per tile list for a colour of nboxes boxes with |J| <= maxJ.
 int schur_tile_capx(int nboxes, int maxJ);
-// Returns -1 when tl.capx is below schur_tile_capx(nboxes, maxJ) (nothing launched).
-// fp64_tiles: the S x S tiles of a mixed factorization (list tl64 of launch_elim), with FP64
-// products; otherwise the tiles of tl with the factorization's product type.
-int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, int fp64_tiles,
-                 const TileList& tl, hipStream_t s);
+// The Schur update of the tiles of tl with the factorization's product type.  Mixed
+// precision leaves out S x S of each step (launch_schur_self).  Returns -1 when tl.capx is
+// below schur_tile_capx(nboxes, maxJ) (nothing launched).
+int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mixed, const TileList& tl, hipStream_t s);
+// Mixed precision: the S x S block of each step with FP64 products into its FP64 entries.
+// Returns the number of kernels launched.
+int launch_schur_self(const Level& L, const int* boxes, int nboxes, hipStream_t s);
 
 // dense top block (rss_solve.hip)
 // piv: lu_piv_ints(n) ints (interchanges, row permutation, panel swap lists)

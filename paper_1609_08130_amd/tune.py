@@ -26,16 +26,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 BUCKET_LO = [1, 64, 256, 512, 1024]
-FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads", "gram_i8", "schur_atomic"]
+FIELDS = ["gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads", "gram_i8", "schur_atomic",
+          "schur_form"]
 # the order in which the fields are tuned (the Gram kernel first: it decides the slicing)
 ORDER = ["gram_i8", "gram_many", "gram_min_wg", "pchol_kc", "elim_tpw", "elim_tw", "inv_threads", "sweep_threads",
-         "schur_atomic"]
+         "schur_atomic", "schur_form"]
 DEFAULTS = [
-    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0],
-    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0],
-    [0, 2048, 0, 1, 16, 256, 256, 0, 0],
-    [1, 2048, 16, 1, 16, 256, 256, 0, 0],
-    [1, 2048, 16, 4, 16, 256, 256, 0, 0],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0, 0],
+    [0, 2048, 0, 1, 16, 1024, 1024, 0, 0, 0],
+    [0, 2048, 0, 1, 16, 256, 256, 0, 0, 0],
+    [1, 2048, 16, 1, 16, 256, 256, 0, 0, 0],
+    [1, 2048, 16, 4, 16, 256, 256, 0, 0, 0],
 ]
 # candidate values and the phase each field is judged by
 CANDIDATES = {
@@ -48,6 +49,7 @@ CANDIDATES = {
     "sweep_threads": ([256, 1024], "solve"),
     "gram_i8": ([0, 1], "id"),
     "schur_atomic": ([0, 1], "schur"),
+    "schur_form": ([0, 1], "schur"),
 }
 
 

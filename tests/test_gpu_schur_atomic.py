@@ -5,7 +5,7 @@ Within one launch every store entry has exactly one writer (the 3 x 3 neighbourh
 boxes of one colour are disjoint, Section 3.1 and the 3^d colouring), so adding -(X_JR G)_e
 atomically rounds once, exactly as old - (X_JR G)_e: the two factorizations must be equal
 bit for bit (F^{-1} b, F b, log|det F|, every skeleton set), in FP64 and in mixed precision
-(FP32 store with FP64 self blocks and FP64 S x S products).
+(FP32 store with FP64 self blocks, second pass included, and FP64 S x S products).
 """
 import numpy as np
 import pytest
