@@ -197,6 +197,39 @@ def run_gpu(args, precision: str):
                 gmres_ms=statistics.median(g[0] for g in gm) * 1e3, gmres_iters=gm[-1][1], gmres_relres=gm[-1][2])
 
 
+def run_level_graphs(args, stream_infos):
+    """The mixed factorization with every level pass launched as one HIP graph
+    (level_graphs = 1; the thread's executable graphs are updated in place from the second
+    factorization on): median factor time and the time of the passes at depth <= 5 (the
+    levels with at most 121 boxes per colour), against the same quantities of the
+    kernel-by-kernel factorizations timed above."""
+    import torch
+
+    from paper_1609_08130_amd import rss
+    n = args.n
+    prm = W.problem(n, args.tol)
+    prm.pop("dim")
+    pts = torch.tensor(W.grid_points(n), device="cuda")
+    infos = []
+    for rep in range(args.warmup + args.steps):
+        F = rss.Factor(pts, precision="mixed", level_graphs=1, **prm)
+        if rep >= args.warmup:
+            infos.append(F.info())
+        F.close()
+    torch.cuda.synchronize()
+
+    def upper(info, key):
+        return sum(key(l) for l in info["levels"] if l["depth"] <= 5)
+
+    stream_pass = lambda l: l["ms_id"] + l["ms_elim"] + l["ms_schur"] + l["ms_schur_self"]
+    return dict(factor_ms=statistics.median(i["phase_ms"]["total"] for i in infos),
+                factor_ms_stream=statistics.median(i["phase_ms"]["total"] for i in stream_infos),
+                passes_ms=statistics.median(i["phase_ms"]["level_graphs"] for i in infos),
+                passes_ms_stream=statistics.median(sum(stream_pass(l) for l in i["levels"]) for i in stream_infos),
+                upper_levels_ms=statistics.median(upper(i, lambda l: l["ms_graph"]) for i in infos),
+                upper_levels_ms_stream=statistics.median(upper(i, stream_pass) for i in stream_infos))
+
+
 def approximation_error(F, N, torch):
     """e_a = |A - F| / |A| by the power method to 1e-2 relative (Section 4), on the
     operators themselves (A symmetric, F symmetric up to its approximation error)."""
@@ -321,6 +354,7 @@ def main():
         sys.exit(2)
     mixed = run_gpu(args, "mixed")
     fp64 = None if args.no_fp64 else run_gpu(args, "fp64")
+    graphs = None if args.profile else run_level_graphs(args, mixed["infos"])
     roof = dominant_roofline(mixed["infos"], True)
     out = {
         "metric": "RS-S factor s + solves/s, N=1M 2D Laplace ε=1e-6, mixed vs FP64, one GPU",
@@ -344,6 +378,7 @@ def main():
         "fp64": None if fp64 is None else {k: fp64[k] for k in KEYS},
         "phase_ms_mixed": mixed["info"]["phase_ms"],
         "phase_ms_fp64": None if fp64 is None else fp64["info"]["phase_ms"],
+        "level_graphs": graphs,
         "roofline": roof,
         "levels": [dict({k: (round(l[k], 3) if isinstance(l[k], float) else l[k])
                          for k in ("depth", "boxes", "nmax", "records", "sum_k", "max_k", "max_J", "ms_id", "ms_elim",

@@ -95,6 +95,13 @@ typedef struct {
                                copy is accurate to a few 2^-24 and rss_gmres refines to
                                any rtol */
     int32_t  method;        /* rss_method */
+    int32_t  level_graphs;  /* 1: the launches of each pass over a level (the ID, elimination
+                               and Schur kernels of all its colours, Section 5's colouring
+                               making the boxes of one colour independent) are captured into
+                               one HIP graph and launched as one; a thread reuses the
+                               executable graph of the same level and pass of its previous
+                               factorization, updated in place.  0: launched one by one
+                               (the per-phase times of rss_info are split by kernel then) */
     uint64_t arena_bytes;   /* 0: no limit; otherwise the most device memory the factor may
                                hold at any time (store, records, workspaces), failing with
                                RSS_E_ARENA (nothing leaked) when the build needs more */

@@ -13,7 +13,9 @@
 #include <cstring>
 #include <sstream>
 #include <string>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -400,12 +402,67 @@ void destroy_all(rss_factor f) {
     f->pending_free.clear();
 }
 
+// Executable graphs of the level passes (level_graphs = 1), per thread and keyed by (device,
+// depth, pass, precision): a thread's factorizations run one after another and each
+// synchronizes before it returns, so an executable graph is never updated while a launch of
+// it is in flight.  A new capture updates the cached graph in place when its topology
+// matches (same kernels, new arguments), else replaces it.  rss_trim releases the calling
+// thread's graphs; the others live until the process ends.
+struct GraphKey {
+    int dev, depth, weak, mixed;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(dev, depth, weak, mixed) < std::tie(o.dev, o.depth, o.weak, o.mixed);
+    }
+};
+static thread_local std::map<GraphKey, hipGraphExec_t>* g_graph_exec = nullptr;
+
+hipGraphExec_t graph_exec_for(const GraphKey& key, hipGraph_t g) {
+    if (!g_graph_exec) g_graph_exec = new std::map<GraphKey, hipGraphExec_t>();
+    auto it = g_graph_exec->find(key);
+    if (it != g_graph_exec->end()) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(it->second, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess)
+            return it->second;
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(it->second);
+        g_graph_exec->erase(it);
+    }
+    hipGraphExec_t ex = nullptr;
+    HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    (*g_graph_exec)[key] = ex;
+    return ex;
+}
+
+void release_thread_graphs() {
+    if (!g_graph_exec) return;
+    for (auto& kv : *g_graph_exec) (void)hipGraphExecDestroy(kv.second);
+    g_graph_exec->clear();
+}
+
+// The stream the level passes are captured on (capture records launches; nothing runs on it),
+// one per thread and device, at the default priority.
+static thread_local std::map<int, hipStream_t>* g_capture_streams = nullptr;
+
+hipStream_t capture_stream() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (!g_capture_streams) g_capture_streams = new std::map<int, hipStream_t>();
+    auto it = g_capture_streams->find(dev);
+    if (it != g_capture_streams->end()) return it->second;
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    (*g_capture_streams)[dev] = cs;
+    return cs;
+}
+
 // phase indices of rss_factor_s::phase_ms
 // schur: the Schur-update tile launches with the factorization's product type; schur_self:
 // the launches of the self blocks a mixed factorization keeps in FP64
-enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_SCHUR_SELF, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
-const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "schur_self", "transition", "top",
-                                "total"};
+// level_graphs: the passes launched as HIP graphs (their split by kernel is not measured)
+enum { PH_TREE = 0, PH_KGEN, PH_ID, PH_ELIM, PH_SCHUR, PH_SCHUR_SELF, PH_GRAPH, PH_TRANS, PH_TOP, PH_TOTAL, PH_N };
+const char* kPhaseName[PH_N] = {"tree", "leaf_store", "id", "elim", "schur", "schur_self", "level_graphs",
+                                "transition", "top", "total"};
 
 void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     const rss_params& p = f->params;
@@ -562,34 +619,71 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         std::vector<hipEvent_t>& ev = L.pass_ev;
         ev.clear();
         ev.push_back(evs.rec(s));
-        for (int col = 0; col < 9; ++col) {
-            int nbx = (int)L.colour_boxes[col].size();
-            if (nbx == 0) continue;
-            const int* bx = L.d_colour_boxes[col];
-            const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, f->flag, s);
-            check_launch();
-            ev.push_back(evs.rec(s));
-            rss::TileList tl;
-            tl.cnt = tl_cnt + 8 * col;
-            tl.tiles = tl_tiles;
-            tl.capx = capx;
-            const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, s);
-            if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
-            check_launch();
-            ev.push_back(evs.rec(s));
-            // mixed: the self blocks kept in FP64 first (their own event pair), then the tiles
-            if (mixed) {
-                f->kernel_launches[PH_SCHUR_SELF] += rss::launch_schur_self(L, bx, nbx, s);
+        // level_graphs: the colour loop below is captured (no event, memset or host
+        // synchronization inside it) on the thread's capture stream and the graph is launched
+        // on s, which may be the null stream (not capturable)
+        const bool graphs = p.level_graphs != 0;
+        L.graphed = graphs ? 1 : 0;
+        const hipStream_t sl = graphs ? capture_stream() : s;
+        auto mark = [&]() {
+            if (!graphs) ev.push_back(evs.rec(s));
+        };
+        if (graphs) HIPCHK(hipStreamBeginCapture(sl, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int col = 0; col < 9; ++col) {
+                int nbx = (int)L.colour_boxes[col].size();
+                if (nbx == 0) continue;
+                const int* bx = L.d_colour_boxes[col];
+                const int ni = rss::launch_id_gram(L, bx, nbx, f->pts, ptmpl, kpw, work, f->flag, sl);
                 check_launch();
+                mark();
+                rss::TileList tl;
+                tl.cnt = tl_cnt + 8 * col;
+                tl.tiles = tl_tiles;
+                tl.capx = capx;
+                const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, sl);
+                if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");
+                check_launch();
+                mark();
+                // mixed: S x S in FP64 first (its own event pair), then the tiles
+                if (mixed) {
+                    f->kernel_launches[PH_SCHUR_SELF] += rss::launch_schur_self(L, bx, nbx, sl);
+                    check_launch();
+                }
+                mark();
+                if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, tl, sl) < 0)
+                    fail(RSS_E_DEVICE, "Schur tile list too small");
+                check_launch();
+                mark();
+                f->kernel_launches[PH_ID] += ni;
+                f->kernel_launches[PH_ELIM] += ne;
+                f->kernel_launches[PH_SCHUR] += 1;
             }
+        } catch (...) {
+            if (graphs) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(sl, &g);
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+            }
+            throw;
+        }
+        if (graphs) {
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamEndCapture(sl, &g));
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            hipGraphExec_t ex = nullptr;
+            try {
+                ex = graph_exec_for(GraphKey{dev, L.t, weak, mixed ? 1 : 0}, g);
+            } catch (...) {
+                (void)hipGraphDestroy(g);
+                throw;
+            }
+            (void)hipGraphDestroy(g);
+            HIPCHK(hipGraphLaunch(ex, s));
             ev.push_back(evs.rec(s));
-            if (rss::launch_schur(L, bx, nbx, L.ldJ, mixed ? 1 : 0, tl, s) < 0)
-                fail(RSS_E_DEVICE, "Schur tile list too small");
-            check_launch();
-            ev.push_back(evs.rec(s));
-            f->kernel_launches[PH_ID] += ni;
-            f->kernel_launches[PH_ELIM] += ne;
-            f->kernel_launches[PH_SCHUR] += 1;
+            f->kernel_launches[PH_GRAPH] += 1;
         }
     };
 
@@ -749,8 +843,9 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         for (size_t li = 0; li < f->levels.size(); ++li) {
             rss::Level& Lv = f->levels[li];
             const std::vector<hipEvent_t>& ev = Lv.pass_ev;
-            double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_self = 0;
-            for (size_t i = 1; i + 2 < ev.size(); i += 4) {
+            double lv_id = 0, lv_elim = 0, lv_schur = 0, lv_self = 0, lv_graph = 0;
+            if (Lv.graphed && ev.size() >= 2) lv_graph = ev_ms(ev.front(), ev.back());
+            for (size_t i = 1; !Lv.graphed && i + 2 < ev.size(); i += 4) {
                 lv_id += ev_ms(ev[i - 1], ev[i]);
                 lv_elim += ev_ms(ev[i], ev[i + 1]);
                 lv_self += ev_ms(ev[i + 1], ev[i + 2]);
@@ -760,6 +855,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             f->phase_ms[PH_ELIM] += lv_elim;
             f->phase_ms[PH_SCHUR] += lv_schur;
             f->phase_ms[PH_SCHUR_SELF] += lv_self;
+            f->phase_ms[PH_GRAPH] += lv_graph;
             Lv.h_cnt = std::move(hv[1 + 5 * li]);
             Lv.h_k = std::move(hv[2 + 5 * li]);
             const std::vector<int>& hJ = hv[3 + 5 * li];
@@ -773,6 +869,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
             rss::LevelStats st;
             st.depth = Lv.t; st.weak = Lv.weak; st.boxes = Lv.nbox; st.nmax = Lv.nmax;
             st.ms_id = lv_id; st.ms_elim = lv_elim; st.ms_schur = lv_schur; st.ms_schur_self = lv_self;
+            st.ms_graph = lv_graph;
             for (int b = 0; b < Lv.nbox; ++b) {
                 double n = Lv.h_cnt[b], k = Lv.h_k[b], r = n - k, J = hJ[b], m = hm[b];
                 if (n > 0) st.flops_id += 2.0 * m * n * n - 2.0 / 3.0 * n * n * n;
@@ -868,6 +965,7 @@ rss_status rss_trim(void) {
         blocks.swap(g_cache);
     }
     for (auto& b : blocks) (void)hipFree(b.ptr);
+    release_thread_graphs();
     return RSS_OK;
 }
 
@@ -907,6 +1005,7 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     }
     if (!std::isfinite(p->diag) || !std::isfinite(p->weight)) { g_err = "diag/weight not finite"; return RSS_E_ARG; }
     if (p->precision != RSS_FP64 && p->precision != RSS_MIXED) { g_err = "bad precision"; return RSS_E_ARG; }
+    if (p->level_graphs != 0 && p->level_graphs != 1) { g_err = "level_graphs must be 0 or 1"; return RSS_E_ARG; }
     rss_factor f = new (std::nothrow) rss_factor_s();
     if (!f) { g_err = "host allocation failed"; return RSS_E_NOMEM; }
     f->params = *p;
@@ -1456,6 +1555,7 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
       << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
       << ",\"method\":\"" << (f->params.method == RSS_METHOD_HYBRID ? "rs-ws" : "rs-s") << "\""
+      << ",\"level_graphs\":" << f->params.level_graphs
       << ",\"exact_operator\":\"" << (f->fft.ready ? "fft" : "direct") << "\""
       << ",\"bytes_device\":" << f->bytes_device << ",\"lds_limit\":" << rss::elim_lds_limit() << ",\"wall_ms\":" << f->wall_ms << ",\"phase_ms\":{";
     for (int i = 0; i < PH_N; ++i) o << (i ? "," : "") << "\"" << kPhaseName[i] << "\":" << f->phase_ms[i];
@@ -1475,7 +1575,8 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
           << ",\"bytes_schur\":" << s.bytes_schur << ",\"bytes_solve64\":" << s.bytes_solve64
           << ",\"bytes_solve32\":" << s.bytes_solve32 << ",\"ms_id\":" << s.ms_id << ",\"ms_elim\":" << s.ms_elim
           << ",\"ms_schur\":" << s.ms_schur << ",\"flops_schur_self\":" << s.flops_schur_self
-          << ",\"bytes_schur_self\":" << s.bytes_schur_self << ",\"ms_schur_self\":" << s.ms_schur_self << "}";
+          << ",\"bytes_schur_self\":" << s.bytes_schur_self << ",\"ms_schur_self\":" << s.ms_schur_self
+          << ",\"ms_graph\":" << s.ms_graph << "}";
     }
     o << "]}";
     std::string js = o.str();

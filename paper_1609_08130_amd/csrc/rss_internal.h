@@ -82,6 +82,7 @@ struct Level {
     std::vector<std::vector<int>> rec_boxes;      // boxes with a record, per colour
     std::vector<int*> d_rec_boxes;
     std::vector<hipEvent_t> pass_ev;              // timing events of the pass (read at the end)
+    int graphed = 0;                              // the pass ran as one HIP graph (pass_ev: start, end)
 };
 
 // FFT plan of the exact operator on a uniform n x n grid (L x L circulant embedding).
@@ -107,6 +108,7 @@ struct LevelStats {
     // flops_schur, bytes_schur and ms_schur then count the main (FP32) launch only
     double flops_schur_self = 0, bytes_schur_self = 0, ms_schur_self = 0;
     double ms_id = 0, ms_elim = 0, ms_schur = 0, ms_transition = 0;
+    double ms_graph = 0;   // the whole pass, when it ran as one HIP graph (the split above is then 0)
 };
 
 }  // namespace rss

@@ -62,6 +62,7 @@ class Params(ctypes.Structure):
         ("root_side", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("method", ctypes.c_int32),
+        ("level_graphs", ctypes.c_int32),
         ("arena_bytes", ctypes.c_uint64),
     ]
 

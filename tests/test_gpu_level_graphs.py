@@ -1,0 +1,68 @@
+"""Level passes launched as one HIP graph each (rss_params.level_graphs = 1) against the same
+factorization launched kernel by kernel.
+
+The boxes of one colour are independent (Section 5's colouring, widened to 3^d colours), and
+a pass over a level is the sequence of its colours' ID, elimination and Schur launches: the
+graph holds exactly those launches with the same arguments, so the factorizations must be
+equal bit for bit.  A thread reuses its executable graph of the same level and pass, updated
+in place for the next factorization's buffers: three factorizations in a row, with other
+work and a factorization of another size between them, each compared with the stream form.
+"""
+import numpy as np
+import pytest
+
+from paper_1609_08130_amd import workloads as W
+from tests.parity_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_08130_amd import rss as mod
+    return mod
+
+
+def _factor(rss, n, precision, method, graphs, tol=1e-6):
+    prm = W.problem(n, tol)
+    prm.pop("dim")
+    pts = torch.tensor(W.grid_points(n), device="cuda")
+    return rss.Factor(pts, precision=precision, method=method, level_graphs=graphs, **prm)
+
+
+def _same(rss, Fa, Fb, n):
+    b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
+    assert torch.equal(Fa.solve(b), Fb.solve(b))
+    assert torch.equal(Fa.apply(b), Fb.apply(b))
+    assert Fa.logdet() == Fb.logdet()
+    assert np.array_equal(Fa.top_set(), Fb.top_set())
+    depth, _ = Fa.shape()
+    for t in range(depth, 1, -1):
+        for box in range(0, 4 ** t, max(1, 4 ** t // 32)):
+            (Sa, Ra), (Sb, Rb) = Fa.box_sets(t, box), Fb.box_sets(t, box)
+            assert np.array_equal(Sa, Sb) and np.array_equal(Ra, Rb), (t, box)
+
+
+@pytest.mark.parametrize("n,precision,method", [(64, "fp64", "rs-s"), (100, "mixed", "rs-s"), (64, "mixed", "rs-ws"),
+                                                (512, "mixed", "rs-s")])
+def test_level_graphs_equal_stream_launches(rss, n, precision, method):
+    say(f"[level_graphs] N={n * n} precision={precision} method={method}")
+    Fs = _factor(rss, n, precision, method, 0)
+    for rep in range(3):
+        Fg = _factor(rss, n, precision, method, 1)
+        info = Fg.info()
+        assert info["level_graphs"] == 1 and info["phase_ms"]["level_graphs"] > 0
+        assert info["phase_ms"]["schur"] == 0 and info["phase_ms"]["id"] == 0
+        _same(rss, Fg, Fs, n)
+        say(f"[level_graphs] N={n * n} {precision} {method} rep {rep}: bitwise equal; factor "
+            f"{info['phase_ms']['total']:.2f} ms (graphs) vs {Fs.info()['phase_ms']['total']:.2f} ms")
+        Fg.close()
+        # other work between the replays: a smaller factorization (new graphs for its
+        # levels) and a solve with the stream factor
+        Fo = _factor(rss, 32, precision, method, 1)
+        Fo.solve(torch.tensor(W.rhs(32 * 32, seed=1), device="cuda"))
+        Fo.close()
+    Fs.close()

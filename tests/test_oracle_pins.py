@@ -90,6 +90,33 @@ def test_tree_depth_rule_and_order():
         assert max(len(l) for l in lists) <= leaf
 
 
+def test_root_box_bounding_square():
+    # Root box left to the points (root_side <= 0): the smallest square with the lower-left
+    # corner at the coordinate-wise minimum that holds every point, side = the larger extent.
+    rng = np.random.default_rng(11)
+    pts = np.column_stack([rng.uniform(0.2, 0.7, 500), rng.uniform(0.1, 0.4, 500)])
+    pts[0] = (0.2, 0.1)      # the corners that fix the extents: 0.5 in x, 0.3 in y
+    pts[1] = (0.7, 0.4)
+    p = O.Params(weight=1.0 / 500, tol=1e-6, leaf_size=16, root_side=0.0)
+    lo, side = O.root_box(pts, p)
+    assert np.array_equal(lo, [0.2, 0.1]) and side == pytest.approx(0.5, abs=1e-15)
+    tree = O.build_tree(pts, p)
+    nb = 2 ** tree.depth
+    # every point lies in the leaf box whose square contains it (the top edge clamps)
+    for box, lst in enumerate(tree.leaf_lists):
+        bx, by = box % nb, box // nb
+        x0, y0 = 0.2 + bx * 0.5 / nb, 0.1 + by * 0.5 / nb
+        q = pts[lst]
+        assert np.all(q[:, 0] >= x0 - 1e-15) and np.all(q[:, 0] <= x0 + 0.5 / nb + 1e-15)
+        assert np.all(q[:, 1] >= y0 - 1e-15) and np.all(q[:, 1] <= y0 + 0.5 / nb + 1e-15)
+    # boxes above y = 0.4 stay empty: the square is taller than the point set
+    assert all(len(tree.leaf_lists[bx + nb * by]) == 0 for by in range(nb) for bx in range(nb)
+               if 0.1 + by * 0.5 / nb > 0.4 + 1e-12)
+    # an explicit root box that misses a point is an error
+    with pytest.raises(O.OracleError):
+        O.root_box(pts, O.Params(weight=1.0, tol=1e-6, root_lo=(0.25, 0.0), root_side=1.0))
+
+
 def test_duplicate_points_rejected():
     pts = W.grid_points(8)
     pts[5] = pts[9]
@@ -147,6 +174,49 @@ def test_id_tie_rule_lowest_position():
     assert res.perm[0] == 2
     # exact duplicate columns are reproduced exactly by the skeleton
     assert 4 not in res.perm[:res.k]
+
+
+# ---------------------------------------------------------------- proxy surface (Section 3.2)
+
+def _proxy_id_far_residual(n, tol, box, proxies=True):
+    """The ID of box `box` at the leaf level from [A(O, B); w K(Gamma, B)] (or from A(O, B)
+    alone), applied to the true far block A(P, B), P = every DOF at Chebyshev distance >= 3:
+    |A(P, R) - A(P, S) T|_2 / |A(P, B)|_2."""
+    pts = W.grid_points(n)
+    p = _params(n, tol)
+    tree = O.build_tree(pts, p)
+    nb = 2 ** tree.depth
+    B = tree.leaf_lists
+    c = box[0] + nb * box[1]
+    rows = [O.matrix_block(pts, B[o], B[c], p) for o in O.ring(c, nb, 2)]
+    if proxies:
+        rows.append(O.kernel_block(O.proxy_points(c, tree.depth, tree, p), pts[B[c]], p))
+    spos, rpos, T = O.id_sorted(O.cpqr_id(np.vstack(rows), tol))
+    P = np.concatenate([B[b] for b in range(nb * nb) if O.cheb(b, c, nb) >= 3])
+    AP = O.matrix_block(pts, P, B[c], p)
+    return np.linalg.norm(AP[:, rpos] - AP[:, spos] @ T, 2) / np.linalg.norm(AP, 2)
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
+def test_proxy_id_compresses_the_true_far_field(tol):
+    # Section 3.2: by Green's identity the proxy circle stands in for every source outside
+    # it, so the ID of the small stacked matrix is an ID of the whole far block A(P, B),
+    # which the test forms explicitly (64 x 64 grid, 8 x 8 leaf boxes: interior, corner,
+    # edge boxes).  Measured <= 3.4 tol over these cases.
+    for box in [(3, 3), (0, 0), (0, 4), (7, 2)]:
+        e = _proxy_id_far_residual(64, tol, box)
+        assert e <= 5 * tol, (tol, box, e)
+
+
+def test_far_field_needs_the_proxy_rows():
+    # Planted mistake: without the proxy rows, the ID of a boundary box sees only the part of
+    # the far field its O ring surrounds, and misses A(P, B) by more than tol (measured
+    # 1.4-1.7 tol at 1e-3 and 2.2 tol at 1e-6 for the corner box), while the proxy form stays
+    # at <= 0.1 tol there.
+    for tol in (1e-3, 1e-6):
+        e_with = _proxy_id_far_residual(64, tol, (0, 0))
+        e_without = _proxy_id_far_residual(64, tol, (0, 0), proxies=False)
+        assert e_with <= 0.2 * tol and e_without > tol, (tol, e_with, e_without)
 
 
 def test_id_degenerate_cases():
