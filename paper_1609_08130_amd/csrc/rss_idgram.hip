@@ -64,16 +64,14 @@ __device__ inline dd dd_mul(dd a, dd b) {
     return {s, t};
 }
 
-__device__ inline dd dd_div(dd a, dd b) {
+// 1 / b in double-double: one FP64 division and one Newton correction.
+__device__ inline dd dd_recip(dd b) {
 #pragma clang fp contract(off)
-    double q1 = a.hi / b.hi;
-    dd r = dd_sub(a, dd_mul({q1, 0.0}, b));
-    double q2 = r.hi / b.hi;
-    r = dd_sub(r, dd_mul({q2, 0.0}, b));
-    double q3 = r.hi / b.hi;
+    const double q1 = 1.0 / b.hi;
+    const dd r = dd_sub({1.0, 0.0}, dd_mul({q1, 0.0}, b));   // 1 - q1 b
     double s, t;
-    fast_two_sum(q1, q2, s, t);
-    return dd_add({s, t}, {q3, 0.0});
+    fast_two_sum(q1, r.hi * q1, s, t);
+    return {s, t};
 }
 
 __device__ inline dd dd_sqrt(dd a) {
@@ -897,9 +895,17 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
             nuv[buf][q] = done ? -1.0 : d.hi + d.lo;
         }
         __syncthreads();
-        // largest trailing norm, then the lowest column within tau rnorm0 of it
+        // largest trailing norm, then the lowest column within tau rnorm0 of it; the lane's
+        // norms stay in registers for the second pass
+        constexpr int NU = (NQ + 63) / 64;
+        double nul[NU];
         double wm = -1.0;
-        for (int t = lane; t < n; t += 64) wm = fmax(wm, nuv[buf][t]);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int t = lane + 64 * u;
+            nul[u] = t < n ? nuv[buf][t] : -1.0;
+            wm = fmax(wm, nul[u]);
+        }
         const double numax = wave_max_d(wm);
         const double mu = sqrt(fmax(numax, 0.0));
         if (!(numax == numax)) break;
@@ -909,29 +915,32 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
         } else if (mu <= kp.tol * rnorm0) {
             break;
         }
+        // candidates: norm >= thr, compared as nu >= thr^2 (every column when thr <= 0)
         const double thr = mu - kp.tau * rnorm0;
+        const double thr2 = thr > 0.0 ? thr * thr : 0.0;
         int p = 1 << 30;
-        for (int t0 = 0; t0 < n; t0 += 64) {
-            const double nu = t0 + lane < n ? nuv[buf][t0 + lane] : -1.0;
-            const unsigned long long b = __ballot(nu >= 0.0 && sqrt(nu) >= thr);
-            if (b) {
-                p = t0 + __ffsll((long long)b) - 1;
-                break;
-            }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const unsigned long long b = __ballot(nul[u] >= 0.0 && nul[u] >= thr2);
+            if (b && p == (1 << 30)) p = 64 * u + __ffsll((long long)b) - 1;
         }
         if (p >= n) break;
-        // every thread forms r_jj itself (no extra barrier)
+        // the pivot row's Gram entry is requested before r_jj is formed, so that its load
+        // overlaps the square root and the reciprocal (every thread forms r_jj itself: no
+        // extra barrier)
+        const bool active = !done && q != p;
+        dd gpq = {0.0, 0.0};
+        if (active) gpq = gram_entry(G, nsl, nmax, sstride, p, q);
         const dd rjj = dd_sqrt({dh[buf][p], dl[buf][p]});
         if (q == p) {
             if (sub == 0) piv[j] = p;
             rput(j, p, rjj);
             done = true;
         }
-        if (!done) {
+        if (active) {
             // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2.  Thread sub of the
-            // column takes i = sub, sub + SUB, ... in two partial sums while the load of G_pq
-            // is in flight.
-            const dd gpq = gram_entry(G, nsl, nmax, sstride, p, q);
+            // column takes i = sub, sub + SUB, ... in two partial sums.
+            const dd rinv = dd_recip(rjj);
             dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
             int i = sub;
             for (; i + SUB < j; i += 2 * SUB) {
@@ -940,7 +949,7 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
             }
             if (i < j) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
             const dd sum = group_sum_dd<SUB>(dd_add(s0, s1));
-            const dd rjq = dd_div(dd_sub(gpq, sum), rjj);
+            const dd rjq = dd_mul(dd_sub(gpq, sum), rinv);
             rput(j, q, rjq);
             d = dd_sub(d, dd_mul(rjq, rjq));
         }

@@ -525,29 +525,46 @@ void launch_compact(const Level& L, Level& C, hipStream_t s) {
 // ------------------------------------------------------------------------------------
 // Top block (Section 3.3, final factorization): the remaining active DOFs of the last
 // level, ascending; tmap[p] = (box << 16) | position in the box's level-start list.
-__global__ void k_top_lists(const int* __restrict__ nact, const int* __restrict__ apos, const int* __restrict__ gidx,
-                            int nbox, int nmax, int* top_idx, int* tmap) {
-    // one block; nbox <= 16 boxes of <= kMaxBox DOFs
-    for (int b = 0; b < nbox; ++b) {
-        int nb_ = nact[b];
-        for (int i = threadIdx.x; i < nb_; i += blockDim.x) {
-            int p = apos[(int64_t)b * nmax + i];
-            int g = gidx[(int64_t)b * nmax + p];
-            int rank = 0;
-            for (int c = 0; c < nbox; ++c) {
-                int nc = nact[c];
-                if (c == b) { rank += i; continue; }
-                int lo = 0, hi = nc;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    int gm = gidx[(int64_t)c * nmax + apos[(int64_t)c * nmax + mid]];
-                    if (gm < g) lo = mid + 1; else hi = mid;
-                }
-                rank += lo;
+__global__ void __launch_bounds__(1024) k_top_lists(const int* __restrict__ nact, const int* __restrict__ apos,
+                                                   const int* __restrict__ gidx, int nbox, int nmax, int* top_idx,
+                                                   int* tmap) {
+    // one block; nbox <= 16 boxes of <= kMaxBox DOFs.  The boxes' active global indices
+    // (ascending in each box) and positions are staged in LDS first, so the rank searches
+    // below read no global memory.
+    __shared__ int ag[16 * kMaxBox], ap[16 * kMaxBox];
+    __shared__ int off[17];
+    if (threadIdx.x == 0) {
+        off[0] = 0;
+        for (int b = 0; b < nbox; ++b) off[b + 1] = off[b] + nact[b];
+    }
+    __syncthreads();
+    const int tot = off[nbox];
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        int b = 0;
+        while (off[b + 1] <= e) ++b;
+        const int p = apos[(int64_t)b * nmax + (e - off[b])];
+        ap[e] = p;
+        ag[e] = gidx[(int64_t)b * nmax + p];
+    }
+    __syncthreads();
+    // rank of entry e of box b: its place in b plus, in every other box, the number of
+    // indices below its own (a binary search)
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        int b = 0;
+        while (off[b + 1] <= e) ++b;
+        const int g = ag[e];
+        int rank = e - off[b];
+        for (int c = 0; c < nbox; ++c) {
+            if (c == b) continue;
+            int lo = off[c], hi = off[c + 1];
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ag[mid] < g) lo = mid + 1; else hi = mid;
             }
-            top_idx[rank] = g;
-            tmap[rank] = (b << 16) | p;
+            rank += lo - off[c];
         }
+        top_idx[rank] = g;
+        tmap[rank] = (b << 16) | ap[e];
     }
 }
 
