@@ -606,13 +606,14 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         // Schur tile lists: 8 counters per colour, zero at the level start; one entry buffer
         // reused by the colours in turn
-        // a tile-list entry packs the box position in 19 bits
-        if (maxc >= ((size_t)1 << 19)) fail(RSS_E_UNSUPPORTED, "more than 2^19 boxes in one colour of a level");
+        // a tile-list entry packs the box in 19 bits; the entries and the per-tile box sizes
+        // share one buffer
+        if ((size_t)L.nbox >= ((size_t)1 << 19)) fail(RSS_E_UNSUPPORTED, "more than 2^19 boxes in one level");
         const int capx = rss::schur_tile_capx((int)maxc, L.ldJ);
         if (!tl_cnt) tl_cnt = dalloc<int>(f, 9 * 8);
-        if ((size_t)capx * 8 > tl_n) {
+        if ((size_t)capx * 16 > tl_n) {
             if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
-            tl_n = (size_t)capx * 8;
+            tl_n = (size_t)capx * 16;
             tl_tiles = dalloc<int>(f, tl_n);
         }
         HIPCHK(hipMemsetAsync(tl_cnt, 0, sizeof(int) * 9 * 8, s));
@@ -640,6 +641,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
                 rss::TileList tl;
                 tl.cnt = tl_cnt + 8 * col;
                 tl.tiles = tl_tiles;
+                tl.info = tl_tiles + (size_t)8 * capx;
                 tl.capx = capx;
                 const int ne = rss::launch_elim(L, bx, nbx, mixed ? 1 : 0, weak, work, f->flag, tl, sl);
                 if (ne < 0) fail(RSS_E_UNSUPPORTED, "box too large for the elimination kernel's LDS tiles");

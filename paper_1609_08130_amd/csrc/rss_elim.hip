@@ -27,6 +27,7 @@ struct ElimArgs {
     const double* dstore;   // self blocks of an FP32 store (FP64), or nullptr
     int* tl_cnt;         // Schur tile lists of the colour (TileList)
     int* tl_tiles;
+    int* tl_info;
     int tl_capx;
     int nb, nmax, ldJ;
     const int* cnt;
@@ -813,8 +814,11 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
         int off = 0;
         if (tid == 0) off = atomicAdd(a.tl_cnt + x, ntl);
         off = __shfl(off, 0, 64);
-        int* lst = a.tl_tiles + (int64_t)x * a.tl_capx + off;
-        for (int t = tid; t < ntl; t += 64) lst[t] = ((int)blockIdx.x << 12) | ((t % nt1) << 6) | (t / nt1);
+        const int64_t o = (int64_t)x * a.tl_capx + off;
+        for (int t = tid; t < ntl; t += 64) {
+            a.tl_tiles[o + t] = (c << 12) | ((t % nt1) << 6) | (t / nt1);
+            a.tl_info[o + t] = (nj << 16) | r;
+        }
     } else if (tid < 64 + 9) {
         // J rows of the box at 3x3 slot s = (dy + 1) 3 + (dx + 1) (slot 4: S of c)
         const int sl = tid - 64;
@@ -896,7 +900,7 @@ static int launch_elim_t(const Level& L, const int* boxes, int nboxes, int mixed
     if (nboxes <= 0) return 0;
     ElimArgs a;
     a.weak = weak;
-    a.tl_cnt = tl.cnt; a.tl_tiles = tl.tiles; a.tl_capx = tl.capx;
+    a.tl_cnt = tl.cnt; a.tl_tiles = tl.tiles; a.tl_info = tl.info; a.tl_capx = tl.capx;
     a.jseg = L.jseg;
     a.store = L.store; a.dstore = L.dstore; a.nb = L.nb; a.nmax = L.nmax; a.ldJ = L.ldJ;
     a.cnt = L.cnt; a.gidx = L.gidx; a.nact = L.nact; a.apos = L.apos; a.krank = L.krank; a.nJ = L.nJ;

@@ -272,7 +272,8 @@ size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak, bool stor
 // start at tiles + x * capx.  Filled by launch_elim, read by launch_schur.
 struct TileList {
     int* cnt = nullptr;     // 8 counters, zero before the colour's elimination
-    int* tiles = nullptr;   // 8 * capx entries
+    int* tiles = nullptr;   // 8 * capx entries: (box << 12) | (tile row << 6) | tile column
+    int* info = nullptr;    // 8 * capx entries beside tiles: (|J| << 16) | |R| of the tile's box
     int capx = 0;           // ceil(boxes / 8) * ceil(ldJ / 64)^2
 };
 // Every active tile goes to tl; the J segment of each 3x3 slot goes to L.jseg.

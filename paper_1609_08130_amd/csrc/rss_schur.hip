@@ -43,8 +43,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));    // accumulator of on
 // MF (TT = float only): the FP32 products on the matrix cores (v_mfma_f32_16x16x4f32) instead
 // of vector FMAs.
 template <typename TT, typename ST, bool ATOM, bool MF = false>
-__global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restrict__ boxes,
-                                               const int* __restrict__ tl_cnt, const int* __restrict__ tl_tiles,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<TT, double>::value ? 4 : 7))) k_schur(SchurArgs a, const int* __restrict__ tl_cnt,
+                                               const int* __restrict__ tl_tiles, const int* __restrict__ tl_info,
                                                int tl_capx) {
     constexpr int TM = 64, TK = 16;
     __shared__ TT As[TK][TM + 1];
@@ -59,16 +59,16 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
     // Workgroups are dealt to the 8 XCDs round-robin in launch order: workgroup x + 8 s
     // takes entry s of tile list x, which holds the active tiles of the boxes at positions
     // bi = x mod 8 of the colour, so all tiles of a box run on one XCD and its X_JR and G
-    // stay in one L2.  Workgroups past the end of their list leave after one load.
+    // stay in one L2.  The list count, the entry (box, tile) and the box's |J| and |R| are
+    // loaded together (every workgroup index is below the list capacity), so the slab loads
+    // wait for one load latency; workgroups past the end of their list leave there.
     const int xcd = blockIdx.x & 7, sidx = blockIdx.x >> 3;
-    if (sidx >= tl_cnt[xcd]) return;
-    const int ent = tl_tiles[(int64_t)xcd * tl_capx + sidx];
-    const int bi = ent >> 12, ti = (ent >> 6) & 63, tj = ent & 63;
-    const int c = boxes[bi];
-    const int nj = a.nJ[c];
-    if (nj == 0 || ti * TM >= nj || tj * TM >= nj) return;
-    const int n = a.cnt[c], k = a.krank[c], r = n - k;
-    if (r <= 0) return;
+    const int64_t li = (int64_t)xcd * tl_capx + sidx;
+    const int lcnt = tl_cnt[xcd], ent = tl_tiles[li], inf = tl_info[li];
+    if (sidx >= lcnt) return;
+    const int c = ent >> 12, ti = (ent >> 6) & 63, tj = ent & 63;
+    const int nj = inf >> 16, r = inf & 0xffff;
+    if (nj == 0 || r <= 0 || ti * TM >= nj || tj * TM >= nj) return;
     const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
     const int cx = c % nb, cy = c / nb;
@@ -181,17 +181,22 @@ __global__ void __launch_bounds__(256) k_schur(SchurArgs a, const int* __restric
                     }
             }
         } else {
+            // the last slab stops at the first multiple of 4 not below |R| (its zero padding
+            // would add only zero products)
+            const int kn = min(TK, r - k0);
+            for (int k4 = 0; k4 < kn; k4 += 4) {
 #pragma unroll
-            for (int kk = 0; kk < TK; ++kk) {
-                TT av[4], bv[4];
+                for (int kk = k4; kk < k4 + 4; ++kk) {
+                    TT av[4], bv[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) av[u] = As[kk][tx + 16 * u];
+                    for (int u = 0; u < 4; ++u) av[u] = As[kk][tx + 16 * u];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][ty + 16 * v];
+                    for (int v = 0; v < 4; ++v) bv[v] = Bs[kk][ty + 16 * v];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                    for (int v = 0; v < 4; ++v)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) vacc[u + 4 * v] += av[u] * bv[v];
+                        for (int u = 0; u < 4; ++u) vacc[u + 4 * v] += av[u] * bv[v];
+                }
             }
         }
     }
@@ -383,25 +388,25 @@ int launch_schur(const Level& L, const int* boxes, int nboxes, int maxJ, int mix
         note_shape(std::string("schur_f32") + (L.store32 ? "_store32" : "_store64") + form);
         a.XJR = L.XJR32; a.G = L.G32;
         if (L.store32) {
-            if (sf == 1 && atom) k_schur<float, float, true, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else if (sf == 1) k_schur<float, float, false, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else if (atom) k_schur<float, float, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else k_schur<float, float, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            if (sf == 1 && atom) k_schur<float, float, true, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else if (sf == 1) k_schur<float, float, false, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else if (atom) k_schur<float, float, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else k_schur<float, float, false><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
         } else {
-            if (sf == 1 && atom) k_schur<float, double, true, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else if (sf == 1) k_schur<float, double, false, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else if (atom) k_schur<float, double, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else k_schur<float, double, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            if (sf == 1 && atom) k_schur<float, double, true, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else if (sf == 1) k_schur<float, double, false, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else if (atom) k_schur<float, double, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else k_schur<float, double, false><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
         }
     } else {
         note_shape(std::string("schur_f64") + (L.store32 ? "_store32" : "_store64") + form);
         a.XJR = L.XJR; a.G = L.G;
         if (L.store32) {
-            if (atom) k_schur<double, float, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else k_schur<double, float, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            if (atom) k_schur<double, float, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else k_schur<double, float, false><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
         } else {
-            if (atom) k_schur<double, double, true><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
-            else k_schur<double, double, false><<<grid, block, 0, s>>>(a, boxes, tl.cnt, tl.tiles, tl.capx);
+            if (atom) k_schur<double, double, true><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
+            else k_schur<double, double, false><<<grid, block, 0, s>>>(a, tl.cnt, tl.tiles, tl.info, tl.capx);
         }
     }
     return 0;
