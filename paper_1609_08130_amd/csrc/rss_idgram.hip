@@ -779,10 +779,20 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const int* __restrict__ cnt
 __device__ inline dd gram_entry(const double2* G, int nsl, int nmax, int64_t sstride, int a, int b) {
 #pragma clang fp contract(off)
     if (a > b) { int t0 = a; a = b; b = t0; }
+    const double2* g = G + (int64_t)a * nmax + b;
+    // the first kGramPf slices are loaded together, then summed in slice order (one load
+    // latency per entry instead of one per slice)
+    constexpr int kGramPf = 6;
+    double2 v[kGramPf];
+#pragma unroll
+    for (int s = 0; s < kGramPf; ++s) v[s] = s < nsl ? g[s * sstride] : make_double2(0.0, 0.0);
     dd acc = {0.0, 0.0};
-    for (int s = 0; s < nsl; ++s) {
-        double2 v = G[s * sstride + (int64_t)a * nmax + b];
-        acc = dd_add(acc, {v.x, v.y});
+#pragma unroll
+    for (int s = 0; s < kGramPf; ++s)
+        if (s < nsl) acc = dd_add(acc, {v[s].x, v[s].y});
+    for (int s = kGramPf; s < nsl; ++s) {
+        const double2 w = g[s * sstride];
+        acc = dd_add(acc, {w.x, w.y});
     }
     return acc;
 }
@@ -941,13 +951,56 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
             // r_jq = (G_pq - sum_{i<j} r_ip r_iq) / r_jj ; d_q -= r_jq^2.  Thread sub of the
             // column takes i = sub, sub + SUB, ... in two partial sums.
             const dd rinv = dd_recip(rjj);
+            // term t (row i = sub + SUB t) goes to s0 for even t, s1 for odd t, each in
+            // increasing t; rows < kc from LDS, then rows >= kc from the workspace, four
+            // terms per pass with all their loads issued first
             dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+            const int jl = min(j, kc);
             int i = sub;
-            for (; i + SUB < j; i += 2 * SUB) {
+            for (; i + 3 * SUB < jl; i += 4 * SUB) {
+                dd a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = {Rh[(i + u * SUB) * nmax + p], Rl[(i + u * SUB) * nmax + p]};
+                    b[u] = {Rh[(i + u * SUB) * nmax + q], Rl[(i + u * SUB) * nmax + q]};
+                }
+                s0 = dd_add(s0, dd_mul(a[0], b[0]));
+                s1 = dd_add(s1, dd_mul(a[1], b[1]));
+                s0 = dd_add(s0, dd_mul(a[2], b[2]));
+                s1 = dd_add(s1, dd_mul(a[3], b[3]));
+            }
+            for (; i + SUB < jl; i += 2 * SUB) {
                 s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
                 s1 = dd_add(s1, dd_mul(rget(i + SUB, p), rget(i + SUB, q)));
             }
-            if (i < j) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+            bool odd = false;   // the next term goes to s1
+            if (i < jl) {
+                s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+                i += SUB;
+                odd = true;
+            }
+            if (i < j) {
+                if (odd) { const dd t0 = s0; s0 = s1; s1 = t0; }
+                for (; i + 3 * SUB < j; i += 4 * SUB) {
+                    double2 a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = Rg[(int64_t)(i + u * SUB) * nmax + p];
+                        b[u] = Rg[(int64_t)(i + u * SUB) * nmax + q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u += 2) {
+                        s0 = dd_add(s0, dd_mul({a[u].x, a[u].y}, {b[u].x, b[u].y}));
+                        s1 = dd_add(s1, dd_mul({a[u + 1].x, a[u + 1].y}, {b[u + 1].x, b[u + 1].y}));
+                    }
+                }
+                for (; i + SUB < j; i += 2 * SUB) {
+                    s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+                    s1 = dd_add(s1, dd_mul(rget(i + SUB, p), rget(i + SUB, q)));
+                }
+                if (i < j) s0 = dd_add(s0, dd_mul(rget(i, p), rget(i, q)));
+                if (odd) { const dd t0 = s0; s0 = s1; s1 = t0; }
+            }
             const dd sum = group_sum_dd<SUB>(dd_add(s0, s1));
             const dd rjq = dd_mul(dd_sub(gpq, sum), rinv);
             rput(j, q, rjq);
@@ -980,7 +1033,26 @@ __global__ void __launch_bounds__(NTH) k_pchol(const int* __restrict__ cnt, cons
             // split over the column's threads
             for (int a = k - 1; a >= 0; --a) {
                 double part = 0.0;
-                for (int b = a + 1 + sub; b < k; b += SUB) part += rhi(a, piv[b]) * rhi(b, q);
+                int b = a + 1 + sub;
+                if (a < kc) {
+                    // rows a and b in LDS: four terms per pass, their loads issued first
+                    const double* ra = Rh + (int64_t)a * nmax;
+                    const int bl = min(k, kc);
+                    for (; b + 3 * SUB < bl; b += 4 * SUB) {
+                        int pb[4];
+                        double xa[4], yb[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            pb[u] = piv[b + u * SUB];
+                            yb[u] = Rh[(int64_t)(b + u * SUB) * nmax + q];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) xa[u] = ra[pb[u]];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) part += xa[u] * yb[u];
+                    }
+                }
+                for (; b < k; b += SUB) part += rhi(a, piv[b]) * rhi(b, q);
                 const double acc = rhi(a, q) - group_sum<SUB>(part);
                 rset_hi(a, q, acc / rhi(a, piv[a]));
             }
