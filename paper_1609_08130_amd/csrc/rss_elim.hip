@@ -468,8 +468,9 @@ __device__ inline double lane_read(double v, int ln) {
 // interchanging form.  At the end row p_j of the array holds row j of the interchanging form,
 // and the column interchanges of that form (the transposition of j with the position row p_j
 // had reached there) are undone on the way out.  One barrier per step: the wave that owns
-// column j picks the pivot and publishes column j, which goes through a buffer of two halves
-// used in alternate steps; every wave reads row p of its own columns from the lane holding it.
+// column j picks the pivot and publishes column j (through a buffer of two halves used in
+// alternate steps), p and 1 / x_pj, so the other waves load all three together; every wave
+// reads row p of its own columns from the lane holding it.
 // x holds the matrix on entry (zero outside r x r); the inverse is written to Xs (ld ldx).
 // sc: 4 * ldx doubles of LDS.
 template <int NTH, int RB, int CB>
@@ -480,6 +481,7 @@ __device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, float* 
     const int wv = tid >> 6, lane = tid & 63;
     double* colj = sc;                  // two halves of ldx
     double* pivs = sc + 2 * ldx;
+    double* rinvs = sc + 3 * ldx;       // 1 / pivot, by step parity
     unsigned used = 0;   // bit h: row lane + 64 h has been a pivot row
     for (int j = 0; j < r; ++j) {
         double* cb = colj + (j & 1) * ldx;
@@ -487,12 +489,14 @@ __device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, float* 
         if (wv == j % NW) {
             unsigned long long kb = 0;
             int hb = 0;
+            double vc[RB];
 #pragma unroll
             for (int h = 0; h < RB; ++h) {
                 double v = 0.0;
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
                     if (c == cj) v = x[h][c];
+                vc[h] = v;
                 const int i = lane + 64 * h;
                 if (i < r) cb[i] = v;
                 const bool cand = i < r && !((used >> h) & 1u);
@@ -508,15 +512,24 @@ __device__ bool gj_inverse_reg(double (&x)[RB][CB], double* Xs, int ldx, float* 
                     if (b) p = 64 * h + __ffsll((long long)b) - 1;
                 }
             }
-            if (lane == 0) colswap[j] = p;
+            // the pivot and its reciprocal go out with p (-1: no usable pivot)
+            double d = 0.0;
+            if (p >= 0) {
+#pragma unroll
+                for (int h = 0; h < RB; ++h)
+                    if (h == (p >> 6)) d = lane_read(vc[h], p & 63);
+            }
+            if (!(fabs(d) > 0.0)) p = -1;
+            if (lane == 0) {
+                colswap[j] = p;
+                pivs[j] = d;
+                rinvs[j & 1] = 1.0 / d;
+            }
         }
         __syncthreads();
         const int p = __builtin_amdgcn_readfirstlane(colswap[j]);
         if (p < 0) return false;
-        const double d = cb[p];
-        if (!(fabs(d) > 0.0)) return false;
-        if (tid == 0) pivs[j] = d;
-        const double rinv = 1.0 / d;
+        const double rinv = rinvs[j & 1];
         const int pl = p & 63, ph = p >> 6;
         double fv[RB];
 #pragma unroll
