@@ -59,6 +59,7 @@ struct ElimArgs {
 };
 
 constexpr int kTileMax = 32;   // rows (or columns) of J per tile, at most
+constexpr int kLineMax = 128;  // lines of the tiles one row workgroup takes, at most
 constexpr int kElimGLds = 98304;   // LDS bytes of k_elim_g with X_RR^{-1} held for all its tiles
 
 // Workgroups are dealt to the 8 XCDs round-robin in launch order.  With a grid of
@@ -118,9 +119,9 @@ struct ElimShared {
     int nbox[8];
     int joff[9];                    // J segments: [0, k) is S, then one per adjacent box
     int nN;
-    const void* srcp[kTileMax];     // source block and row/column of each tile line ...
-    int srcpos[kTileMax];
-    unsigned char src64[kTileMax];  // ... and whether that block holds FP64 entries
+    const void* srcp[kLineMax];     // source block and row/column of each tile line ...
+    int srcpos[kLineMax];
+    unsigned char src64[kLineMax];  // ... and whether that block holds FP64 entries
 };
 
 // Entry idx of the source block of tile line `line`.
@@ -203,46 +204,44 @@ __device__ inline int j_map(const ElimShared<ST>& sh, const ElimArgs& a, int c, 
 // Rows [r0, r0 + tr) of E = [J; R] against the columns R: rows of J give X_JR (and its
 // FP32 copy when XJR32 != nullptr), rows past J give Y_RR = A_RR - A_RS T (into Y, ld nmax).
 // tA: tw x n.
+// Source of lines l < nl of [J; R] starting at row r0 (J rows r0 + l < nj, then R rows):
+// the block holding the line, its row there and the block's entry type.  The caller
+// synchronizes.
 template <int NTH, typename ST>
-__device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
-                               int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
-    const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
-    const int n = k + r;
+__device__ void elim_rows_src(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int nj, int r0, int nl) {
     bool acc64;
     const void* Acc = self_block<ST>(a, c, acc64);
-    if (tid < tr) {
-        const int jj = r0 + tid;
+    for (int l = threadIdx.x; l < nl; l += NTH) {
+        const int jj = r0 + l;
         if (jj < k) {
-            sh.srcp[tid] = Acc;
-            sh.src64[tid] = acc64;
-            sh.srcpos[tid] = sh.sp[jj];
+            sh.srcp[l] = Acc;
+            sh.src64[l] = acc64;
+            sh.srcpos[l] = sh.sp[jj];
         } else if (jj < nj) {
             int s = 0;
             while (sh.joff[s + 1] <= jj) ++s;
-            sh.srcp[tid] = sh.blk_nc[s];
-            sh.src64[tid] = sizeof(ST) == 8;
-            sh.srcpos[tid] = sh.nap[s][jj - sh.joff[s]];
+            sh.srcp[l] = sh.blk_nc[s];
+            sh.src64[l] = sizeof(ST) == 8;
+            sh.srcpos[l] = sh.nap[s][jj - sh.joff[s]];
         } else {
-            sh.srcp[tid] = Acc;
-            sh.src64[tid] = acc64;
-            sh.srcpos[tid] = sh.rp[jj - nj];
+            sh.srcp[l] = Acc;
+            sh.src64[l] = acc64;
+            sh.srcpos[l] = sh.rp[jj - nj];
         }
     }
-    __syncthreads();
-    // tA[i + tw col]: line i of the tile at B position (col < k ? sp[col] : rp[col - k])
-    stage2d<NTH>(
-        tr, n,
-        [&](int i, int col) {
-            const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
-            return src_entry(sh, i, sh.srcpos[i] + (int64_t)pos * nmax);
-        },
-        [&](int i, int col, double v) { tA[i + tw * col] = v; });
-    __syncthreads();
-    // The transposed tile (r x tr) on the FP64 matrix cores, so that the 16 lanes of a
-    // result row hold 16 consecutive lines: D = A_(tile, R)^T - T^T A_(tile, S)^T with
-    // A = -T^T (A[b][q] = -Ts[b + r q]) and B[q][i] = tA[i + tw q]; D starts at the R
-    // columns of the tile.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-    // receives D[l / 16 + 4 v][l % 16].  16 x 16 blocks are dealt to the waves.
+}
+
+// The products of a tile of tr lines starting at row r0, its lines in tA[i + tw col] (col
+// a B position: col < k ? sp[col] : rp[col - k]).  The transposed tile (r x tr) on the FP64
+// matrix cores, so that the 16 lanes of a result row hold 16 consecutive lines:
+// D = A_(tile, R)^T - T^T A_(tile, S)^T with A = -T^T (A[b][q] = -Ts[b + r q]) and
+// B[q][i] = tA[i + tw q]; D starts at the R columns of the tile.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 v][l % 16].  16 x 16
+// blocks are dealt to the waves.  Rows of J go to X_JR (and its FP32 copy), rows of R to Y.
+template <int NTH>
+__device__ void elim_rows_product(const ElimArgs& a, int k, int r, int nj, int r0, int tr, int tw, const double* Ts,
+                                  const double* tA, double* XJR, float* XJR32, double* Y) {
+    const int tid = threadIdx.x, nmax = a.nmax, ldJ = a.ldJ;
     const int lane = tid & 63, wv = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     const int nrb = (r + 15) / 16, nblk = nrb * ((tr + 15) / 16);
@@ -276,6 +275,26 @@ __device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int
             }
         }
     }
+}
+
+// One tile of tr lines starting at row r0: sources, lines staged into tA, products.
+template <int NTH, typename ST>
+__device__ void elim_rows_tile(ElimShared<ST>& sh, const ElimArgs& a, int c, int k, int r, int nj, int r0, int tr,
+                               int tw, const double* Ts, double* tA, double* XJR, float* XJR32, double* Y) {
+    const int nmax = a.nmax;
+    const int n = k + r;
+    elim_rows_src<NTH, ST>(sh, a, c, k, nj, r0, tr);
+    __syncthreads();
+    // tA[i + tw col]: line i of the tile at B position (col < k ? sp[col] : rp[col - k])
+    stage2d<NTH>(
+        tr, n,
+        [&](int i, int col) {
+            const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
+            return src_entry(sh, i, sh.srcpos[i] + (int64_t)pos * nmax);
+        },
+        [&](int i, int col, double v) { tA[i + tw * col] = v; });
+    __syncthreads();
+    elim_rows_product<NTH>(a, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
     __syncthreads();
 }
 
@@ -772,15 +791,53 @@ __global__ void __launch_bounds__(NTH) k_elim_rows(ElimArgs a, const int* __rest
     double* XJR = a.XJR + (int64_t)c * ldJ * nmax;
     float* XJR32 = mixed ? a.XJR32 + (int64_t)c * ldJ * nmax : nullptr;
     double* Y = work + (int64_t)bi * nmax * nmax;
-    for (int t = tile * tpw; t < (tile + 1) * tpw; ++t) {   // tpw consecutive tiles share the setup
-        const int r0 = t * tw;
-        if (r0 >= nj + r) break;
-        const int tr = min(tw, nj + r - r0);
-        for (int jj = r0 + tid; jj < min(nj, r0 + tr); jj += NTH) {
-            a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
-            a.jmap[(int64_t)c * ldJ + jj] = j_map(sh, a, c, jj, k);
+    // tpw consecutive tiles share the set-up: rows [rlo, rhi) of [J; R]
+    const int rlo = tile * tpw * tw, rhi = min((tile + 1) * tpw * tw, nj + r);
+    if (rlo >= rhi) return;
+    for (int jj = rlo + tid; jj < min(nj, rhi); jj += NTH) {
+        a.Jg[(int64_t)c * ldJ + jj] = j_global(sh, a, c, jj, k);
+        a.jmap[(int64_t)c * ldJ + jj] = j_map(sh, a, c, jj, k);
+    }
+    constexpr int PF = 8;   // tile entries per thread held in registers
+    if (rhi - rlo > kLineMax || tw * n > PF * NTH) {
+        for (int r0 = rlo; r0 < rhi; r0 += tw)
+            elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, min(tw, rhi - r0), tw, Ts, tA, XJR, XJR32, Y);
+        return;
+    }
+    // The sources of all lines at once; then the lines of tile t + 1 are loaded into
+    // registers while the products of tile t run (one barrier after each landing and
+    // after each product, as the tile form)
+    elim_rows_src<NTH, ST>(sh, a, c, k, nj, rlo, rhi - rlo);
+    __syncthreads();
+    double v[PF];
+    auto issue = [&](int r0) {
+        const int tr = min(tw, rhi - r0), total = tr * n, l0 = r0 - rlo;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + NTH * u;
+            v[u] = 0.0;
+            if (e < total) {
+                const int i = e % tr, col = e / tr;
+                const int pos = col < k ? sh.sp[col] : sh.rp[col - k];
+                v[u] = src_entry(sh, l0 + i, sh.srcpos[l0 + i] + (int64_t)pos * nmax);
+            }
         }
-        elim_rows_tile<NTH, ST>(sh, a, c, k, r, nj, r0, tr, tw, Ts, tA, XJR, XJR32, Y);
+    };
+    auto land = [&](int r0) {
+        const int tr = min(tw, rhi - r0), total = tr * n;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int e = tid + NTH * u;
+            if (e < total) tA[e % tr + tw * (e / tr)] = v[u];
+        }
+    };
+    issue(rlo);
+    for (int r0 = rlo; r0 < rhi; r0 += tw) {
+        land(r0);
+        __syncthreads();
+        if (r0 + tw < rhi) issue(r0 + tw);
+        elim_rows_product<NTH>(a, k, r, nj, r0, min(tw, rhi - r0), tw, Ts, tA, XJR, XJR32, Y);
+        __syncthreads();
     }
 }
 
