@@ -37,9 +37,11 @@ def rss():
     # Cholesky with 16 LDS rows, 256-thread inverse) and the few-box shapes of the upper levels
     ("grid512_leaf16_tol1e-6", ["elim_rows_w*_tpw4", "elim_inv_256*", "elim_inv_1024*", "pchol_64x1_kc16",
                                 "solve_fwd_256_f64", "solve_fwd_1024_f64", "gram_reduce"]),
-    # leaf 64: 455 boxes per colour at the leaves (the tuned plans of 256..511 boxes: two
-    # tiles per elimination workgroup, 1024-thread inverse, 256-thread sweeps)
-    ("grid512_leaf64_tol1e-6", ["elim_rows_w*_tpw2", "elim_inv_1024*", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
+    # leaf 64: 455 boxes per colour at the leaves (the tuned plans of 256..511 boxes: four
+    # 32-line tiles per elimination workgroup, 1024-thread inverse, 256-thread sweeps)
+    ("grid512_leaf64_tol1e-6", ["elim_rows_w32_tpw4", "elim_inv_1024*", "solve_fwd_256_f64", "solve_bwd_256_f64"]),
+    # the same with two 16-line tiles per workgroup (an earlier tuned plan of those colours)
+    ("grid512_leaf64_tol1e-6@b2.elim_tpw=2,b2.elim_tw=16", ["elim_rows_w16_tpw2", "elim_inv_1024*"]),
     # the same with the former plans of those colours forced (256-thread inverse, one tile per
     # workgroup, 16-line tiles), so both variants stay checked
     ("grid512_leaf64_tol1e-6@b2.inv_threads=256,b2.elim_tpw=1,b2.elim_tw=16",
