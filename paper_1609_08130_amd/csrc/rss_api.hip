@@ -606,9 +606,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         // Schur tile lists: 8 counters per colour, zero at the level start; one entry buffer
         // reused by the colours in turn
-        // a tile-list entry packs the box in 19 bits; the entries and the per-tile box sizes
-        // share one buffer
-        if ((size_t)L.nbox >= ((size_t)1 << 19)) fail(RSS_E_UNSUPPORTED, "more than 2^19 boxes in one level");
+        // the tile-list entries and the per-tile box sizes share one buffer
         const int capx = rss::schur_tile_capx((int)maxc, L.ldJ);
         if (!tl_cnt) tl_cnt = dalloc<int>(f, 9 * 8);
         if ((size_t)capx * 16 > tl_n) {

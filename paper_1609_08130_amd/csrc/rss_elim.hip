@@ -886,8 +886,8 @@ __global__ void __launch_bounds__(NTH) k_elim_inv(ElimArgs a, const int* __restr
         off = __shfl(off, 0, 64);
         const int64_t o = (int64_t)x * a.tl_capx + off;
         for (int t = tid; t < ntl; t += 64) {
-            a.tl_tiles[o + t] = (c << 12) | ((t % nt1) << 6) | (t / nt1);
-            a.tl_info[o + t] = (nj << 16) | r;
+            a.tl_tiles[o + t] = (int)(((unsigned)c << 12) | ((t % nt1) << 6) | (t / nt1));
+            a.tl_info[o + t] = (int)(((unsigned)(c >> 20) << 21) | ((unsigned)nj << 9) | (unsigned)r);
         }
     } else if (tid < 64 + 9) {
         // J rows of the box at 3x3 slot s = (dy + 1) 3 + (dx + 1) (slot 4: S of c)

@@ -13,6 +13,7 @@ namespace rss {
 
 constexpr int kMaxDepth = 12;      // deepest uniform tree level (4^12 leaf boxes)
 constexpr int kMaxBox = 256;       // largest active DOF count of one box
+static_assert(kMaxBox < 512 && 9 * kMaxBox < 4096, "Schur tile-list info packs |R| in 9 and |J| in 12 bits");
 constexpr int kMaxProxy = 64;
 constexpr int kNbr = 25;           // stored block pairs per box: offsets (dx, dy) in [-2, 2]^2
 constexpr double kTau = 1e-11;     // pivot tie window relative to the first pivot norm
@@ -272,8 +273,9 @@ size_t id_work_doubles(int nmax, int n_proxy, size_t nboxes, int weak, bool stor
 // start at tiles + x * capx.  Filled by launch_elim, read by launch_schur.
 struct TileList {
     int* cnt = nullptr;     // 8 counters, zero before the colour's elimination
-    int* tiles = nullptr;   // 8 * capx entries: (box << 12) | (tile row << 6) | tile column
-    int* info = nullptr;    // 8 * capx entries beside tiles: (|J| << 16) | |R| of the tile's box
+    int* tiles = nullptr;   // 8 * capx entries: (box mod 2^20 << 12) | (tile row << 6) | tile column
+    int* info = nullptr;    // 8 * capx entries beside tiles: (box / 2^20 << 21) | (|J| << 9) | |R|
+                            // (|J| <= 9 kMaxBox < 4096, |R| <= kMaxBox < 512)
     int capx = 0;           // ceil(boxes / 8) * ceil(ldJ / 64)^2
 };
 // Every active tile goes to tl; the J segment of each 3x3 slot goes to L.jseg.

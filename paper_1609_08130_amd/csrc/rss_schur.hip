@@ -66,8 +66,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::i
     const int64_t li = (int64_t)xcd * tl_capx + sidx;
     const int lcnt = tl_cnt[xcd], ent = tl_tiles[li], inf = tl_info[li];
     if (sidx >= lcnt) return;
-    const int c = ent >> 12, ti = (ent >> 6) & 63, tj = ent & 63;
-    const int nj = inf >> 16, r = inf & 0xffff;
+    const int c = (int)(((unsigned)ent >> 12) | (((unsigned)inf >> 21) << 20)), ti = (ent >> 6) & 63, tj = ent & 63;
+    const int nj = (inf >> 9) & 0xfff, r = inf & 0x1ff;
     if (nj == 0 || r <= 0 || ti * TM >= nj || tj * TM >= nj) return;
     const int nmax = a.nmax, ldJ = a.ldJ, nb = a.nb;
     const int64_t bsz = (int64_t)nmax * nmax;
