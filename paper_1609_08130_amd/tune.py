@@ -9,8 +9,11 @@ time for the sweep widths, one bucket at a time), assigns each level to the buck
 largest colour, and keeps per bucket the fastest value; fields are tuned in order, each
 with the best values found so far.  It then writes the table and a JSON summary.
 
-    python -m paper_1609_08130_amd.tune [--n 1024] [--reps 3] [--out csrc/tuned_plans.inc]
+    python -m paper_1609_08130_amd.tune [--n 1024] [--tols 1e-6] [--reps 3] [--out csrc/tuned_plans.inc]
 
+With several tolerances (--tols 1e-3,1e-6,1e-9) every candidate is measured at each, and a
+bucket's score is the sum over tolerances of its phase time divided by the same bucket's
+time with the starting table at that tolerance, so each tolerance weighs the same.
 Buckets that no level of the workload falls into keep their previous values.
 """
 from __future__ import annotations
@@ -97,6 +100,25 @@ def measure(rss, torch, W, n, tol, table, reps, solves=0):
     return med, solve_ms
 
 
+def combine(per_tol, base_tol):
+    """Per bucket: sum over tolerances of time / the starting table's time (each tolerance
+    weighs the same); per_tol and base_tol map tolerance -> {bucket: ms}."""
+    out = {}
+    for tol, per_bucket in per_tol.items():
+        for b, t in per_bucket.items():
+            ref = base_tol.get(tol, {}).get(b, 0.0)
+            out[b] = out.get(b, 0.0) + (t / ref if ref > 0 else t)
+    return out
+
+
+def bucket_times(med, idx):
+    """Phase idx (0 ID, 1 elimination, 2 Schur) summed per bucket of the levels."""
+    per_bucket = {}
+    for (d, p), t in med.items():
+        per_bucket[level_bucket(d)] = per_bucket.get(level_bucket(d), 0.0) + t[idx]
+    return per_bucket
+
+
 def write_table(path, table, note):
     rows = ",\n".join("    {" + ", ".join(str(v) for v in row) + "}" for row in table)
     text = (f"// Launch-plan table, one row per bucket of boxes per colour (lower bounds kPlanBucketLo).\n"
@@ -111,7 +133,8 @@ def write_table(path, table, note):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--tol", type=float, default=None, help="one tolerance (same as --tols T)")
+    ap.add_argument("--tols", default="1e-6", help="comma-separated tolerances, weighed equally")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--solves", type=int, default=20)
     ap.add_argument("--out", default=os.path.join(HERE, "csrc", "tuned_plans.inc"))
@@ -121,12 +144,18 @@ def main():
 
     from paper_1609_08130_amd import rss
     from paper_1609_08130_amd import workloads as W
+    tols = [args.tol] if args.tol is not None else [float(t) for t in args.tols.split(",")]
     table = [list(r) for r in DEFAULTS]
-    base, base_solve = measure(rss, torch, W, args.n, args.tol, table, args.reps, args.solves)
-    used = sorted({level_bucket(d) for d, _ in base})
-    log = {"n": args.n, "tol": args.tol, "reps": args.reps, "buckets_used": used, "baseline_solve_ms": base_solve,
+    base_by_tol = {}
+    base_phase = {}   # tolerance -> phase index -> {bucket: ms} with the starting table
+    for tol in tols:
+        base_by_tol[tol] = measure(rss, torch, W, args.n, tol, table, args.reps, args.solves)
+        base_phase[tol] = {i: bucket_times(base_by_tol[tol][0], i) for i in range(3)}
+    base, base_solve = base_by_tol[tols[0]]
+    used = sorted({level_bucket(d) for tol in tols for d, _ in base_by_tol[tol][0]})
+    log = {"n": args.n, "tols": tols, "reps": args.reps, "buckets_used": used, "baseline_solve_ms": base_solve,
            "baseline": {f"{d}/{p}": v for (d, p), v in base.items()}, "steps": []}
-    print(f"[tune] baseline solve {base_solve:.3f} ms; levels {sorted(base)}", flush=True)
+    print(f"[tune] tolerances {tols}; baseline solve {base_solve:.3f} ms; levels {sorted(base)}", flush=True)
     for field in ORDER:
         fi = FIELDS.index(field)
         cands, phase = CANDIDATES[field]
@@ -136,32 +165,36 @@ def main():
                 for v in cands:
                     trial = [list(r) for r in table]
                     trial[b][fi] = v
-                    _, t = measure(rss, torch, W, args.n, args.tol, trial, 1, args.solves)
-                    log["steps"].append({"field": field, "bucket": b, "value": v, "solve_ms": t})
-                    print(f"[tune] {field} bucket {b} = {v}: solve {t:.3f} ms", flush=True)
+                    t = 0.0
+                    for tol in tols:
+                        _, ts = measure(rss, torch, W, args.n, tol, trial, 1, args.solves)
+                        t += ts / base_by_tol[tol][1]
+                    log["steps"].append({"field": field, "bucket": b, "value": v, "solve_score": t})
+                    print(f"[tune] {field} bucket {b} = {v}: solve score {t:.4f}", flush=True)
                     if best_t is None or t < best_t:
                         best_v, best_t = v, t
                 table[b][fi] = best_v
             continue
+        idx = {"id": 0, "elim": 1, "schur": 2}[phase]
         results = {}
         for v in cands:
             trial = [list(r) for r in table]
             for b in range(len(trial)):
                 trial[b][fi] = v
-            med, _ = measure(rss, torch, W, args.n, args.tol, trial, args.reps)
-            idx = {"id": 0, "elim": 1, "schur": 2}[phase]
-            per_bucket = {}
-            for (d, p), t in med.items():
-                per_bucket.setdefault(level_bucket(d), 0.0)
-                per_bucket[level_bucket(d)] += t[idx]
-            results[v] = per_bucket
+            per_tol = {}
+            for tol in tols:
+                med, _ = measure(rss, torch, W, args.n, tol, trial, args.reps)
+                per_tol[tol] = bucket_times(med, idx)
+            results[v] = combine(per_tol, {tol: base_phase[tol][idx] for tol in tols})
             log["steps"].append({"field": field, "value": v, "phase": phase,
-                                 "ms_by_bucket": {str(b): round(t, 4) for b, t in per_bucket.items()}})
-            print(f"[tune] {field} = {v}: {phase} ms by bucket "
-                  f"{ {b: round(t, 3) for b, t in sorted(per_bucket.items())} }", flush=True)
+                                 "ms_by_tol_bucket": {str(tol): {str(b): round(t, 4) for b, t in pb.items()}
+                                                      for tol, pb in per_tol.items()},
+                                 "score_by_bucket": {str(b): round(t, 4) for b, t in results[v].items()}})
+            print(f"[tune] {field} = {v}: {phase} score by bucket "
+                  f"{ {b: round(t, 4) for b, t in sorted(results[v].items())} }", flush=True)
         for b in used:
             table[b][fi] = min(cands, key=lambda v: results[v].get(b, float("inf")))
-    final, final_solve = measure(rss, torch, W, args.n, args.tol, table, args.reps, args.solves)
+    final, final_solve = measure(rss, torch, W, args.n, tols[0], table, args.reps, args.solves)
     log["table"] = table
     log["final_solve_ms"] = final_solve
     log["final"] = {f"{d}/{p}": v for (d, p), v in final.items()}
@@ -170,8 +203,8 @@ def main():
     ssc = lambda m: sum(v[2] for v in m.values())
     print(f"[tune] ID {sid(base):.3f} -> {sid(final):.3f} ms, elimination {sel(base):.3f} -> {sel(final):.3f} ms, "
           f"Schur {ssc(base):.3f} -> {ssc(final):.3f} ms, solve {base_solve:.3f} -> {final_solve:.3f} ms", flush=True)
-    write_table(args.out, table, f"{args.n}x{args.n} grid, tol {args.tol:g}, mixed precision, median of "
-                f"{args.reps} factorizations per candidate")
+    write_table(args.out, table, f"{args.n}x{args.n} grid, tol {', '.join(f'{t:g}' for t in tols)}, mixed "
+                f"precision, median of {args.reps} factorizations per candidate")
     if args.summary:
         with open(args.summary, "w") as fh:
             json.dump(log, fh, indent=1)

@@ -58,3 +58,21 @@ def test_committed_table_is_in_the_tuners_space(tmp_path):
     out = tmp_path / "plans.inc"
     tune.write_table(str(out), rows, "test")
     assert _read_table(str(out)) == (lo, rows)
+
+
+def test_tolerances_weigh_the_same():
+    # two tolerances, one 10x slower overall: a value 10% faster at the slow one and 10%
+    # slower at the fast one scores the same as the starting value
+    base = {1e-6: {0: 10.0, 4: 20.0}, 1e-9: {0: 100.0, 4: 200.0}}
+    same = tune.combine(base, base)
+    assert same == {0: 2.0, 4: 2.0}
+    mixed = tune.combine({1e-6: {0: 11.0, 4: 20.0}, 1e-9: {0: 90.0, 4: 200.0}}, base)
+    assert abs(mixed[0] - 2.0) < 1e-12 and mixed[4] == 2.0
+
+
+def test_bucket_times_sum_the_levels_of_a_bucket():
+    # depths 2, 3, 4 share bucket 0; depth 7 is bucket 4; phases (ID, elimination, Schur)
+    med = {(2, "strong"): (1.0, 2.0, 3.0), (3, "strong"): (1.0, 2.0, 3.0), (4, "strong"): (1.0, 2.0, 3.0),
+           (7, "strong"): (5.0, 6.0, 7.0)}
+    assert tune.bucket_times(med, 0) == {0: 3.0, 4: 5.0}
+    assert tune.bucket_times(med, 2) == {0: 9.0, 4: 7.0}
