@@ -49,6 +49,10 @@ Readings of points the paper leaves open:
   each run in the colour-major order.  After the strong pass at depth 2 one more weak pass
   runs at depth 1 (the final weak step Section 3.4 reports using), and the top block is
   formed from what remains.
+* Box-size limit (max_box > 0): when a box of the next level up would hold more than
+  max_box active DOFs, the recursion ends after the current level and every active DOF
+  left forms the top block (Algorithm 1 with its upper levels left uncompressed, so F
+  is no less accurate).  The RS-WS final weak step at depth 1 is skipped likewise.
 
 parity pinned by tests/test_oracle_*.py (dense operator products, LAPACK pivoted
 QR, brute-force factors at tiny N, closed-form counts).
@@ -80,6 +84,7 @@ class Params:
     root_lo: tuple = (0.0, 0.0)
     root_side: float = 1.0          # <= 0: bounding square of the points
     hybrid: bool = False            # RS-WS (Section 3.4, Algorithm 2) instead of RS-S
+    max_box: int = 0                # > 0: end the recursion before a level with larger boxes
 
     @staticmethod
     def from_dict(d: dict) -> "Params":
@@ -318,6 +323,7 @@ class Factor:
     skeletons: dict = field(default_factory=dict)   # (depth, box) -> (S, R) global indices
     level_stats: list = field(default_factory=list)
     weak_skeletons: dict = field(default_factory=dict)   # RS-WS: (depth, box) -> (S, R) of the weak step
+    top_depth: int = -1           # level whose remaining active DOFs form the top block
 
 
 def _lu(X: np.ndarray):
@@ -358,6 +364,19 @@ def _leaf_level(tree: Tree, pts, p) -> _Level:
             for b in ([a] if d == 0 else ring(a, nb, d)):
                 store[(a, b)] = matrix_block(pts, B[a], B[b], p)
     return _Level(tree, t, B, store)
+
+
+def _parent_too_large(lev: _Level, p: Params) -> bool:
+    """Whether a box one level up would hold more than p.max_box active DOFs."""
+    if p.max_box <= 0 or lev.t < 1:
+        return False
+    nb = lev.nb // 2
+    for P in range(nb * nb):
+        px, py = P % nb, P // nb
+        size = sum(len(lev.B[(2 * px + ix) + lev.nb * (2 * py + iy)]) for iy in range(2) for ix in range(2))
+        if size > p.max_box:
+            return True
+    return False
 
 
 def _parent_level(lev: _Level, pts, p) -> _Level:
@@ -545,10 +564,10 @@ def factor(pts: np.ndarray, params, hook=None) -> Factor:
                 skeletons[(lev.t, c)] = (before, np.zeros(0, dtype=np.int64))
         stats.append(dict(depth=lev.t, boxes=lev.nb ** 2, records=nrec,
                           active_after=int(sum(len(b) for b in lev.B))))
-        if lev.t == 2:
+        if lev.t == 2 or _parent_too_large(lev, p):
             break
         lev = _parent_level(lev, pts, p)
-    if p.hybrid and tree.depth >= 2:
+    if p.hybrid and lev.t == 2 and not _parent_too_large(lev, p):
         # the final weak step at depth 1 (Section 3.4)
         lev = _parent_level(lev, pts, p)
         _weak_pass(lev, pts, p, records, weak_skeletons)
@@ -563,7 +582,7 @@ def factor(pts: np.ndarray, params, hook=None) -> Factor:
     top_lu, top_piv = _lu(A_top) if len(top) else (np.zeros((0, 0)), np.zeros(0, dtype=np.int32))
     return Factor(n=len(pts), params=p, depth=tree.depth, records=records, top=top,
                   top_lu=top_lu, top_piv=top_piv, A_top=A_top, skeletons=skeletons,
-                  level_stats=stats, weak_skeletons=weak_skeletons)
+                  level_stats=stats, weak_skeletons=weak_skeletons, top_depth=lev.t)
 
 
 # --------------------------------------------------------------------------

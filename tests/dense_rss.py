@@ -16,6 +16,10 @@ ID rows are all active DOFs at distance 1 and 2 plus the proxies, X[R, C] = X[C,
 for every active DOF C outside the box, and the elimination has J = S; one more weak pass
 runs at depth 1 after the strong pass at depth 2.
 
+With p.max_box > 0 the recursion ends after the first level whose parent boxes would
+hold more than max_box active DOFs (counted here from the geometry and the active mask);
+the final weak pass of RS-WS is skipped when the depth-1 boxes would.
+
 Box membership, near/far sets and the active mask are computed here from the
 geometry directly, not from the oracle's block store or level transitions.  Only
 the ID itself (`cpqr_id`, pinned separately against LAPACK) is shared.
@@ -93,7 +97,17 @@ def replay(pts: np.ndarray, p: O.Params, check_far_unmodified: bool = True):
             A = eliminate(A, S, R, S, T, UT, LT, X, "weak", t, c)
         return A
 
+    def parent_too_large(t):
+        # p.max_box: the largest box one level up, counted from the geometry and the mask
+        if p.max_box <= 0:
+            return False
+        nb = 2 ** (t - 1)
+        bx, by = _box_of(pts, t - 1, lo, side)
+        return np.bincount((bx + nb * by)[active], minlength=nb * nb).max(initial=0) > p.max_box
+
+    top_depth = D
     for t in range(D, 1, -1):
+        top_depth = t
         level_start[t] = A.copy()
         if p.hybrid:
             A = weak_pass(A, t)
@@ -133,11 +147,14 @@ def replay(pts: np.ndarray, p: O.Params, check_far_unmodified: bool = True):
             X[np.ix_(far, R)] = 0.0
             J = np.concatenate([S, Nset])
             A = eliminate(A, S, R, J, T, UT, LT, X, "strong", t, c)
-    if p.hybrid and D >= 2:
+        if parent_too_large(t):
+            break
+    if p.hybrid and D >= 2 and top_depth == 2 and not parent_too_large(2):
+        top_depth = 1
         A = weak_pass(A, 1)
     top = np.nonzero(active)[0]
     Fm = A.copy()
     for st in reversed(steps):
         Fm = st["V"] @ Fm @ st["W"]
     return dict(steps=steps, top=top, A_final=A, F=Fm, K=K, depth=D, far_checks=far_checks,
-                level_start=level_start)
+                level_start=level_start, top_depth=top_depth)

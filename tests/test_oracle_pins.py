@@ -241,9 +241,14 @@ def test_oracle_matches_dense_operator_replay(case):
         pts, p = W.grid_points(24), _params(24, 1e-3, leaf_size=16)
     else:
         pts, p = W.random_points(300, seed=2), O.Params(weight=1.0 / 300, tol=1e-6, leaf_size=8)
+    _check_against_replay(pts, p)
+
+
+def _check_against_replay(pts, p):
     F = O.factor(pts, p)
     ref = dense_rss.replay(pts, p)
     assert ref["far_checks"] > 0
+    assert F.top_depth == ref["top_depth"]
     steps = ref["steps"]
     assert len(steps) == len(F.records)
     scale = np.abs(ref["K"]).max()
@@ -263,6 +268,40 @@ def test_oracle_matches_dense_operator_replay(case):
     eye = np.eye(len(pts))
     np.testing.assert_allclose(O.apply(F, eye), ref["F"], rtol=0, atol=t_tol * scale)
     np.testing.assert_allclose(O.solve(F, eye), np.linalg.inv(ref["F"]), rtol=0, atol=10 * t_tol)
+    return F, ref
+
+
+# Level-start box maxima of these cases without a limit: grid 24 leaf 4 tol 1e-3 (RS-S):
+# 4, 9, 32 at depths 4, 3, 2; grid 20 leaf 4 tol 1e-6 (RS-WS): 4, 9, 25, and about 40 at
+# depth 1 for the final weak step.
+@pytest.mark.parametrize("n,leaf,tol,hybrid,max_box,top_depth", [
+    (24, 4, 1e-3, False, 31, 3),    # the depth-2 boxes (32) exceed: stop after depth 3
+    (24, 4, 1e-3, False, 32, 2),    # exactly at the limit: no stop
+    (24, 4, 1e-3, False, 8, 4),     # the depth-3 boxes (9) exceed: only the leaves
+    (20, 4, 1e-6, True, 20, 3),     # RS-WS: stop after depth 3
+    (20, 4, 1e-6, True, 30, 2),     # RS-WS: the final weak step at depth 1 is skipped
+])
+def test_box_limit_matches_dense_replay(n, leaf, tol, hybrid, max_box, top_depth):
+    # The recursion ends before the first level with a box of more than max_box active
+    # DOFs; the dense replay decides it from the geometry and its own active mask.
+    pts, p = W.grid_points(n), _params(n, tol, leaf_size=leaf, hybrid=hybrid, max_box=max_box)
+    F, ref = _check_against_replay(pts, p)
+    assert F.top_depth == top_depth
+    full = O.factor(pts, _params(n, tol, leaf_size=leaf, hybrid=hybrid))
+    assert full.top_depth == (1 if hybrid else 2)
+    # the records up to the stop are those of the unlimited factorization, and the top
+    # block holds the skeletons of the last level's strong pass
+    kept = [r for r in full.records if r.depth >= top_depth]
+    assert len(F.records) == len(kept)
+    assert (len(kept) < len(full.records)) == (top_depth != full.top_depth)
+    for a, b in zip(F.records, kept):
+        assert (a.depth, a.box) == (b.depth, b.box)
+        assert np.array_equal(a.S, b.S) and np.array_equal(a.R, b.R)
+    last = [S for (t, _), (S, _) in sorted(full.skeletons.items()) if t == top_depth]
+    assert np.array_equal(F.top, np.sort(np.concatenate(last)))
+    A = ref["K"]
+    e_a = np.linalg.norm(A - ref["F"], 2) / np.linalg.norm(A, 2)
+    assert e_a <= 10 * tol
 
 
 @pytest.mark.parametrize("n,leaf,tol", [(24, 9, 1e-6), (24, 4, 1e-3)])
