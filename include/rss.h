@@ -67,6 +67,9 @@ typedef enum { RSS_FP64 = 0, RSS_MIXED = 1 } rss_precision;
  * eq. rws).  RS-WS stores less (Section 3.4). */
 typedef enum { RSS_METHOD_STRONG = 0, RSS_METHOD_HYBRID = 1 } rss_method;
 
+/* Most DOFs the top block (Section 3.3, the final dense factorization) may hold. */
+#define RSS_MAX_TOP 16384
+
 typedef struct {
     uint32_t struct_size;   /* sizeof(rss_params); checked as an ABI guard */
     int32_t  dim;           /* spatial dimension d of the points: 2 */
@@ -102,6 +105,13 @@ typedef struct {
                                executable graph of the same level and pass of its previous
                                factorization, updated in place.  0: launched one by one
                                (the per-phase times of rss_info are split by kernel then) */
+    int32_t  max_box;       /* largest box the recursion compresses, in active DOFs: when a box
+                               of the next level up would hold more, Algorithm 1 ends after the
+                               current level and every active DOF left forms the top block
+                               (its upper levels left uncompressed, so F is no less accurate;
+                               the RS-WS weak step at depth 1 is skipped likewise).  0: the
+                               kernels' limit, 256.  Otherwise 1..256.  A top block of more
+                               than RSS_MAX_TOP DOFs fails with RSS_E_UNSUPPORTED */
     uint64_t arena_bytes;   /* 0: no limit; otherwise the most device memory the factor may
                                hold at any time (store, records, workspaces), failing with
                                RSS_E_ARENA (nothing leaked) when the build needs more */

@@ -688,15 +688,23 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     };
 
     // Level transition to the parent level (B_parent = union of the children's active DOFs);
-    // L goes to the factor's levels.
+    // L goes to the factor's levels.  When a parent box would hold more than max_box active
+    // DOFs nothing is built, L stays, and the returned level has t = -1: the recursion ends
+    // and L's active DOFs form the top block.
+    const int max_box = p.max_box > 0 ? p.max_box : rss::kMaxBox;
     auto transition = [&](rss::Level& L) -> rss::Level {
         hipEvent_t et0 = evs.rec(s);
         rss::Level P;
         P.t = L.t - 1; P.nb = L.nb / 2; P.nbox = P.nb * P.nb;
         P.cnt = dalloc<int>(f, P.nbox);
         const int pmax = std::max(1, level_sizes(L, 2, P.cnt).first);
-        if (pmax > rss::kMaxBox) fail(RSS_E_UNSUPPORTED, "a box holds " + std::to_string(pmax) +
-                                                             " active DOFs (limit 256); lower the tolerance demand");
+        if (pmax > max_box) {
+            defer_free(f, P.cnt, sizeof(int) * (size_t)P.nbox);
+            trans_ev.push_back({et0, evs.rec(s)});
+            rss::Level none;
+            none.t = -1;
+            return none;
+        }
         P.nmax = pmax;
         P.ldJ = 9 * P.nmax;
         P.gidx = dalloc<int>(f, (size_t)P.nbox * P.nmax);
@@ -757,13 +765,19 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
         }
         run_pass(L, 0);
         if (L.t == 2) break;
-        L = transition(L);
+        rss::Level P = transition(L);
+        if (P.t < 0) break;
+        L = std::move(P);
     }
     if (hybrid && L.t == 2) {
         // the final weak step at depth 1 (Section 3.4)
-        L = transition(L);
-        run_pass(L, 1);
+        rss::Level P = transition(L);
+        if (P.t >= 0) {
+            L = std::move(P);
+            run_pass(L, 1);
+        }
     }
+    f->top_depth = L.t;
     if (work) defer_free(f, work, work_n * sizeof(double));
     if (tl_tiles) defer_free(f, tl_tiles, tl_n * sizeof(int));
     if (tl_cnt) defer_free(f, tl_cnt, sizeof(int) * 9 * 8);
@@ -771,6 +785,9 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     // top block
     hipEvent_t eT0 = evs.rec(s);
     const int64_t ntop = level_sizes(L, 1, nullptr).second;
+    if (ntop > RSS_MAX_TOP)
+        fail(RSS_E_UNSUPPORTED, "the top block at depth " + std::to_string(L.t) + " holds " + std::to_string(ntop) +
+                                    " DOFs (limit " + std::to_string(RSS_MAX_TOP) + "): boxes above it exceed max_box");
     f->ntop = ntop;
     f->top_idx = dalloc<int>(f, ntop);
     int* tmap = dalloc<int>(f, ntop);
@@ -780,8 +797,10 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     int* piv = dalloc<int>(f, (size_t)rss::lu_piv_ints(ntop));
     double* dlog = dalloc<double>(f, 1);
     int* dsign = dalloc<int>(f, 1);
-    rss::launch_top_lists(L, f->top_idx, tmap, ntop, s);
+    int* tw = L.nbox > 16 ? dalloc<int>(f, (size_t)2 * ntop) : nullptr;
+    rss::launch_top_lists(L, f->top_idx, tmap, ntop, tw, s);
     check_launch();
+    if (tw) defer_free(f, tw, sizeof(int) * (size_t)2 * ntop);
     rss::launch_top_assemble(L, tmap, f->top_idx, ntop, f->pts, f->kp, f->top_A, s);
     check_launch();
     HIPCHK(hipMemcpyAsync(LU, f->top_A, sizeof(double) * ntop * ntop, hipMemcpyDeviceToDevice, s));
@@ -812,7 +831,7 @@ void factor_impl(rss_factor f, const double* d_points, hipStream_t s) {
     }
     dfree(f, LU, sizeof(double) * ntop * ntop);
     dfree(f, tmap, sizeof(int) * ntop);
-    dfree(f, piv, sizeof(int) * 2 * ntop);
+    dfree(f, piv, sizeof(int) * (size_t)rss::lu_piv_ints(ntop));
     free_store(f, L);
     if (L.krank) f->levels.push_back(std::move(L));
     else {
@@ -1006,6 +1025,7 @@ rss_status rss_factor_create(const double* d_points, int64_t n, const rss_params
     if (!std::isfinite(p->diag) || !std::isfinite(p->weight)) { g_err = "diag/weight not finite"; return RSS_E_ARG; }
     if (p->precision != RSS_FP64 && p->precision != RSS_MIXED) { g_err = "bad precision"; return RSS_E_ARG; }
     if (p->level_graphs != 0 && p->level_graphs != 1) { g_err = "level_graphs must be 0 or 1"; return RSS_E_ARG; }
+    if (p->max_box < 0 || p->max_box > rss::kMaxBox) { g_err = "max_box must be in [0, 256]"; return RSS_E_ARG; }
     rss_factor f = new (std::nothrow) rss_factor_s();
     if (!f) { g_err = "host allocation failed"; return RSS_E_NOMEM; }
     f->params = *p;
@@ -1552,7 +1572,8 @@ rss_status rss_info(rss_factor f, char* buf, int64_t cap) {
     if (!buf || cap < 1) { g_err = "bad buffer"; return RSS_E_ARG; }
     std::ostringstream o;
     o.precision(17);
-    o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"n_top\":" << f->ntop
+    o << "{\"n\":" << f->n << ",\"depth\":" << f->depth << ",\"top_depth\":" << f->top_depth
+      << ",\"n_top\":" << f->ntop
       << ",\"precision\":\"" << (f->params.precision == RSS_MIXED ? "mixed" : "fp64") << "\""
       << ",\"method\":\"" << (f->params.method == RSS_METHOD_HYBRID ? "rs-ws" : "rs-s") << "\""
       << ",\"level_graphs\":" << f->params.level_graphs

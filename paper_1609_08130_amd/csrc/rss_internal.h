@@ -125,6 +125,7 @@ struct rss_factor_s {
     hipStream_t stream = nullptr;   // stream of rss_factor_create (allocations of the factor)
     rss::FFTPlan fft;               // exact operator by FFT when the points form a grid
     int lds_limit = 0;
+    int top_depth = 0;              // level whose remaining active DOFs form the top block
     int64_t ntop = 0;
     int* top_idx = nullptr;
     double* top_A = nullptr;        // ntop x ntop
@@ -258,7 +259,8 @@ void launch_level_sizes(const int* nact, int nb, int group, int* pc, int* out, h
 void launch_compact(const Level& L, Level& C, hipStream_t s);
 void launch_top_assemble(const Level& L, const int* tmap, const int* top_idx, int64_t ntop,
                          const double* pts, const KernelParams& kp, double* A, hipStream_t s);
-void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s);
+// work: 2 ntop ints (used when the level has more than 16 boxes)
+void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, int* work, hipStream_t s);
 
 // skeletonization (rss_idgram.hip, rss_elim.hip, rss_schur.hip)
 // Returns the number of kernels launched.  flag: the factor's device flag word; bit 128

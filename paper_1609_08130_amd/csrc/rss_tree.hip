@@ -6,6 +6,8 @@
 // index.  The block store of a level holds A(B_a, B_b) for every ordered pair of boxes
 // at Chebyshev distance <= 2; pairs further apart are never modified (Theorem 1,
 // Corollary 1) and are evaluated from the kernel when needed.
+#include <climits>
+
 #include "rss_internal.h"
 
 namespace rss {
@@ -524,7 +526,10 @@ void launch_compact(const Level& L, Level& C, hipStream_t s) {
 
 // ------------------------------------------------------------------------------------
 // Top block (Section 3.3, final factorization): the remaining active DOFs of the last
-// level, ascending; tmap[p] = (box << 16) | position in the box's level-start list.
+// level, ascending; tmap[p] = (box << 8) | position in the box's level-start list (as
+// unsigned: positions < kMaxBox = 256, boxes < 2^24).
+static_assert(kMaxBox <= 256, "top map packs a box position into 8 bits");
+
 __global__ void __launch_bounds__(1024) k_top_lists(const int* __restrict__ nact, const int* __restrict__ apos,
                                                    const int* __restrict__ gidx, int nbox, int nmax, int* top_idx,
                                                    int* tmap) {
@@ -564,13 +569,73 @@ __global__ void __launch_bounds__(1024) k_top_lists(const int* __restrict__ nact
             rank += lo - off[c];
         }
         top_idx[rank] = g;
-        tmap[rank] = (b << 16) | ap[e];
+        tmap[rank] = (int)(((unsigned)b << 8) | (unsigned)ap[e]);
     }
 }
 
-void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, hipStream_t s) {
-    (void)ntop;
-    k_top_lists<<<dim3(1), dim3(1024), 0, s>>>(L.nact, L.apos, L.gidx, L.nbox, L.nmax, top_idx, tmap);
+// Any number of boxes (a recursion that ended above depth 2): the active entries are first
+// gathered in box order (one workgroup, a scan of the per-box counts), then each entry's
+// rank is the number of entries with a smaller global index.
+__global__ void __launch_bounds__(1024) k_top_gather(const int* __restrict__ nact, const int* __restrict__ apos,
+                                                    const int* __restrict__ gidx, int nbox, int nmax,
+                                                    int* __restrict__ eg, int* __restrict__ etm) {
+    __shared__ int sc[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nbox; b0 += 1024) {
+        const int b = b0 + (int)threadIdx.x;
+        const int c = b < nbox ? nact[b] : 0;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {   // inclusive scan (Hillis-Steele)
+            const int v = threadIdx.x >= (unsigned)d ? sc[threadIdx.x - d] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const int off = carry + sc[threadIdx.x] - c;
+        for (int i = 0; i < c; ++i) {
+            const int pos = apos[(int64_t)b * nmax + i];
+            eg[off + i] = gidx[(int64_t)b * nmax + pos];
+            etm[off + i] = (int)(((unsigned)b << 8) | (unsigned)pos);
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sc[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_top_rank(const int* __restrict__ eg, const int* __restrict__ etm,
+                                                  int ntop, int* __restrict__ top_idx, int* __restrict__ tmap) {
+    __shared__ int chunk[256];
+    const int e = (int)(blockIdx.x * 256 + threadIdx.x);
+    const int g = e < ntop ? eg[e] : 0;
+    int rank = 0;
+    for (int j0 = 0; j0 < ntop; j0 += 256) {
+        const int j = j0 + (int)threadIdx.x;
+        chunk[threadIdx.x] = j < ntop ? eg[j] : INT_MAX;
+        __syncthreads();
+        const int m = min(256, ntop - j0);
+        for (int q = 0; q < m; ++q) rank += chunk[q] < g ? 1 : 0;
+        __syncthreads();
+    }
+    if (e < ntop) {
+        top_idx[rank] = g;
+        tmap[rank] = etm[e];
+    }
+}
+
+void launch_top_lists(const Level& L, int* top_idx, int* tmap, int64_t ntop, int* work, hipStream_t s) {
+    if (ntop <= 0) return;
+    if (L.nbox <= 16) {
+        k_top_lists<<<dim3(1), dim3(1024), 0, s>>>(L.nact, L.apos, L.gidx, L.nbox, L.nmax, top_idx, tmap);
+        return;
+    }
+    int* eg = work;
+    int* etm = work + ntop;
+    k_top_gather<<<dim3(1), dim3(1024), 0, s>>>(L.nact, L.apos, L.gidx, L.nbox, L.nmax, eg, etm);
+    k_top_rank<<<dim3((unsigned)((ntop + 255) / 256)), dim3(256), 0, s>>>(eg, etm, (int)ntop, top_idx, tmap);
 }
 
 template <typename ST>
@@ -581,8 +646,8 @@ __global__ void k_top_assemble(const ST* __restrict__ store, const double* __res
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ntop * ntop) return;
     int64_t i = e % ntop, j = e / ntop;
-    int a = tmap[i] >> 16, pa = tmap[i] & 0xffff;
-    int b = tmap[j] >> 16, qb = tmap[j] & 0xffff;
+    const int a = (int)((unsigned)tmap[i] >> 8), pa = tmap[i] & 0xff;
+    const int b = (int)((unsigned)tmap[j] >> 8), qb = tmap[j] & 0xff;
     int dx = b % nb - a % nb, dy = b / nb - a / nb;
     double v;
     if (dstore && a == b) {

@@ -63,6 +63,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("method", ctypes.c_int32),
         ("level_graphs", ctypes.c_int32),
+        ("max_box", ctypes.c_int32),
         ("arena_bytes", ctypes.c_uint64),
     ]
 

@@ -56,6 +56,7 @@ def test_params_default_and_argument_errors():
     for field, val, want in [("tol", -1.0, 1), ("tol", float("nan"), 1), ("leaf_size", 0, 1),
                              ("leaf_size", 100000, 1), ("n_proxy", 0, 1), ("proxy_radius", 0.5, 1),
                              ("proxy_radius", 3.0, 1), ("dim", 4, 1), ("kernel", 9, 1), ("method", 2, 1),
+                             ("max_box", -1, 1), ("max_box", 257, 1),
                              ("kernel", rss.RSS_K_HELMHOLTZ2D, 5), ("symmetric", 0, 5)]:
         q = rss.Params()
         lib.rss_params_default(ctypes.byref(q), 2, rss.RSS_K_LAPLACE2D)

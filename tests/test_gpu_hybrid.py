@@ -30,7 +30,8 @@ def rss():
 def _factor(rss, pts, p: O.Params, precision="fp64"):
     return rss.Factor(torch.tensor(pts, dtype=torch.float64, device="cuda"), diag=p.diag, weight=p.weight, tol=p.tol,
                       leaf_size=p.leaf_size, n_proxy=p.n_proxy, proxy_radius=p.proxy_radius, root_lo=p.root_lo,
-                      root_side=p.root_side, precision=precision, method="rs-ws" if p.hybrid else "rs-s")
+                      root_side=p.root_side, precision=precision, method="rs-ws" if p.hybrid else "rs-s",
+                      max_box=p.max_box)
 
 
 def _sets_match(F, sk, weak):
@@ -49,6 +50,12 @@ CASES = {
     "grid100": lambda: (W.grid_points(100), O.Params(**W.problem(100, 1e-6), hybrid=True)),
     "random3000_leaf24": lambda: (W.random_points(3000, seed=7),
                                   O.Params(weight=1.0 / 3000, tol=1e-6, leaf_size=24, hybrid=True)),
+    # box-size limit (level-start maxima 16, 48, 96 at depths 4, 3, 2): the recursion ends
+    # after the leaves (256 boxes form the top block) or after depth 3 (64 boxes)
+    "grid64_leaf16_max40": lambda: (W.grid_points(64), O.Params(**W.problem(64, 1e-6, leaf_size=16), hybrid=True,
+                                                                 max_box=40)),
+    "grid64_leaf16_max60": lambda: (W.grid_points(64), O.Params(**W.problem(64, 1e-6, leaf_size=16), hybrid=True,
+                                                                 max_box=60)),
 }
 
 
@@ -58,7 +65,7 @@ def test_hybrid_parity(rss, case):
     say(f"[hybrid] case={case} N={len(pts)} tol={p.tol} leaf={p.leaf_size}")
     F = _factor(rss, pts, p)
     R = O.factor(pts, p)
-    assert F.shape()[0] == R.depth
+    assert F.shape()[0] == R.depth and F.info()["top_depth"] == R.top_depth
     _sets_match(F, R.weak_skeletons, True)
     _sets_match(F, R.skeletons, False)
     assert np.array_equal(F.top_set(), R.top)

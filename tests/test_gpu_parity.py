@@ -49,7 +49,7 @@ def _gpu_factor(rss, pts, p: O.Params, precision="fp64"):
     d = torch.tensor(pts, dtype=torch.float64, device="cuda")
     return rss.Factor(d, diag=p.diag, weight=p.weight, tol=p.tol, leaf_size=p.leaf_size, n_proxy=p.n_proxy,
                       proxy_radius=p.proxy_radius, root_lo=p.root_lo, root_side=p.root_side,
-                      precision=precision)
+                      precision=precision, max_box=p.max_box)
 
 
 def _compare(rss, name, pts, p, nrhs=1, precision="fp64", records=True, bound=None):
@@ -59,7 +59,7 @@ def _compare(rss, name, pts, p, nrhs=1, precision="fp64", records=True, bound=No
     F = _gpu_factor(rss, pts, p, precision)
     R = O.factor(pts, p)
     depth, ntop = F.shape()
-    assert depth == R.depth
+    assert depth == R.depth and F.info()["top_depth"] == R.top_depth
     compare_skeletons(F, R.skeletons)
     assert np.array_equal(F.top_set(), R.top)
     worst = 0.0
@@ -96,6 +96,27 @@ def test_parity_grid64_tol1e6(rss):
 def test_parity_grid64_other_tolerances(rss, tol):
     n = 64
     _compare(rss, f"grid64_tol{tol}", W.grid_points(n), O.Params(**W.problem(n, tol)))
+
+
+# Box-size limit: level-start box maxima without a limit are 16, 48, 93 (grid 64, leaf 16,
+# tol 1e-6), 16, 64, 122 (tol 1e-9) and 49, 85, 97 (grid 100, leaf 64) at depths 4, 3, 2.
+@pytest.mark.parametrize("name,n,leaf,tol,max_box,precision,top_depth", [
+    ("grid64_leaf16_max40", 64, 16, 1e-6, 40, "fp64", 4),       # top: the 256 leaf boxes
+    ("grid64_leaf16_max40_mixed", 64, 16, 1e-6, 40, "mixed", 4),
+    ("grid64_leaf16_tol1e-9_max100", 64, 16, 1e-9, 100, "fp64", 3),
+    ("grid64_leaf16_tol1e-9_max122", 64, 16, 1e-9, 122, "fp64", 2),   # at the limit: no stop
+    ("grid100_max90", 100, 64, 1e-6, 90, "fp64", 3),
+])
+def test_parity_box_limit_ends_the_recursion(rss, name, n, leaf, tol, max_box, precision, top_depth):
+    p = O.Params(**W.problem(n, tol, leaf_size=leaf), max_box=max_box)
+    assert O.factor(W.grid_points(n), p).top_depth == top_depth
+    # mixed: the FP32 store rounds the ID inputs, so the records are not compared element
+    # by element and F b, F^{-1} b take the mixed factor's bound (as for the full depth)
+    mixed = precision == "mixed"
+    _, _, info = _compare(rss, name, W.grid_points(n), p, nrhs=2, precision=precision, records=not mixed,
+                          bound=mixed_factor_bound(W.grid_points(n), p) if mixed else None)
+    assert info["top_depth"] == top_depth
+    assert min(l["depth"] for l in info["levels"]) == top_depth
 
 
 def test_parity_ragged_grid100_three_levels(rss):
