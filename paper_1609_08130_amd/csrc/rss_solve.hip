@@ -644,11 +644,12 @@ void launch_copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, 
 // run over many workgroups.  Pivots: largest magnitude, lowest row on ties.  The
 // explicit inverse follows by blocked triangular solves against identity columns.
 constexpr int kNB = 32;
+constexpr int kPanelTall = 4096;   // panel rows from which the panel takes the wide-row form
 
 // Panel [k0, k0 + nb): ipiv[k0 + j] = global pivot row of step j.  Also publishes the
 // net row permutation of the panel's interchanges restricted to the rows it moves:
 // sw[0] = count, then pairs (row, source row) meaning new A[row, :] = old A[source, :].
-template <bool INLDS>
+template <bool INLDS, bool TALL>
 __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n, int k0, int* __restrict__ ipiv,
                                                    int* __restrict__ sw, int* flag, double* logdet, int* sign) {
     extern __shared__ double pl[];
@@ -669,10 +670,35 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
         }
         __syncthreads();
     }
+    __shared__ double wbest[16], rowj[kNB];
+    __shared__ int wbi[16];
+    // TALL (panels of kPanelTall rows or more): the pivot search over all 16 waves and one
+    // row per thread in the update; otherwise one wave searches and each wave updates whole
+    // columns (fewer steps per thread).  Same pivots and the same operations either way.
+    constexpr bool tall = TALL;
     double lsum = 0.0;
     int sgn = 1;
     for (int j = 0; j < nb; ++j) {
-        if (wv == 0) {
+        if constexpr (tall) {
+            // largest magnitude, lowest row on ties: per wave, then across the waves
+            double best = -1.0;
+            int bi = m;
+            for (int i = j + tid; i < m; i += 1024) {
+                double v = fabs(P[i + (int64_t)j * ld]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+            }
+            wave_argmax(best, bi);
+            if (lane == 0) { wbest[wv] = best; wbi[wv] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                best = wbest[0];
+                bi = wbi[0];
+                for (int w = 1; w < 16; ++w)
+                    if (wbest[w] > best || (wbest[w] == best && wbi[w] < bi)) { best = wbest[w]; bi = wbi[w]; }
+                piv_idx = bi;
+                piv_val = best;
+            }
+        } else if (wv == 0) {
             double best = -1.0;
             int bi = m;
             for (int i = j + lane; i < m; i += 64) {
@@ -702,11 +728,35 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
         lsum += log(fabs(d));
         if (d < 0) sgn = -sgn;
         const double rinv = 1.0 / d;
-        for (int i = j + 1 + tid; i < m; i += 1024) P[i + (int64_t)j * ld] *= rinv;
+        if constexpr (!tall) {
+            for (int i = j + 1 + tid; i < m; i += 1024) P[i + (int64_t)j * ld] *= rinv;
+            __syncthreads();
+            for (int l = j + 1 + wv; l < nb; l += 16) {
+                const double ajl = P[j + (int64_t)l * ld];
+                for (int i = j + 1 + lane; i < m; i += 64) P[i + (int64_t)l * ld] -= P[i + (int64_t)j * ld] * ajl;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (tid < nb) rowj[tid] = P[j + (int64_t)tid * ld];
         __syncthreads();
-        for (int l = j + 1 + wv; l < nb; l += 16) {
-            const double ajl = P[j + (int64_t)l * ld];
-            for (int i = j + 1 + lane; i < m; i += 64) P[i + (int64_t)l * ld] -= P[i + (int64_t)j * ld] * ajl;
+        // one row per thread: the multiplier, then the row's update right of column j, eight
+        // of the row's entries loaded together at a time
+        for (int i = j + 1 + tid; i < m; i += 1024) {
+            double* Pi = P + i;
+            const double mult = Pi[(int64_t)j * ld] * rinv;
+            Pi[(int64_t)j * ld] = mult;
+#pragma unroll
+            for (int l0 = 0; l0 < kNB; l0 += 8) {
+                if (l0 + 7 <= j || l0 >= nb) continue;
+                double* col = Pi + (int64_t)l0 * ld;
+                double r[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r[q] = (l0 + q > j && l0 + q < nb) ? col[(int64_t)q * ld] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (l0 + q > j && l0 + q < nb) col[(int64_t)q * ld] = r[q] - mult * rowj[l0 + q];
+            }
         }
         __syncthreads();
     }
@@ -950,6 +1000,80 @@ __global__ void __launch_bounds__(256) k_top_inverse_blk(const double* __restric
     }
 }
 
+// The same solves for n beyond what an LDS column block holds: NC columns per workgroup,
+// kept in their own output columns of Ainv (global memory), the solved rows of the current
+// diagonal block staged in LDS.  Each workgroup reads the LU factors once for its NC
+// columns (the one-column form read them once per column).  Same operations in the same
+// order as k_top_inverse_blk.
+template <int NC>
+__global__ void __launch_bounds__(256) k_top_inverse_glb(const double* __restrict__ LU, const int* __restrict__ perm,
+                                                         int n, double* __restrict__ Ainv, const double* __restrict__ Dinv,
+                                                         const int* flag) {
+    __shared__ double D[kNB * kNB];
+    __shared__ double xb[kNB * NC];   // xb[i * NC + c]: row jb + i of the current block
+    const int nblk = (n + kNB - 1) / kNB;
+    const int tid = threadIdx.x;
+    if (*flag & 8) return;
+    const int c0 = blockIdx.x * NC;
+    const int nc = min(NC, n - c0);
+    double* X = Ainv + (int64_t)c0 * n;   // X[i + n c], c < nc
+    for (int64_t e = tid; e < (int64_t)n * nc; e += 256) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        X[e] = (perm[i] == c0 + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // x_blk <- (inverse of the diagonal block) x_blk; xb keeps the result (zero beyond bs)
+    auto diag_apply = [&](int jb, int bs, bool lower) {
+        for (int e = tid; e < kNB * NC; e += 256) {
+            const int i = e / NC, c = e % NC;
+            double v = 0.0;
+            if (i < bs && c < nc) {
+                const double* x = X + (int64_t)n * c + jb;
+                if (lower) for (int j = 0; j <= i; ++j) v += D[i + kNB * j] * x[j];
+                else for (int j = i; j < bs; ++j) v += D[i + kNB * j] * x[j];
+            }
+            xb[e] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < bs * NC; e += 256) {
+            const int i = e / NC, c = e % NC;
+            if (c < nc) X[(int64_t)n * c + jb + i] = xb[e];
+        }
+        __syncthreads();
+    };
+    auto offdiag = [&](int i0, int i1, int jb, int bs) {
+        for (int i = i0 + tid; i < i1; i += 256) {
+            double l[kNB];
+#pragma unroll
+            for (int j = 0; j < kNB; ++j) l[j] = j < bs ? LU[i + (int64_t)(jb + j) * n] : 0.0;
+            for (int c = 0; c < nc; ++c) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < kNB; ++j) v += l[j] * xb[j * NC + c];
+                X[(int64_t)n * c + i] -= v;
+            }
+        }
+    };
+    for (int jb = 0; jb < n; jb += kNB) {            // L y = P e (unit lower)
+        const int bs = min(kNB, n - jb);
+        const double* Di = Dinv + (int64_t)(jb / kNB) * kNB * kNB;
+        for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
+        __syncthreads();
+        diag_apply(jb, bs, true);
+        offdiag(jb + bs, n, jb, bs);
+        __syncthreads();
+    }
+    for (int b = nblk - 1; b >= 0; --b) {            // U x = y
+        const int jb = b * kNB, bs = min(kNB, n - jb);
+        const double* Di = Dinv + (int64_t)(nblk + b) * kNB * kNB;
+        for (int e = tid; e < kNB * kNB; e += 256) D[e] = Di[e];
+        __syncthreads();
+        diag_apply(jb, bs, false);
+        offdiag(0, jb, jb, bs);
+        __syncthreads();
+    }
+}
+
 int64_t lu_piv_ints(int64_t n) { return 2 * n + 4 * kNB + 1; }
 int64_t lu_work_doubles(int64_t n) { return 2 * ((n + kNB - 1) / kNB) * kNB * kNB; }
 
@@ -966,9 +1090,11 @@ void launch_lu_inverse(double* A, double* Ainv, int64_t n64, int* piv, double* w
         const int m = n - k0, nb = std::min(kNB, m);
         const size_t pl = sizeof(double) * (size_t)m * nb;
         if ((long)pl + 1024 <= lim)
-            k_lu_panel<true><<<dim3(1), dim3(1024), pl, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
+            k_lu_panel<true, false><<<dim3(1), dim3(1024), pl, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
+        else if (m >= kPanelTall)
+            k_lu_panel<false, true><<<dim3(1), dim3(1024), 0, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
         else
-            k_lu_panel<false><<<dim3(1), dim3(1024), 0, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
+            k_lu_panel<false, false><<<dim3(1), dim3(1024), 0, s>>>(A, n, k0, ipiv, sw, flag, logdet, sign);
         if (nblk > 1) k_lu_swap_trsm<<<dim3(nblk), dim3(256), 0, s>>>(A, n, k0, sw, flag);
         const int rest = n - k0 - nb;
         if (rest > 0) {
@@ -983,8 +1109,16 @@ void launch_lu_inverse(double* A, double* Ainv, int64_t n64, int* piv, double* w
     const size_t lds = sizeof(double) * (size_t)n * NC;
     if ((long)lds + (long)sizeof(double) * kNB * (kNB + NC) + 1024 > lim) {
         // n beyond what one LDS column block holds (about 2000 DOFs)
-        hipLaunchKernelGGL(k_top_inverse_blk<1>, dim3((unsigned)n), dim3(256), sizeof(double) * (size_t)n, s, A, perm, n,
-                           Ainv, (const double*)work, flag);
+        // columns per workgroup: as many as keep at least 256 workgroups (one per CU)
+        if (n >= 256 * 32)
+            k_top_inverse_glb<32><<<dim3((unsigned)((n + 31) / 32)), dim3(256), 0, s>>>(A, perm, n, Ainv,
+                                                                                        (const double*)work, flag);
+        else if (n >= 256 * 16)
+            k_top_inverse_glb<16><<<dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s>>>(A, perm, n, Ainv,
+                                                                                        (const double*)work, flag);
+        else
+            k_top_inverse_glb<8><<<dim3((unsigned)((n + 7) / 8)), dim3(256), 0, s>>>(A, perm, n, Ainv,
+                                                                                      (const double*)work, flag);
     } else {
         k_top_inverse_blk<NC><<<dim3((unsigned)((n + NC - 1) / NC)), dim3(256), lds, s>>>(A, perm, n, Ainv,
                                                                                           (const double*)work, flag);
