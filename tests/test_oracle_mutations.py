@@ -100,3 +100,28 @@ def test_sqrt_pins_catch_planted_mistake(name):
     old, new = SQRT_MUTATIONS[name]
     assert not _sqrt_pins_hold(_mutant(old, new)), f"mutation {name} not caught"
 
+
+
+LIMIT_MUTATIONS = {
+    # grid 24, leaf 4, tol 1e-3: the depth-2 boxes hold 32 active DOFs
+    "limit_off_by_one": (32, "if size > p.max_box:", "if size >= p.max_box:"),
+    "limit_ignored": (31, "if lev.t == 2 or _parent_too_large(lev, p):", "if lev.t == 2:"),
+    "limit_one_level_late": (8, "size = sum(len(lev.B[(2 * px + ix) + lev.nb * (2 * py + iy)])",
+                             "size = sum(len(lev.B[(2 * px + ix) + lev.nb * (2 * py + iy)]) // 2"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LIMIT_MUTATIONS))
+def test_box_limit_mutation_is_caught(name):
+    max_box, old, new = LIMIT_MUTATIONS[name]
+    pts = W.grid_points(24)
+    p = O.Params(**W.problem(24, 1e-3, leaf_size=4), max_box=max_box)
+    ref = dense_rss.replay(pts, p)
+
+    def agrees(mod):
+        F = mod.factor(pts, mod.Params(**p.__dict__))
+        return (len(F.records) == len(ref["steps"]) and np.array_equal(F.top, ref["top"])
+                and F.top_depth == ref["top_depth"])
+
+    assert agrees(_mutant("TAU = 1e-11", "TAU = 1e-11"))
+    assert not agrees(_mutant(old, new))
