@@ -678,6 +678,74 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
     constexpr bool tall = TALL;
     double lsum = 0.0;
     int sgn = 1;
+    if constexpr (INLDS) {
+        // Panel in LDS: two barriers per column.  Wave 0 updates column j + 1 and finds its
+        // pivot while doing so; the multipliers of column j are formed on the fly in the
+        // update and stored scaled in the next step, beside the row interchange.  Same
+        // pivots and the same operations as the steps below.
+        if (wv == 0) {
+            double best = -1.0;
+            int bi = m;
+            for (int i = lane; i < m; i += 64) {
+                double v = fabs(P[i]);
+                if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+            }
+            wave_argmax(best, bi);
+            if (lane == 0) { piv_idx = bi; piv_val = best; }
+        }
+        __syncthreads();
+        double rprev = 0.0;   // 1 / pivot of column j - 1
+        for (int j = 0; j < nb; ++j) {
+            const int p = piv_idx;
+            if (!(piv_val > 0.0) || p >= m) {
+                if (tid == 0) atomicOr(flag, 8);
+                return;
+            }
+            if (tid == 0) { ipiv[k0 + j] = k0 + p; sp[j] = p; }
+            // column j - 1's multipliers below row j - 1; rows j and p go with the interchange
+            if (j > 0)
+                for (int i = j + tid; i < m; i += 1024)
+                    if (i != j && i != p) P[i + (int64_t)(j - 1) * ld] *= rprev;
+            if (p != j) {
+                for (int l = tid; l < nb; l += 1024) {
+                    double a = P[j + (int64_t)l * ld], b = P[p + (int64_t)l * ld];
+                    if (l == j - 1) { a *= rprev; b *= rprev; }
+                    P[j + (int64_t)l * ld] = b;
+                    P[p + (int64_t)l * ld] = a;
+                }
+                sgn = -sgn;
+            } else if (j > 0 && tid == 0) {
+                P[j + (int64_t)(j - 1) * ld] *= rprev;
+            }
+            __syncthreads();
+            const double d = P[j + (int64_t)j * ld];
+            lsum += log(fabs(d));
+            if (d < 0) sgn = -sgn;
+            const double rinv = 1.0 / d;
+            double best = -1.0;
+            int bi = m;
+            for (int l = j + 1 + wv; l < nb; l += 16) {
+                const double ajl = P[j + (int64_t)l * ld];
+                for (int i = j + 1 + lane; i < m; i += 64) {
+                    const double mult = P[i + (int64_t)j * ld] * rinv;
+                    const double v = P[i + (int64_t)l * ld] - mult * ajl;
+                    P[i + (int64_t)l * ld] = v;
+                    if (l == j + 1) {
+                        const double a = fabs(v);
+                        if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+                    }
+                }
+            }
+            if (wv == 0 && j + 1 < nb) {
+                wave_argmax(best, bi);
+                if (lane == 0) { piv_idx = bi; piv_val = best; }
+            }
+            rprev = rinv;
+            __syncthreads();
+        }
+        for (int i = nb + tid; i < m; i += 1024) P[i + (int64_t)(nb - 1) * ld] *= rprev;
+        __syncthreads();
+    } else
     for (int j = 0; j < nb; ++j) {
         if constexpr (tall) {
             // largest magnitude, lowest row on ties: per wave, then across the waves
