@@ -26,11 +26,11 @@ def rss():
     return mod
 
 
-def _factor(rss, n, precision, method, graphs, tol=1e-6):
-    prm = W.problem(n, tol)
+def _factor(rss, n, precision, method, graphs, tol=1e-6, **kw):
+    prm = W.problem(n, tol, **kw.pop("problem", {}))
     prm.pop("dim")
     pts = torch.tensor(W.grid_points(n), device="cuda")
-    return rss.Factor(pts, precision=precision, method=method, level_graphs=graphs, **prm)
+    return rss.Factor(pts, precision=precision, method=method, level_graphs=graphs, **prm, **kw)
 
 
 def _same(rss, Fa, Fb, n):
@@ -40,7 +40,7 @@ def _same(rss, Fa, Fb, n):
     assert Fa.logdet() == Fb.logdet()
     assert np.array_equal(Fa.top_set(), Fb.top_set())
     depth, _ = Fa.shape()
-    for t in range(depth, 1, -1):
+    for t in range(depth, max(2, Fa.info()["top_depth"]) - 1, -1):
         for box in range(0, 4 ** t, max(1, 4 ** t // 32)):
             (Sa, Ra), (Sb, Rb) = Fa.box_sets(t, box), Fb.box_sets(t, box)
             assert np.array_equal(Sa, Sb) and np.array_equal(Ra, Rb), (t, box)
@@ -65,4 +65,18 @@ def test_level_graphs_equal_stream_launches(rss, n, precision, method):
         Fo = _factor(rss, 32, precision, method, 1)
         Fo.solve(torch.tensor(W.rhs(32 * 32, seed=1), device="cuda"))
         Fo.close()
+    Fs.close()
+
+
+@pytest.mark.parametrize("method", ["rs-s", "rs-ws"])
+def test_level_graphs_with_the_box_limit(rss, method):
+    # the recursion ends after depth 3 (grid 64, leaf 16, max_box 60): the graphs of the
+    # levels it reaches, the same factor as the stream launches
+    say(f"[level_graphs] N=4096 leaf 16 max_box 60 {method}")
+    kw = dict(problem=dict(leaf_size=16), max_box=60)
+    Fs = _factor(rss, 64, "fp64", method, 0, **dict(kw))
+    Fg = _factor(rss, 64, "fp64", method, 1, **dict(kw))
+    assert Fs.info()["top_depth"] == 3 and Fg.info()["top_depth"] == 3
+    _same(rss, Fg, Fs, 64)
+    Fg.close()
     Fs.close()
