@@ -99,3 +99,23 @@ def test_unsupported_kernels_and_modes(rss):
         with pytest.raises(rss.RSSError) as ei:
             _factor(rss, pts, W.problem(16, 1e-6), **kw)
         assert ei.value.name == "RSS_E_UNSUPPORTED", kw
+
+
+def test_top_block_beyond_its_cap(rss):
+    # grid 256, leaf 16, max_box 40: the depth-5 boxes would exceed 40 active DOFs, so the
+    # recursion ends after the leaves with ~49000 DOFs left, beyond the 16384 of the top
+    # block: a clean error naming the top block, and the next factorization still works
+    n = 256
+    pts = W.grid_points(n)
+    prm = W.problem(n, 1e-6, leaf_size=16)
+    say("[errors] top block beyond RSS_MAX_TOP -> RSS_E_UNSUPPORTED")
+    with pytest.raises(rss.RSSError) as ei:
+        _factor(rss, pts, prm, max_box=40)
+    assert ei.value.name == "RSS_E_UNSUPPORTED" and "top block" in str(ei.value)
+    F = _factor(rss, pts, prm, max_box=100)
+    info = F.info()
+    assert 2 <= info["top_depth"] and info["n_top"] <= 16384
+    b = torch.tensor(W.rhs(n * n, seed=0), device="cuda")
+    x = F.solve(b)
+    assert torch.isfinite(x).all() and float(torch.linalg.norm(F.apply(x) - b) / torch.linalg.norm(b)) < 1e-12
+    F.close()
