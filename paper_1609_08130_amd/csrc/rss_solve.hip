@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
             }
             __syncthreads();
             const double d = P[j + (int64_t)j * ld];
-            lsum += log(fabs(d));
+            if (wv == 15) lsum += log(fabs(d));   // off wave 0's pivot chain
             if (d < 0) sgn = -sgn;
             const double rinv = 1.0 / d;
             double best = -1.0;
@@ -834,11 +834,11 @@ __global__ void __launch_bounds__(1024) k_lu_panel(double* __restrict__ A, int n
             A[(k0 + i) + (int64_t)(k0 + j) * n] = P[e];
         }
     }
-    if (tid == 0) {
+    if (tid == (INLDS ? 1023 : 0)) {   // a thread that summed the logarithms
         *logdet = (k0 == 0 ? 0.0 : *logdet) + lsum;
         *sign = (k0 == 0 ? 1 : *sign) * sgn;
-        cnt = 0;
     }
+    if (tid == 0) cnt = 0;
     __syncthreads();
     // net permutation: candidate rows are the panel rows and the pivot rows below it
     if (wv == 0) {
