@@ -106,6 +106,9 @@ def test_parity_grid64_other_tolerances(rss, tol):
     ("grid64_leaf16_tol1e-9_max100", 64, 16, 1e-9, 100, "fp64", 3),
     ("grid64_leaf16_tol1e-9_max122", 64, 16, 1e-9, 122, "fp64", 2),   # at the limit: no stop
     ("grid100_max90", 100, 64, 1e-6, 90, "fp64", 3),
+    # boxes of at most 9 points keep every DOF at the leaves: the top block is all 5184
+    # DOFs (the inverse with 16 columns per workgroup, tall panels, 1024 boxes in the lists)
+    ("grid72_leaf16_max20", 72, 16, 1e-6, 20, "fp64", 5),
 ])
 def test_parity_box_limit_ends_the_recursion(rss, name, n, leaf, tol, max_box, precision, top_depth):
     p = O.Params(**W.problem(n, tol, leaf_size=leaf), max_box=max_box)
